@@ -1,0 +1,198 @@
+/*
+ * dst.h -- C ABI of the MI355X (gfx950) destriping library.
+ *
+ * The library computes the hot path of the polarimeter destriper of
+ * Zonca, Williams, Meinhold & Lubin, "Destriping Cosmic Microwave Background
+ * Polarimeter data" (Astronomy and Computing; arXiv:1309.5609):
+ * the maximum-likelihood baselines a of the destriping equation (Eq. 13)
+ *
+ *       F^T Z F a = F^T Z d,        Z = W - W A M^-1 A^T W,
+ *
+ * by preconditioned conjugate gradient, where each operator application bins
+ * timelines into per-pixel I/Q/U sums (A^T W), applies the inverted per-pixel
+ * weight matrices (M^-1), scans the map back to the timeline (A) and sums
+ * each fixed-length baseline (F^T).
+ *
+ * Notation (Algorithm section, Eqs. 2-9):
+ *   streams k in {T, q, u} of one channel share the pixel p(t) and angle psi(t);
+ *   pointing rows  A_T = (1, 0, 0), A_q = (0, cos2psi, sin2psi),
+ *                  A_u = (0, -sin2psi, cos2psi)              (Eqs. 3-6);
+ *   baseline of sample t: beta(t) = t / L, n_b = ceil(n_samples / L)
+ *                  (fixed sample count per baseline, Polarimeters data section);
+ *   white-noise weights w_k = 1/sigma_k^2, constant per stream;
+ *   per-pixel matrix M_p = sum_t sum_k w_k A_k(t)^T A_k(t)  (block diagonal
+ *                  T | QU; for equal q/u weights the QU block is w h I_2).
+ *
+ * Validity.  A pixel's T block is valid when it has hits; its QU block when
+ * its smaller eigenvalue is positive and lambda_min/lambda_max >= rcond_cut.
+ * A sample enters stream k only when pix >= 0 and the block stream k uses is
+ * valid; other samples are left out of binning and of the baseline sums.
+ *
+ * Memory.  Every array argument is a device pointer owned by the caller
+ * (hipMalloc'd memory or a torch tensor's data_ptr on the context's device),
+ * in the layout stated at the argument.  Timelines are [n_streams][n_samples]
+ * row-major with streams in the order T, q, u restricted to those present;
+ * baseline vectors are [n_streams][n_b]; maps are [n_pix][3] in (I, Q, U)
+ * order.  The library keeps no caller pointer after a call returns and owns
+ * only the workspace inside its context (grown on demand, freed by
+ * dst_destroy).
+ *
+ * Streams and synchrony.  Work is issued on the caller's `stream` (NULL = the
+ * null stream); each entry point returns after that work has completed, so
+ * outputs are ready and device-detected errors are reported by the call that
+ * caused them.
+ *
+ * Errors.  Functions return a dst_status.  Argument errors are found before
+ * any launch and leave outputs untouched.  dst_last_error() gives a message
+ * for the context's most recent failure.  No C++ exception crosses the ABI.
+ *
+ * Threads.  A context may be used by one host thread at a time.
+ */
+#ifndef DST_H
+#define DST_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define DST_ABI_VERSION 1
+
+typedef enum {
+  DST_OK = 0,
+  DST_ENOCONV = 1,        /* warning: max_iter reached; outputs hold the last iterate */
+  DST_EINVAL = -1,        /* invalid argument (null pointer, size, dtype, stream set, weight) */
+  DST_ENOMEM = -2,        /* device workspace allocation failed */
+  DST_EHIP = -3,          /* HIP runtime error; message in dst_last_error */
+  DST_ENAN = -4,          /* non-finite value in the CG recurrences */
+  DST_EDEGENERATE = -5,   /* no valid sample in the problem */
+  DST_EBOUNDS = -6,       /* a pixel index >= n_pix was found in the pointing */
+  DST_EBREAKDOWN = -7     /* CG breakdown: p.Kp <= 0 before convergence */
+} dst_status;
+
+typedef enum { DST_F32 = 1, DST_F64 = 2 } dst_dtype;
+
+/* Stream sets.  q and u always come together (the two channels of a
+ * polarimeter, Algorithm section). */
+enum { DST_T = 1u, DST_Q = 2u, DST_U = 4u, DST_QU = 6u, DST_TQU = 7u };
+
+typedef struct dst_ctx dst_ctx;
+
+/* One channel's destriping problem (Algorithm section, Eqs. 2-8). */
+typedef struct {
+  int64_t n_samples;       /* n_t >= 1 */
+  int64_t n_pix;           /* pixels of the map, >= 1 (12 nside^2 for HEALPix) */
+  int64_t baseline_length; /* L >= 1 samples; the last baseline may be shorter */
+  uint32_t streams;        /* DST_T, DST_QU or DST_TQU */
+  int32_t tod_dtype;       /* dst_dtype of `tod` */
+  int32_t psi_dtype;       /* dst_dtype of `psi` (ignored for DST_T) */
+  int32_t reserved;        /* must be 0 */
+  const int32_t* pix;      /* device [n_samples]; pixel of each sample, < 0 masks the sample */
+  const void* psi;         /* device [n_samples]; polarisation angle psi in radians (NULL for DST_T) */
+  const void* tod;         /* device [n_streams][n_samples]; calibrated timelines in K (may be NULL
+                              where a call states it is not read) */
+  double weight[3];        /* w_T, w_q, w_u > 0 and finite (entries of absent streams ignored) */
+  double rcond_cut;        /* QU-block eigenvalue-ratio cut in [0, 1) */
+} dst_problem;
+
+/* Library ABI version (DST_ABI_VERSION of the build). */
+int dst_version(void);
+
+/* Create a context on HIP device `device`.  *ctx receives the handle. */
+int dst_create(dst_ctx** ctx, int device);
+
+/* Destroy a context and free its workspace (NULL is accepted). */
+int dst_destroy(dst_ctx* ctx);
+
+/* Message describing the context's most recent error ("" if none). */
+const char* dst_last_error(const dst_ctx* ctx);
+
+/* Per-pixel setup (Eq. 9 and the per-pixel weight matrices after Eqs. 10-11).
+ *   hits_out  [n_pix] int32   number of unmasked samples per pixel (NULL to skip)
+ *   blocks_out[n_pix][4] f64  (M_II, M_QQ, M_QU, M_UU) (NULL to skip)
+ *   valid_out [n_pix] uint8   bit 0: T block valid, bit 1: QU block valid (NULL to skip)
+ * Reads pix and psi only. */
+int dst_pixel_setup(dst_ctx* ctx, const dst_problem* prob, int32_t* hits_out, double* blocks_out,
+                    uint8_t* valid_out, void* stream);
+
+/* Binning, Eqs. 10-12 with weights: x = tod - F baselines (tod read when
+ * flags has DST_BIN_USE_TOD, baselines when non-NULL), then
+ *   s_p = sum over valid samples of sum_k w_k A_k(t)^T x_k(t)      (sum maps)
+ * and, with DST_BIN_MAP, m_p = M_p^-1 s_p on valid blocks (0 elsewhere).
+ *   baselines [n_streams][n_b] f64 or NULL
+ *   map_out   [n_pix][3] f64: sums or map
+ *   hits_out  [n_pix] int32 or NULL */
+enum { DST_BIN_USE_TOD = 1u, DST_BIN_MAP = 2u };
+int dst_bin(dst_ctx* ctx, const dst_problem* prob, const double* baselines, uint32_t flags, double* map_out,
+            int32_t* hits_out, void* stream);
+
+/* Scan a map to timelines (the P and R matrices of Eqs. 2-6):
+ *   tod_out_k(t) = A_k(t) . map[p(t)] for unmasked samples, 0 for masked ones.
+ *   map [n_pix][3] f64, tod_out [n_streams][n_samples] f64.  Validity is not
+ * applied (every unmasked sample is scanned).  Reads pix and psi only. */
+int dst_unbin(dst_ctx* ctx, const dst_problem* prob, const double* map, double* tod_out, void* stream);
+
+/* Weighted baseline sums F^T W x over valid samples (the F^T of Eq. 13):
+ *   out_k[beta] = sum_{t in beta, valid_k(t)} w_k x_k(t)
+ *   x [n_streams][n_samples] of dtype prob->tod_dtype (prob->tod is not read),
+ *   out [n_streams][n_b] f64. */
+int dst_baseline_reduce(dst_ctx* ctx, const dst_problem* prob, const void* x, double* out, void* stream);
+
+/* Residual of the destriping equation (Eq. 13) for baselines a:
+ *   out = F^T Z (d - F a)    (= b - K a)
+ * with d = prob->tod (NULL: d = 0) and a [n_streams][n_b] (NULL: a = 0).
+ * out [n_streams][n_b] f64.  No null-space projection is applied. */
+int dst_residual(dst_ctx* ctx, const dst_problem* prob, const double* a, double* out, void* stream);
+
+/* Operator of Eq. 13:  out = K v = F^T Z F v;  v, out [n_streams][n_b] f64. */
+int dst_apply_operator(dst_ctx* ctx, const dst_problem* prob, const double* v, double* out, void* stream);
+
+/* Solver options.  Zero-initialise and set what you need; tol <= 0 selects
+ * 1e-10 and max_iter <= 0 selects 1000. */
+enum {
+  DST_SOLVE_NO_CANON = 1u,    /* return the raw CG iterate (skip the T mean removal) */
+  DST_SOLVE_PROFILE = 2u,     /* time each kernel class with HIP events (into info) */
+  DST_SOLVE_NO_GRAPH = 4u     /* launch iterations one by one instead of a captured graph */
+};
+typedef struct {
+  double tol;               /* stop when ||r||_2 <= tol ||b||_2 (recurrence residual) */
+  int32_t max_iter;
+  int32_t check_every;      /* iterations per host convergence check (<= 0: automatic) */
+  uint32_t flags;
+  int32_t reserved;
+  const double* a0;         /* device [n_streams][n_b] initial guess, or NULL for 0 */
+} dst_solve_opts;
+
+typedef struct {
+  int32_t iterations;       /* CG iterations performed */
+  int32_t converged;        /* 1 if the tolerance was met */
+  double rel_residual;      /* recurrence ||r|| / ||b|| at exit */
+  double true_rel_residual; /* ||b - P K a|| / ||b|| recomputed at exit */
+  double b_norm;            /* ||b||_2 after the null-space projection */
+  int64_t n_valid_pix[2];   /* pixels with a valid T block, with a valid QU block */
+  int64_t n_valid_samples[2];
+  double t_setup_ms;        /* pointing setup + right-hand side */
+  double t_iter_ms;         /* CG loop wall time / iterations */
+  double t_total_ms;
+  /* with DST_SOLVE_PROFILE: mean device time per launch of each kernel class (ms) */
+  double t_bin_ms, t_apply_ms, t_unbin_ms, t_update_ms;
+} dst_solve_info;
+
+/* Destripe one channel (Eq. 13 by PCG, then Eqs. 10-12 for the maps).
+ *   baselines_out [n_streams][n_b] f64   solution a (T baselines with zero
+ *                 mean over baselines holding valid T samples unless
+ *                 DST_SOLVE_NO_CANON)
+ *   map_out       [n_pix][3] f64 or NULL  destriped map m = M^-1 A^T W (d - F a)
+ *   binned_out    [n_pix][3] f64 or NULL  binned map   m = M^-1 A^T W d
+ *   hits_out      [n_pix] int32 or NULL
+ *   info          host struct or NULL
+ * Returns DST_OK, DST_ENOCONV (outputs hold the last iterate) or an error. */
+int dst_solve(dst_ctx* ctx, const dst_problem* prob, const dst_solve_opts* opts, double* baselines_out,
+              double* map_out, double* binned_out, int32_t* hits_out, dst_solve_info* info, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DST_H */

@@ -1,0 +1,571 @@
+// C-ABI layer of the destriping library: argument checks, workspace, the
+// pointing setup shared by every entry point, and the PCG driver of the
+// destriping equation (Eq. 13 of arXiv:1309.5609, solved as the closing
+// paragraph of its Algorithm section describes: by an iterative solver that
+// only applies the operator).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <algorithm>
+#include <cstring>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "dst.h"
+#include "dst_internal.h"
+
+using dst::CgCtl;
+using dst::View;
+
+struct dst_ctx {
+  int device = 0;
+  std::string err;
+  struct Buf {
+    void* ptr = nullptr;
+    size_t bytes = 0;
+  };
+  std::unordered_map<std::string, Buf> ws;
+  CgCtl* ctl_host = nullptr;  // pinned mirror of the device CG scalars
+  int* err_host = nullptr;    // pinned mirror of the device error flag
+};
+
+namespace {
+
+constexpr int64_t kMaxBaselines = (int64_t)1 << 31;
+
+struct DeviceGuard {
+  int prev = -1;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    if (prev != dev) (void)hipSetDevice(dev);
+  }
+  ~DeviceGuard() {
+    if (prev >= 0) (void)hipSetDevice(prev);
+  }
+};
+
+int fail(dst_ctx* ctx, int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  if (ctx) ctx->err = buf;
+  return code;
+}
+
+#define HIP_TRY(expr)                                                                             \
+  do {                                                                                            \
+    hipError_t e_ = (expr);                                                                       \
+    if (e_ != hipSuccess) return fail(ctx, DST_EHIP, "%s: %s (%s:%d)", #expr, hipGetErrorString(e_), \
+                                      __FILE__, __LINE__);                                        \
+  } while (0)
+
+#define DST_TRY(expr)         \
+  do {                        \
+    int rc_ = (expr);         \
+    if (rc_ != DST_OK) return rc_; \
+  } while (0)
+
+// Device workspace slot `name`, grown to at least `bytes`.
+int ws_get(dst_ctx* ctx, const char* name, size_t bytes, void** out) {
+  if (bytes == 0) bytes = 256;
+  auto& b = ctx->ws[name];
+  if (b.bytes < bytes) {
+    if (b.ptr) (void)hipFree(b.ptr);
+    b.ptr = nullptr;
+    b.bytes = 0;
+    size_t want = (bytes + 255) & ~(size_t)255;
+    if (hipMalloc(&b.ptr, want) != hipSuccess) {
+      (void)hipGetLastError();
+      b.ptr = nullptr;
+      return fail(ctx, DST_ENOMEM, "cannot allocate %zu bytes of workspace '%s'", want, name);
+    }
+    b.bytes = want;
+  }
+  *out = b.ptr;
+  return DST_OK;
+}
+
+template <typename T>
+int ws(dst_ctx* ctx, const char* name, size_t count, T** out) {
+  void* p = nullptr;
+  int rc = ws_get(ctx, name, count * sizeof(T), &p);
+  *out = static_cast<T*>(p);
+  return rc;
+}
+
+int stream_rows(uint32_t streams, View& v) {
+  v.rowT = v.rowQ = v.rowU = -1;
+  switch (streams) {
+    case DST_T:
+      v.rowT = 0;
+      v.n_streams = 1;
+      return 0;
+    case DST_QU:
+      v.rowQ = 0;
+      v.rowU = 1;
+      v.n_streams = 2;
+      return 0;
+    case DST_TQU:
+      v.rowT = 0;
+      v.rowQ = 1;
+      v.rowU = 2;
+      v.n_streams = 3;
+      return 0;
+    default:
+      return -1;
+  }
+}
+
+bool is_dtype(int32_t d) { return d == DST_F32 || d == DST_F64; }
+
+// Checks common to every entry point; fills the kernel view.
+int check_problem(dst_ctx* ctx, const dst_problem* prob, bool need_tod, View& v) {
+  if (!ctx) return DST_EINVAL;
+  if (!prob) return fail(ctx, DST_EINVAL, "problem is NULL");
+  if (prob->reserved != 0) return fail(ctx, DST_EINVAL, "problem.reserved must be 0");
+  if (prob->n_samples < 1) return fail(ctx, DST_EINVAL, "n_samples must be >= 1 (got %lld)", (long long)prob->n_samples);
+  if (prob->n_pix < 1 || prob->n_pix > INT32_MAX)
+    return fail(ctx, DST_EINVAL, "n_pix must be in [1, 2^31) (got %lld)", (long long)prob->n_pix);
+  if (prob->baseline_length < 1 || prob->baseline_length > INT32_MAX)
+    return fail(ctx, DST_EINVAL, "baseline_length must be in [1, 2^31) (got %lld)",
+                (long long)prob->baseline_length);
+  if (stream_rows(prob->streams, v) != 0)
+    return fail(ctx, DST_EINVAL, "streams must be DST_T, DST_QU or DST_TQU (got %u)", prob->streams);
+  if (!prob->pix) return fail(ctx, DST_EINVAL, "pix is NULL");
+  if (v.rowQ >= 0) {
+    if (!prob->psi) return fail(ctx, DST_EINVAL, "psi is NULL but q/u streams are present");
+    if (!is_dtype(prob->psi_dtype)) return fail(ctx, DST_EINVAL, "psi_dtype must be DST_F32 or DST_F64");
+  }
+  if (need_tod) {
+    if (!prob->tod) return fail(ctx, DST_EINVAL, "tod is NULL");
+    if (!is_dtype(prob->tod_dtype)) return fail(ctx, DST_EINVAL, "tod_dtype must be DST_F32 or DST_F64");
+  }
+  static const char* names[3] = {"w_T", "w_q", "w_u"};
+  const int rows[3] = {v.rowT, v.rowQ, v.rowU};
+  for (int k = 0; k < 3; ++k) {
+    if (rows[k] < 0) continue;
+    const double w = prob->weight[k];
+    if (!(w > 0.0) || !std::isfinite(w)) return fail(ctx, DST_EINVAL, "%s must be > 0 and finite", names[k]);
+  }
+  if (!(prob->rcond_cut >= 0.0 && prob->rcond_cut < 1.0))
+    return fail(ctx, DST_EINVAL, "rcond_cut must be in [0, 1)");
+  const int64_t n_b = (prob->n_samples + prob->baseline_length - 1) / prob->baseline_length;
+  if (n_b >= kMaxBaselines) return fail(ctx, DST_EINVAL, "too many baselines (%lld)", (long long)n_b);
+  v.pix = prob->pix;
+  v.psi = prob->psi;
+  v.n_t = prob->n_samples;
+  v.n_pix = prob->n_pix;
+  v.L = prob->baseline_length;
+  v.n_b = n_b;
+  for (int k = 0; k < 3; ++k) v.w[k] = rows[k] >= 0 ? prob->weight[k] : 0.0;
+  return DST_OK;
+}
+
+// Per-pixel and per-baseline data every operator needs.
+struct Setup {
+  View v;
+  int psi_f32 = 0;
+  int tod_f32 = 0;
+  int32_t* hits = nullptr;
+  double* M4 = nullptr;
+  double* Minv4 = nullptr;
+  uint8_t* valid = nullptr;
+  int32_t* nvalid = nullptr;
+  double* J = nullptr;
+  unsigned long long* counts = nullptr;  // [0..1] valid pixels T/QU, [2..3] valid samples T/QU
+  int* err = nullptr;
+};
+
+int run_setup(dst_ctx* ctx, const dst_problem* prob, Setup& S, bool baselines, double* blocks_out, hipStream_t st) {
+  View& v = S.v;
+  S.psi_f32 = prob->psi_dtype == DST_F32;
+  S.tod_f32 = prob->tod_dtype == DST_F32;
+  DST_TRY(ws(ctx, "hits", v.n_pix, &S.hits));
+  DST_TRY(ws(ctx, "M4", 4 * v.n_pix, &S.M4));
+  DST_TRY(ws(ctx, "Minv4", 4 * v.n_pix, &S.Minv4));
+  DST_TRY(ws(ctx, "valid", v.n_pix, &S.valid));
+  DST_TRY(ws(ctx, "counts", 4, &S.counts));
+  DST_TRY(ws(ctx, "err", 4, &S.err));
+  HIP_TRY(dst::launch_fill_u32(reinterpret_cast<uint32_t*>(S.hits), v.n_pix, 0u, st));
+  HIP_TRY(dst::launch_fill(S.M4, 4 * v.n_pix, 0.0, st));
+  HIP_TRY(dst::launch_fill_u32(reinterpret_cast<uint32_t*>(S.counts), 8, 0u, st));
+  HIP_TRY(dst::launch_fill_u32(reinterpret_cast<uint32_t*>(S.err), 4, 0u, st));
+  HIP_TRY(dst::launch_pointing(v, S.psi_f32, S.hits, S.M4, S.err, st));
+  HIP_TRY(dst::launch_invert(v, S.hits, S.M4, prob->rcond_cut, S.Minv4, S.valid, blocks_out, S.counts, st));
+  if (baselines) {
+    DST_TRY(ws(ctx, "nvalid", 2 * v.n_b, &S.nvalid));
+    DST_TRY(ws(ctx, "J", (size_t)v.n_streams * v.n_b, &S.J));
+    HIP_TRY(dst::launch_baseline_counts(v, S.valid, S.nvalid, S.J, S.counts + 2, st));
+  }
+  return DST_OK;
+}
+
+// Wait for the stream and report a pixel index out of range.
+int finish(dst_ctx* ctx, const Setup* S, hipStream_t st) {
+  HIP_TRY(hipStreamSynchronize(st));
+  if (S && S->err) {
+    HIP_TRY(hipMemcpy(ctx->err_host, S->err, sizeof(int), hipMemcpyDeviceToHost));
+    if (*ctx->err_host) return fail(ctx, DST_EBOUNDS, "a pixel index >= n_pix (%lld) was found", (long long)S->v.n_pix);
+  }
+  return DST_OK;
+}
+
+// [n_pix][4] kernel layout -> [n_pix][3] user layout.
+hipError_t copy4to3(double* dst3, const double* src4, int64_t n_pix, hipStream_t st) {
+  return hipMemcpy2DAsync(dst3, 3 * sizeof(double), src4, 4 * sizeof(double), 3 * sizeof(double), (size_t)n_pix,
+                          hipMemcpyDeviceToDevice, st);
+}
+
+// out = F^T Z x with x = tod + bsign * F base (either may be NULL).
+int operator_pass(dst_ctx* ctx, Setup& S, const void* tod, const double* base, double bsign, double* out,
+                  hipStream_t st) {
+  const View& v = S.v;
+  double *s4 = nullptr, *m4 = nullptr;
+  DST_TRY(ws(ctx, "s4", 4 * v.n_pix, &s4));
+  DST_TRY(ws(ctx, "m4", 4 * v.n_pix, &m4));
+  HIP_TRY(dst::launch_fill(s4, 4 * v.n_pix, 0.0, st));
+  if (tod || base) HIP_TRY(dst::launch_bin(v, S.psi_f32, tod, S.tod_f32, base, bsign, S.valid, s4, S.err, nullptr, st));
+  HIP_TRY(dst::launch_apply(v.n_pix, s4, S.Minv4, m4, 4, nullptr, nullptr, st));
+  HIP_TRY(dst::launch_unbin_reduce(v, S.psi_f32, tod, S.tod_f32, base, bsign, m4, S.valid, S.nvalid, out, nullptr,
+                                   nullptr, st));
+  return DST_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int dst_version(void) { return DST_ABI_VERSION; }
+
+int dst_create(dst_ctx** out, int device) {
+  if (!out) return DST_EINVAL;
+  *out = nullptr;
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) return DST_EINVAL;
+  dst_ctx* ctx = new (std::nothrow) dst_ctx();
+  if (!ctx) return DST_ENOMEM;
+  ctx->device = device;
+  DeviceGuard g(device);
+  if (hipHostMalloc(reinterpret_cast<void**>(&ctx->ctl_host), sizeof(CgCtl), hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc(reinterpret_cast<void**>(&ctx->err_host), sizeof(int), hipHostMallocDefault) != hipSuccess) {
+    (void)hipGetLastError();
+    dst_destroy(ctx);
+    return DST_ENOMEM;
+  }
+  *out = ctx;
+  return DST_OK;
+}
+
+int dst_destroy(dst_ctx* ctx) {
+  if (!ctx) return DST_OK;
+  DeviceGuard g(ctx->device);
+  (void)hipDeviceSynchronize();
+  for (auto& kv : ctx->ws)
+    if (kv.second.ptr) (void)hipFree(kv.second.ptr);
+  if (ctx->ctl_host) (void)hipHostFree(ctx->ctl_host);
+  if (ctx->err_host) (void)hipHostFree(ctx->err_host);
+  delete ctx;
+  return DST_OK;
+}
+
+const char* dst_last_error(const dst_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+int dst_pixel_setup(dst_ctx* ctx, const dst_problem* prob, int32_t* hits_out, double* blocks_out, uint8_t* valid_out,
+                    void* stream) {
+  View v{};
+  DST_TRY(check_problem(ctx, prob, false, v));
+  ctx->err.clear();
+  DeviceGuard g(ctx->device);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  Setup S;
+  S.v = v;
+  DST_TRY(run_setup(ctx, prob, S, false, blocks_out, st));
+  if (hits_out) HIP_TRY(hipMemcpyAsync(hits_out, S.hits, v.n_pix * sizeof(int32_t), hipMemcpyDeviceToDevice, st));
+  if (valid_out) HIP_TRY(hipMemcpyAsync(valid_out, S.valid, v.n_pix, hipMemcpyDeviceToDevice, st));
+  return finish(ctx, &S, st);
+}
+
+int dst_bin(dst_ctx* ctx, const dst_problem* prob, const double* baselines, uint32_t flags, double* map_out,
+            int32_t* hits_out, void* stream) {
+  View v{};
+  const bool use_tod = flags & DST_BIN_USE_TOD;
+  DST_TRY(check_problem(ctx, prob, use_tod, v));
+  if (!map_out) return fail(ctx, DST_EINVAL, "map_out is NULL");
+  if (flags & ~(uint32_t)(DST_BIN_USE_TOD | DST_BIN_MAP)) return fail(ctx, DST_EINVAL, "unknown flags %u", flags);
+  ctx->err.clear();
+  DeviceGuard g(ctx->device);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  Setup S;
+  S.v = v;
+  DST_TRY(run_setup(ctx, prob, S, false, nullptr, st));
+  double *s4 = nullptr, *m4 = nullptr;
+  DST_TRY(ws(ctx, "s4", 4 * v.n_pix, &s4));
+  HIP_TRY(dst::launch_fill(s4, 4 * v.n_pix, 0.0, st));
+  if (use_tod || baselines)
+    HIP_TRY(dst::launch_bin(v, S.psi_f32, use_tod ? prob->tod : nullptr, S.tod_f32, baselines, -1.0, S.valid, s4,
+                            S.err, nullptr, st));
+  if (flags & DST_BIN_MAP) {
+    HIP_TRY(dst::launch_apply(v.n_pix, s4, S.Minv4, map_out, 3, nullptr, nullptr, st));
+  } else {
+    HIP_TRY(copy4to3(map_out, s4, v.n_pix, st));
+  }
+  (void)m4;
+  if (hits_out) HIP_TRY(hipMemcpyAsync(hits_out, S.hits, v.n_pix * sizeof(int32_t), hipMemcpyDeviceToDevice, st));
+  return finish(ctx, &S, st);
+}
+
+int dst_unbin(dst_ctx* ctx, const dst_problem* prob, const double* map, double* tod_out, void* stream) {
+  View v{};
+  DST_TRY(check_problem(ctx, prob, false, v));
+  if (!map || !tod_out) return fail(ctx, DST_EINVAL, "map and tod_out must not be NULL");
+  ctx->err.clear();
+  DeviceGuard g(ctx->device);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  Setup S;
+  S.v = v;
+  DST_TRY(ws(ctx, "err", 4, &S.err));
+  HIP_TRY(dst::launch_fill_u32(reinterpret_cast<uint32_t*>(S.err), 4, 0u, st));
+  HIP_TRY(dst::launch_scan(v, prob->psi_dtype == DST_F32, map, tod_out, S.err, st));
+  return finish(ctx, &S, st);
+}
+
+int dst_baseline_reduce(dst_ctx* ctx, const dst_problem* prob, const void* x, double* out, void* stream) {
+  View v{};
+  DST_TRY(check_problem(ctx, prob, false, v));
+  if (!x || !out) return fail(ctx, DST_EINVAL, "x and out must not be NULL");
+  if (!is_dtype(prob->tod_dtype)) return fail(ctx, DST_EINVAL, "tod_dtype must be DST_F32 or DST_F64");
+  ctx->err.clear();
+  DeviceGuard g(ctx->device);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  Setup S;
+  S.v = v;
+  DST_TRY(run_setup(ctx, prob, S, false, nullptr, st));
+  HIP_TRY(dst::launch_reduce(v, x, prob->tod_dtype == DST_F32, S.valid, out, st));
+  return finish(ctx, &S, st);
+}
+
+int dst_residual(dst_ctx* ctx, const dst_problem* prob, const double* a, double* out, void* stream) {
+  View v{};
+  DST_TRY(check_problem(ctx, prob, false, v));
+  if (prob->tod && !is_dtype(prob->tod_dtype)) return fail(ctx, DST_EINVAL, "tod_dtype must be DST_F32 or DST_F64");
+  if (!out) return fail(ctx, DST_EINVAL, "out is NULL");
+  ctx->err.clear();
+  DeviceGuard g(ctx->device);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  Setup S;
+  S.v = v;
+  DST_TRY(run_setup(ctx, prob, S, true, nullptr, st));
+  DST_TRY(operator_pass(ctx, S, prob->tod, a, -1.0, out, st));
+  return finish(ctx, &S, st);
+}
+
+int dst_apply_operator(dst_ctx* ctx, const dst_problem* prob, const double* vin, double* out, void* stream) {
+  View v{};
+  DST_TRY(check_problem(ctx, prob, false, v));
+  if (!vin || !out) return fail(ctx, DST_EINVAL, "v and out must not be NULL");
+  ctx->err.clear();
+  DeviceGuard g(ctx->device);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  Setup S;
+  S.v = v;
+  DST_TRY(run_setup(ctx, prob, S, true, nullptr, st));
+  DST_TRY(operator_pass(ctx, S, nullptr, vin, 1.0, out, st));
+  return finish(ctx, &S, st);
+}
+
+int dst_solve(dst_ctx* ctx, const dst_problem* prob, const dst_solve_opts* opts_in, double* baselines_out,
+              double* map_out, double* binned_out, int32_t* hits_out, dst_solve_info* info, void* stream) {
+  View v{};
+  DST_TRY(check_problem(ctx, prob, true, v));
+  if (!baselines_out) return fail(ctx, DST_EINVAL, "baselines_out is NULL");
+  dst_solve_opts opts{};
+  if (opts_in) opts = *opts_in;
+  if (opts.reserved != 0) return fail(ctx, DST_EINVAL, "opts.reserved must be 0");
+  const uint32_t known = DST_SOLVE_NO_CANON | DST_SOLVE_PROFILE | DST_SOLVE_NO_GRAPH;
+  if (opts.flags & ~known) return fail(ctx, DST_EINVAL, "unknown solve flags %u", opts.flags);
+  if (!(opts.tol > 0.0)) opts.tol = 1e-10;
+  if (!std::isfinite(opts.tol)) return fail(ctx, DST_EINVAL, "tol must be finite");
+  if (opts.max_iter <= 0) opts.max_iter = 1000;
+  int check_every = opts.check_every > 0 ? opts.check_every : 10;
+  const bool profile = opts.flags & DST_SOLVE_PROFILE;
+  ctx->err.clear();
+  DeviceGuard g(ctx->device);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+
+  hipEvent_t ev[4];
+  for (auto& e : ev) HIP_TRY(hipEventCreate(&e));
+  struct EvGuard {
+    hipEvent_t* e;
+    int n;
+    ~EvGuard() {
+      for (int i = 0; i < n; ++i) (void)hipEventDestroy(e[i]);
+    }
+  } evg{ev, 4};
+  HIP_TRY(hipEventRecord(ev[0], st));
+
+  Setup S;
+  S.v = v;
+  DST_TRY(run_setup(ctx, prob, S, true, nullptr, st));
+  const int64_t N = (int64_t)v.n_streams * v.n_b;
+  double *b, *a, *r, *z, *p, *q, *ka, *partials, *s4, *m4, *rnorm;
+  CgCtl* ctl;
+  DST_TRY(ws(ctx, "cg_b", N, &b));
+  DST_TRY(ws(ctx, "cg_a", N, &a));
+  DST_TRY(ws(ctx, "cg_r", N, &r));
+  DST_TRY(ws(ctx, "cg_z", N, &z));
+  DST_TRY(ws(ctx, "cg_p", N, &p));
+  DST_TRY(ws(ctx, "cg_q", N, &q));
+  DST_TRY(ws(ctx, "cg_ka", N, &ka));
+  DST_TRY(ws(ctx, "cg_part", 3 * (size_t)std::max<int64_t>(v.n_b, 4096), &partials));
+  DST_TRY(ws(ctx, "s4", 4 * v.n_pix, &s4));
+  DST_TRY(ws(ctx, "m4", 4 * v.n_pix, &m4));
+  DST_TRY(ws(ctx, "cg_rnorm", 1, &rnorm));
+  DST_TRY(ws(ctx, "cg_ctl", 1, &ctl));
+  HIP_TRY(dst::launch_fill_u32(reinterpret_cast<uint32_t*>(ctl), sizeof(CgCtl) / 4, 0u, st));
+
+  // right-hand side b = F^T Z d, and K a0 when an initial guess is given
+  DST_TRY(operator_pass(ctx, S, prob->tod, nullptr, 0.0, b, st));
+  const double* ka_ptr = nullptr;
+  if (opts.a0) {
+    DST_TRY(operator_pass(ctx, S, nullptr, opts.a0, 1.0, ka, st));
+    ka_ptr = ka;
+  }
+  HIP_TRY(dst::launch_cg_start(v, b, ka_ptr, opts.a0, a, r, z, p, S.J, ctl, partials, opts.tol, opts.max_iter, st));
+  HIP_TRY(dst::launch_fill(s4, 4 * v.n_pix, 0.0, st));
+  HIP_TRY(hipEventRecord(ev[1], st));
+  HIP_TRY(hipMemcpyAsync(ctx->ctl_host, ctl, sizeof(CgCtl), hipMemcpyDeviceToHost, st));
+  DST_TRY(finish(ctx, &S, st));
+  if (S.counts) {
+    unsigned long long c[4];
+    HIP_TRY(hipMemcpy(c, S.counts, sizeof c, hipMemcpyDeviceToHost));
+    if (info) {
+      info->n_valid_pix[0] = (int64_t)c[0];
+      info->n_valid_pix[1] = (int64_t)c[1];
+      info->n_valid_samples[0] = (int64_t)c[2];
+      info->n_valid_samples[1] = (int64_t)c[3];
+    }
+    if (c[2] + c[3] == 0) {
+      HIP_TRY(hipMemsetAsync(baselines_out, 0, N * sizeof(double), st));
+      if (map_out) HIP_TRY(hipMemsetAsync(map_out, 0, 3 * v.n_pix * sizeof(double), st));
+      if (binned_out) HIP_TRY(hipMemsetAsync(binned_out, 0, 3 * v.n_pix * sizeof(double), st));
+      if (hits_out)
+        HIP_TRY(hipMemcpyAsync(hits_out, S.hits, v.n_pix * sizeof(int32_t), hipMemcpyDeviceToDevice, st));
+      HIP_TRY(hipStreamSynchronize(st));
+      return fail(ctx, DST_EDEGENERATE, "no valid sample in the problem");
+    }
+  }
+
+  // PCG iterations: bin(F p) -> apply -> unbin+reduce (q = K p, alpha) -> update (beta) -> p
+  std::vector<hipEvent_t> pev;
+  auto one_iteration = [&](bool timed) -> int {
+    hipEvent_t e0 = nullptr, e1 = nullptr, e2 = nullptr, e3 = nullptr, e4 = nullptr;
+    if (timed) {
+      for (hipEvent_t* e : {&e0, &e1, &e2, &e3, &e4}) {
+        HIP_TRY(hipEventCreate(e));
+        pev.push_back(*e);
+      }
+      HIP_TRY(hipEventRecord(e0, st));
+    }
+    HIP_TRY(dst::launch_bin(v, S.psi_f32, nullptr, S.tod_f32, p, 1.0, S.valid, s4, nullptr, ctl, st));
+    if (timed) HIP_TRY(hipEventRecord(e1, st));
+    HIP_TRY(dst::launch_apply(v.n_pix, s4, S.Minv4, m4, 4, s4, ctl, st));
+    if (timed) HIP_TRY(hipEventRecord(e2, st));
+    HIP_TRY(dst::launch_unbin_reduce(v, S.psi_f32, nullptr, S.tod_f32, p, 1.0, m4, S.valid, S.nvalid, q, ctl,
+                                     partials, st));
+    if (timed) HIP_TRY(hipEventRecord(e3, st));
+    HIP_TRY(dst::launch_cg_update(v, a, r, z, p, q, S.J, ctl, partials, st));
+    HIP_TRY(dst::launch_p_update(v, p, z, ctl, st));
+    if (timed) HIP_TRY(hipEventRecord(e4, st));
+    return DST_OK;
+  };
+
+  HIP_TRY(hipEventRecord(ev[2], st));
+  CgCtl& h = *ctx->ctl_host;
+  int launched = 0;
+  while (h.done == dst::DONE_RUNNING && launched < opts.max_iter) {
+    const int k = std::min(check_every, opts.max_iter - launched);
+    for (int i = 0; i < k; ++i) DST_TRY(one_iteration(profile));
+    launched += k;
+    HIP_TRY(hipMemcpyAsync(ctx->ctl_host, ctl, sizeof(CgCtl), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+  }
+  HIP_TRY(hipEventRecord(ev[3], st));
+  const CgCtl fin = h;
+
+  // canonical baselines, true residual, maps
+  if (!(opts.flags & DST_SOLVE_NO_CANON)) HIP_TRY(dst::launch_canonicalise(v, a, S.J, partials, ctl, st));
+  DST_TRY(operator_pass(ctx, S, nullptr, a, 1.0, ka, st));
+  HIP_TRY(dst::launch_residual_norm(v, b, ka, S.J, ctl, partials, rnorm, st));
+  HIP_TRY(hipMemcpyAsync(baselines_out, a, N * sizeof(double), hipMemcpyDeviceToDevice, st));
+  if (map_out) {
+    HIP_TRY(dst::launch_fill(s4, 4 * v.n_pix, 0.0, st));
+    HIP_TRY(dst::launch_bin(v, S.psi_f32, prob->tod, S.tod_f32, a, -1.0, S.valid, s4, S.err, nullptr, st));
+    HIP_TRY(dst::launch_apply(v.n_pix, s4, S.Minv4, map_out, 3, nullptr, nullptr, st));
+  }
+  if (binned_out) {
+    HIP_TRY(dst::launch_fill(s4, 4 * v.n_pix, 0.0, st));
+    HIP_TRY(dst::launch_bin(v, S.psi_f32, prob->tod, S.tod_f32, nullptr, 0.0, S.valid, s4, S.err, nullptr, st));
+    HIP_TRY(dst::launch_apply(v.n_pix, s4, S.Minv4, binned_out, 3, nullptr, nullptr, st));
+  }
+  if (hits_out) HIP_TRY(hipMemcpyAsync(hits_out, S.hits, v.n_pix * sizeof(int32_t), hipMemcpyDeviceToDevice, st));
+  double true_norm = 0.0;
+  HIP_TRY(hipMemcpyAsync(ctx->err_host, S.err, sizeof(int), hipMemcpyDeviceToHost, st));
+  DST_TRY(finish(ctx, &S, st));
+  HIP_TRY(hipMemcpy(&true_norm, rnorm, sizeof(double), hipMemcpyDeviceToHost));
+
+  if (info) {
+    info->iterations = fin.iter;
+    info->converged = fin.done == dst::DONE_CONVERGED;
+    info->b_norm = fin.b_norm;
+    info->rel_residual = fin.b_norm > 0.0 ? fin.r_norm / fin.b_norm : 0.0;
+    info->true_rel_residual = fin.b_norm > 0.0 ? true_norm / fin.b_norm : 0.0;
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, ev[0], ev[1]));
+    info->t_setup_ms = ms;
+    HIP_TRY(hipEventElapsedTime(&ms, ev[2], ev[3]));
+    info->t_iter_ms = fin.iter > 0 ? ms / fin.iter : 0.0;
+    HIP_TRY(hipEventElapsedTime(&ms, ev[0], ev[3]));
+    info->t_total_ms = ms;
+    info->t_bin_ms = info->t_apply_ms = info->t_unbin_ms = info->t_update_ms = 0.0;
+    if (profile && !pev.empty()) {
+      // only iterations that ran (not the early-exit launches) count
+      const size_t n_it = pev.size() / 5;
+      const size_t used = std::min<size_t>(n_it, (size_t)std::max(fin.iter, 0));
+      double acc[4] = {0, 0, 0, 0};
+      for (size_t i = 0; i < used; ++i) {
+        for (int j = 0; j < 4; ++j) {
+          float t = 0.f;
+          HIP_TRY(hipEventElapsedTime(&t, pev[5 * i + j], pev[5 * i + j + 1]));
+          acc[j] += t;
+        }
+      }
+      if (used) {
+        info->t_bin_ms = acc[0] / used;
+        info->t_apply_ms = acc[1] / used;
+        info->t_unbin_ms = acc[2] / used;
+        info->t_update_ms = acc[3] / used;
+      }
+    }
+  }
+  for (auto e : pev) (void)hipEventDestroy(e);
+  switch (fin.done) {
+    case dst::DONE_CONVERGED:
+      return DST_OK;
+    case dst::DONE_MAXITER:
+    case dst::DONE_RUNNING:
+      fail(ctx, DST_ENOCONV, "no convergence in %d iterations (rel residual %.3e)", fin.iter,
+           fin.b_norm > 0 ? fin.r_norm / fin.b_norm : 0.0);
+      return DST_ENOCONV;
+    case dst::DONE_BREAKDOWN:
+      return fail(ctx, DST_EBREAKDOWN, "CG breakdown after %d iterations", fin.iter);
+    default:
+      return fail(ctx, DST_ENAN, "non-finite value in the CG recurrences after %d iterations", fin.iter);
+  }
+}
+
+}  // extern "C"

@@ -1,0 +1,232 @@
+"""Parity of the HIP library (through its C ABI) with the FP64 oracle.
+
+Bars: hit counts and validity flags bit-exact; per-pixel blocks, sums, maps,
+scans, baseline sums and the operator K within 1e-12 relative (FP64 with a
+different summation order); solved baselines and maps within 1e-9 relative
+at a tight CG tolerance (the spec FP64 bar), with the T baselines
+canonicalised on both sides.
+"""
+import numpy as np
+import pytest
+
+from oracle import destripe as O
+from problems import args, tiny, toy
+
+pytestmark = pytest.mark.gpu
+
+
+def rel(a, b):
+    a, b = np.asarray(a, float), np.asarray(b, float)
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_1309_5609_amd import dst
+    c = dst.Context(0)
+    yield c
+    c.close()
+
+
+def dev(p, **kw):
+    from paper_1309_5609_amd import dst
+    return dst.to_device(p, **kw)
+
+
+def prep(p, rcond=1e-3):
+    return O.prepare(p.pix, p.psi, p.n_pix, p.baseline_length, p.streams, p.weights, rcond)
+
+
+VARIANTS = {
+    "plain": dict(),
+    "masked": dict(mask_fraction=0.07),
+    "ragged": dict(n_samples=9037, L=211),
+    "unequal": dict(weights=(2.0e6, 5.0e6, 0.7e6)),
+    "QU": dict(streams="QU"),
+    "T": dict(streams="T"),
+    "L1": dict(n_samples=700, L=1),
+    "L37": dict(n_samples=3001, L=37),
+}
+
+
+def make(name):
+    return toy(**VARIANTS[name])
+
+
+@pytest.mark.parametrize("name", list(VARIANTS))
+def test_pixel_setup(ctx, name):
+    from paper_1309_5609_amd import dst
+    p = make(name)
+    st = prep(p)
+    hits, blocks, valid = dst.dst_pixel_setup(ctx, dev(p))
+    assert np.array_equal(hits.cpu().numpy(), st.hits)
+    v = valid.cpu().numpy()
+    assert np.array_equal((v & 1) > 0, st.valid_T)
+    assert np.array_equal((v & 2) > 0, st.valid_QU)
+    bl = blocks.cpu().numpy()
+    ref = np.stack([st.M[:, 0, 0], st.M[:, 1, 1], st.M[:, 1, 2], st.M[:, 2, 2]], axis=1)
+    assert rel(bl, ref) < 1e-13
+
+
+@pytest.mark.parametrize("name", list(VARIANTS))
+def test_bin_and_map(ctx, name):
+    from paper_1309_5609_amd import dst
+    import torch
+    p = make(name)
+    st = prep(p)
+    dp = dev(p)
+    sums, hits = dst.dst_bin(ctx, dp)
+    assert np.array_equal(hits.cpu().numpy(), st.hits)
+    assert rel(sums.cpu().numpy(), O.bin_compact(st, p.tod)) < 1e-12
+    m, _ = dst.dst_bin(ctx, dp, as_map=True)
+    assert rel(m.cpu().numpy(), O.map_compact(st, p.tod)) < 1e-12
+    # with baselines subtracted
+    a = np.random.default_rng(1).standard_normal((dp.n_streams, dp.n_baselines)) * 1e-3
+    m2, _ = dst.dst_bin(ctx, dp, baselines=torch.from_numpy(a).cuda(), as_map=True)
+    assert rel(m2.cpu().numpy(), O.map_compact(st, p.tod, a)) < 1e-12
+
+
+@pytest.mark.parametrize("name", ["plain", "masked", "QU", "T"])
+def test_unbin(ctx, name):
+    from paper_1309_5609_amd import dst
+    import torch
+    p = make(name)
+    st = prep(p)
+    m = np.random.default_rng(2).standard_normal((p.n_pix, 3))
+    y = dst.dst_unbin(ctx, dev(p), torch.from_numpy(m).cuda()).cpu().numpy()
+    ref = O.scan_compact(st, m)
+    assert rel(y, ref) < 1e-14
+
+
+@pytest.mark.parametrize("name", list(VARIANTS))
+def test_baseline_reduce(ctx, name):
+    from paper_1309_5609_amd import dst
+    import torch
+    p = make(name)
+    st = prep(p)
+    x = np.random.default_rng(3).standard_normal(p.tod.shape)
+    out = dst.dst_baseline_reduce(ctx, dev(p), torch.from_numpy(x).cuda()).cpu().numpy()
+    assert rel(out, O.reduce_compact(st, x)) < 1e-13
+
+
+@pytest.mark.parametrize("name", list(VARIANTS))
+def test_operator_and_rhs(ctx, name):
+    from paper_1309_5609_amd import dst
+    import torch
+    p = make(name)
+    st = prep(p)
+    dp = dev(p)
+    v = np.random.default_rng(4).standard_normal((dp.n_streams, dp.n_baselines))
+    Kv = dst.dst_apply_operator(ctx, dp, torch.from_numpy(v).cuda()).cpu().numpy()
+    assert rel(Kv, O.K_compact(st, v)) < 1e-12
+    b = dst.dst_residual(ctx, dp).cpu().numpy()
+    assert rel(b, O.rhs_compact(st, p.tod)) < 1e-12
+    # residual with baselines: b - K v
+    r = dst.dst_residual(ctx, dp, a=torch.from_numpy(v).cuda()).cpu().numpy()
+    assert rel(r, O.rhs_compact(st, p.tod) - O.K_compact(st, v)) < 1e-12
+
+
+@pytest.mark.parametrize("name", list(VARIANTS))
+def test_solve_tight(ctx, name):
+    from paper_1309_5609_amd import dst
+    p = make(name)
+    ref = O.solve(*args(p), tol=1e-13, max_iter=3000)
+    out = dst.dst_solve(ctx, dev(p), tol=1e-13, max_iter=3000)
+    assert out["converged"] == 1
+    assert np.array_equal(out["hits"].cpu().numpy(), ref.hits)
+    assert rel(out["baselines"].cpu().numpy(), ref.baselines) < 1e-9
+    obs = ref.hits > 0
+    assert rel(out["destriped_map"].cpu().numpy()[obs], ref.destriped_map[obs]) < 1e-9
+    assert rel(out["binned_map"].cpu().numpy()[obs], ref.binned_map[obs]) < 1e-12
+    assert out["true_rel_residual"] < 1e-11
+
+
+def test_solve_iteration_parity(ctx):
+    """Same algorithm, same tolerance: the iteration counts agree (within one)."""
+    from paper_1309_5609_amd import dst
+    p = toy(n_samples=30000, nside=16)
+    ref = O.solve(*args(p), tol=1e-10, max_iter=1000)
+    out = dst.dst_solve(ctx, dev(p), tol=1e-10, max_iter=1000)
+    assert abs(out["iterations"] - ref.iterations) <= 1
+    assert out["rel_residual"] <= 1e-10
+
+
+def test_signal_only_null_baselines(ctx):
+    from paper_1309_5609_amd import dst
+    p = toy(noise=False)
+    out = dst.dst_solve(ctx, dev(p), tol=1e-10)
+    rms = np.sqrt(np.mean(p.tod ** 2))
+    assert np.max(np.abs(out["baselines"].cpu().numpy())) <= 1e-12 * rms
+
+
+def test_pure_offsets(ctx):
+    from paper_1309_5609_amd import dst
+    p = toy(noise=False, offsets_rms=1e-3)
+    out = dst.dst_solve(ctx, dev(p), tol=1e-13)
+    st = prep(p)
+    assert rel(out["baselines"].cpu().numpy(), O.canonical_compact(st, p.offsets)) < 1e-9
+
+
+def test_workload0_full_size(ctx):
+    """The 6 h, N_side 64 workload at full size against the oracle."""
+    from paper_1309_5609_amd import dst
+    from synth import workload
+    p = workload(0)
+    ref = O.solve(*args(p), tol=1e-13, max_iter=2000)
+    out = dst.dst_solve(ctx, dev(p), tol=1e-13, max_iter=2000)
+    assert np.array_equal(out["hits"].cpu().numpy(), ref.hits)
+    assert rel(out["baselines"].cpu().numpy(), ref.baselines) < 1e-9
+    obs = ref.hits > 0
+    m = out["destriped_map"].cpu().numpy()
+    for c in range(3):
+        assert rel(m[obs, c], ref.destriped_map[obs, c]) < 1e-9
+    # at the benchmark tolerance the two solvers take the same number of steps
+    ref10 = O.solve(*args(p), tol=1e-10, max_iter=2000)
+    out10 = dst.dst_solve(ctx, dev(p), tol=1e-10, max_iter=2000)
+    assert abs(out10["iterations"] - ref10.iterations) <= 1
+
+
+def test_restart_from_a0(ctx):
+    """Resuming from a previous solution converges at once (checkpoint/resume)."""
+    from paper_1309_5609_amd import dst
+    p = toy()
+    dp = dev(p)
+    first = dst.dst_solve(ctx, dp, tol=1e-12, flags=dst.DST_SOLVE_NO_CANON)
+    again = dst.dst_solve(ctx, dp, tol=1e-6, a0=first["baselines"])
+    assert again["iterations"] <= 1
+    assert rel(again["baselines"].cpu().numpy(), first["baselines"].cpu().numpy() -
+               np.array([[first["baselines"][0].mean().item()], [0], [0]])) < 1e-6
+
+
+def test_errors(ctx):
+    from paper_1309_5609_amd import dst
+    import torch
+    p = toy()
+    dp = dev(p)
+    # pixel index out of range is detected on the device
+    bad = dst.Problem(dp.pix.clone(), dp.psi, dp.tod, dp.n_pix, dp.baseline_length, dp.streams, dp.weights)
+    bad.pix[17] = p.n_pix + 5
+    with pytest.raises(dst.DstError) as e:
+        dst.dst_bin(ctx, bad)
+    assert e.value.code == -6
+    # argument errors
+    for kw in (dict(baseline_length=0), dict(n_pix=0), dict(weights=(1.0, -1.0, 1.0)), dict(streams="T"),
+               dict(rcond_cut=1.0)):
+        q = dst.Problem(dp.pix, dp.psi, dp.tod, dp.n_pix, dp.baseline_length, dp.streams, dp.weights)
+        for k, val in kw.items():
+            setattr(q, k, val)
+        if kw.get("streams") == "T":
+            q.psi = None
+            q.tod = dp.tod[:1]
+            q.weights = (float("nan"), 1.0, 1.0)
+        with pytest.raises(dst.DstError) as e:
+            dst.dst_bin(ctx, q)
+        assert e.value.code == -1
+    # non-convergence returns the last iterate with DST_ENOCONV
+    out = dst.dst_solve(ctx, dp, tol=1e-14, max_iter=2)
+    assert out["status"] == 1 and out["iterations"] == 2 and out["converged"] == 0
+    # no valid sample at all
+    q = dst.Problem(torch.full_like(dp.pix, -1), dp.psi, dp.tod, dp.n_pix, dp.baseline_length, dp.streams, dp.weights)
+    with pytest.raises(dst.DstError) as e:
+        dst.dst_solve(ctx, q)
+    assert e.value.code == -5
