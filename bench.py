@@ -1,0 +1,198 @@
+#!/usr/bin/env python3
+"""Destriping throughput on one MI355X: samples x CG-iterations per second.
+
+One step is one complete destriping solve of the workload through the C ABI
+(``dst_solve``): pointing setup (hits, per-pixel blocks and their inverse,
+baseline counts), right-hand side, preconditioned CG to the tolerance, and
+the binned and destriped maps.  ``value`` is n_samples x CG iterations summed
+over the timed steps divided by their wall time, with the inputs already in
+HBM.  The per-kernel device times come from HIP events the library records
+on its stream during the timed steps.
+
+Workloads (seeded synthetic inputs, see ``synth``):
+  1 (default): 30 days at 50 Hz = 129,600,000 samples, HEALPix N_side 256,
+     3000-sample baselines (43,200 per stream), T/q/u streams, white 1 mK +
+     1/f noise (f_k = 50 mHz, alpha = 1.7), FP64, CG to 1e-10.
+  0: 6 h = 1,080,000 samples at N_side 64, same scan and noise, FP64.
+  2: workload 1 with FP32 timelines and angles (FP64 accumulation and CG).
+
+Prints one JSON line on stdout; progress goes to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "samples x CG-iters/s per GPU (FP64 plain vs FP32-mixed batched); HBM GB/s % of peak"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg: str) -> None:
+    print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
+
+
+def workload_name(w: int, fk: float) -> str:
+    if w == 0:
+        return (f"6-hour single-channel destripe: 1,080,000 samples at 50 Hz, HEALPix N_side 64, "
+                f"3000-sample baselines, T/q/u, f_k {fk * 1e3:g} mHz, alpha 1.7, FP64")
+    prec = "FP64" if w == 1 else "FP32 timelines and angles, FP64 accumulation and CG"
+    return (f"30-day single-channel destripe: 129,600,000 samples at 50 Hz, HEALPix N_side 256, "
+            f"3000-sample baselines (43,200 per stream), T/q/u, f_k {fk * 1e3:g} mHz, alpha 1.7, {prec}")
+
+
+def algorithmic_bytes(n_t: int, n_obs: int, n_b: int, s_psi: int) -> dict:
+    """Bytes each kernel of one CG iteration must move (per launch).
+
+    bin:    pointing (4 B pixel + s_psi angle) per sample, p (3 x 8 B per
+            baseline) in, the 3 sums of each observed pixel out (24 B);
+    unbin:  pointing per sample, the 3 map values of each observed pixel in,
+            p in and q out (2 x 3 x 8 B per baseline).
+    """
+    return {
+        "bin": n_t * (4 + s_psi) + n_obs * 24 + 3 * n_b * 8,
+        "unbin": n_t * (4 + s_psi) + n_obs * 24 + 2 * 3 * n_b * 8,
+    }
+
+
+def cpu_baseline(p, seconds_target: float = 20.0) -> dict:
+    """The oracle's operator on the first day of the workload, single-threaded NumPy."""
+    import numpy as np
+
+    from oracle import destripe as O
+
+    n = min(p.n_samples, 4_320_000)
+    sl = slice(0, n)
+    psi = None if p.psi is None else np.asarray(p.psi[sl], dtype=np.float64)
+    st = O.prepare(p.pix[sl], psi, p.n_pix, p.baseline_length, p.streams, p.weights)
+    v = np.random.default_rng(0).standard_normal((3, st.pt.n_b))
+    iters = 0
+    t0 = time.perf_counter()
+    while True:
+        O.apply_K(st, v)
+        iters += 1
+        el = time.perf_counter() - t0
+        if el > seconds_target or iters >= 8:
+            break
+    return {"value": n * iters / el, "unit": "samples*CG-iters/s", "cores": 1, "kind": "oracle",
+            "sample": (f"first {n:,} samples (1 day) of the same workload; {iters} applications of the oracle's "
+                       f"K = F^T Z F (one CG iteration each), NumPy FP64 single-threaded, after its setup; "
+                       f"{el:.1f} s")}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", type=int, default=1, choices=(0, 1, 2))
+    ap.add_argument("--fknee", type=float, default=0.05)
+    ap.add_argument("--tol", type=float, default=1e-10)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a 1 GiB device copy (reference kernel for HBM counters)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): the destriping path of this library is "
+              f"single-GPU; independent channels and realizations shard across GPUs with no exchange.",
+              file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    from paper_1309_5609_amd import dst
+    from synth import workload
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        return 1
+    log(f"generating workload {args.workload} (f_k {args.fknee} Hz)")
+    t = time.perf_counter()
+    p = workload(args.workload, fknee_hz=args.fknee)
+    log(f"generated {p.n_samples:,} samples in {time.perf_counter() - t:.1f} s")
+    dp = dst.to_device(p)
+    torch.cuda.synchronize()
+    log("inputs resident in HBM")
+    ctx = dst.Context(0)
+
+    if args.copy_calibration:
+        src = torch.empty(1 << 27, dtype=torch.float64, device="cuda")
+        dstb = torch.empty_like(src)
+        src.fill_(1.0)
+        dstb.copy_(src)
+        torch.cuda.synchronize()
+        del src, dstb
+
+    for i in range(args.warmup):
+        out = dst.dst_solve(ctx, dp, tol=args.tol, max_iter=2000, flags=dst.DST_SOLVE_PROFILE)
+        log(f"warmup {i}: {out['iterations']} iterations, {out['t_total_ms']:.1f} ms")
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    runs = []
+    for i in range(args.steps):
+        runs.append(dst.dst_solve(ctx, dp, tol=args.tol, max_iter=2000, flags=dst.DST_SOLVE_PROFILE))
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    iters = sum(r["iterations"] for r in runs)
+    value = p.n_samples * iters / wall
+    r0 = runs[-1]
+    log(f"timed {args.steps} solves: {wall * 1e3:.1f} ms, {iters} iterations, {value:.3e} samples*iters/s")
+
+    n_obs = int(r0["n_valid_pix"][0])
+    s_psi = 4 if args.workload == 2 else 8
+    algo = algorithmic_bytes(p.n_samples, n_obs, p.n_baselines, s_psi)
+    k_ms = {k: float(np.mean([r[f"t_{k}_ms"] for r in runs])) for k in ("bin", "apply", "unbin", "update")}
+    dom = max(("bin", "unbin"), key=lambda k: k_ms[k])
+    achieved = algo[dom] / (k_ms[dom] * 1e-3) / 1e9
+    iter_ms = float(np.mean([r["t_iter_ms"] for r in runs]))
+    b_iter = algo["bin"] + algo["unbin"]
+
+    line = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "samples*CG-iters/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if args.workload != 2 else "f32-in/f64",
+        "data": "synthetic",
+        "config": {"workload": workload_name(args.workload, args.fknee), "n_samples": p.n_samples,
+                   "n_pix": p.n_pix, "baseline_length": p.baseline_length, "n_baselines": p.n_baselines,
+                   "streams": p.streams, "tol": args.tol, "parallelism": "1 GPU"},
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "algorithmic_bytes_per_launch": algo[dom], "avg_launch_ms": k_ms[dom]},
+        "iterations_per_solve": r0["iterations"],
+        "iter_ms": iter_ms,
+        "iteration_throughput": p.n_samples / (iter_ms * 1e-3),
+        "iteration_hbm_frac": b_iter / (iter_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+        "setup_ms": float(np.mean([r["t_setup_ms"] for r in runs])),
+        "kernel_ms": k_ms,
+        "rel_residual": r0["rel_residual"],
+        "true_rel_residual": r0["true_rel_residual"],
+        "observed_pixels": n_obs,
+    }
+    if not args.no_cpu_baseline:
+        log("timing the oracle on the host")
+        line["cpu_baseline"] = cpu_baseline(p)
+    else:
+        line["cpu_baseline"] = None
+    ctx.close()
+    print(json.dumps(line), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -16,6 +16,7 @@
 
 #include "dst.h"
 #include "dst_internal.h"
+#include "dst_pixel.h"
 
 using dst::CgCtl;
 using dst::View;
@@ -236,6 +237,84 @@ int operator_pass(dst_ctx* ctx, Setup& S, const void* tod, const double* base, d
   return DST_OK;
 }
 
+
+// Solver setup: the pixel-major transpose of the pointing with compact pixel
+// ids, per-pixel blocks from it (no atomics), and the per-baseline counts and
+// Jacobi diagonal.  Every solver kernel works in compact pixel space (S.v has
+// pix = the compact ids, n_pix = observed pixels); outputs are scattered back.
+struct Plan {
+  Setup S;
+  View full;
+  dst::Transpose T;
+  double* m4 = nullptr;   // per-iteration map (zero on invalid pixels)
+  double* pw4 = nullptr;  // weighted interleaved baseline vector
+};
+
+int build_plan(dst_ctx* ctx, const dst_problem* prob, Plan& P, hipStream_t st) {
+  Setup& S = P.S;
+  const View& v = P.full;
+  if ((uint64_t)v.n_t >= ((uint64_t)1 << 32))
+    return fail(ctx, DST_EINVAL, "the solver needs n_samples < 2^32 (got %lld)", (long long)v.n_t);
+  S.psi_f32 = prob->psi_dtype == DST_F32;
+  S.tod_f32 = prob->tod_dtype == DST_F32;
+  dst::Transpose& T = P.T;
+  DST_TRY(ws(ctx, "keys0", v.n_t, &T.keys[0]));
+  DST_TRY(ws(ctx, "keys1", v.n_t, &T.keys[1]));
+  DST_TRY(ws(ctx, "vals0", v.n_t, &T.vals[0]));
+  DST_TRY(ws(ctx, "vals1", v.n_t, &T.vals[1]));
+  DST_TRY(ws(ctx, "pk0", v.n_pix, &T.pk[0]));
+  DST_TRY(ws(ctx, "pk1", v.n_pix, &T.pk[1]));
+  DST_TRY(ws(ctx, "pv0", v.n_pix, &T.pv[0]));
+  DST_TRY(ws(ctx, "pv1", v.n_pix, &T.pv[1]));
+  size_t tmp_bytes = 0;
+  HIP_TRY(dst::transpose_tmp_bytes(v.n_t, v.n_pix, &tmp_bytes));
+  DST_TRY(ws_get(ctx, "sort_tmp", tmp_bytes, &T.tmp));
+  T.tmp_bytes = tmp_bytes;
+  DST_TRY(ws(ctx, "n_obs", 1, &T.n_obs_dev));
+  DST_TRY(ws(ctx, "seg", 2 * (size_t)(v.n_pix + 1), &T.seg));
+  DST_TRY(ws(ctx, "cid", v.n_pix, &T.cid));
+  DST_TRY(ws(ctx, "chits", v.n_pix + 1, &T.chits));
+  DST_TRY(ws(ctx, "cstart", v.n_pix + 1, &T.cstart));
+  DST_TRY(ws(ctx, "cperm", v.n_t, &T.cperm));
+  DST_TRY(ws(ctx, "sb", v.n_t, &T.sb));
+  DST_TRY(ws(ctx, "cpix", v.n_t, &T.cpix));
+  const size_t psz = S.psi_f32 ? sizeof(float) : sizeof(double);
+  DST_TRY(ws_get(ctx, "spsi", (v.rowQ >= 0 ? (size_t)v.n_t : 1) * psz, &T.spsi));
+  DST_TRY(ws(ctx, "counts", 4, &S.counts));
+  DST_TRY(ws(ctx, "err", 4, &S.err));
+  HIP_TRY(dst::launch_fill_u32(reinterpret_cast<uint32_t*>(T.seg), 4 * (v.n_pix + 1), 0u, st));
+  HIP_TRY(dst::launch_fill_u32(reinterpret_cast<uint32_t*>(T.cid), v.n_pix, 0xffffffffu, st));
+  HIP_TRY(dst::launch_fill_u32(reinterpret_cast<uint32_t*>(T.n_obs_dev), 2, 0u, st));
+  HIP_TRY(dst::launch_fill_u32(reinterpret_cast<uint32_t*>(S.counts), 8, 0u, st));
+  HIP_TRY(dst::launch_fill_u32(reinterpret_cast<uint32_t*>(S.err), 4, 0u, st));
+  HIP_TRY(dst::transpose_build(v, S.psi_f32, T, S.err, st));
+  // compact view
+  S.v = v;
+  S.v.pix = T.cpix;
+  S.v.n_pix = T.n_obs;
+  const int64_t n_obs = T.n_obs;
+  DST_TRY(ws(ctx, "hits", n_obs, &S.hits));
+  DST_TRY(ws(ctx, "Minv4", 4 * n_obs, &S.Minv4));
+  DST_TRY(ws(ctx, "valid", n_obs, &S.valid));
+  DST_TRY(ws(ctx, "m4", 4 * n_obs, &P.m4));
+  DST_TRY(ws(ctx, "pw4", 4 * v.n_b, &P.pw4));
+  DST_TRY(ws(ctx, "nvalid", 2 * v.n_b, &S.nvalid));
+  DST_TRY(ws(ctx, "J", (size_t)v.n_streams * v.n_b, &S.J));
+  HIP_TRY(dst::launch_pixel_blocks(S.v, S.psi_f32, T, prob->rcond_cut, S.hits, S.Minv4, S.valid, P.m4, nullptr,
+                                   S.counts, st));
+  HIP_TRY(dst::launch_baseline_counts(S.v, S.valid, S.nvalid, S.J, S.counts + 2, st));
+  return DST_OK;
+}
+
+// out = K v = F^T Z F v through the solver's kernels (pixel-major bin, time-major rescan).
+int plan_operator(dst_ctx* ctx, Plan& P, const double* vin, double* out, hipStream_t st) {
+  Setup& S = P.S;
+  HIP_TRY(dst::launch_p_update4(S.v, const_cast<double*>(vin), nullptr, P.pw4, nullptr, 0, st));
+  HIP_TRY(dst::launch_bin_pixel(S.v, S.psi_f32, P.T, P.pw4, S.Minv4, S.valid, P.m4, nullptr, st));
+  HIP_TRY(dst::launch_unbin_cg(S.v, S.psi_f32, P.m4, S.nvalid, vin, out, nullptr, nullptr, st));
+  return DST_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -371,11 +450,11 @@ int dst_apply_operator(dst_ctx* ctx, const dst_problem* prob, const double* vin,
   ctx->err.clear();
   DeviceGuard g(ctx->device);
   hipStream_t st = static_cast<hipStream_t>(stream);
-  Setup S;
-  S.v = v;
-  DST_TRY(run_setup(ctx, prob, S, true, nullptr, st));
-  DST_TRY(operator_pass(ctx, S, nullptr, vin, 1.0, out, st));
-  return finish(ctx, &S, st);
+  Plan P;
+  P.full = v;
+  DST_TRY(build_plan(ctx, prob, P, st));
+  DST_TRY(plan_operator(ctx, P, vin, out, st));
+  return finish(ctx, &P.S, st);
 }
 
 int dst_solve(dst_ctx* ctx, const dst_problem* prob, const dst_solve_opts* opts_in, double* baselines_out,
@@ -391,7 +470,7 @@ int dst_solve(dst_ctx* ctx, const dst_problem* prob, const dst_solve_opts* opts_
   if (!(opts.tol > 0.0)) opts.tol = 1e-10;
   if (!std::isfinite(opts.tol)) return fail(ctx, DST_EINVAL, "tol must be finite");
   if (opts.max_iter <= 0) opts.max_iter = 1000;
-  int check_every = opts.check_every > 0 ? opts.check_every : 10;
+  const int check_every = opts.check_every > 0 ? opts.check_every : 10;
   const bool profile = opts.flags & DST_SOLVE_PROFILE;
   ctx->err.clear();
   DeviceGuard g(ctx->device);
@@ -399,20 +478,24 @@ int dst_solve(dst_ctx* ctx, const dst_problem* prob, const dst_solve_opts* opts_
 
   hipEvent_t ev[4];
   for (auto& e : ev) HIP_TRY(hipEventCreate(&e));
+  std::vector<hipEvent_t> pev;
   struct EvGuard {
     hipEvent_t* e;
-    int n;
+    std::vector<hipEvent_t>* more;
     ~EvGuard() {
-      for (int i = 0; i < n; ++i) (void)hipEventDestroy(e[i]);
+      for (int i = 0; i < 4; ++i) (void)hipEventDestroy(e[i]);
+      for (auto x : *more) (void)hipEventDestroy(x);
     }
-  } evg{ev, 4};
+  } evg{ev, &pev};
   HIP_TRY(hipEventRecord(ev[0], st));
 
-  Setup S;
-  S.v = v;
-  DST_TRY(run_setup(ctx, prob, S, true, nullptr, st));
+  Plan P;
+  P.full = v;
+  DST_TRY(build_plan(ctx, prob, P, st));
+  Setup& S = P.S;
+  const View& vc = S.v;
   const int64_t N = (int64_t)v.n_streams * v.n_b;
-  double *b, *a, *r, *z, *p, *q, *ka, *partials, *s4, *m4, *rnorm;
+  double *b, *a, *r, *z, *p, *q, *ka, *partials, *sd4, *md4, *rnorm;
   CgCtl* ctl;
   DST_TRY(ws(ctx, "cg_b", N, &b));
   DST_TRY(ws(ctx, "cg_a", N, &a));
@@ -422,25 +505,27 @@ int dst_solve(dst_ctx* ctx, const dst_problem* prob, const dst_solve_opts* opts_
   DST_TRY(ws(ctx, "cg_q", N, &q));
   DST_TRY(ws(ctx, "cg_ka", N, &ka));
   DST_TRY(ws(ctx, "cg_part", 3 * (size_t)std::max<int64_t>(v.n_b, 4096), &partials));
-  DST_TRY(ws(ctx, "s4", 4 * v.n_pix, &s4));
-  DST_TRY(ws(ctx, "m4", 4 * v.n_pix, &m4));
+  DST_TRY(ws(ctx, "sd4", 4 * vc.n_pix, &sd4));
+  DST_TRY(ws(ctx, "md4", 4 * vc.n_pix, &md4));
   DST_TRY(ws(ctx, "cg_rnorm", 1, &rnorm));
   DST_TRY(ws(ctx, "cg_ctl", 1, &ctl));
   HIP_TRY(dst::launch_fill_u32(reinterpret_cast<uint32_t*>(ctl), sizeof(CgCtl) / 4, 0u, st));
 
-  // right-hand side b = F^T Z d, and K a0 when an initial guess is given
-  DST_TRY(operator_pass(ctx, S, prob->tod, nullptr, 0.0, b, st));
+  // right-hand side b = F^T W (d - A m_d), m_d = M^-1 A^T W d (the binned map)
+  HIP_TRY(dst::launch_bin_pixel_tod(vc, S.psi_f32, P.T, prob->tod, S.tod_f32, S.Minv4, S.valid, sd4, md4, st));
+  HIP_TRY(dst::launch_unbin_reduce(vc, S.psi_f32, prob->tod, S.tod_f32, nullptr, 0.0, md4, S.valid, S.nvalid, b,
+                                   nullptr, nullptr, st));
   const double* ka_ptr = nullptr;
   if (opts.a0) {
-    DST_TRY(operator_pass(ctx, S, nullptr, opts.a0, 1.0, ka, st));
+    DST_TRY(plan_operator(ctx, P, opts.a0, ka, st));
     ka_ptr = ka;
   }
   HIP_TRY(dst::launch_cg_start(v, b, ka_ptr, opts.a0, a, r, z, p, S.J, ctl, partials, opts.tol, opts.max_iter, st));
-  HIP_TRY(dst::launch_fill(s4, 4 * v.n_pix, 0.0, st));
+  HIP_TRY(dst::launch_p_update4(v, p, nullptr, P.pw4, nullptr, 0, st));
   HIP_TRY(hipEventRecord(ev[1], st));
   HIP_TRY(hipMemcpyAsync(ctx->ctl_host, ctl, sizeof(CgCtl), hipMemcpyDeviceToHost, st));
   DST_TRY(finish(ctx, &S, st));
-  if (S.counts) {
+  {
     unsigned long long c[4];
     HIP_TRY(hipMemcpy(c, S.counts, sizeof c, hipMemcpyDeviceToHost));
     if (info) {
@@ -453,34 +538,33 @@ int dst_solve(dst_ctx* ctx, const dst_problem* prob, const dst_solve_opts* opts_
       HIP_TRY(hipMemsetAsync(baselines_out, 0, N * sizeof(double), st));
       if (map_out) HIP_TRY(hipMemsetAsync(map_out, 0, 3 * v.n_pix * sizeof(double), st));
       if (binned_out) HIP_TRY(hipMemsetAsync(binned_out, 0, 3 * v.n_pix * sizeof(double), st));
-      if (hits_out)
-        HIP_TRY(hipMemcpyAsync(hits_out, S.hits, v.n_pix * sizeof(int32_t), hipMemcpyDeviceToDevice, st));
+      if (hits_out) HIP_TRY(dst::launch_scatter(v.n_pix, P.T, S.hits, hits_out, md4, nullptr, nullptr, st));
       HIP_TRY(hipStreamSynchronize(st));
       return fail(ctx, DST_EDEGENERATE, "no valid sample in the problem");
     }
   }
 
-  // PCG iterations: bin(F p) -> apply -> unbin+reduce (q = K p, alpha) -> update (beta) -> p
-  std::vector<hipEvent_t> pev;
+  // PCG iterations: pixel-major bin + inverse (m = M^-1 A^T W F p) -> rescan and
+  // baseline sums (q = K p, alpha) -> a, r, z update (beta) -> p and its copy
   auto one_iteration = [&](bool timed) -> int {
-    hipEvent_t e0 = nullptr, e1 = nullptr, e2 = nullptr, e3 = nullptr, e4 = nullptr;
+    hipEvent_t e[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
     if (timed) {
-      for (hipEvent_t* e : {&e0, &e1, &e2, &e3, &e4}) {
-        HIP_TRY(hipEventCreate(e));
-        pev.push_back(*e);
+      for (auto& x : e) {
+        HIP_TRY(hipEventCreate(&x));
+        pev.push_back(x);
       }
-      HIP_TRY(hipEventRecord(e0, st));
+      HIP_TRY(hipEventRecord(e[0], st));
     }
-    HIP_TRY(dst::launch_bin(v, S.psi_f32, nullptr, S.tod_f32, p, 1.0, S.valid, s4, nullptr, ctl, st));
-    if (timed) HIP_TRY(hipEventRecord(e1, st));
-    HIP_TRY(dst::launch_apply(v.n_pix, s4, S.Minv4, m4, 4, s4, ctl, st));
-    if (timed) HIP_TRY(hipEventRecord(e2, st));
-    HIP_TRY(dst::launch_unbin_reduce(v, S.psi_f32, nullptr, S.tod_f32, p, 1.0, m4, S.valid, S.nvalid, q, ctl,
-                                     partials, st));
-    if (timed) HIP_TRY(hipEventRecord(e3, st));
+    HIP_TRY(dst::launch_bin_pixel(vc, S.psi_f32, P.T, P.pw4, S.Minv4, S.valid, P.m4, ctl, st));
+    if (timed) HIP_TRY(hipEventRecord(e[1], st));
+    if (timed) HIP_TRY(hipEventRecord(e[2], st));
+    HIP_TRY(dst::launch_unbin_cg(vc, S.psi_f32, P.m4, S.nvalid, p, q, ctl, partials, st));
+    HIP_TRY(dst::launch_cg_alpha(vc, ctl, partials, st));
+    if (timed) HIP_TRY(hipEventRecord(e[3], st));
     HIP_TRY(dst::launch_cg_update(v, a, r, z, p, q, S.J, ctl, partials, st));
-    HIP_TRY(dst::launch_p_update(v, p, z, ctl, st));
-    if (timed) HIP_TRY(hipEventRecord(e4, st));
+    HIP_TRY(dst::launch_cg_beta(dst::cg_update_blocks(v), ctl, partials, st));
+    HIP_TRY(dst::launch_p_update4(v, p, z, P.pw4, ctl, 1, st));
+    if (timed) HIP_TRY(hipEventRecord(e[4], st));
     return DST_OK;
   };
 
@@ -497,24 +581,15 @@ int dst_solve(dst_ctx* ctx, const dst_problem* prob, const dst_solve_opts* opts_
   HIP_TRY(hipEventRecord(ev[3], st));
   const CgCtl fin = h;
 
-  // canonical baselines, true residual, maps
+  // canonical baselines, true residual, maps (destriped = m_d - M^-1 A^T W F a)
   if (!(opts.flags & DST_SOLVE_NO_CANON)) HIP_TRY(dst::launch_canonicalise(v, a, S.J, partials, ctl, st));
-  DST_TRY(operator_pass(ctx, S, nullptr, a, 1.0, ka, st));
+  DST_TRY(plan_operator(ctx, P, a, ka, st));
   HIP_TRY(dst::launch_residual_norm(v, b, ka, S.J, ctl, partials, rnorm, st));
   HIP_TRY(hipMemcpyAsync(baselines_out, a, N * sizeof(double), hipMemcpyDeviceToDevice, st));
-  if (map_out) {
-    HIP_TRY(dst::launch_fill(s4, 4 * v.n_pix, 0.0, st));
-    HIP_TRY(dst::launch_bin(v, S.psi_f32, prob->tod, S.tod_f32, a, -1.0, S.valid, s4, S.err, nullptr, st));
-    HIP_TRY(dst::launch_apply(v.n_pix, s4, S.Minv4, map_out, 3, nullptr, nullptr, st));
-  }
-  if (binned_out) {
-    HIP_TRY(dst::launch_fill(s4, 4 * v.n_pix, 0.0, st));
-    HIP_TRY(dst::launch_bin(v, S.psi_f32, prob->tod, S.tod_f32, nullptr, 0.0, S.valid, s4, S.err, nullptr, st));
-    HIP_TRY(dst::launch_apply(v.n_pix, s4, S.Minv4, binned_out, 3, nullptr, nullptr, st));
-  }
-  if (hits_out) HIP_TRY(hipMemcpyAsync(hits_out, S.hits, v.n_pix * sizeof(int32_t), hipMemcpyDeviceToDevice, st));
+  if (map_out) HIP_TRY(dst::launch_scatter(v.n_pix, P.T, nullptr, nullptr, md4, P.m4, map_out, st));
+  if (binned_out) HIP_TRY(dst::launch_scatter(v.n_pix, P.T, nullptr, nullptr, md4, nullptr, binned_out, st));
+  if (hits_out) HIP_TRY(dst::launch_scatter(v.n_pix, P.T, S.hits, hits_out, md4, nullptr, nullptr, st));
   double true_norm = 0.0;
-  HIP_TRY(hipMemcpyAsync(ctx->err_host, S.err, sizeof(int), hipMemcpyDeviceToHost, st));
   DST_TRY(finish(ctx, &S, st));
   HIP_TRY(hipMemcpy(&true_norm, rnorm, sizeof(double), hipMemcpyDeviceToHost));
 
@@ -533,7 +608,7 @@ int dst_solve(dst_ctx* ctx, const dst_problem* prob, const dst_solve_opts* opts_
     info->t_total_ms = ms;
     info->t_bin_ms = info->t_apply_ms = info->t_unbin_ms = info->t_update_ms = 0.0;
     if (profile && !pev.empty()) {
-      // only iterations that ran (not the early-exit launches) count
+      // only iterations that ran (not the launches after the stop) count
       const size_t n_it = pev.size() / 5;
       const size_t used = std::min<size_t>(n_it, (size_t)std::max(fin.iter, 0));
       double acc[4] = {0, 0, 0, 0};
@@ -552,7 +627,6 @@ int dst_solve(dst_ctx* ctx, const dst_problem* prob, const dst_solve_opts* opts_
       }
     }
   }
-  for (auto e : pev) (void)hipEventDestroy(e);
   switch (fin.done) {
     case dst::DONE_CONVERGED:
       return DST_OK;

@@ -72,8 +72,10 @@ hipError_t launch_reduce(const View& v, const void* x, int x_f32, const uint8_t*
 hipError_t launch_cg_start(const View& v, double* b, const double* ka, const double* a0, double* a, double* r,
                            double* z, double* p, const double* J, CgCtl* ctl, double* partials, double tol,
                            int max_iter, hipStream_t st);
+// per-block partials of r.z and r.r at partials[0 .. 2 * cg_update_blocks(v))
 hipError_t launch_cg_update(const View& v, double* a, double* r, double* z, const double* p, const double* q,
                             const double* J, CgCtl* ctl, double* partials, hipStream_t st);
+int cg_update_blocks(const View& v);
 hipError_t launch_p_update(const View& v, double* p, const double* z, const CgCtl* ctl, hipStream_t st);
 // a_T -= mean of a_T over baselines with valid T samples (J_T > 0).
 hipError_t launch_canonicalise(const View& v, double* a, const double* J, double* partials, CgCtl* ctl,

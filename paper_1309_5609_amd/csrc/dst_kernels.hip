@@ -611,15 +611,14 @@ __global__ void __launch_bounds__(kBlock) k_cg_init(View v, double* __restrict__
   }
 }
 
-// a += alpha p;  r -= alpha P q;  z = J r;  then (last block) the stopping
-// test and beta = r'.z' / r.z.
+// a += alpha p;  r -= alpha P q;  z = J r;  per-block partials of r.z and r.r
+// (finished by a single-workgroup kernel).
 __global__ void __launch_bounds__(kBlock) k_cg_update(View v, double* __restrict__ a, double* __restrict__ r,
                                                       double* __restrict__ z, const double* __restrict__ p,
                                                       const double* __restrict__ q, const double* __restrict__ J,
                                                       CgCtl* __restrict__ ctl, double* __restrict__ partials) {
   if (ctl->done) return;
   __shared__ double lds[2 * 16];
-  __shared__ bool last;
   const int64_t N = (int64_t)v.n_streams * v.n_b;
   const double alpha = ctl->alpha, mu = ctl->mu;
   double acc[2] = {0.0, 0.0};
@@ -638,26 +637,6 @@ __global__ void __launch_bounds__(kBlock) k_cg_update(View v, double* __restrict
   if (threadIdx.x == 0) {
     partials[blockIdx.x] = acc[0];
     partials[gridDim.x + blockIdx.x] = acc[1];
-  }
-  if (!arrive_last(&ctl->counter[1], &last)) return;
-  double tot[2];
-  sum_partials<2>(partials, gridDim.x, tot, lds);
-  if (threadIdx.x == 0) {
-    const double rz_new = tot[0];
-    const double rn = sqrt(tot[1]);
-    ctl->iter += 1;
-    ctl->r_norm = rn;
-    if (!isfinite(rz_new) || !isfinite(rn)) {
-      ctl->done = DONE_NAN;
-    } else if (rn <= ctl->tol * ctl->b_norm) {
-      ctl->done = DONE_CONVERGED;
-    } else if (ctl->iter >= ctl->max_iter) {
-      ctl->done = DONE_MAXITER;
-    } else {
-      ctl->beta = rz_new / ctl->rz;
-      ctl->rz = rz_new;
-    }
-    ctl->counter[1] = 0;
   }
 }
 
@@ -900,6 +879,8 @@ hipError_t launch_cg_start(const View& v, double* b, const double* ka, const dou
                      tol, max_iter);
   return hipGetLastError();
 }
+
+int cg_update_blocks(const View& v) { return (int)vec_grid(v); }
 
 hipError_t launch_cg_update(const View& v, double* a, double* r, double* z, const double* p, const double* q,
                             const double* J, CgCtl* ctl, double* partials, hipStream_t st) {

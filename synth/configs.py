@@ -33,6 +33,7 @@ holds no step of the destriping method.
 """
 from __future__ import annotations
 
+import os
 from concurrent.futures import ThreadPoolExecutor
 from dataclasses import dataclass, field
 
@@ -96,7 +97,8 @@ def signal_timelines(sky: np.ndarray, pix: np.ndarray, psi, streams: str, out: n
     """Add the sky seen through the pointing to ``out`` [n_streams][n_t] (Eqs. 2-6)."""
     names = STREAM_SETS[streams]
     n = pix.shape[0]
-    for c0 in range(0, n, chunk):
+
+    def work(c0):
         c1 = min(n, c0 + chunk)
         p = pix[c0:c1]
         good = p >= 0
@@ -112,6 +114,14 @@ def signal_timelines(sky: np.ndarray, pix: np.ndarray, psi, streams: str, out: n
             else:
                 sig = -sky[pp, 1] * s + sky[pp, 2] * c
             out[row, c0:c1] += np.where(good, sig, 0.0)
+
+    starts = list(range(0, n, chunk))
+    if len(starts) > 1:
+        with ThreadPoolExecutor(max_workers=min(8, os.cpu_count() or 1)) as ex:
+            list(ex.map(work, starts))
+    else:
+        for c0 in starts:
+            work(c0)
 
 
 def make_problem(*, nside: int, n_samples: int, baseline_length: int, streams: str = "TQU",

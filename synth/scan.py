@@ -24,6 +24,8 @@ holds no step of the destriping method.
 """
 from __future__ import annotations
 
+import os
+from concurrent.futures import ThreadPoolExecutor
 from dataclasses import dataclass
 
 import numpy as np
@@ -81,7 +83,8 @@ def pointing(spec: ScanSpec, nside: int, n_samples: int, start: int = 0, chunk: 
     theta_per = 0.5 * np.pi - dec
     pix = np.empty(n_samples, dtype=np.int32)
     psi = np.empty(n_samples, dtype=np.float64)
-    for c0 in range(0, n_samples, chunk):
+
+    def work(c0):
         c1 = min(n_samples, c0 + chunk)
         idx = np.arange(start + c0, start + c1, dtype=np.int64)
         ph = idx % n_per
@@ -90,4 +93,13 @@ def pointing(spec: ScanSpec, nside: int, n_samples: int, start: int = 0, chunk: 
         ra = lst - ha[ph]
         pix[c0:c1] = ang2pix_ring(nside, theta_per[ph], ra).astype(np.int32)
         psi[c0:c1] = psi_per[ph]
+
+    starts = list(range(0, n_samples, chunk))
+    if len(starts) > 1:
+        # chunks are independent; NumPy releases the GIL inside its kernels
+        with ThreadPoolExecutor(max_workers=min(8, os.cpu_count() or 1)) as ex:
+            list(ex.map(work, starts))
+    else:
+        for c0 in starts:
+            work(c0)
     return pix, psi
