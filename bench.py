@@ -47,18 +47,27 @@ def workload_name(w: int, fk: float) -> str:
             f"3000-sample baselines (43,200 per stream), T/q/u, f_k {fk * 1e3:g} mHz, alpha 1.7, {prec}")
 
 
-def algorithmic_bytes(n_t: int, n_obs: int, n_b: int, s_psi: int) -> dict:
+def algorithmic_bytes(n_t: int, n_obs: int, n_b: int, s_psi: int, n_runs: int = 0) -> dict:
     """Bytes each kernel of one CG iteration must move (per launch).
 
-    bin:    pointing (4 B pixel + s_psi angle) per sample, p (3 x 8 B per
-            baseline) in, the 3 sums of each observed pixel out (24 B);
-    unbin:  pointing per sample, the 3 map values of each observed pixel in,
-            p in and q out (2 x 3 x 8 B per baseline).
+    Per-sample form (the method as written, samples streamed every iteration):
+      bin:    pointing (4 B pixel or baseline index + s_psi angle) per sample,
+              p (3 x 8 B per baseline) in, the 3 values of each observed
+              pixel out (24 B);
+      unbin:  pointing per sample, the 3 map values of each observed pixel
+              in, p in and q out (2 x 3 x 8 B per baseline).
+    Run form (default): one 24 B record per run (baseline or pixel index,
+    length, sums of cos 2psi and sin 2psi) replaces the per-sample pointing;
+    per-pixel and per-baseline terms as above.
     """
-    return {
-        "bin": n_t * (4 + s_psi) + n_obs * 24 + 3 * n_b * 8,
-        "unbin": n_t * (4 + s_psi) + n_obs * 24 + 2 * 3 * n_b * 8,
+    out = {
+        "bin_samples": n_t * (4 + s_psi) + n_obs * 24 + 3 * n_b * 8,
+        "unbin_samples": n_t * (4 + s_psi) + n_obs * 24 + 2 * 3 * n_b * 8,
     }
+    if n_runs:
+        out["bin_runs"] = n_runs * 24 + n_obs * 24 + 3 * n_b * 8
+        out["unbin_runs"] = n_runs * 24 + n_obs * 24 + 2 * 3 * n_b * 8
+    return out
 
 
 def cpu_baseline(p, seconds_target: float = 20.0) -> dict:
@@ -147,13 +156,23 @@ def main() -> int:
     log(f"timed {args.steps} solves: {wall * 1e3:.1f} ms, {iters} iterations, {value:.3e} samples*iters/s")
 
     n_obs = int(r0["n_valid_pix"][0])
+    n_runs = int(r0["n_runs"])
     s_psi = 4 if args.workload == 2 else 8
-    algo = algorithmic_bytes(p.n_samples, n_obs, p.n_baselines, s_psi)
+    algo = algorithmic_bytes(p.n_samples, n_obs, p.n_baselines, s_psi, n_runs)
     k_ms = {k: float(np.mean([r[f"t_{k}_ms"] for r in runs])) for k in ("bin", "apply", "unbin", "update")}
     dom = max(("bin", "unbin"), key=lambda k: k_ms[k])
-    achieved = algo[dom] / (k_ms[dom] * 1e-3) / 1e9
+    dom_bytes = algo[f"{dom}_runs"]
+    achieved = dom_bytes / (k_ms[dom] * 1e-3) / 1e9
     iter_ms = float(np.mean([r["t_iter_ms"] for r in runs]))
-    b_iter = algo["bin"] + algo["unbin"]
+    b_iter = algo["bin_samples"] + algo["unbin_samples"]
+
+    # the per-sample form of the same solve, for comparison with the per-sample byte model
+    log("per-sample form: one profiled solve")
+    ps = dst.dst_solve(ctx, dp, tol=args.tol, max_iter=2000,
+                       flags=dst.DST_SOLVE_PROFILE | dst.DST_SOLVE_PER_SAMPLE)
+    ps_ms = {k: ps[f"t_{k}_ms"] for k in ("bin", "unbin", "update")}
+    ps_dom = max(("bin", "unbin"), key=lambda k: ps_ms[k])
+    ps_ach = algo[f"{ps_dom}_samples"] / (ps_ms[ps_dom] * 1e-3) / 1e9
 
     line = {
         "metric": METRIC,
@@ -171,9 +190,15 @@ def main() -> int:
         "config": {"workload": workload_name(args.workload, args.fknee), "n_samples": p.n_samples,
                    "n_pix": p.n_pix, "baseline_length": p.baseline_length, "n_baselines": p.n_baselines,
                    "streams": p.streams, "tol": args.tol, "parallelism": "1 GPU"},
-        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "algorithmic_bytes_per_launch": algo[dom], "avg_launch_ms": k_ms[dom]},
+        "roofline": {"bound": "hbm", "kernel": f"{dom}_runs", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "algorithmic_bytes_per_launch": dom_bytes, "avg_launch_ms": k_ms[dom]},
+        "per_sample_model": {"bytes_per_iteration": b_iter,
+                             "equivalent_GBs": b_iter / (iter_ms * 1e-3) / 1e9,
+                             "note": "per-sample algorithmic bytes of one CG iteration / measured iteration time"},
+        "per_sample_form": {"iter_ms": ps["t_iter_ms"], "kernel_ms": ps_ms, "iterations": ps["iterations"],
+                            "dominant": ps_dom, "achieved_GBs": ps_ach, "frac": ps_ach / HBM_PEAK_GBS},
+        "n_runs": n_runs,
         "iterations_per_solve": r0["iterations"],
         "iter_ms": iter_ms,
         "iteration_throughput": p.n_samples / (iter_ms * 1e-3),

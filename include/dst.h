@@ -153,7 +153,9 @@ int dst_apply_operator(dst_ctx* ctx, const dst_problem* prob, const double* v, d
 enum {
   DST_SOLVE_NO_CANON = 1u,    /* return the raw CG iterate (skip the T mean removal) */
   DST_SOLVE_PROFILE = 2u,     /* time each kernel class with HIP events (into info) */
-  DST_SOLVE_NO_GRAPH = 4u     /* launch iterations one by one instead of a captured graph */
+  DST_SOLVE_NO_GRAPH = 4u,    /* launch iterations one by one instead of a captured graph */
+  DST_SOLVE_PER_SAMPLE = 8u   /* iterate on per-sample pointing (recomputing cos 2psi, sin 2psi)
+                                 instead of the default run-compressed pointing */
 };
 typedef struct {
   double tol;               /* stop when ||r||_2 <= tol ||b||_2 (recurrence residual) */
@@ -177,6 +179,7 @@ typedef struct {
   double t_total_ms;
   /* with DST_SOLVE_PROFILE: mean device time per launch of each kernel class (ms) */
   double t_bin_ms, t_apply_ms, t_unbin_ms, t_update_ms;
+  int64_t n_runs;           /* runs of the run-compressed pointing (0 in the per-sample form) */
 } dst_solve_info;
 
 /* Destripe one channel (Eq. 13 by PCG, then Eqs. 10-12 for the maps).

@@ -17,6 +17,7 @@
 #include "dst.h"
 #include "dst_internal.h"
 #include "dst_pixel.h"
+#include "dst_runs.h"
 
 using dst::CgCtl;
 using dst::View;
@@ -245,12 +246,86 @@ int operator_pass(dst_ctx* ctx, Setup& S, const void* tod, const double* base, d
 struct Plan {
   Setup S;
   View full;
-  dst::Transpose T;
+  bool runs = true;       // run-compressed form (default) or per-sample form
+  dst::Transpose T;       // per-sample form
+  dst::Runs W;            // run form
   double* m4 = nullptr;   // per-iteration map (zero on invalid pixels)
   double* pw4 = nullptr;  // weighted interleaved baseline vector
+  const int32_t* cid() const { return runs ? W.cid : T.cid; }
 };
 
-int build_plan(dst_ctx* ctx, const dst_problem* prob, Plan& P, hipStream_t st) {
+// Run form of the setup: runs in time and pixel order, compact ids in pixel
+// order, per-pixel blocks and (with tod) binned map, per-baseline counts and b.
+int build_runs_plan(dst_ctx* ctx, const dst_problem* prob, Plan& P, const void* tod, double** sd4, double** md4,
+                    double* b, hipStream_t st) {
+  Setup& S = P.S;
+  const View& v = P.full;
+  if ((uint64_t)v.n_t >= ((uint64_t)1 << 32))
+    return fail(ctx, DST_EINVAL, "the solver needs n_samples < 2^32 (got %lld)", (long long)v.n_t);
+  S.psi_f32 = prob->psi_dtype == DST_F32;
+  S.tod_f32 = prob->tod_dtype == DST_F32;
+  dst::Runs& W = P.W;
+  DST_TRY(ws(ctx, "r_head", v.n_t, &W.head));
+  DST_TRY(ws(ctx, "r_hidx", v.n_t, &W.hidx));
+  size_t tmp_bytes = 0;
+  HIP_TRY(dst::runs_tmp_bytes(v.n_t, v.n_pix, &tmp_bytes));
+  DST_TRY(ws_get(ctx, "r_tmp", tmp_bytes, &W.tmp));
+  W.tmp_bytes = tmp_bytes;
+  DST_TRY(ws(ctx, "r_bstart", v.n_b + 1, &W.bstart));
+  DST_TRY(ws(ctx, "r_seg", 2 * (size_t)v.n_pix, &W.seg));
+  DST_TRY(ws(ctx, "r_obs", v.n_pix + 1, &W.obs));
+  DST_TRY(ws(ctx, "r_oidx", v.n_pix + 1, &W.oidx));
+  DST_TRY(ws(ctx, "r_cid", v.n_pix, &W.cid));
+  DST_TRY(ws(ctx, "r_order", v.n_pix, &W.order));
+  DST_TRY(ws(ctx, "r_pstart", v.n_pix + 1, &W.pstart));
+  DST_TRY(ws(ctx, "counts", 4, &S.counts));
+  DST_TRY(ws(ctx, "err", 4, &S.err));
+  HIP_TRY(dst::launch_fill_u32(reinterpret_cast<uint32_t*>(W.seg), 4 * v.n_pix, 0u, st));
+  HIP_TRY(dst::launch_fill_u32(reinterpret_cast<uint32_t*>(S.counts), 8, 0u, st));
+  HIP_TRY(dst::launch_fill_u32(reinterpret_cast<uint32_t*>(S.err), 4, 0u, st));
+  HIP_TRY(dst::runs_count(v, W, S.err, st));
+  const int64_t R = W.R;
+  DST_TRY(ws(ctx, "r_t0", R, &W.t0));
+  DST_TRY(ws(ctx, "r_tpix", R, &W.tpix));
+  DST_TRY(ws(ctx, "r_tn", R, &W.tn));
+  DST_TRY(ws(ctx, "r_tc", R, &W.tc));
+  DST_TRY(ws(ctx, "r_ts", R, &W.ts));
+  DST_TRY(ws(ctx, "r_mom", (size_t)dst::kMom * R, &W.mom));
+  DST_TRY(ws(ctx, "r_keys0", R, &W.keys[0]));
+  DST_TRY(ws(ctx, "r_keys1", R, &W.keys[1]));
+  DST_TRY(ws(ctx, "r_vals0", R, &W.vals[0]));
+  DST_TRY(ws(ctx, "r_vals1", R, &W.vals[1]));
+  DST_TRY(ws(ctx, "r_pb", R, &W.pb));
+  DST_TRY(ws(ctx, "r_pn", R, &W.pn));
+  DST_TRY(ws(ctx, "r_pc", R, &W.pc));
+  DST_TRY(ws(ctx, "r_ps", R, &W.ps));
+  // per-pixel arrays sized for every pixel (the observed count is known later)
+  DST_TRY(ws(ctx, "hits", v.n_pix, &S.hits));
+  DST_TRY(ws(ctx, "Minv4", 4 * v.n_pix, &S.Minv4));
+  DST_TRY(ws(ctx, "valid", v.n_pix, &S.valid));
+  DST_TRY(ws(ctx, "m4", 4 * v.n_pix, &P.m4));
+  DST_TRY(ws(ctx, "pw4", 4 * v.n_b, &P.pw4));
+  DST_TRY(ws(ctx, "nvalid", 2 * v.n_b, &S.nvalid));
+  DST_TRY(ws(ctx, "J", (size_t)v.n_streams * v.n_b, &S.J));
+  double *s4 = nullptr, *m4d = nullptr;
+  if (tod) {
+    DST_TRY(ws(ctx, "sd4", 4 * v.n_pix, &s4));
+    DST_TRY(ws(ctx, "md4", 4 * v.n_pix, &m4d));
+  }
+  if (sd4) *sd4 = s4;
+  if (md4) *md4 = m4d;
+  HIP_TRY(dst::runs_build(v, S.psi_f32, tod, S.tod_f32, prob->rcond_cut, W, S.hits, S.Minv4, S.valid, P.m4, s4, m4d,
+                          S.counts, st));
+  S.v = v;
+  S.v.n_pix = W.n_obs;
+  HIP_TRY(dst::launch_rhs_runs(S.v, W, tod, m4d, S.valid, S.nvalid, S.J, b, st));
+  return DST_OK;
+}
+
+// With tod: also the sum map sd4, binned map md4 (compact [n_obs][4]) and the
+// right-hand side b = F^T W (d - A m_d) ([n_streams][n_b]).
+int build_sample_plan(dst_ctx* ctx, const dst_problem* prob, Plan& P, const void* tod, double** sd4,
+                      double** md4, double* b, hipStream_t st) {
   Setup& S = P.S;
   const View& v = P.full;
   if ((uint64_t)v.n_t >= ((uint64_t)1 << 32))
@@ -287,8 +362,8 @@ int build_plan(dst_ctx* ctx, const dst_problem* prob, Plan& P, hipStream_t st) {
   HIP_TRY(dst::launch_fill_u32(reinterpret_cast<uint32_t*>(T.n_obs_dev), 2, 0u, st));
   HIP_TRY(dst::launch_fill_u32(reinterpret_cast<uint32_t*>(S.counts), 8, 0u, st));
   HIP_TRY(dst::launch_fill_u32(reinterpret_cast<uint32_t*>(S.err), 4, 0u, st));
-  HIP_TRY(dst::transpose_build(v, S.psi_f32, T, S.err, st));
-  // compact view
+  HIP_TRY(dst::transpose_build(v, T, S.err, st));
+  // compact view: pixel ids are the compact ids, n_pix the observed pixels
   S.v = v;
   S.v.pix = T.cpix;
   S.v.n_pix = T.n_obs;
@@ -300,18 +375,51 @@ int build_plan(dst_ctx* ctx, const dst_problem* prob, Plan& P, hipStream_t st) {
   DST_TRY(ws(ctx, "pw4", 4 * v.n_b, &P.pw4));
   DST_TRY(ws(ctx, "nvalid", 2 * v.n_b, &S.nvalid));
   DST_TRY(ws(ctx, "J", (size_t)v.n_streams * v.n_b, &S.J));
-  HIP_TRY(dst::launch_pixel_blocks(S.v, S.psi_f32, T, prob->rcond_cut, S.hits, S.Minv4, S.valid, P.m4, nullptr,
-                                   S.counts, st));
-  HIP_TRY(dst::launch_baseline_counts(S.v, S.valid, S.nvalid, S.J, S.counts + 2, st));
+  double *s4 = nullptr, *m4d = nullptr;
+  if (tod) {
+    DST_TRY(ws(ctx, "sd4", 4 * n_obs, &s4));
+    DST_TRY(ws(ctx, "md4", 4 * n_obs, &m4d));
+  }
+  if (sd4) *sd4 = s4;
+  if (md4) *md4 = m4d;
+  HIP_TRY(dst::launch_setup_pixels(v, S.psi_f32, T, tod, S.tod_f32, prob->rcond_cut, S.hits, S.Minv4, S.valid, P.m4,
+                                   s4, m4d, S.counts, st));
+  HIP_TRY(dst::launch_rhs_unbin(S.v, S.psi_f32, tod, S.tod_f32, m4d, S.valid, S.nvalid, S.J, b, st));
   return DST_OK;
 }
 
-// out = K v = F^T Z F v through the solver's kernels (pixel-major bin, time-major rescan).
+int build_plan(dst_ctx* ctx, const dst_problem* prob, Plan& P, const void* tod, double** sd4, double** md4,
+               double* b, hipStream_t st) {
+  return P.runs ? build_runs_plan(ctx, prob, P, tod, sd4, md4, b, st)
+                : build_sample_plan(ctx, prob, P, tod, sd4, md4, b, st);
+}
+
+// The two halves of K p: m = M^-1 A^T W F p (pixel order), then
+// q = F^T W (F p - A m) (time order).  With ctl, the CG partials.
+int plan_bin(dst_ctx* ctx, Plan& P, const CgCtl* gate, hipStream_t st) {
+  Setup& S = P.S;
+  if (P.runs)
+    HIP_TRY(dst::launch_bin_runs(S.v, P.W, P.pw4, S.Minv4, S.valid, P.m4, gate, st));
+  else
+    HIP_TRY(dst::launch_bin_pixel(S.v, S.psi_f32, P.T, P.pw4, S.Minv4, S.valid, P.m4, gate, st));
+  return DST_OK;
+}
+
+int plan_unbin(dst_ctx* ctx, Plan& P, const double* p, double* q, CgCtl* ctl, double* partials, hipStream_t st) {
+  Setup& S = P.S;
+  if (P.runs)
+    HIP_TRY(dst::launch_unbin_runs(S.v, P.W, P.m4, S.nvalid, p, q, ctl, partials, st));
+  else
+    HIP_TRY(dst::launch_unbin_cg(S.v, S.psi_f32, P.m4, S.nvalid, p, q, ctl, partials, st));
+  return DST_OK;
+}
+
+// out = K v = F^T Z F v through the solver's kernels.
 int plan_operator(dst_ctx* ctx, Plan& P, const double* vin, double* out, hipStream_t st) {
   Setup& S = P.S;
   HIP_TRY(dst::launch_p_update4(S.v, const_cast<double*>(vin), nullptr, P.pw4, nullptr, 0, st));
-  HIP_TRY(dst::launch_bin_pixel(S.v, S.psi_f32, P.T, P.pw4, S.Minv4, S.valid, P.m4, nullptr, st));
-  HIP_TRY(dst::launch_unbin_cg(S.v, S.psi_f32, P.m4, S.nvalid, vin, out, nullptr, nullptr, st));
+  DST_TRY(plan_bin(ctx, P, nullptr, st));
+  DST_TRY(plan_unbin(ctx, P, vin, out, nullptr, nullptr, st));
   return DST_OK;
 }
 
@@ -452,7 +560,7 @@ int dst_apply_operator(dst_ctx* ctx, const dst_problem* prob, const double* vin,
   hipStream_t st = static_cast<hipStream_t>(stream);
   Plan P;
   P.full = v;
-  DST_TRY(build_plan(ctx, prob, P, st));
+  DST_TRY(build_plan(ctx, prob, P, nullptr, nullptr, nullptr, nullptr, st));
   DST_TRY(plan_operator(ctx, P, vin, out, st));
   return finish(ctx, &P.S, st);
 }
@@ -465,7 +573,7 @@ int dst_solve(dst_ctx* ctx, const dst_problem* prob, const dst_solve_opts* opts_
   dst_solve_opts opts{};
   if (opts_in) opts = *opts_in;
   if (opts.reserved != 0) return fail(ctx, DST_EINVAL, "opts.reserved must be 0");
-  const uint32_t known = DST_SOLVE_NO_CANON | DST_SOLVE_PROFILE | DST_SOLVE_NO_GRAPH;
+  const uint32_t known = DST_SOLVE_NO_CANON | DST_SOLVE_PROFILE | DST_SOLVE_NO_GRAPH | DST_SOLVE_PER_SAMPLE;
   if (opts.flags & ~known) return fail(ctx, DST_EINVAL, "unknown solve flags %u", opts.flags);
   if (!(opts.tol > 0.0)) opts.tol = 1e-10;
   if (!std::isfinite(opts.tol)) return fail(ctx, DST_EINVAL, "tol must be finite");
@@ -489,15 +597,17 @@ int dst_solve(dst_ctx* ctx, const dst_problem* prob, const dst_solve_opts* opts_
   } evg{ev, &pev};
   HIP_TRY(hipEventRecord(ev[0], st));
 
-  Plan P;
-  P.full = v;
-  DST_TRY(build_plan(ctx, prob, P, st));
-  Setup& S = P.S;
-  const View& vc = S.v;
   const int64_t N = (int64_t)v.n_streams * v.n_b;
-  double *b, *a, *r, *z, *p, *q, *ka, *partials, *sd4, *md4, *rnorm;
+  double *b, *a, *r, *z, *p, *q, *ka, *partials, *sd4 = nullptr, *md4 = nullptr, *rnorm;
   CgCtl* ctl;
   DST_TRY(ws(ctx, "cg_b", N, &b));
+  // pointing setup, binned map and right-hand side b = F^T W (d - A m_d)
+  Plan P;
+  P.full = v;
+  P.runs = !(opts.flags & DST_SOLVE_PER_SAMPLE);
+  DST_TRY(build_plan(ctx, prob, P, prob->tod, &sd4, &md4, b, st));
+  Setup& S = P.S;
+  const View& vc = S.v;
   DST_TRY(ws(ctx, "cg_a", N, &a));
   DST_TRY(ws(ctx, "cg_r", N, &r));
   DST_TRY(ws(ctx, "cg_z", N, &z));
@@ -505,16 +615,10 @@ int dst_solve(dst_ctx* ctx, const dst_problem* prob, const dst_solve_opts* opts_
   DST_TRY(ws(ctx, "cg_q", N, &q));
   DST_TRY(ws(ctx, "cg_ka", N, &ka));
   DST_TRY(ws(ctx, "cg_part", 3 * (size_t)std::max<int64_t>(v.n_b, 4096), &partials));
-  DST_TRY(ws(ctx, "sd4", 4 * vc.n_pix, &sd4));
-  DST_TRY(ws(ctx, "md4", 4 * vc.n_pix, &md4));
   DST_TRY(ws(ctx, "cg_rnorm", 1, &rnorm));
   DST_TRY(ws(ctx, "cg_ctl", 1, &ctl));
   HIP_TRY(dst::launch_fill_u32(reinterpret_cast<uint32_t*>(ctl), sizeof(CgCtl) / 4, 0u, st));
 
-  // right-hand side b = F^T W (d - A m_d), m_d = M^-1 A^T W d (the binned map)
-  HIP_TRY(dst::launch_bin_pixel_tod(vc, S.psi_f32, P.T, prob->tod, S.tod_f32, S.Minv4, S.valid, sd4, md4, st));
-  HIP_TRY(dst::launch_unbin_reduce(vc, S.psi_f32, prob->tod, S.tod_f32, nullptr, 0.0, md4, S.valid, S.nvalid, b,
-                                   nullptr, nullptr, st));
   const double* ka_ptr = nullptr;
   if (opts.a0) {
     DST_TRY(plan_operator(ctx, P, opts.a0, ka, st));
@@ -538,7 +642,7 @@ int dst_solve(dst_ctx* ctx, const dst_problem* prob, const dst_solve_opts* opts_
       HIP_TRY(hipMemsetAsync(baselines_out, 0, N * sizeof(double), st));
       if (map_out) HIP_TRY(hipMemsetAsync(map_out, 0, 3 * v.n_pix * sizeof(double), st));
       if (binned_out) HIP_TRY(hipMemsetAsync(binned_out, 0, 3 * v.n_pix * sizeof(double), st));
-      if (hits_out) HIP_TRY(dst::launch_scatter(v.n_pix, P.T, S.hits, hits_out, md4, nullptr, nullptr, st));
+      if (hits_out) HIP_TRY(dst::launch_scatter(v.n_pix, P.cid(), S.hits, hits_out, md4, nullptr, nullptr, st));
       HIP_TRY(hipStreamSynchronize(st));
       return fail(ctx, DST_EDEGENERATE, "no valid sample in the problem");
     }
@@ -555,10 +659,10 @@ int dst_solve(dst_ctx* ctx, const dst_problem* prob, const dst_solve_opts* opts_
       }
       HIP_TRY(hipEventRecord(e[0], st));
     }
-    HIP_TRY(dst::launch_bin_pixel(vc, S.psi_f32, P.T, P.pw4, S.Minv4, S.valid, P.m4, ctl, st));
+    DST_TRY(plan_bin(ctx, P, ctl, st));
     if (timed) HIP_TRY(hipEventRecord(e[1], st));
     if (timed) HIP_TRY(hipEventRecord(e[2], st));
-    HIP_TRY(dst::launch_unbin_cg(vc, S.psi_f32, P.m4, S.nvalid, p, q, ctl, partials, st));
+    DST_TRY(plan_unbin(ctx, P, p, q, ctl, partials, st));
     HIP_TRY(dst::launch_cg_alpha(vc, ctl, partials, st));
     if (timed) HIP_TRY(hipEventRecord(e[3], st));
     HIP_TRY(dst::launch_cg_update(v, a, r, z, p, q, S.J, ctl, partials, st));
@@ -586,9 +690,9 @@ int dst_solve(dst_ctx* ctx, const dst_problem* prob, const dst_solve_opts* opts_
   DST_TRY(plan_operator(ctx, P, a, ka, st));
   HIP_TRY(dst::launch_residual_norm(v, b, ka, S.J, ctl, partials, rnorm, st));
   HIP_TRY(hipMemcpyAsync(baselines_out, a, N * sizeof(double), hipMemcpyDeviceToDevice, st));
-  if (map_out) HIP_TRY(dst::launch_scatter(v.n_pix, P.T, nullptr, nullptr, md4, P.m4, map_out, st));
-  if (binned_out) HIP_TRY(dst::launch_scatter(v.n_pix, P.T, nullptr, nullptr, md4, nullptr, binned_out, st));
-  if (hits_out) HIP_TRY(dst::launch_scatter(v.n_pix, P.T, S.hits, hits_out, md4, nullptr, nullptr, st));
+  if (map_out) HIP_TRY(dst::launch_scatter(v.n_pix, P.cid(), nullptr, nullptr, md4, P.m4, map_out, st));
+  if (binned_out) HIP_TRY(dst::launch_scatter(v.n_pix, P.cid(), nullptr, nullptr, md4, nullptr, binned_out, st));
+  if (hits_out) HIP_TRY(dst::launch_scatter(v.n_pix, P.cid(), S.hits, hits_out, md4, nullptr, nullptr, st));
   double true_norm = 0.0;
   DST_TRY(finish(ctx, &S, st));
   HIP_TRY(hipMemcpy(&true_norm, rnorm, sizeof(double), hipMemcpyDeviceToHost));
@@ -607,6 +711,7 @@ int dst_solve(dst_ctx* ctx, const dst_problem* prob, const dst_solve_opts* opts_
     HIP_TRY(hipEventElapsedTime(&ms, ev[0], ev[3]));
     info->t_total_ms = ms;
     info->t_bin_ms = info->t_apply_ms = info->t_unbin_ms = info->t_update_ms = 0.0;
+    info->n_runs = P.runs ? P.W.R : 0;
     if (profile && !pev.empty()) {
       // only iterations that ran (not the launches after the stop) count
       const size_t n_it = pev.size() / 5;

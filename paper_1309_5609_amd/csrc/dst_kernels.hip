@@ -20,6 +20,7 @@
 #include <cstdint>
 
 #include "dst_internal.h"
+#include "dst_trig.h"
 
 namespace dst {
 namespace {
@@ -30,7 +31,7 @@ constexpr int kWaves = kBlock / 64;
 __device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
 
 // cos(2 psi), sin(2 psi) in FP64 (pointing rows of Eqs. 3-6).
-__device__ __forceinline__ void rot2(double psi, double& c, double& s) { sincos(2.0 * psi, &s, &c); }
+__device__ __forceinline__ void rot2(double psi, double& c, double& s) { fast_sincos(2.0 * psi, &s, &c); }
 
 // Sum of N doubles over each run of equal consecutive keys of the wavefront.
 // The first lane of a run gets the run total and its length; returns whether

@@ -44,16 +44,21 @@ struct Transpose {
 };
 
 hipError_t transpose_tmp_bytes(int64_t n_t, int64_t n_pix, size_t* bytes);
-// Builds the transpose; synchronises `st` once to learn n_obs.
-hipError_t transpose_build(const View& v, int psi_f32, Transpose& T, int* err, hipStream_t st);
-// Per-pixel blocks in compact space: vc is the view with pix = cpix, n_pix = n_obs.
-hipError_t launch_pixel_blocks(const View& vc, int psi_f32, const Transpose& T, double rcond_cut, int32_t* hits,
-                               double* Minv4, uint8_t* valid, double* m4_zero, double* blocks_out,
-                               unsigned long long* counts, hipStream_t st);
+// Sort, segments, first-visit compact ids, offsets and cpix; synchronises `st`
+// once to learn n_obs.  The per-sample arrays (cperm, sb, spsi) are filled by
+// launch_setup_pixels.
+hipError_t transpose_build(const View& v, Transpose& T, int* err, hipStream_t st);
+// Per compact pixel: the transposed sample arrays, hits, block inverse and
+// validity, zeroed m4, and (tod != NULL) the sum map sd4 and binned map md4.
+// counts: [valid T pixels, valid QU pixels, valid T samples, valid QU samples].
+hipError_t launch_setup_pixels(const View& v, int psi_f32, const Transpose& T, const void* tod, int tod_f32,
+                               double rcond_cut, int32_t* hits, double* Minv4, uint8_t* valid, double* m4_zero,
+                               double* sd4, double* md4, unsigned long long* counts, hipStream_t st);
+// Per baseline: n_valid, Jacobi diagonal and (tod != NULL) b = F^T W (d - A m_d).
+hipError_t launch_rhs_unbin(const View& vc, int psi_f32, const void* tod, int tod_f32, const double* md4,
+                            const uint8_t* valid, int32_t* nvalid, double* J, double* b, hipStream_t st);
 hipError_t launch_bin_pixel(const View& vc, int psi_f32, const Transpose& T, const double* pw4, const double* Minv4,
                             const uint8_t* valid, double* m4, const CgCtl* gate, hipStream_t st);
-hipError_t launch_bin_pixel_tod(const View& vc, int psi_f32, const Transpose& T, const void* tod, int tod_f32,
-                                const double* Minv4, const uint8_t* valid, double* s4, double* m4, hipStream_t st);
 hipError_t launch_unbin_cg(const View& vc, int psi_f32, const double* m4, const int32_t* nvalid, const double* p,
                            double* q, CgCtl* ctl, double* partials, hipStream_t st);
 // Single-workgroup finishes of the CG step (alpha) and of the residual update (beta).
@@ -64,7 +69,7 @@ hipError_t launch_p_update4(const View& v, double* p, const double* z, double* p
                             hipStream_t st);
 // Full-sky outputs: hits[p] and out3[p] = a4[cid[p]] - b4[cid[p]] (0 where unobserved;
 // any of hits / b4 / out3 may be NULL).
-hipError_t launch_scatter(int64_t n_pix, const Transpose& T, const int32_t* chits, int32_t* hits, const double* a4,
+hipError_t launch_scatter(int64_t n_pix, const int32_t* cid, const int32_t* chits, int32_t* hits, const double* a4,
                           const double* b4, double* out3, hipStream_t st);
 
 }  // namespace dst

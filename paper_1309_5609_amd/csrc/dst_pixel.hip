@@ -19,6 +19,7 @@
 #include <cstdint>
 
 #include "dst_internal.h"
+#include "dst_trig.h"
 #include "dst_pixel.h"
 
 namespace dst {
@@ -29,7 +30,8 @@ constexpr int kWaves = kBlock / 64;
 
 __device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
 
-__device__ __forceinline__ void rot2(double psi, double& c, double& s) { sincos(2.0 * psi, &s, &c); }
+// cos(2 psi), sin(2 psi) in FP64 (pointing rows of Eqs. 3-6).
+__device__ __forceinline__ void rot2(double psi, double& c, double& s) { fast_sincos(2.0 * psi, &s, &c); }
 
 template <int N>
 __device__ __forceinline__ void wave_sum(double (&v)[N]) {
@@ -139,30 +141,6 @@ __global__ void __launch_bounds__(kBlock) k_compact_ids(const uint32_t* __restri
   }
 }
 
-// Samples of compact pixel c, in time order, at [cstart[c], cstart[c+1]):
-// sample index, baseline index and angle.  One wavefront per pixel.
-template <typename PT>
-__global__ void __launch_bounds__(kBlock) k_reorder(const uint32_t* __restrict__ order, int64_t n_obs,
-                                                    const int64_t* __restrict__ seg,
-                                                    const int64_t* __restrict__ cstart,
-                                                    const uint32_t* __restrict__ perm, int64_t L,
-                                                    const PT* __restrict__ psi, uint32_t* __restrict__ cperm,
-                                                    int32_t* __restrict__ sb, PT* __restrict__ spsi) {
-  const int lane = lane_id();
-  const int64_t nw = (int64_t)gridDim.x * kWaves;
-  for (int64_t c = (int64_t)blockIdx.x * kWaves + (threadIdx.x >> 6); c < n_obs; c += nw) {
-    const int64_t src = seg[2 * (int64_t)order[c]];
-    const int64_t dst = cstart[c];
-    const int64_t h = cstart[c + 1] - dst;
-    for (int64_t k = lane; k < h; k += 64) {
-      const uint32_t t = perm[src + k];
-      cperm[dst + k] = t;
-      sb[dst + k] = (int32_t)((int64_t)t / L);
-      if (psi) spsi[dst + k] = psi[t];
-    }
-  }
-}
-
 // Compact pixel id of every sample (-1 for masked samples).
 __global__ void __launch_bounds__(kBlock) k_cpix(const int32_t* __restrict__ pix, int64_t n_t, int64_t n_pix,
                                                  const int32_t* __restrict__ cid, int32_t* __restrict__ cpix) {
@@ -199,84 +177,183 @@ __global__ void __launch_bounds__(kBlock) k_scatter(int64_t n_pix, const int32_t
   }
 }
 
-// Per-pixel hits, weight blocks, their inverse and validity, from the pixel's
-// sorted samples (one wavefront per pixel; fixed summation order).
-template <typename PT, bool HAS_QU>
-__global__ void __launch_bounds__(kBlock) k_pixel_blocks(View v, const int64_t* __restrict__ cstart,
-                                                         const PT* __restrict__ spsi, double rcond_cut,
-                                                         int32_t* __restrict__ hits, double* __restrict__ Minv4,
-                                                         uint8_t* __restrict__ valid, double* __restrict__ m4_zero,
-                                                         double* __restrict__ blocks_out,
+// One wavefront per compact pixel c (first-visit order): lay out the pixel's
+// samples -- sample index, baseline index, angle -- at [cstart[c], cstart[c+1])
+// in time order; sum its weight block (hits, M_QQ, M_QU, M_UU; the T block is
+// w_T h) and, with TOD, its sum map A^T W d; then invert the block with the
+// validity cut (Eqs. 9-11 and the remark after them) and form the binned map.
+// Fixed summation order per pixel; no atomics on pixel data.
+template <typename PT, typename TT, bool HAS_T, bool HAS_QU, bool TOD>
+__global__ void __launch_bounds__(kBlock) k_setup_pixels(View v, const uint32_t* __restrict__ order, int64_t n_obs,
+                                                         const int64_t* __restrict__ seg,
+                                                         const int64_t* __restrict__ cstart,
+                                                         const uint32_t* __restrict__ perm,
+                                                         const TT* __restrict__ tod, double rcond_cut,
+                                                         uint32_t* __restrict__ cperm, int32_t* __restrict__ sb,
+                                                         PT* __restrict__ spsi, int32_t* __restrict__ hits,
+                                                         double* __restrict__ Minv4, uint8_t* __restrict__ valid,
+                                                         double* __restrict__ m4_zero, double* __restrict__ sd4,
+                                                         double* __restrict__ md4,
                                                          unsigned long long* __restrict__ counts) {
-  __shared__ unsigned long long lds[2 * 16];
-  unsigned long long cnt[2] = {0, 0};
+  __shared__ unsigned long long lds[4 * 16];
+  unsigned long long cnt[4] = {0, 0, 0, 0};
   const int lane = lane_id();
   const int64_t nw = (int64_t)gridDim.x * kWaves;
-  const bool has_t = v.rowT >= 0;
-  for (int64_t p = (int64_t)blockIdx.x * kWaves + (threadIdx.x >> 6); p < v.n_pix; p += nw) {
-    const int64_t j0 = cstart[p], j1 = cstart[p + 1];
-    const int64_t h = j1 - j0;
-    double acc[3] = {0.0, 0.0, 0.0};
-    if (HAS_QU) {
-      for (int64_t j = j0 + lane; j < j1; j += 64) {
-        double c, s;
-        rot2((double)spsi[j], c, s);
-        acc[0] += c * c;
-        acc[1] += c * s;
-        acc[2] += s * s;
+  const PT* psi = static_cast<const PT*>(v.psi);
+  const int64_t n_t = v.n_t;
+  const uint32_t L = (uint32_t)v.L;
+  for (int64_t c = (int64_t)blockIdx.x * kWaves + (threadIdx.x >> 6); c < n_obs; c += nw) {
+    const int64_t src = seg[2 * (int64_t)order[c]];
+    const int64_t dst = cstart[c];
+    const int64_t h = cstart[c + 1] - dst;
+    double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};  // cc, cs, ss, d_I, d_Q, d_U
+    for (int64_t k = lane; k < h; k += 64) {
+      const uint32_t t = perm[src + k];
+      cperm[dst + k] = t;
+      sb[dst + k] = (int32_t)(t / L);
+      double cs = 1.0, sn = 0.0;
+      if (HAS_QU) {
+        const PT a = psi[t];
+        spsi[dst + k] = a;
+        rot2((double)a, cs, sn);
+        acc[0] += cs * cs;
+        acc[1] += cs * sn;
+        acc[2] += sn * sn;
       }
-      wave_sum<3>(acc);
+      if (TOD) {
+        if (HAS_T) acc[3] += (double)tod[v.rowT * n_t + t];
+        if (HAS_QU) {
+          const double xq = v.w[1] * (double)tod[v.rowQ * n_t + t];
+          const double xu = v.w[2] * (double)tod[v.rowU * n_t + t];
+          acc[4] += cs * xq - sn * xu;
+          acc[5] += sn * xq + cs * xu;
+        }
+      }
     }
+    wave_sum<6>(acc);
     if (lane == 0) {
       double inv[4] = {0.0, 0.0, 0.0, 0.0};
       uint8_t f = 0;
-      const double mII = has_t ? v.w[0] * (double)h : 0.0;
-      double a = 0.0, b = 0.0, d = 0.0;
-      if (has_t && h > 0) {
+      const double mII = HAS_T ? v.w[0] * (double)h : 0.0;
+      if (HAS_T && h > 0) {
         f |= 1;
         inv[0] = 1.0 / mII;
       }
-      if (HAS_QU) {
+      if (HAS_QU && h > 0) {
         const double wq = v.w[1], wu = v.w[2];
-        a = wq * acc[0] + wu * acc[2];
-        b = (wq - wu) * acc[1];
-        d = wq * acc[2] + wu * acc[0];
-        if (h > 0) {
-          const double half = 0.5 * (a - d);
-          const double rad = sqrt(half * half + b * b);
-          const double lmax = 0.5 * (a + d) + rad;
-          const double det = a * d - b * b;
-          const double lmin = lmax > 0.0 ? det / lmax : 0.0;
-          if (lmax > 0.0 && lmin > 0.0 && lmin >= rcond_cut * lmax) {
-            f |= 2;
-            inv[1] = d / det;
-            inv[2] = -b / det;
-            inv[3] = a / det;
-          }
+        const double a = wq * acc[0] + wu * acc[2];
+        const double b = (wq - wu) * acc[1];
+        const double d = wq * acc[2] + wu * acc[0];
+        // eigenvalues of the symmetric 2x2 block [[a, b], [b, d]]
+        const double half = 0.5 * (a - d);
+        const double rad = sqrt(half * half + b * b);
+        const double lmax = 0.5 * (a + d) + rad;
+        const double det = a * d - b * b;
+        const double lmin = lmax > 0.0 ? det / lmax : 0.0;
+        if (lmax > 0.0 && lmin > 0.0 && lmin >= rcond_cut * lmax) {
+          f |= 2;
+          inv[1] = d / det;
+          inv[2] = -b / det;
+          inv[3] = a / det;
         }
       }
-      hits[p] = (int32_t)h;
-      double2* mi = reinterpret_cast<double2*>(Minv4 + 4 * p);
+      hits[c] = (int32_t)h;
+      double2* mi = reinterpret_cast<double2*>(Minv4 + 4 * c);
       mi[0] = make_double2(inv[0], inv[1]);
       mi[1] = make_double2(inv[2], inv[3]);
-      valid[p] = f;
-      double2* mz = reinterpret_cast<double2*>(m4_zero + 4 * p);
+      valid[c] = f;
+      double2* mz = reinterpret_cast<double2*>(m4_zero + 4 * c);
       mz[0] = make_double2(0.0, 0.0);
       mz[1] = make_double2(0.0, 0.0);
-      if (blocks_out) {
-        blocks_out[4 * p + 0] = mII;
-        blocks_out[4 * p + 1] = a;
-        blocks_out[4 * p + 2] = b;
-        blocks_out[4 * p + 3] = d;
+      if (TOD) {
+        const double sI = (f & 1) ? v.w[0] * acc[3] : 0.0;
+        const double sQ = (f & 2) ? acc[4] : 0.0;
+        const double sU = (f & 2) ? acc[5] : 0.0;
+        double2* sp = reinterpret_cast<double2*>(sd4 + 4 * c);
+        sp[0] = make_double2(sI, sQ);
+        sp[1] = make_double2(sU, 0.0);
+        double2* mp = reinterpret_cast<double2*>(md4 + 4 * c);
+        mp[0] = make_double2(inv[0] * sI, inv[1] * sQ + inv[2] * sU);
+        mp[1] = make_double2(inv[2] * sQ + inv[3] * sU, 0.0);
       }
       cnt[0] += f & 1;
       cnt[1] += (f >> 1) & 1;
+      cnt[2] += (f & 1) ? (unsigned long long)h : 0ull;
+      cnt[3] += (f & 2) ? (unsigned long long)h : 0ull;
     }
   }
-  block_sum<2>(cnt, lds);
+  block_sum<4>(cnt, lds);
   if (threadIdx.x == 0 && counts) {
-    atomicAdd(&counts[0], cnt[0]);
-    atomicAdd(&counts[1], cnt[1]);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) atomicAdd(&counts[i], cnt[i]);
+  }
+}
+
+// Time-major pass over each baseline (one workgroup, XCD-local order):
+// valid-sample counts n_valid and the Jacobi diagonal 1/(w_k n_valid), and
+// with TOD the right-hand side of Eq. 13,
+//   b_k[beta] = w_k sum_{t in beta, valid_k} (d_k(t) - A_k(t) . m_d[p(t)]).
+template <typename PT, typename TT, bool HAS_T, bool HAS_QU, bool TOD>
+__global__ void __launch_bounds__(kBlock) k_rhs_unbin(View v, const TT* __restrict__ tod,
+                                                      const double* __restrict__ md4,
+                                                      const uint8_t* __restrict__ valid, int32_t* __restrict__ nvalid,
+                                                      double* __restrict__ J, double* __restrict__ b_out) {
+  __shared__ double lds[5 * 16];
+  const PT* psi = static_cast<const PT*>(v.psi);
+  const int64_t n_b = v.n_b, n_t = v.n_t;
+  const int64_t b = xcd_baseline(n_b);
+  if (b < 0) return;
+  const int64_t t0 = b * v.L;
+  const int64_t t1 = min(t0 + v.L, n_t);
+  double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};  // d_T - m, d_q - A m, d_u - A m, n_T, n_QU
+  constexpr int U = 8;
+  for (int64_t tb = t0 + threadIdx.x; tb < t1; tb += U * kBlock) {
+    int pp[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t t = tb + u * kBlock;
+      pp[u] = t < t1 ? v.pix[t] : -1;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int pu = pp[u];
+      if (pu < 0 || pu >= v.n_pix) continue;
+      const int64_t t = tb + u * kBlock;
+      const uint8_t f = valid[pu];
+      const double2* mp = reinterpret_cast<const double2*>(md4 + 4 * (int64_t)pu);
+      if (HAS_T && (f & 1)) {
+        acc[3] += 1.0;
+        if (TOD) acc[0] += (double)tod[v.rowT * n_t + t] - mp[0].x;
+      }
+      if (HAS_QU && (f & 2)) {
+        acc[4] += 1.0;
+        if (TOD) {
+          const double mQ = mp[0].y, mU = mp[1].x;
+          double c, s;
+          rot2((double)psi[t], c, s);
+          acc[1] += (double)tod[v.rowQ * n_t + t] - (c * mQ + s * mU);
+          acc[2] += (double)tod[v.rowU * n_t + t] - (c * mU - s * mQ);
+        }
+      }
+    }
+  }
+  block_sum<5>(acc, lds);
+  if (threadIdx.x == 0) {
+    const int nT = (int)acc[3], nQ = (int)acc[4];
+    nvalid[b] = nT;
+    nvalid[n_b + b] = nQ;
+    if (HAS_T) {
+      J[v.rowT * n_b + b] = nT ? 1.0 / (v.w[0] * nT) : 0.0;
+      if (TOD) b_out[v.rowT * n_b + b] = v.w[0] * acc[0];
+    }
+    if (HAS_QU) {
+      J[v.rowQ * n_b + b] = nQ ? 1.0 / (v.w[1] * nQ) : 0.0;
+      J[v.rowU * n_b + b] = nQ ? 1.0 / (v.w[2] * nQ) : 0.0;
+      if (TOD) {
+        b_out[v.rowQ * n_b + b] = v.w[1] * acc[1];
+        b_out[v.rowU * n_b + b] = v.w[2] * acc[2];
+      }
+    }
   }
 }
 
@@ -298,87 +375,37 @@ __global__ void __launch_bounds__(kBlock) k_bin_pixel(int64_t n_pix, const int64
     if (valid[p] == 0) continue;  // m stays 0 on invalid pixels
     const int64_t j0 = cstart[p], j1 = cstart[p + 1];
     double acc[3] = {0.0, 0.0, 0.0};
-    int64_t j = j0 + lane;
-    // two samples per lane per step for memory-level parallelism
-    for (; j + 64 < j1; j += 128) {
-      const int32_t b0 = sb[j], b1 = sb[j + 64];
-      double c0 = 1.0, s0 = 0.0, c1 = 1.0, s1 = 0.0;
-      if (HAS_QU) {
-        const double a0 = (double)spsi[j], a1 = (double)spsi[j + 64];
-        rot2(a0, c0, s0);
-        rot2(a1, c1, s1);
+    // U samples per lane per step: all streaming loads first, then the gathers
+    constexpr int U = 4;
+    for (int64_t jb = j0 + lane; jb < j1; jb += 64 * U) {
+      int32_t bb[U];
+      double aa[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int64_t j = jb + 64 * u;
+        const bool in = j < j1;
+        bb[u] = in ? sb[j] : -1;
+        aa[u] = (HAS_QU && in) ? (double)spsi[j] : 0.0;
       }
-      const double2* q0 = reinterpret_cast<const double2*>(pw4 + 4 * (int64_t)b0);
-      const double2* q1 = reinterpret_cast<const double2*>(pw4 + 4 * (int64_t)b1);
-      const double2 x0 = q0[0], x1 = q1[0];
-      if (HAS_T) acc[0] += x0.x + x1.x;
-      if (HAS_QU) {
-        const double u0 = q0[1].x, u1 = q1[1].x;
-        acc[1] += (c0 * x0.y - s0 * u0) + (c1 * x1.y - s1 * u1);
-        acc[2] += (s0 * x0.y + c0 * u0) + (s1 * x1.y + c1 * u1);
-      }
-    }
-    if (j < j1) {
-      const int32_t b0 = sb[j];
-      const double2* q0 = reinterpret_cast<const double2*>(pw4 + 4 * (int64_t)b0);
-      const double2 x0 = q0[0];
-      if (HAS_T) acc[0] += x0.x;
-      if (HAS_QU) {
-        double c0, s0;
-        rot2((double)spsi[j], c0, s0);
-        const double u0 = q0[1].x;
-        acc[1] += c0 * x0.y - s0 * u0;
-        acc[2] += s0 * x0.y + c0 * u0;
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        if (bb[u] < 0) continue;
+        const double2* q0 = reinterpret_cast<const double2*>(pw4 + 4 * (int64_t)bb[u]);
+        const double2 x0 = q0[0];
+        if (HAS_T) acc[0] += x0.x;
+        if (HAS_QU) {
+          const double u0 = q0[1].x;
+          double c0, s0;
+          rot2(aa[u], c0, s0);
+          acc[1] += c0 * x0.y - s0 * u0;
+          acc[2] += s0 * x0.y + c0 * u0;
+        }
       }
     }
     wave_sum<3>(acc);
     if (lane == 0) {
       const double2* ip = reinterpret_cast<const double2*>(Minv4 + 4 * p);
       const double2 i01 = ip[0], i23 = ip[1];
-      double2* mp = reinterpret_cast<double2*>(m4 + 4 * p);
-      mp[0] = make_double2(i01.x * acc[0], i01.y * acc[1] + i23.x * acc[2]);
-      mp[1] = make_double2(i23.x * acc[1] + i23.y * acc[2], 0.0);
-    }
-  }
-}
-
-// Binning of the timelines (right-hand side), pixel-major through the sort
-// permutation: s_p = sum_{t in p} sum_k v_k w_k A_k(t)^T d_k(t); also m = M^-1 s.
-template <typename PT, typename TT, bool HAS_T, bool HAS_QU>
-__global__ void __launch_bounds__(kBlock) k_bin_pixel_tod(View v, const int64_t* __restrict__ cstart,
-                                                          const uint32_t* __restrict__ perm,
-                                                          const PT* __restrict__ spsi, const TT* __restrict__ tod,
-                                                          const double* __restrict__ Minv4,
-                                                          const uint8_t* __restrict__ valid,
-                                                          double* __restrict__ s4, double* __restrict__ m4) {
-  const int lane = lane_id();
-  const int64_t nw = (int64_t)gridDim.x * kWaves;
-  const int64_t n_t = v.n_t;
-  for (int64_t p = (int64_t)blockIdx.x * kWaves + (threadIdx.x >> 6); p < v.n_pix; p += nw) {
-    const uint8_t f = valid[p];
-    const int64_t j0 = cstart[p], j1 = cstart[p + 1];
-    double acc[3] = {0.0, 0.0, 0.0};
-    if (f) {
-      for (int64_t j = j0 + lane; j < j1; j += 64) {
-        const int64_t t = perm[j];
-        if (HAS_T && (f & 1)) acc[0] += v.w[0] * (double)tod[v.rowT * n_t + t];
-        if (HAS_QU && (f & 2)) {
-          double c, s;
-          rot2((double)spsi[j], c, s);
-          const double xq = v.w[1] * (double)tod[v.rowQ * n_t + t];
-          const double xu = v.w[2] * (double)tod[v.rowU * n_t + t];
-          acc[1] += c * xq - s * xu;
-          acc[2] += s * xq + c * xu;
-        }
-      }
-      wave_sum<3>(acc);
-    }
-    if (lane == 0) {
-      const double2* ip = reinterpret_cast<const double2*>(Minv4 + 4 * p);
-      const double2 i01 = ip[0], i23 = ip[1];
-      double2* sp = reinterpret_cast<double2*>(s4 + 4 * p);
-      sp[0] = make_double2(acc[0], acc[1]);
-      sp[1] = make_double2(acc[2], 0.0);
       double2* mp = reinterpret_cast<double2*>(m4 + 4 * p);
       mp[0] = make_double2(i01.x * acc[0], i01.y * acc[1] + i23.x * acc[2]);
       mp[1] = make_double2(i23.x * acc[1] + i23.y * acc[2], 0.0);
@@ -405,7 +432,7 @@ __global__ void __launch_bounds__(kBlock) k_unbin_cg(View v, const double* __res
     const int64_t t0 = b * v.L;
     const int64_t t1 = min(t0 + v.L, v.n_t);
     double acc[3] = {0.0, 0.0, 0.0};
-    constexpr int U = 4;
+    constexpr int U = 8;
     for (int64_t tb = t0 + threadIdx.x; tb < t1; tb += U * kBlock) {
       int pp[U];
       double ang[U];
@@ -583,7 +610,7 @@ hipError_t transpose_tmp_bytes(int64_t n_t, int64_t n_pix, size_t* bytes) {
   return hipSuccess;
 }
 
-hipError_t transpose_build(const View& v, int psi_f32, Transpose& T, int* err, hipStream_t st) {
+hipError_t transpose_build(const View& v, Transpose& T, int* err, hipStream_t st) {
   const int64_t n_t = v.n_t, n_pix = v.n_pix;
   const unsigned g = grid_for(n_t, kBlock, 8192);
   const unsigned gp = grid_for(n_pix, kBlock, 4096);
@@ -615,7 +642,7 @@ hipError_t transpose_build(const View& v, int psi_f32, Transpose& T, int* err, h
   DST_CHECK(hipMemcpyAsync(&nobs, T.n_obs_dev, sizeof nobs, hipMemcpyDeviceToHost, st));
   DST_CHECK(hipStreamSynchronize(st));
   T.n_obs = (int64_t)nobs;
-  // 4. compact ids, per-pixel offsets, and the transposed sample arrays
+  // 4. compact ids and per-pixel offsets of the transposed arrays
   hipLaunchKernelGGL(k_compact_ids, dim3(grid_for(T.n_obs + 1, kBlock, 4096)), dim3(kBlock), 0, st, T.order,
                      T.n_obs, T.seg, T.cid, T.chits);
   DST_CHECK(hipGetLastError());
@@ -624,42 +651,98 @@ hipError_t transpose_build(const View& v, int psi_f32, Transpose& T, int* err, h
     DST_CHECK(rocprim::exclusive_scan(T.tmp, tmp, T.chits, T.cstart, (int64_t)0, (size_t)T.n_obs + 1,
                                       rocprim::plus<int64_t>(), st));
   }
-  const unsigned gw = grid_for(T.n_obs, kWaves, 65536);
-  if (psi_f32)
-    hipLaunchKernelGGL(k_reorder<float>, dim3(gw), dim3(kBlock), 0, st, T.order, T.n_obs, T.seg, T.cstart, T.perm,
-                       v.L, static_cast<const float*>(v.rowQ >= 0 ? v.psi : nullptr), T.cperm, T.sb,
-                       static_cast<float*>(T.spsi));
-  else
-    hipLaunchKernelGGL(k_reorder<double>, dim3(gw), dim3(kBlock), 0, st, T.order, T.n_obs, T.seg, T.cstart, T.perm,
-                       v.L, static_cast<const double*>(v.rowQ >= 0 ? v.psi : nullptr), T.cperm, T.sb,
-                       static_cast<double*>(T.spsi));
-  DST_CHECK(hipGetLastError());
   hipLaunchKernelGGL(k_cpix, dim3(g), dim3(kBlock), 0, st, v.pix, n_t, n_pix, T.cid, T.cpix);
   return hipGetLastError();
 }
 
-hipError_t launch_pixel_blocks(const View& vc, int psi_f32, const Transpose& T, double rcond_cut, int32_t* hits,
-                               double* Minv4, uint8_t* valid, double* m4_zero, double* blocks_out,
-                               unsigned long long* counts, hipStream_t st) {
-  const unsigned g = grid_for(vc.n_pix, kWaves, 65536);
-  const bool qu = vc.rowQ >= 0;
-  if (qu && psi_f32)
-    hipLaunchKernelGGL((k_pixel_blocks<float, true>), dim3(g), dim3(kBlock), 0, st, vc, T.cstart,
-                       static_cast<const float*>(T.spsi), rcond_cut, hits, Minv4, valid, m4_zero, blocks_out, counts);
-  else if (qu)
-    hipLaunchKernelGGL((k_pixel_blocks<double, true>), dim3(g), dim3(kBlock), 0, st, vc, T.cstart,
-                       static_cast<const double*>(T.spsi), rcond_cut, hits, Minv4, valid, m4_zero, blocks_out,
-                       counts);
+template <typename PT, typename TT, bool HAS_T, bool HAS_QU>
+static void setup_pixels_dispatch(const View& v, const Transpose& T, const void* tod, double rcond_cut,
+                                  int32_t* hits, double* Minv4, uint8_t* valid, double* m4_zero, double* sd4,
+                                  double* md4, unsigned long long* counts, hipStream_t st) {
+  const unsigned g = grid_for(T.n_obs, kWaves, 4096);
+  const TT* x = static_cast<const TT*>(tod);
+  PT* sp = static_cast<PT*>(T.spsi);
+  if (tod)
+    hipLaunchKernelGGL((k_setup_pixels<PT, TT, HAS_T, HAS_QU, true>), dim3(g), dim3(kBlock), 0, st, v, T.order,
+                       T.n_obs, T.seg, T.cstart, T.perm, x, rcond_cut, T.cperm, T.sb, sp, hits, Minv4, valid, m4_zero,
+                       sd4, md4, counts);
   else
-    hipLaunchKernelGGL((k_pixel_blocks<double, false>), dim3(g), dim3(kBlock), 0, st, vc, T.cstart,
-                       static_cast<const double*>(nullptr), rcond_cut, hits, Minv4, valid, m4_zero, blocks_out,
-                       counts);
+    hipLaunchKernelGGL((k_setup_pixels<PT, TT, HAS_T, HAS_QU, false>), dim3(g), dim3(kBlock), 0, st, v, T.order,
+                       T.n_obs, T.seg, T.cstart, T.perm, x, rcond_cut, T.cperm, T.sb, sp, hits, Minv4, valid, m4_zero,
+                       sd4, md4, counts);
+}
+
+template <typename PT, typename TT>
+static void setup_pixels_streams(const View& v, const Transpose& T, const void* tod, double rcond_cut, int32_t* hits,
+                                 double* Minv4, uint8_t* valid, double* m4_zero, double* sd4, double* md4,
+                                 unsigned long long* counts, hipStream_t st) {
+  if (v.rowT >= 0 && v.rowQ >= 0)
+    setup_pixels_dispatch<PT, TT, true, true>(v, T, tod, rcond_cut, hits, Minv4, valid, m4_zero, sd4, md4, counts, st);
+  else if (v.rowQ >= 0)
+    setup_pixels_dispatch<PT, TT, false, true>(v, T, tod, rcond_cut, hits, Minv4, valid, m4_zero, sd4, md4, counts,
+                                               st);
+  else
+    setup_pixels_dispatch<PT, TT, true, false>(v, T, tod, rcond_cut, hits, Minv4, valid, m4_zero, sd4, md4, counts,
+                                               st);
+}
+
+hipError_t launch_setup_pixels(const View& v, int psi_f32, const Transpose& T, const void* tod, int tod_f32,
+                               double rcond_cut, int32_t* hits, double* Minv4, uint8_t* valid, double* m4_zero,
+                               double* sd4, double* md4, unsigned long long* counts, hipStream_t st) {
+  if (T.n_obs == 0) return hipSuccess;
+  const bool pf = psi_f32 && v.rowQ >= 0;
+  if (pf && tod_f32)
+    setup_pixels_streams<float, float>(v, T, tod, rcond_cut, hits, Minv4, valid, m4_zero, sd4, md4, counts, st);
+  else if (pf)
+    setup_pixels_streams<float, double>(v, T, tod, rcond_cut, hits, Minv4, valid, m4_zero, sd4, md4, counts, st);
+  else if (tod_f32)
+    setup_pixels_streams<double, float>(v, T, tod, rcond_cut, hits, Minv4, valid, m4_zero, sd4, md4, counts, st);
+  else
+    setup_pixels_streams<double, double>(v, T, tod, rcond_cut, hits, Minv4, valid, m4_zero, sd4, md4, counts, st);
   return hipGetLastError();
 }
 
-hipError_t launch_scatter(int64_t n_pix, const Transpose& T, const int32_t* chits, int32_t* hits, const double* a4,
+template <typename PT, typename TT, bool HAS_T, bool HAS_QU>
+static void rhs_dispatch(const View& vc, const void* tod, const double* md4, const uint8_t* valid, int32_t* nvalid,
+                         double* J, double* b, hipStream_t st) {
+  const unsigned g = (unsigned)(8 * ((vc.n_b + 7) / 8));
+  const TT* x = static_cast<const TT*>(tod);
+  if (tod)
+    hipLaunchKernelGGL((k_rhs_unbin<PT, TT, HAS_T, HAS_QU, true>), dim3(g), dim3(kBlock), 0, st, vc, x, md4, valid,
+                       nvalid, J, b);
+  else
+    hipLaunchKernelGGL((k_rhs_unbin<PT, TT, HAS_T, HAS_QU, false>), dim3(g), dim3(kBlock), 0, st, vc, x, md4, valid,
+                       nvalid, J, b);
+}
+
+template <typename PT, typename TT>
+static void rhs_streams(const View& vc, const void* tod, const double* md4, const uint8_t* valid, int32_t* nvalid,
+                        double* J, double* b, hipStream_t st) {
+  if (vc.rowT >= 0 && vc.rowQ >= 0)
+    rhs_dispatch<PT, TT, true, true>(vc, tod, md4, valid, nvalid, J, b, st);
+  else if (vc.rowQ >= 0)
+    rhs_dispatch<PT, TT, false, true>(vc, tod, md4, valid, nvalid, J, b, st);
+  else
+    rhs_dispatch<PT, TT, true, false>(vc, tod, md4, valid, nvalid, J, b, st);
+}
+
+hipError_t launch_rhs_unbin(const View& vc, int psi_f32, const void* tod, int tod_f32, const double* md4,
+                            const uint8_t* valid, int32_t* nvalid, double* J, double* b, hipStream_t st) {
+  const bool pf = psi_f32 && vc.rowQ >= 0;
+  if (pf && tod_f32)
+    rhs_streams<float, float>(vc, tod, md4, valid, nvalid, J, b, st);
+  else if (pf)
+    rhs_streams<float, double>(vc, tod, md4, valid, nvalid, J, b, st);
+  else if (tod_f32)
+    rhs_streams<double, float>(vc, tod, md4, valid, nvalid, J, b, st);
+  else
+    rhs_streams<double, double>(vc, tod, md4, valid, nvalid, J, b, st);
+  return hipGetLastError();
+}
+
+hipError_t launch_scatter(int64_t n_pix, const int32_t* cid, const int32_t* chits, int32_t* hits, const double* a4,
                           const double* b4, double* out3, hipStream_t st) {
-  hipLaunchKernelGGL(k_scatter, dim3(grid_for(n_pix, kBlock, 4096)), dim3(kBlock), 0, st, n_pix, T.cid, chits, hits,
+  hipLaunchKernelGGL(k_scatter, dim3(grid_for(n_pix, kBlock, 4096)), dim3(kBlock), 0, st, n_pix, cid, chits, hits,
                      a4, b4, out3);
   return hipGetLastError();
 }
@@ -686,37 +769,6 @@ hipError_t launch_bin_pixel(const View& v, int psi_f32, const Transpose& T, cons
     bin_pixel_dispatch<float>(v, T, pw4, Minv4, valid, m4, gate, st);
   else
     bin_pixel_dispatch<double>(v, T, pw4, Minv4, valid, m4, gate, st);
-  return hipGetLastError();
-}
-
-template <typename PT, typename TT>
-static void bin_tod_dispatch(const View& v, const Transpose& T, const void* tod, const double* Minv4,
-                             const uint8_t* valid, double* s4, double* m4, hipStream_t st) {
-  const unsigned g = grid_for(v.n_pix, kWaves, 65536);
-  const PT* sp = static_cast<const PT*>(T.spsi);
-  const TT* x = static_cast<const TT*>(tod);
-  if (v.rowT >= 0 && v.rowQ >= 0)
-    hipLaunchKernelGGL((k_bin_pixel_tod<PT, TT, true, true>), dim3(g), dim3(kBlock), 0, st, v, T.cstart, T.cperm, sp, x,
-                       Minv4, valid, s4, m4);
-  else if (v.rowQ >= 0)
-    hipLaunchKernelGGL((k_bin_pixel_tod<PT, TT, false, true>), dim3(g), dim3(kBlock), 0, st, v, T.cstart, T.cperm, sp,
-                       x, Minv4, valid, s4, m4);
-  else
-    hipLaunchKernelGGL((k_bin_pixel_tod<PT, TT, true, false>), dim3(g), dim3(kBlock), 0, st, v, T.cstart, T.cperm, sp,
-                       x, Minv4, valid, s4, m4);
-}
-
-hipError_t launch_bin_pixel_tod(const View& v, int psi_f32, const Transpose& T, const void* tod, int tod_f32,
-                                const double* Minv4, const uint8_t* valid, double* s4, double* m4, hipStream_t st) {
-  const bool pf = psi_f32 && v.rowQ >= 0;
-  if (pf && tod_f32)
-    bin_tod_dispatch<float, float>(v, T, tod, Minv4, valid, s4, m4, st);
-  else if (pf)
-    bin_tod_dispatch<float, double>(v, T, tod, Minv4, valid, s4, m4, st);
-  else if (tod_f32)
-    bin_tod_dispatch<double, float>(v, T, tod, Minv4, valid, s4, m4, st);
-  else
-    bin_tod_dispatch<double, double>(v, T, tod, Minv4, valid, s4, m4, st);
   return hipGetLastError();
 }
 

@@ -1,0 +1,75 @@
+// Run-compressed pointing used by the iterative solve (default form).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "dst_internal.h"
+
+namespace dst {
+
+// Setup moments stored per run: sums of c^2, cs, s^2 (weight blocks) and of
+// d_T, d_q, d_u and of the rotated, weighted q/u pair (right-hand side).
+constexpr int kMom = 8;
+
+// A run is a maximal stretch of consecutive unmasked samples on one pixel
+// inside one baseline.  Runs are kept twice: in time order (t*: rescan and
+// baseline sums; bstart[b] .. bstart[b+1] are the runs of baseline b) and in
+// pixel order (p*: binning; pstart[c] .. pstart[c+1] are the runs of compact
+// pixel c, in time order).  Compact ids number observed pixels in pixel order.
+//
+// Buffers belong to the caller's workspace.  Sizes: head, hidx [n_t];
+// bstart [n_b + 1]; t0, tpix, tn, pb, pn [R] and tc, ts, pc, ps [R] (doubles);
+// mom [kMom R]; keys, vals 2 x [R]; seg [2 n_pix] (zero-filled before
+// runs_build); obs, oidx [n_pix + 1]; cid, order [n_pix]; pstart [n_pix + 1].
+struct Runs {
+  uint32_t* head = nullptr;
+  uint32_t* hidx = nullptr;
+  void* tmp = nullptr;
+  size_t tmp_bytes = 0;
+  int64_t R = 0;
+  uint32_t* t0 = nullptr;
+  uint32_t* bstart = nullptr;
+  int32_t* tpix = nullptr;
+  int32_t* tn = nullptr;
+  double* tc = nullptr;
+  double* ts = nullptr;
+  double* mom = nullptr;
+  uint32_t* keys[2] = {nullptr, nullptr};
+  uint32_t* vals[2] = {nullptr, nullptr};
+  const uint32_t* rperm = nullptr;
+  int64_t* seg = nullptr;
+  uint32_t* obs = nullptr;
+  uint32_t* oidx = nullptr;
+  int32_t* cid = nullptr;
+  uint32_t* order = nullptr;
+  int64_t n_obs = 0;
+  int32_t* pb = nullptr;
+  int32_t* pn = nullptr;
+  double* pc = nullptr;
+  double* ps = nullptr;
+  int64_t* pstart = nullptr;
+};
+
+hipError_t runs_tmp_bytes(int64_t n_t, int64_t n_pix, size_t* bytes);
+// Marks run heads and counts the runs (W.R); synchronises `st`.
+hipError_t runs_count(const View& v, Runs& W, int* err, hipStream_t st);
+// Builds the time- and pixel-order runs, compact ids (synchronises `st` once
+// for n_obs), and per compact pixel: hits, block inverse, validity, zeroed
+// m4 and, with tod, the sum map sd4 and binned map md4.
+// counts: [valid T pixels, valid QU pixels, valid T samples, valid QU samples].
+hipError_t runs_build(const View& v, int psi_f32, const void* tod, int tod_f32, double rcond_cut, Runs& W,
+                      int32_t* hits, double* Minv4, uint8_t* valid, double* m4_zero, double* sd4, double* md4,
+                      unsigned long long* counts, hipStream_t st);
+// Per baseline: n_valid, Jacobi diagonal, and with tod b = F^T W (d - A m_d).
+hipError_t launch_rhs_runs(const View& vc, const Runs& W, const void* tod, const double* md4, const uint8_t* valid,
+                           int32_t* nvalid, double* J, double* b, hipStream_t st);
+// m = M^-1 A^T W F p (pw4 = interleaved w .* p).
+hipError_t launch_bin_runs(const View& vc, const Runs& W, const double* pw4, const double* Minv4,
+                           const uint8_t* valid, double* m4, const CgCtl* gate, hipStream_t st);
+// q = K p; with ctl the per-baseline CG partials (finished by launch_cg_alpha).
+hipError_t launch_unbin_runs(const View& vc, const Runs& W, const double* m4, const int32_t* nvalid, const double* p,
+                             double* q, CgCtl* ctl, double* partials, hipStream_t st);
+
+}  // namespace dst

@@ -1,0 +1,705 @@
+// Run-compressed pointing for the iterative solve.
+//
+// Inside one baseline the baseline offset is a constant, so every sample of a
+// run -- a maximal stretch of consecutive samples on the same pixel within one
+// baseline -- meets the same p[beta] in the binning of F p, and the same map
+// values in the rescan.  Grouping the terms of A^T W F p and F^T W A m
+// (Eqs. 10-13 of arXiv:1309.5609) by run gives, exactly up to rounding order,
+//   T:  n_r p_T[beta]            and  n_r m_I
+//   Q:  C_r w_q p_q - S_r w_u p_u    U: S_r w_q p_q + C_r w_u p_u
+//   q:  C_r m_Q + S_r m_U            u: C_r m_U - S_r m_Q
+// with n_r the run length and C_r, S_r the sums of cos 2psi, sin 2psi over the
+// run.  The runs are built once per solve; each CG iteration then reads one
+// small record per run (no trigonometry), in pixel order for the binning and
+// in time order for the rescan.
+#include <hip/hip_runtime.h>
+
+#include <rocprim/device/device_radix_sort.hpp>
+#include <rocprim/device/device_scan.hpp>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+
+#include "dst_internal.h"
+#include "dst_runs.h"
+#include "dst_trig.h"
+
+namespace dst {
+namespace {
+
+constexpr int kBlock = 256;
+constexpr int kWaves = kBlock / 64;
+
+__device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
+
+__device__ __forceinline__ void rot2(double psi, double& c, double& s) { fast_sincos(2.0 * psi, &s, &c); }
+
+template <int N>
+__device__ __forceinline__ void wave_sum(double (&v)[N]) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+#pragma unroll
+    for (int i = 0; i < N; ++i) v[i] += __shfl_xor(v[i], off, 64);
+  }
+}
+
+template <int N, typename T>
+__device__ __forceinline__ void block_sum(T (&v)[N], T* lds) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+#pragma unroll
+    for (int i = 0; i < N; ++i) v[i] += __shfl_xor(v[i], off, 64);
+  }
+  const int wid = threadIdx.x >> 6;
+  const int nw = blockDim.x >> 6;
+  if (lane_id() == 0) {
+#pragma unroll
+    for (int i = 0; i < N; ++i) lds[i * 16 + wid] = v[i];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      T acc = lds[i * 16];
+      for (int w = 1; w < nw; ++w) acc += lds[i * 16 + w];
+      v[i] = acc;
+    }
+  }
+  __syncthreads();
+}
+
+// Workgroup i runs on XCD i mod 8; give each XCD a contiguous range of
+// baselines.  Returns -1 for padding groups.
+__device__ __forceinline__ int64_t xcd_baseline(int64_t n_b) {
+  const int64_t per = (n_b + 7) / 8;
+  const int64_t i = blockIdx.x;
+  const int64_t b = (i & 7) * per + (i >> 3);
+  return b < n_b ? b : -1;
+}
+
+__global__ void __launch_bounds__(kBlock) k_iota(uint32_t* __restrict__ x, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    x[i] = (uint32_t)i;
+}
+
+unsigned grid_for(int64_t n, int64_t per_block, unsigned cap) {
+  int64_t g = (n + per_block - 1) / per_block;
+  if (g < 1) g = 1;
+  if (g > cap) g = cap;
+  return (unsigned)g;
+}
+
+// ---------------------------------------------------------------- run building
+
+// head[t] = 1 where a run starts: an unmasked sample whose predecessor is on
+// another pixel, is masked, or lies in the previous baseline.
+__global__ void __launch_bounds__(kBlock) k_run_heads(const int32_t* __restrict__ pix, int64_t n_t, int64_t n_pix,
+                                                      int64_t L, uint32_t* __restrict__ head, int* __restrict__ err) {
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n_t; t += (int64_t)gridDim.x * blockDim.x) {
+    const int p = pix[t];
+    uint32_t h = 0;
+    if (p >= n_pix) atomicOr(err, 1);
+    if (p >= 0 && p < n_pix) {
+      if (t == 0 || (t % L) == 0)
+        h = 1;
+      else
+        h = pix[t - 1] != p;
+    }
+    head[t] = h;
+  }
+}
+
+// First sample of each run, and the first run of each baseline.
+__global__ void __launch_bounds__(kBlock) k_run_starts(const uint32_t* __restrict__ head,
+                                                       const uint32_t* __restrict__ hidx, int64_t n_t, int64_t L,
+                                                       int64_t n_b, uint32_t* __restrict__ t0,
+                                                       uint32_t* __restrict__ bstart) {
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n_t; t += (int64_t)gridDim.x * blockDim.x) {
+    if (head[t]) t0[hidx[t]] = (uint32_t)t;
+    if ((t % L) == 0) bstart[t / L] = hidx[t];
+    if (t == n_t - 1) bstart[n_b] = hidx[t] + head[t];
+  }
+}
+
+// One thread per run: length, sums of cos 2psi and sin 2psi, and the setup
+// moments (sums of c^2, cs, s^2 for the weight blocks; timeline sums for the
+// right-hand side).  Samples are summed in time order.
+template <typename PT, typename TT, bool HAS_T, bool HAS_QU, bool TOD>
+__global__ void __launch_bounds__(kBlock) k_run_build(View v, const TT* __restrict__ tod,
+                                                      const uint32_t* __restrict__ t0, int64_t R,
+                                                      int32_t* __restrict__ rpix, int32_t* __restrict__ rn,
+                                                      double* __restrict__ rc, double* __restrict__ rs,
+                                                      double* __restrict__ mom) {
+  const PT* psi = static_cast<const PT*>(v.psi);
+  const int64_t n_t = v.n_t, L = v.L;
+  for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < R; r += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t ts = t0[r];
+    const int p = v.pix[ts];
+    const int64_t tend = min(n_t, (ts / L + 1) * L);
+    double C = 0.0, S = 0.0, cc = 0.0, cs = 0.0, ss = 0.0;
+    double dT = 0.0, dq = 0.0, du = 0.0, dQ = 0.0, dU = 0.0;
+    int64_t t = ts;
+    for (; t < tend && v.pix[t] == p; ++t) {
+      double c = 1.0, s = 0.0;
+      if (HAS_QU) {
+        rot2((double)psi[t], c, s);
+        C += c;
+        S += s;
+        cc += c * c;
+        cs += c * s;
+        ss += s * s;
+      }
+      if (TOD) {
+        if (HAS_T) dT += (double)tod[v.rowT * n_t + t];
+        if (HAS_QU) {
+          const double xq = (double)tod[v.rowQ * n_t + t];
+          const double xu = (double)tod[v.rowU * n_t + t];
+          dq += xq;
+          du += xu;
+          const double wq = v.w[1] * xq, wu = v.w[2] * xu;
+          dQ += c * wq - s * wu;
+          dU += s * wq + c * wu;
+        }
+      }
+    }
+    rpix[r] = p;
+    rn[r] = (int32_t)(t - ts);
+    if (HAS_QU) {
+      rc[r] = C;
+      rs[r] = S;
+    }
+    double* m = mom + kMom * r;
+    m[0] = cc;
+    m[1] = cs;
+    m[2] = ss;
+    m[3] = dT;
+    m[4] = dq;
+    m[5] = du;
+    m[6] = dQ;
+    m[7] = dU;
+  }
+}
+
+// seg[2k], seg[2k+1]: range of key k in the sorted key array.
+__global__ void __launch_bounds__(kBlock) k_key_segments(const uint32_t* __restrict__ keys, int64_t n,
+                                                         int64_t* __restrict__ seg) {
+  for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n; j += (int64_t)gridDim.x * blockDim.x) {
+    const uint32_t k = keys[j];
+    if (j == 0 || keys[j - 1] != k) seg[2 * (int64_t)k] = j;
+    if (j == n - 1 || keys[j + 1] != k) seg[2 * (int64_t)k + 1] = j + 1;
+  }
+}
+
+__global__ void __launch_bounds__(kBlock) k_observed(const int64_t* __restrict__ seg, int64_t n_pix,
+                                                     uint32_t* __restrict__ obs) {
+  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p <= n_pix; p += (int64_t)gridDim.x * blockDim.x)
+    obs[p] = (p < n_pix && seg[2 * p + 1] > seg[2 * p]) ? 1u : 0u;
+}
+
+// Compact ids (pixel order) and the compact -> pixel map.
+__global__ void __launch_bounds__(kBlock) k_compact(const uint32_t* __restrict__ obs, const uint32_t* __restrict__ oidx,
+                                                    int64_t n_pix, int32_t* __restrict__ cid,
+                                                    uint32_t* __restrict__ order) {
+  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n_pix; p += (int64_t)gridDim.x * blockDim.x) {
+    if (obs[p]) {
+      cid[p] = (int32_t)oidx[p];
+      order[oidx[p]] = (uint32_t)p;
+    } else {
+      cid[p] = -1;
+    }
+  }
+}
+
+// One wavefront per compact pixel: its runs (pixel order, time order within
+// the pixel) -> the pixel-order run arrays; hits, weight blocks, inverse,
+// validity; with TOD the sum map and binned map.
+template <bool HAS_T, bool HAS_QU, bool TOD>
+__global__ void __launch_bounds__(kBlock) k_pixels_from_runs(
+    View v, int64_t n_obs, const uint32_t* __restrict__ order, const int64_t* __restrict__ seg,
+    const uint32_t* __restrict__ rperm, const uint32_t* __restrict__ t0, const int32_t* __restrict__ rn,
+    const double* __restrict__ rc, const double* __restrict__ rs, const double* __restrict__ mom, double rcond_cut,
+    int32_t* __restrict__ pb, int32_t* __restrict__ pn, double* __restrict__ pc, double* __restrict__ ps,
+    int64_t* __restrict__ pstart, int32_t* __restrict__ hits, double* __restrict__ Minv4,
+    uint8_t* __restrict__ valid, double* __restrict__ m4_zero, double* __restrict__ sd4, double* __restrict__ md4,
+    unsigned long long* __restrict__ counts) {
+  __shared__ unsigned long long lds[4 * 16];
+  unsigned long long cnt[4] = {0, 0, 0, 0};
+  const int lane = lane_id();
+  const int64_t nw = (int64_t)gridDim.x * kWaves;
+  const uint32_t L = (uint32_t)v.L;
+  for (int64_t c = (int64_t)blockIdx.x * kWaves + (threadIdx.x >> 6); c < n_obs; c += nw) {
+    const uint32_t p = order[c];
+    const int64_t j0 = seg[2 * (int64_t)p], j1 = seg[2 * (int64_t)p + 1];
+    double acc[7] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};  // h, cc, cs, ss, dT, dQ, dU
+    for (int64_t j = j0 + lane; j < j1; j += 64) {
+      const uint32_t r = rperm[j];
+      const int32_t n = rn[r];
+      pb[j] = (int32_t)(t0[r] / L);
+      pn[j] = n;
+      acc[0] += (double)n;
+      const double* m = mom + kMom * (int64_t)r;
+      if (HAS_QU) {
+        pc[j] = rc[r];
+        ps[j] = rs[r];
+        acc[1] += m[0];
+        acc[2] += m[1];
+        acc[3] += m[2];
+      }
+      if (TOD) {
+        acc[4] += m[3];
+        acc[5] += m[6];
+        acc[6] += m[7];
+      }
+    }
+    wave_sum<7>(acc);
+    if (lane == 0) {
+      const int64_t h = (int64_t)acc[0];
+      double inv[4] = {0.0, 0.0, 0.0, 0.0};
+      uint8_t f = 0;
+      if (HAS_T && h > 0) {
+        f |= 1;
+        inv[0] = 1.0 / (v.w[0] * (double)h);
+      }
+      if (HAS_QU && h > 0) {
+        const double wq = v.w[1], wu = v.w[2];
+        const double a = wq * acc[1] + wu * acc[3];
+        const double b = (wq - wu) * acc[2];
+        const double d = wq * acc[3] + wu * acc[1];
+        // eigenvalues of the symmetric 2x2 block [[a, b], [b, d]]
+        const double half = 0.5 * (a - d);
+        const double rad = sqrt(half * half + b * b);
+        const double lmax = 0.5 * (a + d) + rad;
+        const double det = a * d - b * b;
+        const double lmin = lmax > 0.0 ? det / lmax : 0.0;
+        if (lmax > 0.0 && lmin > 0.0 && lmin >= rcond_cut * lmax) {
+          f |= 2;
+          inv[1] = d / det;
+          inv[2] = -b / det;
+          inv[3] = a / det;
+        }
+      }
+      pstart[c] = j0;
+      if (c == n_obs - 1) pstart[n_obs] = j1;
+      hits[c] = (int32_t)h;
+      double2* mi = reinterpret_cast<double2*>(Minv4 + 4 * c);
+      mi[0] = make_double2(inv[0], inv[1]);
+      mi[1] = make_double2(inv[2], inv[3]);
+      valid[c] = f;
+      double2* mz = reinterpret_cast<double2*>(m4_zero + 4 * c);
+      mz[0] = make_double2(0.0, 0.0);
+      mz[1] = make_double2(0.0, 0.0);
+      if (TOD) {
+        const double sI = (f & 1) ? v.w[0] * acc[4] : 0.0;
+        const double sQ = (f & 2) ? acc[5] : 0.0;
+        const double sU = (f & 2) ? acc[6] : 0.0;
+        double2* sp = reinterpret_cast<double2*>(sd4 + 4 * c);
+        sp[0] = make_double2(sI, sQ);
+        sp[1] = make_double2(sU, 0.0);
+        double2* mp = reinterpret_cast<double2*>(md4 + 4 * c);
+        mp[0] = make_double2(inv[0] * sI, inv[1] * sQ + inv[2] * sU);
+        mp[1] = make_double2(inv[2] * sQ + inv[3] * sU, 0.0);
+      }
+      cnt[0] += f & 1;
+      cnt[1] += (f >> 1) & 1;
+      cnt[2] += (f & 1) ? (unsigned long long)h : 0ull;
+      cnt[3] += (f & 2) ? (unsigned long long)h : 0ull;
+    }
+  }
+  block_sum<4>(cnt, lds);
+  if (threadIdx.x == 0 && counts) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) atomicAdd(&counts[i], cnt[i]);
+  }
+}
+
+// Time-order runs: pixel -> compact id.
+__global__ void __launch_bounds__(kBlock) k_runs_to_compact(int64_t R, const int32_t* __restrict__ cid,
+                                                            int32_t* __restrict__ rpix) {
+  for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < R; r += (int64_t)gridDim.x * blockDim.x)
+    rpix[r] = cid[rpix[r]];
+}
+
+// Per baseline (time-order runs): n_valid, the Jacobi diagonal and with TOD
+//   b_k = w_k sum_{runs, valid_k} (sum of d_k over the run - A-weighted m_d).
+template <bool HAS_T, bool HAS_QU, bool TOD>
+__global__ void __launch_bounds__(kBlock) k_rhs_runs(View v, const uint32_t* __restrict__ bstart,
+                                                     const int32_t* __restrict__ rpix, const int32_t* __restrict__ rn,
+                                                     const double* __restrict__ rc, const double* __restrict__ rs,
+                                                     const double* __restrict__ mom, const double* __restrict__ md4,
+                                                     const uint8_t* __restrict__ valid, int32_t* __restrict__ nvalid,
+                                                     double* __restrict__ J, double* __restrict__ b_out) {
+  __shared__ double lds[5 * 16];
+  const int64_t n_b = v.n_b;
+  const int64_t b = xcd_baseline(n_b);
+  if (b < 0) return;
+  const int64_t r0 = bstart[b], r1 = bstart[b + 1];
+  double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};  // T, q, u residual sums; n_T, n_QU
+  for (int64_t r = r0 + threadIdx.x; r < r1; r += kBlock) {
+    const int c = rpix[r];
+    const uint8_t f = valid[c];
+    const double n = (double)rn[r];
+    const double* m = mom + kMom * r;
+    const double2* mp = reinterpret_cast<const double2*>(md4 + 4 * (int64_t)c);
+    if (HAS_T && (f & 1)) {
+      acc[3] += n;
+      if (TOD) acc[0] += m[3] - n * mp[0].x;
+    }
+    if (HAS_QU && (f & 2)) {
+      acc[4] += n;
+      if (TOD) {
+        const double C = rc[r], S = rs[r];
+        const double mQ = mp[0].y, mU = mp[1].x;
+        acc[1] += m[4] - (C * mQ + S * mU);
+        acc[2] += m[5] - (C * mU - S * mQ);
+      }
+    }
+  }
+  block_sum<5>(acc, lds);
+  if (threadIdx.x == 0) {
+    const int nT = (int)acc[3], nQ = (int)acc[4];
+    nvalid[b] = nT;
+    nvalid[n_b + b] = nQ;
+    if (HAS_T) {
+      J[v.rowT * n_b + b] = nT ? 1.0 / (v.w[0] * nT) : 0.0;
+      if (TOD) b_out[v.rowT * n_b + b] = v.w[0] * acc[0];
+    }
+    if (HAS_QU) {
+      J[v.rowQ * n_b + b] = nQ ? 1.0 / (v.w[1] * nQ) : 0.0;
+      J[v.rowU * n_b + b] = nQ ? 1.0 / (v.w[2] * nQ) : 0.0;
+      if (TOD) {
+        b_out[v.rowQ * n_b + b] = v.w[1] * acc[1];
+        b_out[v.rowU * n_b + b] = v.w[2] * acc[2];
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------- iteration kernels
+
+// m = M^-1 A^T W F p per compact pixel from its pixel-order runs (one
+// wavefront per pixel).  pw4[b] = (w_T p_T, w_q p_q, w_u p_u, 0).
+template <bool HAS_T, bool HAS_QU>
+__global__ void __launch_bounds__(kBlock) k_bin_runs(int64_t n_obs, const int64_t* __restrict__ pstart,
+                                                     const int32_t* __restrict__ pb, const int32_t* __restrict__ pn,
+                                                     const double* __restrict__ pc, const double* __restrict__ ps,
+                                                     const double* __restrict__ pw4,
+                                                     const double* __restrict__ Minv4,
+                                                     const uint8_t* __restrict__ valid, double* __restrict__ m4,
+                                                     const CgCtl* __restrict__ gate) {
+  if (gate && gate->done) return;
+  const int lane = lane_id();
+  const int64_t nw = (int64_t)gridDim.x * kWaves;
+  for (int64_t c = (int64_t)blockIdx.x * kWaves + (threadIdx.x >> 6); c < n_obs; c += nw) {
+    if (valid[c] == 0) continue;  // m stays 0 on invalid pixels
+    const int64_t j0 = pstart[c], j1 = pstart[c + 1];
+    double acc[3] = {0.0, 0.0, 0.0};
+    constexpr int U = 2;
+    for (int64_t jb = j0 + lane; jb < j1; jb += 64 * U) {
+      int32_t bb[U], nn[U];
+      double cc[U], ss[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int64_t j = jb + 64 * u;
+        const bool in = j < j1;
+        bb[u] = in ? pb[j] : -1;
+        nn[u] = (HAS_T && in) ? pn[j] : 0;
+        cc[u] = (HAS_QU && in) ? pc[j] : 0.0;
+        ss[u] = (HAS_QU && in) ? ps[j] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        if (bb[u] < 0) continue;
+        const double2* q0 = reinterpret_cast<const double2*>(pw4 + 4 * (int64_t)bb[u]);
+        const double2 x0 = q0[0];
+        if (HAS_T) acc[0] += (double)nn[u] * x0.x;
+        if (HAS_QU) {
+          const double u0 = q0[1].x;
+          acc[1] += cc[u] * x0.y - ss[u] * u0;
+          acc[2] += ss[u] * x0.y + cc[u] * u0;
+        }
+      }
+    }
+    wave_sum<3>(acc);
+    if (lane == 0) {
+      const double2* ip = reinterpret_cast<const double2*>(Minv4 + 4 * c);
+      const double2 i01 = ip[0], i23 = ip[1];
+      double2* mp = reinterpret_cast<double2*>(m4 + 4 * c);
+      mp[0] = make_double2(i01.x * acc[0], i01.y * acc[1] + i23.x * acc[2]);
+      mp[1] = make_double2(i23.x * acc[1] + i23.y * acc[2], 0.0);
+    }
+  }
+}
+
+// q = K p = F^T W (F p - A m) per baseline from its time-order runs (one
+// workgroup per baseline, XCD-local order); m is zero on invalid blocks.
+// With CG: per-baseline partials of p.q and of the T-projection sums.
+template <bool HAS_T, bool HAS_QU, bool CG>
+__global__ void __launch_bounds__(kBlock) k_unbin_runs(View v, const uint32_t* __restrict__ bstart,
+                                                       const int32_t* __restrict__ rpix,
+                                                       const int32_t* __restrict__ rn, const double* __restrict__ rc,
+                                                       const double* __restrict__ rs, const double* __restrict__ m4,
+                                                       const int32_t* __restrict__ nvalid,
+                                                       const double* __restrict__ p, double* __restrict__ q,
+                                                       CgCtl* __restrict__ ctl, double* __restrict__ partials) {
+  if (CG && ctl->done) return;
+  __shared__ double lds[3 * 16];
+  const int64_t n_b = v.n_b;
+  const int64_t b = xcd_baseline(n_b);
+  if (b < 0) return;
+  const int64_t r0 = bstart[b], r1 = bstart[b + 1];
+  double acc[3] = {0.0, 0.0, 0.0};
+  constexpr int U = 2;
+  for (int64_t rb = r0 + threadIdx.x; rb < r1; rb += U * kBlock) {
+    int32_t cc_[U], nn[U];
+    double C[U], S[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t r = rb + u * kBlock;
+      const bool in = r < r1;
+      cc_[u] = in ? rpix[r] : -1;
+      nn[u] = (HAS_T && in) ? rn[r] : 0;
+      C[u] = (HAS_QU && in) ? rc[r] : 0.0;
+      S[u] = (HAS_QU && in) ? rs[r] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (cc_[u] < 0) continue;
+      const double2* mp = reinterpret_cast<const double2*>(m4 + 4 * (int64_t)cc_[u]);
+      const double2 m01 = mp[0];
+      if (HAS_T) acc[0] += (double)nn[u] * m01.x;
+      if (HAS_QU) {
+        const double mU = mp[1].x;
+        acc[1] += C[u] * m01.y + S[u] * mU;
+        acc[2] += C[u] * mU - S[u] * m01.y;
+      }
+    }
+  }
+  block_sum<3>(acc, lds);
+  if (threadIdx.x == 0) {
+    const int nT = nvalid[b], nQ = nvalid[n_b + b];
+    double pq = 0.0, eq = 0.0, ep = 0.0;
+    if (HAS_T) {
+      const double pbv = p[v.rowT * n_b + b];
+      const double o = v.w[0] * (pbv * (double)nT - acc[0]);
+      q[v.rowT * n_b + b] = o;
+      pq += pbv * o;
+      if (nT > 0) {
+        eq = o;
+        ep = pbv;
+      }
+    }
+    if (HAS_QU) {
+      const double pbq = p[v.rowQ * n_b + b], pbu = p[v.rowU * n_b + b];
+      const double oq = v.w[1] * (pbq * (double)nQ - acc[1]);
+      const double ou = v.w[2] * (pbu * (double)nQ - acc[2]);
+      q[v.rowQ * n_b + b] = oq;
+      q[v.rowU * n_b + b] = ou;
+      pq += pbq * oq + pbu * ou;
+    }
+    if (CG) {
+      partials[b] = pq;
+      partials[n_b + b] = eq;
+      partials[2 * n_b + b] = ep;
+    }
+  }
+}
+
+// Key bits to sort: keys run over 0..n_pix - 1.
+unsigned key_bits(int64_t n) {
+  unsigned bits = 1;
+  while (bits < 32 && ((uint64_t)1 << bits) < (uint64_t)n) ++bits;
+  return bits;
+}
+
+#define DST_CHECK(x)                 \
+  do {                               \
+    hipError_t e_ = (x);             \
+    if (e_ != hipSuccess) return e_; \
+  } while (0)
+
+}  // namespace
+
+// ---------------------------------------------------------------- host side
+
+hipError_t runs_tmp_bytes(int64_t n_t, int64_t n_pix, size_t* bytes) {
+  size_t a = 0, b = 0, c = 0;
+  DST_CHECK(rocprim::exclusive_scan(nullptr, a, static_cast<const uint32_t*>(nullptr),
+                                    static_cast<uint32_t*>(nullptr), 0u, (size_t)n_t, rocprim::plus<uint32_t>()));
+  {
+    rocprim::double_buffer<uint32_t> keys(nullptr, nullptr);
+    rocprim::double_buffer<uint32_t> vals(nullptr, nullptr);
+    DST_CHECK(rocprim::radix_sort_pairs(nullptr, b, keys, vals, (size_t)n_t, 0u, key_bits(n_pix)));
+  }
+  DST_CHECK(rocprim::exclusive_scan(nullptr, c, static_cast<const uint32_t*>(nullptr),
+                                    static_cast<uint32_t*>(nullptr), 0u, (size_t)n_pix + 1,
+                                    rocprim::plus<uint32_t>()));
+  *bytes = std::max(a, std::max(b, c));
+  return hipSuccess;
+}
+
+hipError_t runs_count(const View& v, Runs& W, int* err, hipStream_t st) {
+  const int64_t n_t = v.n_t;
+  const unsigned g = grid_for(n_t, kBlock, 8192);
+  hipLaunchKernelGGL(k_run_heads, dim3(g), dim3(kBlock), 0, st, v.pix, n_t, v.n_pix, v.L, W.head, err);
+  DST_CHECK(hipGetLastError());
+  size_t tmp = W.tmp_bytes;
+  DST_CHECK(rocprim::exclusive_scan(W.tmp, tmp, W.head, W.hidx, 0u, (size_t)n_t, rocprim::plus<uint32_t>(), st));
+  uint32_t last[2] = {0, 0};
+  DST_CHECK(hipMemcpyAsync(&last[0], W.hidx + n_t - 1, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+  DST_CHECK(hipMemcpyAsync(&last[1], W.head + n_t - 1, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+  DST_CHECK(hipStreamSynchronize(st));
+  W.R = (int64_t)last[0] + last[1];
+  return hipSuccess;
+}
+
+template <typename PT, typename TT>
+static void run_build_dispatch(const View& v, const void* tod, const Runs& W, hipStream_t st) {
+  const unsigned g = grid_for(W.R, kBlock, 16384);
+  const TT* x = static_cast<const TT*>(tod);
+#define DST_RB(T_, Q_, D_)                                                                                        \
+  hipLaunchKernelGGL((k_run_build<PT, TT, T_, Q_, D_>), dim3(g), dim3(kBlock), 0, st, v, x, W.t0, W.R, W.tpix, W.tn, \
+                     W.tc, W.ts, W.mom)
+  const bool T = v.rowT >= 0, Q = v.rowQ >= 0;
+  if (tod) {
+    if (T && Q) DST_RB(true, true, true);
+    else if (Q) DST_RB(false, true, true);
+    else DST_RB(true, false, true);
+  } else {
+    if (T && Q) DST_RB(true, true, false);
+    else if (Q) DST_RB(false, true, false);
+    else DST_RB(true, false, false);
+  }
+#undef DST_RB
+}
+
+hipError_t runs_build(const View& v, int psi_f32, const void* tod, int tod_f32, double rcond_cut, Runs& W,
+                      int32_t* hits, double* Minv4, uint8_t* valid, double* m4_zero, double* sd4, double* md4,
+                      unsigned long long* counts, hipStream_t st) {
+  const int64_t n_t = v.n_t, n_pix = v.n_pix, R = W.R;
+  const unsigned g = grid_for(n_t, kBlock, 8192);
+  // 1. run starts and per-baseline run ranges
+  hipLaunchKernelGGL(k_run_starts, dim3(g), dim3(kBlock), 0, st, W.head, W.hidx, n_t, v.L, v.n_b, W.t0, W.bstart);
+  DST_CHECK(hipGetLastError());
+  // 2. run records and setup moments (time order)
+  const bool pf = psi_f32 && v.rowQ >= 0;
+  if (pf && tod_f32)
+    run_build_dispatch<float, float>(v, tod, W, st);
+  else if (pf)
+    run_build_dispatch<float, double>(v, tod, W, st);
+  else if (tod_f32)
+    run_build_dispatch<double, float>(v, tod, W, st);
+  else
+    run_build_dispatch<double, double>(v, tod, W, st);
+  DST_CHECK(hipGetLastError());
+  // 3. runs sorted by pixel (stable: time order inside a pixel)
+  const unsigned gr = grid_for(R, kBlock, 8192);
+  DST_CHECK(hipMemcpyAsync(W.keys[0], W.tpix, R * sizeof(uint32_t), hipMemcpyDeviceToDevice, st));
+  hipLaunchKernelGGL(k_iota, dim3(gr), dim3(kBlock), 0, st, W.vals[0], R);
+  DST_CHECK(hipGetLastError());
+  {
+    rocprim::double_buffer<uint32_t> keys(W.keys[0], W.keys[1]);
+    rocprim::double_buffer<uint32_t> vals(W.vals[0], W.vals[1]);
+    size_t tmp = W.tmp_bytes;
+    DST_CHECK(rocprim::radix_sort_pairs(W.tmp, tmp, keys, vals, (size_t)R, 0u, key_bits(n_pix), st));
+    W.rperm = vals.current();
+    hipLaunchKernelGGL(k_key_segments, dim3(gr), dim3(kBlock), 0, st, keys.current(), R, W.seg);
+    DST_CHECK(hipGetLastError());
+  }
+  // 4. observed pixels -> compact ids (pixel order)
+  const unsigned gp = grid_for(n_pix + 1, kBlock, 4096);
+  hipLaunchKernelGGL(k_observed, dim3(gp), dim3(kBlock), 0, st, W.seg, n_pix, W.obs);
+  DST_CHECK(hipGetLastError());
+  {
+    size_t tmp = W.tmp_bytes;
+    DST_CHECK(rocprim::exclusive_scan(W.tmp, tmp, W.obs, W.oidx, 0u, (size_t)n_pix + 1, rocprim::plus<uint32_t>(),
+                                      st));
+  }
+  uint32_t nobs = 0;
+  DST_CHECK(hipMemcpyAsync(&nobs, W.oidx + n_pix, sizeof nobs, hipMemcpyDeviceToHost, st));
+  DST_CHECK(hipStreamSynchronize(st));
+  W.n_obs = nobs;
+  hipLaunchKernelGGL(k_compact, dim3(gp), dim3(kBlock), 0, st, W.obs, W.oidx, n_pix, W.cid, W.order);
+  DST_CHECK(hipGetLastError());
+  // 5. per-pixel setup from the runs; pixel-order run arrays
+  if (W.n_obs > 0) {
+    const unsigned gw = grid_for(W.n_obs, kWaves, 4096);
+    const bool T = v.rowT >= 0, Q = v.rowQ >= 0;
+#define DST_PX(T_, Q_, D_)                                                                                          \
+  hipLaunchKernelGGL((k_pixels_from_runs<T_, Q_, D_>), dim3(gw), dim3(kBlock), 0, st, v, W.n_obs, W.order, W.seg,  \
+                     W.rperm, W.t0, W.tn, W.tc, W.ts, W.mom, rcond_cut, W.pb, W.pn, W.pc, W.ps, W.pstart, hits, Minv4, \
+                     valid, m4_zero, sd4, md4, counts)
+    if (tod) {
+      if (T && Q) DST_PX(true, true, true);
+      else if (Q) DST_PX(false, true, true);
+      else DST_PX(true, false, true);
+    } else {
+      if (T && Q) DST_PX(true, true, false);
+      else if (Q) DST_PX(false, true, false);
+      else DST_PX(true, false, false);
+    }
+#undef DST_PX
+    DST_CHECK(hipGetLastError());
+  }
+  // 6. time-order runs carry compact ids from here on
+  hipLaunchKernelGGL(k_runs_to_compact, dim3(gr), dim3(kBlock), 0, st, R, W.cid, W.tpix);
+  return hipGetLastError();
+}
+
+hipError_t launch_rhs_runs(const View& vc, const Runs& W, const void* tod, const double* md4, const uint8_t* valid,
+                           int32_t* nvalid, double* J, double* b, hipStream_t st) {
+  const unsigned g = (unsigned)(8 * ((vc.n_b + 7) / 8));
+  const bool T = vc.rowT >= 0, Q = vc.rowQ >= 0;
+#define DST_RH(T_, Q_, D_)                                                                                           \
+  hipLaunchKernelGGL((k_rhs_runs<T_, Q_, D_>), dim3(g), dim3(kBlock), 0, st, vc, W.bstart, W.tpix, W.tn, W.tc, W.ts, \
+                     W.mom, md4, valid, nvalid, J, b)
+  if (tod) {
+    if (T && Q) DST_RH(true, true, true);
+    else if (Q) DST_RH(false, true, true);
+    else DST_RH(true, false, true);
+  } else {
+    if (T && Q) DST_RH(true, true, false);
+    else if (Q) DST_RH(false, true, false);
+    else DST_RH(true, false, false);
+  }
+#undef DST_RH
+  return hipGetLastError();
+}
+
+hipError_t launch_bin_runs(const View& vc, const Runs& W, const double* pw4, const double* Minv4,
+                           const uint8_t* valid, double* m4, const CgCtl* gate, hipStream_t st) {
+  if (W.n_obs == 0) return hipSuccess;
+  const unsigned g = grid_for(W.n_obs, kWaves, 65536);
+  if (vc.rowT >= 0 && vc.rowQ >= 0)
+    hipLaunchKernelGGL((k_bin_runs<true, true>), dim3(g), dim3(kBlock), 0, st, W.n_obs, W.pstart, W.pb, W.pn, W.pc,
+                       W.ps, pw4, Minv4, valid, m4, gate);
+  else if (vc.rowQ >= 0)
+    hipLaunchKernelGGL((k_bin_runs<false, true>), dim3(g), dim3(kBlock), 0, st, W.n_obs, W.pstart, W.pb, W.pn, W.pc,
+                       W.ps, pw4, Minv4, valid, m4, gate);
+  else
+    hipLaunchKernelGGL((k_bin_runs<true, false>), dim3(g), dim3(kBlock), 0, st, W.n_obs, W.pstart, W.pb, W.pn, W.pc,
+                       W.ps, pw4, Minv4, valid, m4, gate);
+  return hipGetLastError();
+}
+
+hipError_t launch_unbin_runs(const View& vc, const Runs& W, const double* m4, const int32_t* nvalid, const double* p,
+                             double* q, CgCtl* ctl, double* partials, hipStream_t st) {
+  const unsigned g = (unsigned)(8 * ((vc.n_b + 7) / 8));
+  const bool T = vc.rowT >= 0, Q = vc.rowQ >= 0;
+#define DST_UR(T_, Q_, CG_)                                                                                           \
+  hipLaunchKernelGGL((k_unbin_runs<T_, Q_, CG_>), dim3(g), dim3(kBlock), 0, st, vc, W.bstart, W.tpix, W.tn, W.tc, W.ts, \
+                     m4, nvalid, p, q, ctl, partials)
+  if (ctl) {
+    if (T && Q) DST_UR(true, true, true);
+    else if (Q) DST_UR(false, true, true);
+    else DST_UR(true, false, true);
+  } else {
+    if (T && Q) DST_UR(true, true, false);
+    else if (Q) DST_UR(false, true, false);
+    else DST_UR(true, false, false);
+  }
+#undef DST_UR
+  return hipGetLastError();
+}
+
+}  // namespace dst

@@ -26,7 +26,7 @@ DST_F32, DST_F64 = 1, 2
 STREAMS = {"T": 1, "QU": 6, "TQU": 7}
 N_STREAMS = {"T": 1, "QU": 2, "TQU": 3}
 DST_BIN_USE_TOD, DST_BIN_MAP = 1, 2
-DST_SOLVE_NO_CANON, DST_SOLVE_PROFILE, DST_SOLVE_NO_GRAPH = 1, 2, 4
+DST_SOLVE_NO_CANON, DST_SOLVE_PROFILE, DST_SOLVE_NO_GRAPH, DST_SOLVE_PER_SAMPLE = 1, 2, 4, 8
 
 EXPORTS = ("dst_version", "dst_create", "dst_destroy", "dst_last_error", "dst_pixel_setup", "dst_bin", "dst_unbin",
            "dst_baseline_reduce", "dst_residual", "dst_apply_operator", "dst_solve")
@@ -50,7 +50,7 @@ class dst_solve_info(ctypes.Structure):
                 ("n_valid_pix", ctypes.c_int64 * 2), ("n_valid_samples", ctypes.c_int64 * 2),
                 ("t_setup_ms", ctypes.c_double), ("t_iter_ms", ctypes.c_double), ("t_total_ms", ctypes.c_double),
                 ("t_bin_ms", ctypes.c_double), ("t_apply_ms", ctypes.c_double), ("t_unbin_ms", ctypes.c_double),
-                ("t_update_ms", ctypes.c_double)]
+                ("t_update_ms", ctypes.c_double), ("n_runs", ctypes.c_int64)]
 
 
 class DstError(RuntimeError):

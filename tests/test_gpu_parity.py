@@ -126,12 +126,14 @@ def test_operator_and_rhs(ctx, name):
     assert rel(r, O.rhs_compact(st, p.tod) - O.K_compact(st, v)) < 1e-12
 
 
+@pytest.mark.parametrize("form", ["runs", "samples"])
 @pytest.mark.parametrize("name", list(VARIANTS))
-def test_solve_tight(ctx, name):
+def test_solve_tight(ctx, name, form):
     from paper_1309_5609_amd import dst
     p = make(name)
     ref = O.solve(*args(p), tol=1e-13, max_iter=3000)
-    out = dst.dst_solve(ctx, dev(p), tol=1e-13, max_iter=3000)
+    flags = dst.DST_SOLVE_PER_SAMPLE if form == "samples" else 0
+    out = dst.dst_solve(ctx, dev(p), tol=1e-13, max_iter=3000, flags=flags)
     assert out["converged"] == 1
     assert np.array_equal(out["hits"].cpu().numpy(), ref.hits)
     assert rel(out["baselines"].cpu().numpy(), ref.baselines) < 1e-9
@@ -167,13 +169,15 @@ def test_pure_offsets(ctx):
     assert rel(out["baselines"].cpu().numpy(), O.canonical_compact(st, p.offsets)) < 1e-9
 
 
-def test_workload0_full_size(ctx):
+@pytest.mark.parametrize("form", ["runs", "samples"])
+def test_workload0_full_size(ctx, form):
     """The 6 h, N_side 64 workload at full size against the oracle."""
     from paper_1309_5609_amd import dst
     from synth import workload
     p = workload(0)
+    flags = dst.DST_SOLVE_PER_SAMPLE if form == "samples" else 0
     ref = O.solve(*args(p), tol=1e-13, max_iter=2000)
-    out = dst.dst_solve(ctx, dev(p), tol=1e-13, max_iter=2000)
+    out = dst.dst_solve(ctx, dev(p), tol=1e-13, max_iter=2000, flags=flags)
     assert np.array_equal(out["hits"].cpu().numpy(), ref.hits)
     assert rel(out["baselines"].cpu().numpy(), ref.baselines) < 1e-9
     obs = ref.hits > 0
@@ -182,7 +186,7 @@ def test_workload0_full_size(ctx):
         assert rel(m[obs, c], ref.destriped_map[obs, c]) < 1e-9
     # at the benchmark tolerance the two solvers take the same number of steps
     ref10 = O.solve(*args(p), tol=1e-10, max_iter=2000)
-    out10 = dst.dst_solve(ctx, dev(p), tol=1e-10, max_iter=2000)
+    out10 = dst.dst_solve(ctx, dev(p), tol=1e-10, max_iter=2000, flags=flags)
     assert abs(out10["iterations"] - ref10.iterations) <= 1
 
 
