@@ -273,14 +273,19 @@ int build_runs_plan(dst_ctx* ctx, const dst_problem* prob, Plan& P, const void* 
   W.tmp_bytes = tmp_bytes;
   DST_TRY(ws(ctx, "r_bstart", v.n_b + 1, &W.bstart));
   DST_TRY(ws(ctx, "r_seg", 2 * (size_t)v.n_pix, &W.seg));
-  DST_TRY(ws(ctx, "r_obs", v.n_pix + 1, &W.obs));
-  DST_TRY(ws(ctx, "r_oidx", v.n_pix + 1, &W.oidx));
+  DST_TRY(ws(ctx, "r_pk0", v.n_pix, &W.pk[0]));
+  DST_TRY(ws(ctx, "r_pk1", v.n_pix, &W.pk[1]));
+  DST_TRY(ws(ctx, "r_pv0", v.n_pix, &W.pv[0]));
+  DST_TRY(ws(ctx, "r_pv1", v.n_pix, &W.pv[1]));
+  DST_TRY(ws(ctx, "r_nobs", 1, &W.n_obs_dev));
   DST_TRY(ws(ctx, "r_cid", v.n_pix, &W.cid));
-  DST_TRY(ws(ctx, "r_order", v.n_pix, &W.order));
+  DST_TRY(ws(ctx, "r_ccount", v.n_pix + 1, &W.ccount));
   DST_TRY(ws(ctx, "r_pstart", v.n_pix + 1, &W.pstart));
   DST_TRY(ws(ctx, "counts", 4, &S.counts));
   DST_TRY(ws(ctx, "err", 4, &S.err));
   HIP_TRY(dst::launch_fill_u32(reinterpret_cast<uint32_t*>(W.seg), 4 * v.n_pix, 0u, st));
+  HIP_TRY(dst::launch_fill_u32(reinterpret_cast<uint32_t*>(W.cid), v.n_pix, 0xffffffffu, st));
+  HIP_TRY(dst::launch_fill_u32(reinterpret_cast<uint32_t*>(W.n_obs_dev), 2, 0u, st));
   HIP_TRY(dst::launch_fill_u32(reinterpret_cast<uint32_t*>(S.counts), 8, 0u, st));
   HIP_TRY(dst::launch_fill_u32(reinterpret_cast<uint32_t*>(S.err), 4, 0u, st));
   HIP_TRY(dst::runs_count(v, W, S.err, st));

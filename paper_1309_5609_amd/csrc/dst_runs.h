@@ -17,12 +17,15 @@ constexpr int kMom = 8;
 // inside one baseline.  Runs are kept twice: in time order (t*: rescan and
 // baseline sums; bstart[b] .. bstart[b+1] are the runs of baseline b) and in
 // pixel order (p*: binning; pstart[c] .. pstart[c+1] are the runs of compact
-// pixel c, in time order).  Compact ids number observed pixels in pixel order.
+// pixel c, in time order).  Compact ids number observed pixels in order of
+// first visit, so pixels that a stretch of the scan crosses sit close
+// together in per-pixel arrays.
 //
 // Buffers belong to the caller's workspace.  Sizes: head, hidx [n_t];
 // bstart [n_b + 1]; t0, tpix, tn, pb, pn [R] and tc, ts, pc, ps [R] (doubles);
 // mom [kMom R]; keys, vals 2 x [R]; seg [2 n_pix] (zero-filled before
-// runs_build); obs, oidx [n_pix + 1]; cid, order [n_pix]; pstart [n_pix + 1].
+// runs_build); pk, pv 2 x [n_pix]; cid [n_pix] (filled with -1 before
+// runs_build); ccount, pstart [n_pix + 1].
 struct Runs {
   uint32_t* head = nullptr;
   uint32_t* hidx = nullptr;
@@ -40,10 +43,12 @@ struct Runs {
   uint32_t* vals[2] = {nullptr, nullptr};
   const uint32_t* rperm = nullptr;
   int64_t* seg = nullptr;
-  uint32_t* obs = nullptr;
-  uint32_t* oidx = nullptr;
+  uint32_t* pk[2] = {nullptr, nullptr};
+  uint32_t* pv[2] = {nullptr, nullptr};
+  unsigned long long* n_obs_dev = nullptr;  // zero-filled before runs_build
   int32_t* cid = nullptr;
-  uint32_t* order = nullptr;
+  int64_t* ccount = nullptr;
+  const uint32_t* order = nullptr;  // compact id -> pixel (set by runs_build)
   int64_t n_obs = 0;
   int32_t* pb = nullptr;
   int32_t* pn = nullptr;

@@ -191,23 +191,39 @@ __global__ void __launch_bounds__(kBlock) k_key_segments(const uint32_t* __restr
   }
 }
 
-__global__ void __launch_bounds__(kBlock) k_observed(const int64_t* __restrict__ seg, int64_t n_pix,
-                                                     uint32_t* __restrict__ obs) {
-  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p <= n_pix; p += (int64_t)gridDim.x * blockDim.x)
-    obs[p] = (p < n_pix && seg[2 * p + 1] > seg[2 * p]) ? 1u : 0u;
+// First visit of each pixel (start of its earliest run; the run sort is
+// stable, so that run heads the pixel's segment); UINT32_MAX if unobserved.
+__global__ void __launch_bounds__(kBlock) k_first_visit(const int64_t* __restrict__ seg,
+                                                        const uint32_t* __restrict__ rperm,
+                                                        const uint32_t* __restrict__ t0, int64_t n_pix,
+                                                        uint32_t* __restrict__ first, uint32_t* __restrict__ pidx,
+                                                        unsigned long long* __restrict__ n_obs) {
+  __shared__ unsigned long long lds[16];
+  unsigned long long cnt[1] = {0};
+  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n_pix; p += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t j0 = seg[2 * p], j1 = seg[2 * p + 1];
+    const bool hit = j1 > j0;
+    first[p] = hit ? t0[rperm[j0]] : 0xffffffffu;
+    pidx[p] = (uint32_t)p;
+    cnt[0] += hit;
+  }
+  block_sum<1>(cnt, lds);
+  if (threadIdx.x == 0) atomicAdd(n_obs, cnt[0]);
 }
 
-// Compact ids (pixel order) and the compact -> pixel map.
-__global__ void __launch_bounds__(kBlock) k_compact(const uint32_t* __restrict__ obs, const uint32_t* __restrict__ oidx,
-                                                    int64_t n_pix, int32_t* __restrict__ cid,
-                                                    uint32_t* __restrict__ order) {
-  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n_pix; p += (int64_t)gridDim.x * blockDim.x) {
-    if (obs[p]) {
-      cid[p] = (int32_t)oidx[p];
-      order[oidx[p]] = (uint32_t)p;
-    } else {
-      cid[p] = -1;
+// Compact ids in order of first visit (pixels a stretch of the scan touches
+// get neighbouring ids), and run counts per compact pixel.
+__global__ void __launch_bounds__(kBlock) k_compact(const uint32_t* __restrict__ order, int64_t n_obs,
+                                                    const int64_t* __restrict__ seg, int32_t* __restrict__ cid,
+                                                    int64_t* __restrict__ ccount) {
+  for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c <= n_obs; c += (int64_t)gridDim.x * blockDim.x) {
+    if (c == n_obs) {
+      ccount[c] = 0;
+      continue;
     }
+    const uint32_t p = order[c];
+    cid[p] = (int32_t)c;
+    ccount[c] = seg[2 * (int64_t)p + 1] - seg[2 * (int64_t)p];
   }
 }
 
@@ -220,7 +236,7 @@ __global__ void __launch_bounds__(kBlock) k_pixels_from_runs(
     const uint32_t* __restrict__ rperm, const uint32_t* __restrict__ t0, const int32_t* __restrict__ rn,
     const double* __restrict__ rc, const double* __restrict__ rs, const double* __restrict__ mom, double rcond_cut,
     int32_t* __restrict__ pb, int32_t* __restrict__ pn, double* __restrict__ pc, double* __restrict__ ps,
-    int64_t* __restrict__ pstart, int32_t* __restrict__ hits, double* __restrict__ Minv4,
+    const int64_t* __restrict__ pstart, int32_t* __restrict__ hits, double* __restrict__ Minv4,
     uint8_t* __restrict__ valid, double* __restrict__ m4_zero, double* __restrict__ sd4, double* __restrict__ md4,
     unsigned long long* __restrict__ counts) {
   __shared__ unsigned long long lds[4 * 16];
@@ -231,17 +247,19 @@ __global__ void __launch_bounds__(kBlock) k_pixels_from_runs(
   for (int64_t c = (int64_t)blockIdx.x * kWaves + (threadIdx.x >> 6); c < n_obs; c += nw) {
     const uint32_t p = order[c];
     const int64_t j0 = seg[2 * (int64_t)p], j1 = seg[2 * (int64_t)p + 1];
+    const int64_t d0 = pstart[c];
     double acc[7] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};  // h, cc, cs, ss, dT, dQ, dU
     for (int64_t j = j0 + lane; j < j1; j += 64) {
       const uint32_t r = rperm[j];
       const int32_t n = rn[r];
-      pb[j] = (int32_t)(t0[r] / L);
-      pn[j] = n;
+      const int64_t d = d0 + (j - j0);
+      pb[d] = (int32_t)(t0[r] / L);
+      pn[d] = n;
       acc[0] += (double)n;
       const double* m = mom + kMom * (int64_t)r;
       if (HAS_QU) {
-        pc[j] = rc[r];
-        ps[j] = rs[r];
+        pc[d] = rc[r];
+        ps[d] = rs[r];
         acc[1] += m[0];
         acc[2] += m[1];
         acc[3] += m[2];
@@ -279,8 +297,6 @@ __global__ void __launch_bounds__(kBlock) k_pixels_from_runs(
           inv[3] = a / det;
         }
       }
-      pstart[c] = j0;
-      if (c == n_obs - 1) pstart[n_obs] = j1;
       hits[c] = (int32_t)h;
       double2* mi = reinterpret_cast<double2*>(Minv4 + 4 * c);
       mi[0] = make_double2(inv[0], inv[1]);
@@ -431,9 +447,10 @@ __global__ void __launch_bounds__(kBlock) k_bin_runs(int64_t n_obs, const int64_
   }
 }
 
-// q = K p = F^T W (F p - A m) per baseline from its time-order runs (one
-// workgroup per baseline, XCD-local order); m is zero on invalid blocks.
-// With CG: per-baseline partials of p.q and of the T-projection sums.
+// q = K p = F^T W (F p - A m) per baseline from its time-order runs: one
+// wavefront per baseline, four baselines per workgroup, consecutive groups
+// on one XCD; m is zero on invalid blocks.  With CG: per-baseline partials of
+// p.q and of the T-projection sums.
 template <bool HAS_T, bool HAS_QU, bool CG>
 __global__ void __launch_bounds__(kBlock) k_unbin_runs(View v, const uint32_t* __restrict__ bstart,
                                                        const int32_t* __restrict__ rpix,
@@ -443,19 +460,23 @@ __global__ void __launch_bounds__(kBlock) k_unbin_runs(View v, const uint32_t* _
                                                        const double* __restrict__ p, double* __restrict__ q,
                                                        CgCtl* __restrict__ ctl, double* __restrict__ partials) {
   if (CG && ctl->done) return;
-  __shared__ double lds[3 * 16];
+  const int lane = lane_id();
   const int64_t n_b = v.n_b;
-  const int64_t b = xcd_baseline(n_b);
-  if (b < 0) return;
+  const int64_t n_g = (n_b + kWaves - 1) / kWaves;
+  const int64_t per = (n_g + 7) / 8;
+  const int64_t i = blockIdx.x;
+  const int64_t g = (i & 7) * per + (i >> 3);
+  const int64_t b = g * kWaves + (threadIdx.x >> 6);
+  if (g >= n_g || b >= n_b) return;
   const int64_t r0 = bstart[b], r1 = bstart[b + 1];
   double acc[3] = {0.0, 0.0, 0.0};
-  constexpr int U = 2;
-  for (int64_t rb = r0 + threadIdx.x; rb < r1; rb += U * kBlock) {
+  constexpr int U = 4;
+  for (int64_t rb = r0 + lane; rb < r1; rb += 64 * U) {
     int32_t cc_[U], nn[U];
     double C[U], S[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const int64_t r = rb + u * kBlock;
+      const int64_t r = rb + 64 * u;
       const bool in = r < r1;
       cc_[u] = in ? rpix[r] : -1;
       nn[u] = (HAS_T && in) ? rn[r] : 0;
@@ -475,8 +496,8 @@ __global__ void __launch_bounds__(kBlock) k_unbin_runs(View v, const uint32_t* _
       }
     }
   }
-  block_sum<3>(acc, lds);
-  if (threadIdx.x == 0) {
+  wave_sum<3>(acc);
+  if (lane == 0) {
     const int nT = nvalid[b], nQ = nvalid[n_b + b];
     double pq = 0.0, eq = 0.0, ep = 0.0;
     if (HAS_T) {
@@ -531,10 +552,15 @@ hipError_t runs_tmp_bytes(int64_t n_t, int64_t n_pix, size_t* bytes) {
     rocprim::double_buffer<uint32_t> vals(nullptr, nullptr);
     DST_CHECK(rocprim::radix_sort_pairs(nullptr, b, keys, vals, (size_t)n_t, 0u, key_bits(n_pix)));
   }
-  DST_CHECK(rocprim::exclusive_scan(nullptr, c, static_cast<const uint32_t*>(nullptr),
-                                    static_cast<uint32_t*>(nullptr), 0u, (size_t)n_pix + 1,
-                                    rocprim::plus<uint32_t>()));
-  *bytes = std::max(a, std::max(b, c));
+  size_t d = 0;
+  {
+    rocprim::double_buffer<uint32_t> keys(nullptr, nullptr);
+    rocprim::double_buffer<uint32_t> vals(nullptr, nullptr);
+    DST_CHECK(rocprim::radix_sort_pairs(nullptr, d, keys, vals, (size_t)n_pix, 0u, 32u));
+  }
+  DST_CHECK(rocprim::exclusive_scan(nullptr, c, static_cast<const int64_t*>(nullptr), static_cast<int64_t*>(nullptr),
+                                    (int64_t)0, (size_t)n_pix + 1, rocprim::plus<int64_t>()));
+  *bytes = std::max(std::max(a, b), std::max(c, d));
   return hipSuccess;
 }
 
@@ -606,21 +632,30 @@ hipError_t runs_build(const View& v, int psi_f32, const void* tod, int tod_f32, 
     hipLaunchKernelGGL(k_key_segments, dim3(gr), dim3(kBlock), 0, st, keys.current(), R, W.seg);
     DST_CHECK(hipGetLastError());
   }
-  // 4. observed pixels -> compact ids (pixel order)
-  const unsigned gp = grid_for(n_pix + 1, kBlock, 4096);
-  hipLaunchKernelGGL(k_observed, dim3(gp), dim3(kBlock), 0, st, W.seg, n_pix, W.obs);
+  // 4. observed pixels -> compact ids in order of first visit; run offsets
+  const unsigned gp = grid_for(n_pix, kBlock, 4096);
+  hipLaunchKernelGGL(k_first_visit, dim3(gp), dim3(kBlock), 0, st, W.seg, W.rperm, W.t0, n_pix, W.pk[0], W.pv[0],
+                     W.n_obs_dev);
+  DST_CHECK(hipGetLastError());
+  {
+    rocprim::double_buffer<uint32_t> keys(W.pk[0], W.pk[1]);
+    rocprim::double_buffer<uint32_t> vals(W.pv[0], W.pv[1]);
+    size_t tmp = W.tmp_bytes;
+    DST_CHECK(rocprim::radix_sort_pairs(W.tmp, tmp, keys, vals, (size_t)n_pix, 0u, 32u, st));
+    W.order = vals.current();
+  }
+  unsigned long long nobs = 0;
+  DST_CHECK(hipMemcpyAsync(&nobs, W.n_obs_dev, sizeof nobs, hipMemcpyDeviceToHost, st));
+  DST_CHECK(hipStreamSynchronize(st));
+  W.n_obs = (int64_t)nobs;
+  hipLaunchKernelGGL(k_compact, dim3(grid_for(W.n_obs + 1, kBlock, 4096)), dim3(kBlock), 0, st, W.order, W.n_obs,
+                     W.seg, W.cid, W.ccount);
   DST_CHECK(hipGetLastError());
   {
     size_t tmp = W.tmp_bytes;
-    DST_CHECK(rocprim::exclusive_scan(W.tmp, tmp, W.obs, W.oidx, 0u, (size_t)n_pix + 1, rocprim::plus<uint32_t>(),
-                                      st));
+    DST_CHECK(rocprim::exclusive_scan(W.tmp, tmp, W.ccount, W.pstart, (int64_t)0, (size_t)W.n_obs + 1,
+                                      rocprim::plus<int64_t>(), st));
   }
-  uint32_t nobs = 0;
-  DST_CHECK(hipMemcpyAsync(&nobs, W.oidx + n_pix, sizeof nobs, hipMemcpyDeviceToHost, st));
-  DST_CHECK(hipStreamSynchronize(st));
-  W.n_obs = nobs;
-  hipLaunchKernelGGL(k_compact, dim3(gp), dim3(kBlock), 0, st, W.obs, W.oidx, n_pix, W.cid, W.order);
-  DST_CHECK(hipGetLastError());
   // 5. per-pixel setup from the runs; pixel-order run arrays
   if (W.n_obs > 0) {
     const unsigned gw = grid_for(W.n_obs, kWaves, 4096);
@@ -669,7 +704,7 @@ hipError_t launch_rhs_runs(const View& vc, const Runs& W, const void* tod, const
 hipError_t launch_bin_runs(const View& vc, const Runs& W, const double* pw4, const double* Minv4,
                            const uint8_t* valid, double* m4, const CgCtl* gate, hipStream_t st) {
   if (W.n_obs == 0) return hipSuccess;
-  const unsigned g = grid_for(W.n_obs, kWaves, 65536);
+  const unsigned g = grid_for(W.n_obs, kWaves, 16384);
   if (vc.rowT >= 0 && vc.rowQ >= 0)
     hipLaunchKernelGGL((k_bin_runs<true, true>), dim3(g), dim3(kBlock), 0, st, W.n_obs, W.pstart, W.pb, W.pn, W.pc,
                        W.ps, pw4, Minv4, valid, m4, gate);
@@ -684,7 +719,8 @@ hipError_t launch_bin_runs(const View& vc, const Runs& W, const double* pw4, con
 
 hipError_t launch_unbin_runs(const View& vc, const Runs& W, const double* m4, const int32_t* nvalid, const double* p,
                              double* q, CgCtl* ctl, double* partials, hipStream_t st) {
-  const unsigned g = (unsigned)(8 * ((vc.n_b + 7) / 8));
+  const int64_t n_g = (vc.n_b + kWaves - 1) / kWaves;
+  const unsigned g = (unsigned)(8 * ((n_g + 7) / 8));
   const bool T = vc.rowT >= 0, Q = vc.rowQ >= 0;
 #define DST_UR(T_, Q_, CG_)                                                                                           \
   hipLaunchKernelGGL((k_unbin_runs<T_, Q_, CG_>), dim3(g), dim3(kBlock), 0, st, vc, W.bstart, W.tpix, W.tn, W.tc, W.ts, \
