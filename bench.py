@@ -166,6 +166,28 @@ def main() -> int:
     iter_ms = float(np.mean([r["t_iter_ms"] for r in runs]))
     b_iter = algo["bin_samples"] + algo["unbin_samples"]
 
+    # mixed precision on the same data: FP32 timelines and angles (FP64 accumulation, inverse and CG)
+    mixed = None
+    if args.workload == 1:
+        dp32 = dst.Problem(dp.pix, dp.psi.float(), dp.tod.float(), dp.n_pix, dp.baseline_length, dp.streams,
+                           dp.weights)
+        dst.dst_solve(ctx, dp32, tol=args.tol, max_iter=2000)
+        torch.cuda.synchronize()
+        tm = time.perf_counter()
+        mruns = [dst.dst_solve(ctx, dp32, tol=args.tol, max_iter=2000, flags=dst.DST_SOLVE_PROFILE)
+                 for _ in range(args.steps)]
+        torch.cuda.synchronize()
+        mwall = time.perf_counter() - tm
+        mit = sum(r["iterations"] for r in mruns)
+        mixed = {"value": p.n_samples * mit / mwall, "ms_per_step": mwall * 1e3 / args.steps,
+                 "iter_ms": float(np.mean([r["t_iter_ms"] for r in mruns])),
+                 "setup_ms": float(np.mean([r["t_setup_ms"] for r in mruns])),
+                 "iterations_per_solve": mruns[-1]["iterations"],
+                 "kernel_ms": {k: float(np.mean([r[f"t_{k}_ms"] for r in mruns])) for k in ("bin", "unbin")},
+                 "dtype": "f32 timelines and angles, f32 run records, f64 accumulation / inverse / CG"}
+        del dp32
+        log(f"mixed form: {mixed['value']:.3e} samples*iters/s")
+
     # the per-sample form of the same solve, for comparison with the per-sample byte model
     log("per-sample form: one profiled solve")
     ps = dst.dst_solve(ctx, dp, tol=args.tol, max_iter=2000,
@@ -199,6 +221,7 @@ def main() -> int:
         "per_sample_form": {"iter_ms": ps["t_iter_ms"], "kernel_ms": ps_ms, "iterations": ps["iterations"],
                             "dominant": ps_dom, "achieved_GBs": ps_ach, "frac": ps_ach / HBM_PEAK_GBS},
         "n_runs": n_runs,
+        "mixed_form": mixed,
         "iterations_per_solve": r0["iterations"],
         "iter_ms": iter_ms,
         "iteration_throughput": p.n_samples / (iter_ms * 1e-3),

@@ -293,8 +293,11 @@ int build_runs_plan(dst_ctx* ctx, const dst_problem* prob, Plan& P, const void* 
   DST_TRY(ws(ctx, "r_t0", R, &W.t0));
   DST_TRY(ws(ctx, "r_tpix", R, &W.tpix));
   DST_TRY(ws(ctx, "r_tn", R, &W.tn));
-  DST_TRY(ws(ctx, "r_tc", R, &W.tc));
-  DST_TRY(ws(ctx, "r_ts", R, &W.ts));
+  // FP32 angles (mixed precision): run sums of cos 2psi, sin 2psi kept in FP32
+  W.f32 = S.psi_f32 && v.rowQ >= 0;
+  const size_t rsz = W.f32 ? sizeof(float) : sizeof(double);
+  DST_TRY(ws_get(ctx, "r_tc", R * rsz, &W.tc));
+  DST_TRY(ws_get(ctx, "r_ts", R * rsz, &W.ts));
   DST_TRY(ws(ctx, "r_mom", (size_t)dst::kMom * R, &W.mom));
   DST_TRY(ws(ctx, "r_keys0", R, &W.keys[0]));
   DST_TRY(ws(ctx, "r_keys1", R, &W.keys[1]));
@@ -302,8 +305,8 @@ int build_runs_plan(dst_ctx* ctx, const dst_problem* prob, Plan& P, const void* 
   DST_TRY(ws(ctx, "r_vals1", R, &W.vals[1]));
   DST_TRY(ws(ctx, "r_pb", R, &W.pb));
   DST_TRY(ws(ctx, "r_pn", R, &W.pn));
-  DST_TRY(ws(ctx, "r_pc", R, &W.pc));
-  DST_TRY(ws(ctx, "r_ps", R, &W.ps));
+  DST_TRY(ws_get(ctx, "r_pc", R * rsz, &W.pc));
+  DST_TRY(ws_get(ctx, "r_ps", R * rsz, &W.ps));
   // per-pixel arrays sized for every pixel (the observed count is known later)
   DST_TRY(ws(ctx, "hits", v.n_pix, &S.hits));
   DST_TRY(ws(ctx, "Minv4", 4 * v.n_pix, &S.Minv4));

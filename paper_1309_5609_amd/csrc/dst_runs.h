@@ -22,7 +22,8 @@ constexpr int kMom = 8;
 // together in per-pixel arrays.
 //
 // Buffers belong to the caller's workspace.  Sizes: head, hidx [n_t];
-// bstart [n_b + 1]; t0, tpix, tn, pb, pn [R] and tc, ts, pc, ps [R] (doubles);
+// bstart [n_b + 1]; t0, tpix, tn, pb, pn [R] and tc, ts, pc, ps [R] (FP32 when
+// f32, else FP64);
 // mom [kMom R]; keys, vals 2 x [R]; seg [2 n_pix] (zero-filled before
 // runs_build); pk, pv 2 x [n_pix]; cid [n_pix] (filled with -1 before
 // runs_build); ccount, pstart [n_pix + 1].
@@ -34,10 +35,11 @@ struct Runs {
   int64_t R = 0;
   uint32_t* t0 = nullptr;
   uint32_t* bstart = nullptr;
+  bool f32 = false;  // run sums of cos 2psi, sin 2psi stored in FP32 (else FP64)
   int32_t* tpix = nullptr;
   int32_t* tn = nullptr;
-  double* tc = nullptr;
-  double* ts = nullptr;
+  void* tc = nullptr;
+  void* ts = nullptr;
   double* mom = nullptr;
   uint32_t* keys[2] = {nullptr, nullptr};
   uint32_t* vals[2] = {nullptr, nullptr};
@@ -52,8 +54,8 @@ struct Runs {
   int64_t n_obs = 0;
   int32_t* pb = nullptr;
   int32_t* pn = nullptr;
-  double* pc = nullptr;
-  double* ps = nullptr;
+  void* pc = nullptr;
+  void* ps = nullptr;
   int64_t* pstart = nullptr;
 };
 

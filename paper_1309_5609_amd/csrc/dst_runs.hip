@@ -20,6 +20,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdint>
+#include <type_traits>
 
 #include "dst_internal.h"
 #include "dst_runs.h"
@@ -125,11 +126,11 @@ __global__ void __launch_bounds__(kBlock) k_run_starts(const uint32_t* __restric
 // One thread per run: length, sums of cos 2psi and sin 2psi, and the setup
 // moments (sums of c^2, cs, s^2 for the weight blocks; timeline sums for the
 // right-hand side).  Samples are summed in time order.
-template <typename PT, typename TT, bool HAS_T, bool HAS_QU, bool TOD>
+template <typename PT, typename TT, typename RT, bool HAS_T, bool HAS_QU, bool TOD>
 __global__ void __launch_bounds__(kBlock) k_run_build(View v, const TT* __restrict__ tod,
                                                       const uint32_t* __restrict__ t0, int64_t R,
                                                       int32_t* __restrict__ rpix, int32_t* __restrict__ rn,
-                                                      double* __restrict__ rc, double* __restrict__ rs,
+                                                      RT* __restrict__ rc, RT* __restrict__ rs,
                                                       double* __restrict__ mom) {
   const PT* psi = static_cast<const PT*>(v.psi);
   const int64_t n_t = v.n_t, L = v.L;
@@ -166,8 +167,8 @@ __global__ void __launch_bounds__(kBlock) k_run_build(View v, const TT* __restri
     rpix[r] = p;
     rn[r] = (int32_t)(t - ts);
     if (HAS_QU) {
-      rc[r] = C;
-      rs[r] = S;
+      rc[r] = (RT)C;
+      rs[r] = (RT)S;
     }
     double* m = mom + kMom * r;
     m[0] = cc;
@@ -230,12 +231,12 @@ __global__ void __launch_bounds__(kBlock) k_compact(const uint32_t* __restrict__
 // One wavefront per compact pixel: its runs (pixel order, time order within
 // the pixel) -> the pixel-order run arrays; hits, weight blocks, inverse,
 // validity; with TOD the sum map and binned map.
-template <bool HAS_T, bool HAS_QU, bool TOD>
+template <typename RT, bool HAS_T, bool HAS_QU, bool TOD>
 __global__ void __launch_bounds__(kBlock) k_pixels_from_runs(
     View v, int64_t n_obs, const uint32_t* __restrict__ order, const int64_t* __restrict__ seg,
     const uint32_t* __restrict__ rperm, const uint32_t* __restrict__ t0, const int32_t* __restrict__ rn,
-    const double* __restrict__ rc, const double* __restrict__ rs, const double* __restrict__ mom, double rcond_cut,
-    int32_t* __restrict__ pb, int32_t* __restrict__ pn, double* __restrict__ pc, double* __restrict__ ps,
+    const RT* __restrict__ rc, const RT* __restrict__ rs, const double* __restrict__ mom, double rcond_cut,
+    int32_t* __restrict__ pb, int32_t* __restrict__ pn, RT* __restrict__ pc, RT* __restrict__ ps,
     const int64_t* __restrict__ pstart, int32_t* __restrict__ hits, double* __restrict__ Minv4,
     uint8_t* __restrict__ valid, double* __restrict__ m4_zero, double* __restrict__ sd4, double* __restrict__ md4,
     unsigned long long* __restrict__ counts) {
@@ -338,10 +339,10 @@ __global__ void __launch_bounds__(kBlock) k_runs_to_compact(int64_t R, const int
 
 // Per baseline (time-order runs): n_valid, the Jacobi diagonal and with TOD
 //   b_k = w_k sum_{runs, valid_k} (sum of d_k over the run - A-weighted m_d).
-template <bool HAS_T, bool HAS_QU, bool TOD>
+template <typename RT, bool HAS_T, bool HAS_QU, bool TOD>
 __global__ void __launch_bounds__(kBlock) k_rhs_runs(View v, const uint32_t* __restrict__ bstart,
                                                      const int32_t* __restrict__ rpix, const int32_t* __restrict__ rn,
-                                                     const double* __restrict__ rc, const double* __restrict__ rs,
+                                                     const RT* __restrict__ rc, const RT* __restrict__ rs,
                                                      const double* __restrict__ mom, const double* __restrict__ md4,
                                                      const uint8_t* __restrict__ valid, int32_t* __restrict__ nvalid,
                                                      double* __restrict__ J, double* __restrict__ b_out) {
@@ -364,7 +365,7 @@ __global__ void __launch_bounds__(kBlock) k_rhs_runs(View v, const uint32_t* __r
     if (HAS_QU && (f & 2)) {
       acc[4] += n;
       if (TOD) {
-        const double C = rc[r], S = rs[r];
+        const double C = (double)rc[r], S = (double)rs[r];
         const double mQ = mp[0].y, mU = mp[1].x;
         acc[1] += m[4] - (C * mQ + S * mU);
         acc[2] += m[5] - (C * mU - S * mQ);
@@ -395,10 +396,10 @@ __global__ void __launch_bounds__(kBlock) k_rhs_runs(View v, const uint32_t* __r
 
 // m = M^-1 A^T W F p per compact pixel from its pixel-order runs (one
 // wavefront per pixel).  pw4[b] = (w_T p_T, w_q p_q, w_u p_u, 0).
-template <bool HAS_T, bool HAS_QU>
+template <typename RT, bool HAS_T, bool HAS_QU>
 __global__ void __launch_bounds__(kBlock) k_bin_runs(int64_t n_obs, const int64_t* __restrict__ pstart,
                                                      const int32_t* __restrict__ pb, const int32_t* __restrict__ pn,
-                                                     const double* __restrict__ pc, const double* __restrict__ ps,
+                                                     const RT* __restrict__ pc, const RT* __restrict__ ps,
                                                      const double* __restrict__ pw4,
                                                      const double* __restrict__ Minv4,
                                                      const uint8_t* __restrict__ valid, double* __restrict__ m4,
@@ -420,8 +421,8 @@ __global__ void __launch_bounds__(kBlock) k_bin_runs(int64_t n_obs, const int64_
         const bool in = j < j1;
         bb[u] = in ? pb[j] : -1;
         nn[u] = (HAS_T && in) ? pn[j] : 0;
-        cc[u] = (HAS_QU && in) ? pc[j] : 0.0;
-        ss[u] = (HAS_QU && in) ? ps[j] : 0.0;
+        cc[u] = (HAS_QU && in) ? (double)pc[j] : 0.0;
+        ss[u] = (HAS_QU && in) ? (double)ps[j] : 0.0;
       }
 #pragma unroll
       for (int u = 0; u < U; ++u) {
@@ -451,11 +452,11 @@ __global__ void __launch_bounds__(kBlock) k_bin_runs(int64_t n_obs, const int64_
 // wavefront per baseline, four baselines per workgroup, consecutive groups
 // on one XCD; m is zero on invalid blocks.  With CG: per-baseline partials of
 // p.q and of the T-projection sums.
-template <bool HAS_T, bool HAS_QU, bool CG>
+template <typename RT, bool HAS_T, bool HAS_QU, bool CG>
 __global__ void __launch_bounds__(kBlock) k_unbin_runs(View v, const uint32_t* __restrict__ bstart,
                                                        const int32_t* __restrict__ rpix,
-                                                       const int32_t* __restrict__ rn, const double* __restrict__ rc,
-                                                       const double* __restrict__ rs, const double* __restrict__ m4,
+                                                       const int32_t* __restrict__ rn, const RT* __restrict__ rc,
+                                                       const RT* __restrict__ rs, const double* __restrict__ m4,
                                                        const int32_t* __restrict__ nvalid,
                                                        const double* __restrict__ p, double* __restrict__ q,
                                                        CgCtl* __restrict__ ctl, double* __restrict__ partials) {
@@ -480,8 +481,8 @@ __global__ void __launch_bounds__(kBlock) k_unbin_runs(View v, const uint32_t* _
       const bool in = r < r1;
       cc_[u] = in ? rpix[r] : -1;
       nn[u] = (HAS_T && in) ? rn[r] : 0;
-      C[u] = (HAS_QU && in) ? rc[r] : 0.0;
-      S[u] = (HAS_QU && in) ? rs[r] : 0.0;
+      C[u] = (HAS_QU && in) ? (double)rc[r] : 0.0;
+      S[u] = (HAS_QU && in) ? (double)rs[r] : 0.0;
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
@@ -579,24 +580,34 @@ hipError_t runs_count(const View& v, Runs& W, int* err, hipStream_t st) {
   return hipSuccess;
 }
 
-template <typename PT, typename TT>
-static void run_build_dispatch(const View& v, const void* tod, const Runs& W, hipStream_t st) {
-  const unsigned g = grid_for(W.R, kBlock, 16384);
-  const TT* x = static_cast<const TT*>(tod);
-#define DST_RB(T_, Q_, D_)                                                                                        \
-  hipLaunchKernelGGL((k_run_build<PT, TT, T_, Q_, D_>), dim3(g), dim3(kBlock), 0, st, v, x, W.t0, W.R, W.tpix, W.tn, \
-                     W.tc, W.ts, W.mom)
-  const bool T = v.rowT >= 0, Q = v.rowQ >= 0;
-  if (tod) {
-    if (T && Q) DST_RB(true, true, true);
-    else if (Q) DST_RB(false, true, true);
-    else DST_RB(true, false, true);
-  } else {
-    if (T && Q) DST_RB(true, true, false);
-    else if (Q) DST_RB(false, true, false);
-    else DST_RB(true, false, false);
-  }
-#undef DST_RB
+// Compile-time dispatch helpers: f(tag) for a float type chosen at run time,
+// and f(T, Q) for the problem's stream set (T and/or the q/u pair).
+template <typename T>
+struct type_tag {
+  using type = T;
+};
+template <typename F>
+static void by_float(bool f32, F&& f) {
+  if (f32)
+    f(type_tag<float>{});
+  else
+    f(type_tag<double>{});
+}
+template <typename F>
+static void by_streams(const View& v, F&& f) {
+  if (v.rowT >= 0 && v.rowQ >= 0)
+    f(std::true_type{}, std::true_type{});
+  else if (v.rowQ >= 0)
+    f(std::false_type{}, std::true_type{});
+  else
+    f(std::true_type{}, std::false_type{});
+}
+template <typename F>
+static void by_bool(bool b, F&& f) {
+  if (b)
+    f(std::true_type{});
+  else
+    f(std::false_type{});
 }
 
 hipError_t runs_build(const View& v, int psi_f32, const void* tod, int tod_f32, double rcond_cut, Runs& W,
@@ -609,14 +620,23 @@ hipError_t runs_build(const View& v, int psi_f32, const void* tod, int tod_f32, 
   DST_CHECK(hipGetLastError());
   // 2. run records and setup moments (time order)
   const bool pf = psi_f32 && v.rowQ >= 0;
-  if (pf && tod_f32)
-    run_build_dispatch<float, float>(v, tod, W, st);
-  else if (pf)
-    run_build_dispatch<float, double>(v, tod, W, st);
-  else if (tod_f32)
-    run_build_dispatch<double, float>(v, tod, W, st);
-  else
-    run_build_dispatch<double, double>(v, tod, W, st);
+  const unsigned grb = grid_for(R, kBlock, 16384);
+  by_float(pf, [&](auto pt) {
+    using PT = typename decltype(pt)::type;
+    by_float(tod_f32, [&](auto tt) {
+      using TT = typename decltype(tt)::type;
+      by_float(W.f32, [&](auto rt) {
+        using RT = typename decltype(rt)::type;
+        by_streams(v, [&](auto T, auto Q) {
+          by_bool(tod != nullptr, [&](auto D) {
+            hipLaunchKernelGGL((k_run_build<PT, TT, RT, decltype(T)::value, decltype(Q)::value, decltype(D)::value>),
+                               dim3(grb), dim3(kBlock), 0, st, v, static_cast<const TT*>(tod), W.t0, W.R, W.tpix, W.tn,
+                               static_cast<RT*>(W.tc), static_cast<RT*>(W.ts), W.mom);
+          });
+        });
+      });
+    });
+  });
   DST_CHECK(hipGetLastError());
   // 3. runs sorted by pixel (stable: time order inside a pixel)
   const unsigned gr = grid_for(R, kBlock, 8192);
@@ -659,21 +679,18 @@ hipError_t runs_build(const View& v, int psi_f32, const void* tod, int tod_f32, 
   // 5. per-pixel setup from the runs; pixel-order run arrays
   if (W.n_obs > 0) {
     const unsigned gw = grid_for(W.n_obs, kWaves, 4096);
-    const bool T = v.rowT >= 0, Q = v.rowQ >= 0;
-#define DST_PX(T_, Q_, D_)                                                                                          \
-  hipLaunchKernelGGL((k_pixels_from_runs<T_, Q_, D_>), dim3(gw), dim3(kBlock), 0, st, v, W.n_obs, W.order, W.seg,  \
-                     W.rperm, W.t0, W.tn, W.tc, W.ts, W.mom, rcond_cut, W.pb, W.pn, W.pc, W.ps, W.pstart, hits, Minv4, \
-                     valid, m4_zero, sd4, md4, counts)
-    if (tod) {
-      if (T && Q) DST_PX(true, true, true);
-      else if (Q) DST_PX(false, true, true);
-      else DST_PX(true, false, true);
-    } else {
-      if (T && Q) DST_PX(true, true, false);
-      else if (Q) DST_PX(false, true, false);
-      else DST_PX(true, false, false);
-    }
-#undef DST_PX
+    by_float(W.f32, [&](auto rt) {
+      using RT = typename decltype(rt)::type;
+      by_streams(v, [&](auto T, auto Q) {
+        by_bool(tod != nullptr, [&](auto D) {
+          hipLaunchKernelGGL((k_pixels_from_runs<RT, decltype(T)::value, decltype(Q)::value, decltype(D)::value>),
+                             dim3(gw), dim3(kBlock), 0, st, v, W.n_obs, W.order, W.seg, W.rperm, W.t0, W.tn,
+                             static_cast<const RT*>(W.tc), static_cast<const RT*>(W.ts), W.mom, rcond_cut, W.pb, W.pn,
+                             static_cast<RT*>(W.pc), static_cast<RT*>(W.ps), W.pstart, hits, Minv4, valid, m4_zero,
+                             sd4, md4, counts);
+        });
+      });
+    });
     DST_CHECK(hipGetLastError());
   }
   // 6. time-order runs carry compact ids from here on
@@ -684,20 +701,16 @@ hipError_t runs_build(const View& v, int psi_f32, const void* tod, int tod_f32, 
 hipError_t launch_rhs_runs(const View& vc, const Runs& W, const void* tod, const double* md4, const uint8_t* valid,
                            int32_t* nvalid, double* J, double* b, hipStream_t st) {
   const unsigned g = (unsigned)(8 * ((vc.n_b + 7) / 8));
-  const bool T = vc.rowT >= 0, Q = vc.rowQ >= 0;
-#define DST_RH(T_, Q_, D_)                                                                                           \
-  hipLaunchKernelGGL((k_rhs_runs<T_, Q_, D_>), dim3(g), dim3(kBlock), 0, st, vc, W.bstart, W.tpix, W.tn, W.tc, W.ts, \
-                     W.mom, md4, valid, nvalid, J, b)
-  if (tod) {
-    if (T && Q) DST_RH(true, true, true);
-    else if (Q) DST_RH(false, true, true);
-    else DST_RH(true, false, true);
-  } else {
-    if (T && Q) DST_RH(true, true, false);
-    else if (Q) DST_RH(false, true, false);
-    else DST_RH(true, false, false);
-  }
-#undef DST_RH
+  by_float(W.f32, [&](auto rt) {
+    using RT = typename decltype(rt)::type;
+    by_streams(vc, [&](auto T, auto Q) {
+      by_bool(tod != nullptr, [&](auto D) {
+        hipLaunchKernelGGL((k_rhs_runs<RT, decltype(T)::value, decltype(Q)::value, decltype(D)::value>), dim3(g),
+                           dim3(kBlock), 0, st, vc, W.bstart, W.tpix, W.tn, static_cast<const RT*>(W.tc),
+                           static_cast<const RT*>(W.ts), W.mom, md4, valid, nvalid, J, b);
+      });
+    });
+  });
   return hipGetLastError();
 }
 
@@ -705,15 +718,14 @@ hipError_t launch_bin_runs(const View& vc, const Runs& W, const double* pw4, con
                            const uint8_t* valid, double* m4, const CgCtl* gate, hipStream_t st) {
   if (W.n_obs == 0) return hipSuccess;
   const unsigned g = grid_for(W.n_obs, kWaves, 16384);
-  if (vc.rowT >= 0 && vc.rowQ >= 0)
-    hipLaunchKernelGGL((k_bin_runs<true, true>), dim3(g), dim3(kBlock), 0, st, W.n_obs, W.pstart, W.pb, W.pn, W.pc,
-                       W.ps, pw4, Minv4, valid, m4, gate);
-  else if (vc.rowQ >= 0)
-    hipLaunchKernelGGL((k_bin_runs<false, true>), dim3(g), dim3(kBlock), 0, st, W.n_obs, W.pstart, W.pb, W.pn, W.pc,
-                       W.ps, pw4, Minv4, valid, m4, gate);
-  else
-    hipLaunchKernelGGL((k_bin_runs<true, false>), dim3(g), dim3(kBlock), 0, st, W.n_obs, W.pstart, W.pb, W.pn, W.pc,
-                       W.ps, pw4, Minv4, valid, m4, gate);
+  by_float(W.f32, [&](auto rt) {
+    using RT = typename decltype(rt)::type;
+    by_streams(vc, [&](auto T, auto Q) {
+      hipLaunchKernelGGL((k_bin_runs<RT, decltype(T)::value, decltype(Q)::value>), dim3(g), dim3(kBlock), 0, st,
+                         W.n_obs, W.pstart, W.pb, W.pn, static_cast<const RT*>(W.pc), static_cast<const RT*>(W.ps),
+                         pw4, Minv4, valid, m4, gate);
+    });
+  });
   return hipGetLastError();
 }
 
@@ -721,20 +733,16 @@ hipError_t launch_unbin_runs(const View& vc, const Runs& W, const double* m4, co
                              double* q, CgCtl* ctl, double* partials, hipStream_t st) {
   const int64_t n_g = (vc.n_b + kWaves - 1) / kWaves;
   const unsigned g = (unsigned)(8 * ((n_g + 7) / 8));
-  const bool T = vc.rowT >= 0, Q = vc.rowQ >= 0;
-#define DST_UR(T_, Q_, CG_)                                                                                           \
-  hipLaunchKernelGGL((k_unbin_runs<T_, Q_, CG_>), dim3(g), dim3(kBlock), 0, st, vc, W.bstart, W.tpix, W.tn, W.tc, W.ts, \
-                     m4, nvalid, p, q, ctl, partials)
-  if (ctl) {
-    if (T && Q) DST_UR(true, true, true);
-    else if (Q) DST_UR(false, true, true);
-    else DST_UR(true, false, true);
-  } else {
-    if (T && Q) DST_UR(true, true, false);
-    else if (Q) DST_UR(false, true, false);
-    else DST_UR(true, false, false);
-  }
-#undef DST_UR
+  by_float(W.f32, [&](auto rt) {
+    using RT = typename decltype(rt)::type;
+    by_streams(vc, [&](auto T, auto Q) {
+      by_bool(ctl != nullptr, [&](auto CG) {
+        hipLaunchKernelGGL((k_unbin_runs<RT, decltype(T)::value, decltype(Q)::value, decltype(CG)::value>), dim3(g),
+                           dim3(kBlock), 0, st, vc, W.bstart, W.tpix, W.tn, static_cast<const RT*>(W.tc),
+                           static_cast<const RT*>(W.ts), m4, nvalid, p, q, ctl, partials);
+      });
+    });
+  });
   return hipGetLastError();
 }
 
