@@ -298,7 +298,8 @@ int build_runs_plan(dst_ctx* ctx, const dst_problem* prob, Plan& P, const void* 
   const size_t rsz = W.f32 ? sizeof(float) : sizeof(double);
   DST_TRY(ws_get(ctx, "r_tc", R * rsz, &W.tc));
   DST_TRY(ws_get(ctx, "r_ts", R * rsz, &W.ts));
-  DST_TRY(ws(ctx, "r_mom", (size_t)dst::kMom * R, &W.mom));
+  DST_TRY(ws(ctx, "r_raw", 3 * (size_t)R, &W.raw));
+  DST_TRY(ws(ctx, "r_rec", R, &W.rec));
   DST_TRY(ws(ctx, "r_keys0", R, &W.keys[0]));
   DST_TRY(ws(ctx, "r_keys1", R, &W.keys[1]));
   DST_TRY(ws(ctx, "r_vals0", R, &W.vals[0]));

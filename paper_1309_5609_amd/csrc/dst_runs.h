@@ -9,9 +9,16 @@
 
 namespace dst {
 
-// Setup moments stored per run: sums of c^2, cs, s^2 (weight blocks) and of
-// d_T, d_q, d_u and of the rotated, weighted q/u pair (right-hand side).
-constexpr int kMom = 8;
+// Per-run record read by the per-pixel setup (one aligned 64-byte access):
+// length, baseline, sums over the run of cos 2psi, sin 2psi, cos^2 2psi,
+// cos 2psi sin 2psi, d_T and of the rotated, weighted q/u pair
+// (w_q d_q c - w_u d_u s, w_q d_q s + w_u d_u c).
+struct alignas(64) RunRecord {
+  int32_t n;
+  int32_t b;
+  double C, S, cc, cs, dT, dQ, dU;
+};
+static_assert(sizeof(RunRecord) == 64, "run record must be one 64-byte line");
 
 // A run is a maximal stretch of consecutive unmasked samples on one pixel
 // inside one baseline.  Runs are kept twice: in time order (t*: rescan and
@@ -24,7 +31,7 @@ constexpr int kMom = 8;
 // Buffers belong to the caller's workspace.  Sizes: head, hidx [n_t];
 // bstart [n_b + 1]; t0, tpix, tn, pb, pn [R] and tc, ts, pc, ps [R] (FP32 when
 // f32, else FP64);
-// mom [kMom R]; keys, vals 2 x [R]; seg [2 n_pix] (zero-filled before
+// raw [3 R]; rec [R]; keys, vals 2 x [R]; seg [2 n_pix] (zero-filled before
 // runs_build); pk, pv 2 x [n_pix]; cid [n_pix] (filled with -1 before
 // runs_build); ccount, pstart [n_pix + 1].
 struct Runs {
@@ -40,7 +47,8 @@ struct Runs {
   int32_t* tn = nullptr;
   void* tc = nullptr;
   void* ts = nullptr;
-  double* mom = nullptr;
+  double* raw = nullptr;       // [3 R] sums of d_T, d_q, d_u per run (time order)
+  RunRecord* rec = nullptr;    // [R] per-run records (time order)
   uint32_t* keys[2] = {nullptr, nullptr};
   uint32_t* vals[2] = {nullptr, nullptr};
   const uint32_t* rperm = nullptr;

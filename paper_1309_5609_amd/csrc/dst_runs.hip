@@ -124,21 +124,23 @@ __global__ void __launch_bounds__(kBlock) k_run_starts(const uint32_t* __restric
 }
 
 // One thread per run: length, sums of cos 2psi and sin 2psi, and the setup
-// moments (sums of c^2, cs, s^2 for the weight blocks; timeline sums for the
-// right-hand side).  Samples are summed in time order.
+// sums.  Time-order outputs feed the rescan and the right-hand side (pixel,
+// length, C, S, and the sums of d_T, d_q, d_u); a 64-byte record per run
+// feeds the per-pixel setup, which reads it in pixel order with one aligned
+// access.  Samples are summed in time order.
 template <typename PT, typename TT, typename RT, bool HAS_T, bool HAS_QU, bool TOD>
 __global__ void __launch_bounds__(kBlock) k_run_build(View v, const TT* __restrict__ tod,
                                                       const uint32_t* __restrict__ t0, int64_t R,
                                                       int32_t* __restrict__ rpix, int32_t* __restrict__ rn,
                                                       RT* __restrict__ rc, RT* __restrict__ rs,
-                                                      double* __restrict__ mom) {
+                                                      double* __restrict__ raw, RunRecord* __restrict__ rec) {
   const PT* psi = static_cast<const PT*>(v.psi);
   const int64_t n_t = v.n_t, L = v.L;
   for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < R; r += (int64_t)gridDim.x * blockDim.x) {
     const int64_t ts = t0[r];
     const int p = v.pix[ts];
     const int64_t tend = min(n_t, (ts / L + 1) * L);
-    double C = 0.0, S = 0.0, cc = 0.0, cs = 0.0, ss = 0.0;
+    double C = 0.0, S = 0.0, cc = 0.0, cs = 0.0;
     double dT = 0.0, dq = 0.0, du = 0.0, dQ = 0.0, dU = 0.0;
     int64_t t = ts;
     for (; t < tend && v.pix[t] == p; ++t) {
@@ -149,7 +151,6 @@ __global__ void __launch_bounds__(kBlock) k_run_build(View v, const TT* __restri
         S += s;
         cc += c * c;
         cs += c * s;
-        ss += s * s;
       }
       if (TOD) {
         if (HAS_T) dT += (double)tod[v.rowT * n_t + t];
@@ -164,21 +165,29 @@ __global__ void __launch_bounds__(kBlock) k_run_build(View v, const TT* __restri
         }
       }
     }
+    const int32_t n = (int32_t)(t - ts);
     rpix[r] = p;
-    rn[r] = (int32_t)(t - ts);
+    rn[r] = n;
     if (HAS_QU) {
       rc[r] = (RT)C;
       rs[r] = (RT)S;
     }
-    double* m = mom + kMom * r;
-    m[0] = cc;
-    m[1] = cs;
-    m[2] = ss;
-    m[3] = dT;
-    m[4] = dq;
-    m[5] = du;
-    m[6] = dQ;
-    m[7] = dU;
+    if (TOD) {
+      raw[3 * r + 0] = dT;
+      raw[3 * r + 1] = dq;
+      raw[3 * r + 2] = du;
+    }
+    RunRecord x;
+    x.n = n;
+    x.b = (int32_t)(ts / L);
+    x.C = C;
+    x.S = S;
+    x.cc = cc;
+    x.cs = cs;
+    x.dT = dT;
+    x.dQ = dQ;
+    x.dU = dU;
+    rec[r] = x;
   }
 }
 
@@ -230,12 +239,12 @@ __global__ void __launch_bounds__(kBlock) k_compact(const uint32_t* __restrict__
 
 // One wavefront per compact pixel: its runs (pixel order, time order within
 // the pixel) -> the pixel-order run arrays; hits, weight blocks, inverse,
-// validity; with TOD the sum map and binned map.
+// validity; with TOD the sum map and binned map.  The sum of sin^2 2psi over
+// a run is its length minus the sum of cos^2 2psi.
 template <typename RT, bool HAS_T, bool HAS_QU, bool TOD>
 __global__ void __launch_bounds__(kBlock) k_pixels_from_runs(
     View v, int64_t n_obs, const uint32_t* __restrict__ order, const int64_t* __restrict__ seg,
-    const uint32_t* __restrict__ rperm, const uint32_t* __restrict__ t0, const int32_t* __restrict__ rn,
-    const RT* __restrict__ rc, const RT* __restrict__ rs, const double* __restrict__ mom, double rcond_cut,
+    const uint32_t* __restrict__ rperm, const RunRecord* __restrict__ rec, double rcond_cut,
     int32_t* __restrict__ pb, int32_t* __restrict__ pn, RT* __restrict__ pc, RT* __restrict__ ps,
     const int64_t* __restrict__ pstart, int32_t* __restrict__ hits, double* __restrict__ Minv4,
     uint8_t* __restrict__ valid, double* __restrict__ m4_zero, double* __restrict__ sd4, double* __restrict__ md4,
@@ -244,34 +253,30 @@ __global__ void __launch_bounds__(kBlock) k_pixels_from_runs(
   unsigned long long cnt[4] = {0, 0, 0, 0};
   const int lane = lane_id();
   const int64_t nw = (int64_t)gridDim.x * kWaves;
-  const uint32_t L = (uint32_t)v.L;
   for (int64_t c = (int64_t)blockIdx.x * kWaves + (threadIdx.x >> 6); c < n_obs; c += nw) {
     const uint32_t p = order[c];
     const int64_t j0 = seg[2 * (int64_t)p], j1 = seg[2 * (int64_t)p + 1];
     const int64_t d0 = pstart[c];
-    double acc[7] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};  // h, cc, cs, ss, dT, dQ, dU
+    double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};  // h, cc, cs, dT, dQ, dU
     for (int64_t j = j0 + lane; j < j1; j += 64) {
-      const uint32_t r = rperm[j];
-      const int32_t n = rn[r];
+      const RunRecord x = rec[rperm[j]];
       const int64_t d = d0 + (j - j0);
-      pb[d] = (int32_t)(t0[r] / L);
-      pn[d] = n;
-      acc[0] += (double)n;
-      const double* m = mom + kMom * (int64_t)r;
+      pb[d] = x.b;
+      pn[d] = x.n;
+      acc[0] += (double)x.n;
       if (HAS_QU) {
-        pc[d] = rc[r];
-        ps[d] = rs[r];
-        acc[1] += m[0];
-        acc[2] += m[1];
-        acc[3] += m[2];
+        pc[d] = (RT)x.C;
+        ps[d] = (RT)x.S;
+        acc[1] += x.cc;
+        acc[2] += x.cs;
       }
       if (TOD) {
-        acc[4] += m[3];
-        acc[5] += m[6];
-        acc[6] += m[7];
+        acc[3] += x.dT;
+        acc[4] += x.dQ;
+        acc[5] += x.dU;
       }
     }
-    wave_sum<7>(acc);
+    wave_sum<6>(acc);
     if (lane == 0) {
       const int64_t h = (int64_t)acc[0];
       double inv[4] = {0.0, 0.0, 0.0, 0.0};
@@ -282,9 +287,10 @@ __global__ void __launch_bounds__(kBlock) k_pixels_from_runs(
       }
       if (HAS_QU && h > 0) {
         const double wq = v.w[1], wu = v.w[2];
-        const double a = wq * acc[1] + wu * acc[3];
+        const double scc = acc[1], sss = acc[0] - acc[1];
+        const double a = wq * scc + wu * sss;
         const double b = (wq - wu) * acc[2];
-        const double d = wq * acc[3] + wu * acc[1];
+        const double d = wq * sss + wu * scc;
         // eigenvalues of the symmetric 2x2 block [[a, b], [b, d]]
         const double half = 0.5 * (a - d);
         const double rad = sqrt(half * half + b * b);
@@ -307,9 +313,9 @@ __global__ void __launch_bounds__(kBlock) k_pixels_from_runs(
       mz[0] = make_double2(0.0, 0.0);
       mz[1] = make_double2(0.0, 0.0);
       if (TOD) {
-        const double sI = (f & 1) ? v.w[0] * acc[4] : 0.0;
-        const double sQ = (f & 2) ? acc[5] : 0.0;
-        const double sU = (f & 2) ? acc[6] : 0.0;
+        const double sI = (f & 1) ? v.w[0] * acc[3] : 0.0;
+        const double sQ = (f & 2) ? acc[4] : 0.0;
+        const double sU = (f & 2) ? acc[5] : 0.0;
         double2* sp = reinterpret_cast<double2*>(sd4 + 4 * c);
         sp[0] = make_double2(sI, sQ);
         sp[1] = make_double2(sU, 0.0);
@@ -343,7 +349,7 @@ template <typename RT, bool HAS_T, bool HAS_QU, bool TOD>
 __global__ void __launch_bounds__(kBlock) k_rhs_runs(View v, const uint32_t* __restrict__ bstart,
                                                      const int32_t* __restrict__ rpix, const int32_t* __restrict__ rn,
                                                      const RT* __restrict__ rc, const RT* __restrict__ rs,
-                                                     const double* __restrict__ mom, const double* __restrict__ md4,
+                                                     const double* __restrict__ raw, const double* __restrict__ md4,
                                                      const uint8_t* __restrict__ valid, int32_t* __restrict__ nvalid,
                                                      double* __restrict__ J, double* __restrict__ b_out) {
   __shared__ double lds[5 * 16];
@@ -356,19 +362,19 @@ __global__ void __launch_bounds__(kBlock) k_rhs_runs(View v, const uint32_t* __r
     const int c = rpix[r];
     const uint8_t f = valid[c];
     const double n = (double)rn[r];
-    const double* m = mom + kMom * r;
+    const double* m = raw + 3 * r;
     const double2* mp = reinterpret_cast<const double2*>(md4 + 4 * (int64_t)c);
     if (HAS_T && (f & 1)) {
       acc[3] += n;
-      if (TOD) acc[0] += m[3] - n * mp[0].x;
+      if (TOD) acc[0] += m[0] - n * mp[0].x;
     }
     if (HAS_QU && (f & 2)) {
       acc[4] += n;
       if (TOD) {
         const double C = (double)rc[r], S = (double)rs[r];
         const double mQ = mp[0].y, mU = mp[1].x;
-        acc[1] += m[4] - (C * mQ + S * mU);
-        acc[2] += m[5] - (C * mU - S * mQ);
+        acc[1] += m[1] - (C * mQ + S * mU);
+        acc[2] += m[2] - (C * mU - S * mQ);
       }
     }
   }
@@ -631,7 +637,7 @@ hipError_t runs_build(const View& v, int psi_f32, const void* tod, int tod_f32, 
           by_bool(tod != nullptr, [&](auto D) {
             hipLaunchKernelGGL((k_run_build<PT, TT, RT, decltype(T)::value, decltype(Q)::value, decltype(D)::value>),
                                dim3(grb), dim3(kBlock), 0, st, v, static_cast<const TT*>(tod), W.t0, W.R, W.tpix, W.tn,
-                               static_cast<RT*>(W.tc), static_cast<RT*>(W.ts), W.mom);
+                               static_cast<RT*>(W.tc), static_cast<RT*>(W.ts), W.raw, W.rec);
           });
         });
       });
@@ -684,10 +690,9 @@ hipError_t runs_build(const View& v, int psi_f32, const void* tod, int tod_f32, 
       by_streams(v, [&](auto T, auto Q) {
         by_bool(tod != nullptr, [&](auto D) {
           hipLaunchKernelGGL((k_pixels_from_runs<RT, decltype(T)::value, decltype(Q)::value, decltype(D)::value>),
-                             dim3(gw), dim3(kBlock), 0, st, v, W.n_obs, W.order, W.seg, W.rperm, W.t0, W.tn,
-                             static_cast<const RT*>(W.tc), static_cast<const RT*>(W.ts), W.mom, rcond_cut, W.pb, W.pn,
-                             static_cast<RT*>(W.pc), static_cast<RT*>(W.ps), W.pstart, hits, Minv4, valid, m4_zero,
-                             sd4, md4, counts);
+                             dim3(gw), dim3(kBlock), 0, st, v, W.n_obs, W.order, W.seg, W.rperm, W.rec, rcond_cut,
+                             W.pb, W.pn, static_cast<RT*>(W.pc), static_cast<RT*>(W.ps), W.pstart, hits, Minv4,
+                             valid, m4_zero, sd4, md4, counts);
         });
       });
     });
@@ -707,7 +712,7 @@ hipError_t launch_rhs_runs(const View& vc, const Runs& W, const void* tod, const
       by_bool(tod != nullptr, [&](auto D) {
         hipLaunchKernelGGL((k_rhs_runs<RT, decltype(T)::value, decltype(Q)::value, decltype(D)::value>), dim3(g),
                            dim3(kBlock), 0, st, vc, W.bstart, W.tpix, W.tn, static_cast<const RT*>(W.tc),
-                           static_cast<const RT*>(W.ts), W.mom, md4, valid, nvalid, J, b);
+                           static_cast<const RT*>(W.ts), W.raw, md4, valid, nvalid, J, b);
       });
     });
   });
