@@ -194,6 +194,36 @@ typedef struct {
 int dst_solve(dst_ctx* ctx, const dst_problem* prob, const dst_solve_opts* opts, double* baselines_out,
               double* map_out, double* binned_out, int32_t* hits_out, dst_solve_info* info, void* stream);
 
+/* Destripe several problems in one call.
+ *
+ * Problems that share the operator K of Eq. 13 -- the same pix and psi
+ * pointers, n_samples, n_pix, baseline_length, streams, psi_dtype, weights and
+ * rcond_cut, as Monte Carlo noise realizations of one channel do -- are solved
+ * together (up to 64 per group): the pointing setup runs once, each iteration
+ * applies K to every right-hand side in one pass over the pointing, and each
+ * problem keeps its own CG scalars and stops when it meets the tolerance
+ * (later iterations leave its solution unchanged).  Each problem has its own
+ * tod (its tod_dtype may differ).  Problems that share the operator with no
+ * other are solved one after another as by dst_solve.
+ *   n_problems     >= 1
+ *   problems       host array [n_problems]
+ *   opts           as for dst_solve, shared by every problem; a0 must be NULL
+ *                  and DST_SOLVE_PER_SAMPLE is not accepted
+ *   baselines_out  host array [n_problems] of device pointers, each
+ *                  [n_streams][n_b] f64 (none may be NULL)
+ *   map_out, binned_out, hits_out
+ *                  host arrays [n_problems] of device pointers ([n_pix][3] f64,
+ *                  [n_pix][3] f64, [n_pix] int32); the array or any entry may
+ *                  be NULL to skip that output
+ *   infos          host array [n_problems] or NULL; in a group the timings are
+ *                  those of the group (t_iter_ms per iteration of the group)
+ * Returns DST_OK when every problem converged, DST_ENOCONV when at least one
+ * did not (its outputs hold the last iterate), else the first error met
+ * (argument errors are reported before any launch, naming the problem). */
+int dst_solve_batched(dst_ctx* ctx, int32_t n_problems, const dst_problem* problems, const dst_solve_opts* opts,
+                      double* const* baselines_out, double* const* map_out, double* const* binned_out,
+                      int32_t* const* hits_out, dst_solve_info* infos, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -16,6 +16,7 @@
 
 #include "dst.h"
 #include "dst_internal.h"
+#include "dst_multi.h"
 #include "dst_pixel.h"
 #include "dst_runs.h"
 
@@ -32,6 +33,8 @@ struct dst_ctx {
   std::unordered_map<std::string, Buf> ws;
   CgCtl* ctl_host = nullptr;  // pinned mirror of the device CG scalars
   int* err_host = nullptr;    // pinned mirror of the device error flag
+  dst::MultiCtl* mctl_host = nullptr;  // pinned mirror of the batched CG state
+  hipStream_t cap = nullptr;  // private stream on which iteration graphs are captured
 };
 
 namespace {
@@ -432,6 +435,257 @@ int plan_operator(dst_ctx* ctx, Plan& P, const double* vin, double* out, hipStre
   return DST_OK;
 }
 
+// Captures `reps` calls of body(stream) on the context's private stream and
+// instantiates the graph.  The iteration kernels read their scalars from
+// device memory and return at once after the stop, so one graph serves every
+// batch of iterations.
+template <typename F>
+int capture_graph(dst_ctx* ctx, int reps, F&& body, hipGraphExec_t* exec) {
+  *exec = nullptr;
+  if (!ctx->cap) HIP_TRY(hipStreamCreateWithFlags(&ctx->cap, hipStreamNonBlocking));
+  HIP_TRY(hipStreamBeginCapture(ctx->cap, hipStreamCaptureModeThreadLocal));
+  int rc = DST_OK;
+  for (int i = 0; i < reps && rc == DST_OK; ++i) rc = body(ctx->cap);
+  hipGraph_t g = nullptr;
+  const hipError_t e = hipStreamEndCapture(ctx->cap, &g);
+  if (rc != DST_OK) {
+    if (g) (void)hipGraphDestroy(g);
+    return rc;
+  }
+  if (e != hipSuccess) return fail(ctx, DST_EHIP, "graph capture: %s", hipGetErrorString(e));
+  const hipError_t e2 = hipGraphInstantiate(exec, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (e2 != hipSuccess) {
+    *exec = nullptr;
+    return fail(ctx, DST_EHIP, "graph instantiation: %s", hipGetErrorString(e2));
+  }
+  return DST_OK;
+}
+
+struct GraphGuard {
+  hipGraphExec_t exec = nullptr;
+  ~GraphGuard() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+  }
+};
+
+struct EventSet {
+  std::vector<hipEvent_t> ev;
+  ~EventSet() {
+    for (auto e : ev) (void)hipEventDestroy(e);
+  }
+  hipError_t add(hipEvent_t* out) {
+    hipError_t e = hipEventCreate(out);
+    if (e == hipSuccess) ev.push_back(*out);
+    return e;
+  }
+};
+
+// Status of one finished right-hand side.
+int done_status(int done) {
+  switch (done) {
+    case dst::DONE_CONVERGED:
+      return DST_OK;
+    case dst::DONE_BREAKDOWN:
+      return DST_EBREAKDOWN;
+    case dst::DONE_NAN:
+      return DST_ENAN;
+    default:
+      return DST_ENOCONV;
+  }
+}
+
+// Worse of two statuses: errors (negative) over the ENOCONV warning over OK.
+int worse(int a, int b) {
+  if (a < 0) return a;
+  if (b < 0) return b;
+  return std::max(a, b);
+}
+
+bool same_operator(const dst_problem& a, const dst_problem& b) {
+  return a.pix == b.pix && a.psi == b.psi && a.n_samples == b.n_samples && a.n_pix == b.n_pix &&
+         a.baseline_length == b.baseline_length && a.streams == b.streams && a.psi_dtype == b.psi_dtype &&
+         a.weight[0] == b.weight[0] && a.weight[1] == b.weight[1] && a.weight[2] == b.weight[2] &&
+         a.rcond_cut == b.rcond_cut;
+}
+
+struct BatchOut {
+  double* const* baselines;
+  double* const* maps;
+  double* const* binned;
+  int32_t* const* hits;
+  dst_solve_info* infos;
+};
+
+// Multi-right-hand-side solve of the problems idx (same pointing, weights and
+// cut): shared run setup, one binned map and right-hand side per problem, then
+// PCG on every right-hand side at once with per-problem stopping.
+int solve_group(dst_ctx* ctx, const dst_problem* problems, const std::vector<int>& idx, const dst_solve_opts& opts,
+                int check_every, const BatchOut& out, hipStream_t st, int* status) {
+  const dst_problem& p0 = problems[idx[0]];
+  const bool profile = opts.flags & DST_SOLVE_PROFILE;
+  const bool use_graph = !(opts.flags & (DST_SOLVE_NO_GRAPH | DST_SOLVE_PROFILE));
+  View v{};
+  DST_TRY(check_problem(ctx, &p0, true, v));
+  EventSet evs;
+  hipEvent_t ev[4];
+  for (auto& e : ev) HIP_TRY(evs.add(&e));
+  HIP_TRY(hipEventRecord(ev[0], st));
+
+  // shared pointing setup (runs, compact pixels, blocks, counts, Jacobi)
+  Plan P;
+  P.full = v;
+  P.runs = true;
+  DST_TRY(build_runs_plan(ctx, &p0, P, nullptr, nullptr, nullptr, nullptr, st));
+  Setup& S = P.S;
+  const View& vc = S.v;
+  dst::Runs& W = P.W;
+  dst::Multi mu;
+  mu.R = (int)idx.size();
+  mu.Rp = dst::multi_padded(mu.R);
+  const int64_t n_obs = W.n_obs;
+  const size_t NV = (size_t)v.n_b * v.n_streams * mu.Rp;
+  const size_t NM = (size_t)std::max<int64_t>(n_obs, 1) * v.n_streams * mu.Rp;
+  uint32_t* ipos;
+  double *prs, *braw, *b, *a, *r, *z, *p, *q, *ka, *md, *m, *part, *part2;
+  dst::MultiCtl* ctl;
+  DST_TRY(ws(ctx, "mb_ipos", (size_t)std::max<int64_t>(W.R, 1), &ipos));
+  DST_TRY(ws(ctx, "mb_prs", 4 * (size_t)std::max<int64_t>(W.R, 1), &prs));
+  DST_TRY(ws(ctx, "mb_braw", NV, &braw));
+  DST_TRY(ws(ctx, "mb_b", NV, &b));
+  DST_TRY(ws(ctx, "mb_a", NV, &a));
+  DST_TRY(ws(ctx, "mb_r", NV, &r));
+  DST_TRY(ws(ctx, "mb_z", NV, &z));
+  DST_TRY(ws(ctx, "mb_p", NV, &p));
+  DST_TRY(ws(ctx, "mb_q", NV, &q));
+  DST_TRY(ws(ctx, "mb_ka", NV, &ka));
+  DST_TRY(ws(ctx, "mb_md", NM, &md));
+  DST_TRY(ws(ctx, "mb_m", NM, &m));
+  DST_TRY(ws(ctx, "mb_part", (size_t)dst::multi_unbin_blocks(vc) * 3 * mu.Rp, &part));
+  DST_TRY(ws(ctx, "mb_part2", (size_t)std::max(dst::multi_update_blocks(v, mu), 256) * 2 * mu.Rp, &part2));
+  DST_TRY(ws(ctx, "mb_ctl", 1, &ctl));
+  HIP_TRY(dst::launch_fill(m, NM, 0.0, st));
+  HIP_TRY(dst::launch_fill(md, NM, 0.0, st));
+  HIP_TRY(dst::launch_fill(braw, NV, 0.0, st));
+  HIP_TRY(dst::launch_fill_u32(reinterpret_cast<uint32_t*>(ctl), sizeof(dst::MultiCtl) / 4, 0u, st));
+
+  // per problem: run sums of the data, binned map; then every b at once
+  HIP_TRY(dst::launch_run_positions(W, ipos, st));
+  for (int k = 0; k < mu.R; ++k) {
+    const dst_problem& pk = problems[idx[k]];
+    HIP_TRY(dst::launch_multi_tod(vc, S.psi_f32, pk.tod, pk.tod_dtype == DST_F32, W, ipos, S.valid, mu.Rp, k, prs,
+                                  braw, st));
+    HIP_TRY(dst::launch_multi_pixsum(n_obs, vc, W, prs, S.Minv4, mu.Rp, k, md, st));
+  }
+  HIP_TRY(dst::launch_multi_unbin(vc, W, mu, dst::UNBIN_RHS, md, S.nvalid, nullptr, braw, b, nullptr, nullptr, st));
+  HIP_TRY(dst::launch_multi_start(v, mu, b, a, r, z, p, S.J, ctl, part2, opts.tol, opts.max_iter, st));
+  HIP_TRY(hipEventRecord(ev[1], st));
+  dst::MultiCtl& h = *ctx->mctl_host;
+  HIP_TRY(hipMemcpyAsync(&h, ctl, sizeof(dst::MultiCtl), hipMemcpyDeviceToHost, st));
+  DST_TRY(finish(ctx, &S, st));
+  unsigned long long counts[4];
+  HIP_TRY(hipMemcpy(counts, S.counts, sizeof counts, hipMemcpyDeviceToHost));
+  if (counts[2] + counts[3] == 0) return fail(ctx, DST_EDEGENERATE, "no valid sample in the problem");
+
+  // PCG: bin (m = M^-1 A^T W F p) -> rescan + sums (q = K p, alpha) ->
+  // a, r, z (beta) -> p, for every running right-hand side
+  EventSet pev;
+  auto iteration = [&](hipStream_t s, bool timed) -> int {
+    hipEvent_t e[4] = {nullptr, nullptr, nullptr, nullptr};
+    if (timed) {
+      for (auto& x : e) HIP_TRY(pev.add(&x));
+      HIP_TRY(hipEventRecord(e[0], s));
+    }
+    HIP_TRY(dst::launch_multi_bin(vc, W, mu, p, S.Minv4, m, ctl, s));
+    if (timed) HIP_TRY(hipEventRecord(e[1], s));
+    HIP_TRY(dst::launch_multi_unbin(vc, W, mu, dst::UNBIN_CG, m, S.nvalid, p, nullptr, q, ctl, part, s));
+    HIP_TRY(dst::launch_multi_alpha(vc, mu, ctl, part, s));
+    if (timed) HIP_TRY(hipEventRecord(e[2], s));
+    HIP_TRY(dst::launch_multi_update(v, mu, a, r, z, q, p, S.J, ctl, part2, s));
+    HIP_TRY(dst::launch_multi_beta(v, mu, ctl, part2, s));
+    HIP_TRY(dst::launch_multi_p(v, mu, p, z, ctl, s));
+    if (timed) HIP_TRY(hipEventRecord(e[3], s));
+    return DST_OK;
+  };
+  GraphGuard gg;
+  if (use_graph && h.running > 0)
+    DST_TRY(capture_graph(ctx, check_every, [&](hipStream_t s) { return iteration(s, false); }, &gg.exec));
+  HIP_TRY(hipEventRecord(ev[2], st));
+  int launched = 0;
+  while (h.running > 0 && launched < opts.max_iter) {
+    if (gg.exec) {
+      HIP_TRY(hipGraphLaunch(gg.exec, st));
+      launched += check_every;
+    } else {
+      const int k = std::min(check_every, opts.max_iter - launched);
+      for (int i = 0; i < k; ++i) DST_TRY(iteration(st, profile));
+      launched += k;
+    }
+    HIP_TRY(hipMemcpyAsync(&h, ctl, sizeof(dst::MultiCtl), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+  }
+  HIP_TRY(hipEventRecord(ev[3], st));
+
+  // canonical baselines, true residuals, outputs
+  if (!(opts.flags & DST_SOLVE_NO_CANON)) HIP_TRY(dst::launch_multi_canonicalise(v, mu, a, S.J, ctl, part2, st));
+  HIP_TRY(dst::launch_multi_bin(vc, W, mu, a, S.Minv4, m, nullptr, st));
+  HIP_TRY(dst::launch_multi_unbin(vc, W, mu, dst::UNBIN_OPERATOR, m, S.nvalid, a, nullptr, ka, nullptr, nullptr, st));
+  HIP_TRY(dst::launch_multi_resid(v, mu, b, ka, S.J, ctl, part2, st));
+  for (int k = 0; k < mu.R; ++k) {
+    const int i = idx[k];
+    HIP_TRY(dst::launch_multi_extract(v, mu, k, a, out.baselines[i], st));
+    if (out.maps && out.maps[i]) HIP_TRY(dst::launch_multi_scatter(v, vc, W.cid, mu, k, md, m, out.maps[i], st));
+    if (out.binned && out.binned[i])
+      HIP_TRY(dst::launch_multi_scatter(v, vc, W.cid, mu, k, md, nullptr, out.binned[i], st));
+    if (out.hits && out.hits[i])
+      HIP_TRY(dst::launch_scatter(v.n_pix, W.cid, S.hits, out.hits[i], md, nullptr, nullptr, st));
+  }
+  HIP_TRY(hipMemcpyAsync(&h, ctl, sizeof(dst::MultiCtl), hipMemcpyDeviceToHost, st));
+  DST_TRY(finish(ctx, &S, st));
+
+  int max_it = 0;
+  for (int k = 0; k < mu.R; ++k) max_it = std::max(max_it, h.iter[k]);
+  float t_setup = 0.f, t_iter = 0.f, t_total = 0.f;
+  HIP_TRY(hipEventElapsedTime(&t_setup, ev[0], ev[1]));
+  HIP_TRY(hipEventElapsedTime(&t_iter, ev[2], ev[3]));
+  HIP_TRY(hipEventElapsedTime(&t_total, ev[0], ev[3]));
+  double tk[3] = {0.0, 0.0, 0.0};
+  if (profile && !pev.ev.empty()) {
+    const size_t n_it = pev.ev.size() / 4;
+    const size_t used = std::min<size_t>(n_it, (size_t)max_it);
+    for (size_t i = 0; i < used; ++i)
+      for (int j = 0; j < 3; ++j) {
+        float t = 0.f;
+        HIP_TRY(hipEventElapsedTime(&t, pev.ev[4 * i + j], pev.ev[4 * i + j + 1]));
+        tk[j] += t;
+      }
+    for (auto& x : tk) x = used ? x / used : 0.0;
+  }
+  for (int k = 0; k < mu.R; ++k) {
+    *status = worse(*status, done_status(h.done[k]));
+    if (!out.infos) continue;
+    dst_solve_info& in = out.infos[idx[k]];
+    in = dst_solve_info{};
+    in.iterations = h.iter[k];
+    in.converged = h.done[k] == dst::DONE_CONVERGED;
+    in.b_norm = h.b_norm[k];
+    in.rel_residual = h.b_norm[k] > 0.0 ? h.r_norm[k] / h.b_norm[k] : 0.0;
+    in.true_rel_residual = h.b_norm[k] > 0.0 ? h.true_norm[k] / h.b_norm[k] : 0.0;
+    in.n_valid_pix[0] = (int64_t)counts[0];
+    in.n_valid_pix[1] = (int64_t)counts[1];
+    in.n_valid_samples[0] = (int64_t)counts[2];
+    in.n_valid_samples[1] = (int64_t)counts[3];
+    in.t_setup_ms = t_setup;
+    in.t_iter_ms = max_it > 0 ? t_iter / max_it : 0.0;
+    in.t_total_ms = t_total;
+    in.t_bin_ms = tk[0];
+    in.t_unbin_ms = tk[1];
+    in.t_update_ms = tk[2];
+    in.n_runs = W.R;
+  }
+  return DST_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -448,7 +702,9 @@ int dst_create(dst_ctx** out, int device) {
   ctx->device = device;
   DeviceGuard g(device);
   if (hipHostMalloc(reinterpret_cast<void**>(&ctx->ctl_host), sizeof(CgCtl), hipHostMallocDefault) != hipSuccess ||
-      hipHostMalloc(reinterpret_cast<void**>(&ctx->err_host), sizeof(int), hipHostMallocDefault) != hipSuccess) {
+      hipHostMalloc(reinterpret_cast<void**>(&ctx->err_host), sizeof(int), hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc(reinterpret_cast<void**>(&ctx->mctl_host), sizeof(dst::MultiCtl), hipHostMallocDefault) !=
+          hipSuccess) {
     (void)hipGetLastError();
     dst_destroy(ctx);
     return DST_ENOMEM;
@@ -465,6 +721,8 @@ int dst_destroy(dst_ctx* ctx) {
     if (kv.second.ptr) (void)hipFree(kv.second.ptr);
   if (ctx->ctl_host) (void)hipHostFree(ctx->ctl_host);
   if (ctx->err_host) (void)hipHostFree(ctx->err_host);
+  if (ctx->mctl_host) (void)hipHostFree(ctx->mctl_host);
+  if (ctx->cap) (void)hipStreamDestroy(ctx->cap);
   delete ctx;
   return DST_OK;
 }
@@ -659,35 +917,45 @@ int dst_solve(dst_ctx* ctx, const dst_problem* prob, const dst_solve_opts* opts_
 
   // PCG iterations: pixel-major bin + inverse (m = M^-1 A^T W F p) -> rescan and
   // baseline sums (q = K p, alpha) -> a, r, z update (beta) -> p and its copy
-  auto one_iteration = [&](bool timed) -> int {
+  auto one_iteration = [&](hipStream_t s, bool timed) -> int {
     hipEvent_t e[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
     if (timed) {
       for (auto& x : e) {
         HIP_TRY(hipEventCreate(&x));
         pev.push_back(x);
       }
-      HIP_TRY(hipEventRecord(e[0], st));
+      HIP_TRY(hipEventRecord(e[0], s));
     }
-    DST_TRY(plan_bin(ctx, P, ctl, st));
-    if (timed) HIP_TRY(hipEventRecord(e[1], st));
-    if (timed) HIP_TRY(hipEventRecord(e[2], st));
-    DST_TRY(plan_unbin(ctx, P, p, q, ctl, partials, st));
-    HIP_TRY(dst::launch_cg_alpha(vc, ctl, partials, st));
-    if (timed) HIP_TRY(hipEventRecord(e[3], st));
-    HIP_TRY(dst::launch_cg_update(v, a, r, z, p, q, S.J, ctl, partials, st));
-    HIP_TRY(dst::launch_cg_beta(dst::cg_update_blocks(v), ctl, partials, st));
-    HIP_TRY(dst::launch_p_update4(v, p, z, P.pw4, ctl, 1, st));
-    if (timed) HIP_TRY(hipEventRecord(e[4], st));
+    DST_TRY(plan_bin(ctx, P, ctl, s));
+    if (timed) HIP_TRY(hipEventRecord(e[1], s));
+    if (timed) HIP_TRY(hipEventRecord(e[2], s));
+    DST_TRY(plan_unbin(ctx, P, p, q, ctl, partials, s));
+    HIP_TRY(dst::launch_cg_alpha(vc, ctl, partials, s));
+    if (timed) HIP_TRY(hipEventRecord(e[3], s));
+    HIP_TRY(dst::launch_cg_update(v, a, r, z, p, q, S.J, ctl, partials, s));
+    HIP_TRY(dst::launch_cg_beta(dst::cg_update_blocks(v), ctl, partials, s));
+    HIP_TRY(dst::launch_p_update4(v, p, z, P.pw4, ctl, 1, s));
+    if (timed) HIP_TRY(hipEventRecord(e[4], s));
     return DST_OK;
   };
 
-  HIP_TRY(hipEventRecord(ev[2], st));
+  // batches of check_every iterations, replayed from one captured graph
+  // unless profiling or asked not to
   CgCtl& h = *ctx->ctl_host;
+  GraphGuard gg;
+  if (!(opts.flags & (DST_SOLVE_NO_GRAPH | DST_SOLVE_PROFILE)) && h.done == dst::DONE_RUNNING)
+    DST_TRY(capture_graph(ctx, check_every, [&](hipStream_t s) { return one_iteration(s, false); }, &gg.exec));
+  HIP_TRY(hipEventRecord(ev[2], st));
   int launched = 0;
   while (h.done == dst::DONE_RUNNING && launched < opts.max_iter) {
-    const int k = std::min(check_every, opts.max_iter - launched);
-    for (int i = 0; i < k; ++i) DST_TRY(one_iteration(profile));
-    launched += k;
+    if (gg.exec) {
+      HIP_TRY(hipGraphLaunch(gg.exec, st));
+      launched += check_every;
+    } else {
+      const int k = std::min(check_every, opts.max_iter - launched);
+      for (int i = 0; i < k; ++i) DST_TRY(one_iteration(st, profile));
+      launched += k;
+    }
     HIP_TRY(hipMemcpyAsync(ctx->ctl_host, ctl, sizeof(CgCtl), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
   }
@@ -754,6 +1022,68 @@ int dst_solve(dst_ctx* ctx, const dst_problem* prob, const dst_solve_opts* opts_
     default:
       return fail(ctx, DST_ENAN, "non-finite value in the CG recurrences after %d iterations", fin.iter);
   }
+}
+
+int dst_solve_batched(dst_ctx* ctx, int32_t n_problems, const dst_problem* problems, const dst_solve_opts* opts_in,
+                      double* const* baselines_out, double* const* map_out, double* const* binned_out,
+                      int32_t* const* hits_out, dst_solve_info* infos, void* stream) {
+  if (!ctx) return DST_EINVAL;
+  if (n_problems < 1) return fail(ctx, DST_EINVAL, "n_problems must be >= 1 (got %d)", n_problems);
+  if (!problems) return fail(ctx, DST_EINVAL, "problems is NULL");
+  if (!baselines_out) return fail(ctx, DST_EINVAL, "baselines_out is NULL");
+  dst_solve_opts opts{};
+  if (opts_in) opts = *opts_in;
+  if (opts.reserved != 0) return fail(ctx, DST_EINVAL, "opts.reserved must be 0");
+  if (opts.a0) return fail(ctx, DST_EINVAL, "opts.a0 is not supported by the batched solve");
+  const uint32_t known = DST_SOLVE_NO_CANON | DST_SOLVE_PROFILE | DST_SOLVE_NO_GRAPH;
+  if (opts.flags & ~known) return fail(ctx, DST_EINVAL, "unknown or unsupported solve flags %u", opts.flags);
+  if (!(opts.tol > 0.0)) opts.tol = 1e-10;
+  if (!std::isfinite(opts.tol)) return fail(ctx, DST_EINVAL, "tol must be finite");
+  if (opts.max_iter <= 0) opts.max_iter = 1000;
+  const int check_every = opts.check_every > 0 ? opts.check_every : 10;
+  for (int i = 0; i < n_problems; ++i) {
+    View v{};
+    const int rc = check_problem(ctx, &problems[i], true, v);
+    if (rc != DST_OK) {
+      std::string msg = ctx->err;
+      return fail(ctx, rc, "problem %d: %s", i, msg.c_str());
+    }
+    if (!baselines_out[i]) return fail(ctx, DST_EINVAL, "baselines_out[%d] is NULL", i);
+  }
+  ctx->err.clear();
+  DeviceGuard g(ctx->device);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  // groups of problems that share the operator, in order of first appearance
+  std::vector<std::vector<int>> groups;
+  for (int i = 0; i < n_problems; ++i) {
+    bool placed = false;
+    for (auto& grp : groups) {
+      if ((int)grp.size() < dst::kMaxRhs && same_operator(problems[grp[0]], problems[i])) {
+        grp.push_back(i);
+        placed = true;
+        break;
+      }
+    }
+    if (!placed) groups.push_back({i});
+  }
+  const BatchOut out{baselines_out, map_out, binned_out, hits_out, infos};
+  int status = DST_OK;
+  for (const auto& grp : groups) {
+    if (grp.size() == 1) {
+      const int i = grp[0];
+      dst_solve_opts o = opts;
+      const int rc = dst_solve(ctx, &problems[i], &o, baselines_out[i], map_out ? map_out[i] : nullptr,
+                               binned_out ? binned_out[i] : nullptr, hits_out ? hits_out[i] : nullptr,
+                               infos ? &infos[i] : nullptr, stream);
+      if (rc < 0) return rc;
+      status = worse(status, rc);
+      continue;
+    }
+    const int rc = solve_group(ctx, problems, grp, opts, check_every, out, st, &status);
+    if (rc != DST_OK) return rc;
+  }
+  if (status == DST_ENOCONV) fail(ctx, DST_ENOCONV, "at least one problem did not converge");
+  return status;
 }
 
 }  // extern "C"

@@ -1,0 +1,836 @@
+// Multi-right-hand-side kernels: one pass over the run records applies the
+// destriping operator (Eq. 13 of arXiv:1309.5609) to every realization of a
+// batch that shares the pointing.  Lanes of a wavefront are split into
+// 64 / Rp slots of Rp realization lanes: the lanes of one slot read the same
+// run record (one broadcast access) and gather the Rp values of their
+// realizations from one contiguous stretch, so the run stream is read once
+// per iteration for the whole batch.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <type_traits>
+
+#include "dst_device.h"
+#include "dst_multi.h"
+
+namespace dst {
+namespace {
+
+using dev::kBlock;
+using dev::kWaves;
+using dev::lane_id;
+using dev::rot2;
+
+// ---------------------------------------------------------------- setup
+
+// Pixel-order position of every time-order run: runs of compact pixel c sit
+// at pstart[c] .. pstart[c + 1] in the order of the sorted run keys of its
+// original pixel (seg gives that pixel's range of sorted keys).
+__global__ void __launch_bounds__(kBlock) k_run_positions(int64_t n_obs, const uint32_t* __restrict__ order,
+                                                          const int64_t* __restrict__ seg,
+                                                          const uint32_t* __restrict__ rperm,
+                                                          const int64_t* __restrict__ pstart,
+                                                          uint32_t* __restrict__ ipos) {
+  const int lane = lane_id();
+  const int64_t nw = (int64_t)gridDim.x * kWaves;
+  for (int64_t c = (int64_t)blockIdx.x * kWaves + (threadIdx.x >> 6); c < n_obs; c += nw) {
+    const uint32_t p = order[c];
+    const int64_t j0 = seg[2 * (int64_t)p], j1 = seg[2 * (int64_t)p + 1];
+    const int64_t d0 = pstart[c];
+    for (int64_t j = j0 + lane; j < j1; j += 64) ipos[rperm[j]] = (uint32_t)(d0 + (j - j0));
+  }
+}
+
+// One wavefront per baseline; one lane per run.  Per run: w_T sum d_T and the
+// rotated, weighted q/u sums, stored at the run's pixel-order position; per
+// baseline: w_k sum d_k over valid samples (the data part of b = F^T Z d).
+template <typename PT, typename TT, bool HAS_T, bool HAS_QU>
+__global__ void __launch_bounds__(kBlock) k_multi_tod(View v, const TT* __restrict__ tod,
+                                                      const uint32_t* __restrict__ bstart,
+                                                      const uint32_t* __restrict__ t0,
+                                                      const int32_t* __restrict__ tpix, const int32_t* __restrict__ tn,
+                                                      const uint32_t* __restrict__ ipos,
+                                                      const uint8_t* __restrict__ valid, int Rp, int ri,
+                                                      double* __restrict__ prs, double* __restrict__ braw) {
+  const PT* psi = static_cast<const PT*>(v.psi);
+  const int lane = lane_id();
+  const int64_t b = (int64_t)blockIdx.x * kWaves + (threadIdx.x >> 6);
+  if (b >= v.n_b) return;
+  const int64_t n_t = v.n_t;
+  const int64_t r0 = bstart[b], r1 = bstart[b + 1];
+  double acc[3] = {0.0, 0.0, 0.0};
+  for (int64_t j = r0 + lane; j < r1; j += 64) {
+    const int64_t ts = t0[j];
+    const int n = tn[j];
+    const uint8_t f = valid[tpix[j]];
+    double dT = 0.0, dq = 0.0, du = 0.0, dQ = 0.0, dU = 0.0;
+    for (int k = 0; k < n; ++k) {
+      const int64_t t = ts + k;
+      if (HAS_T) dT += (double)tod[v.rowT * n_t + t];
+      if (HAS_QU) {
+        double c, s;
+        rot2((double)psi[t], c, s);
+        const double xq = (double)tod[v.rowQ * n_t + t];
+        const double xu = (double)tod[v.rowU * n_t + t];
+        dq += xq;
+        du += xu;
+        const double wq = v.w[1] * xq, wu = v.w[2] * xu;
+        dQ += c * wq - s * wu;
+        dU += s * wq + c * wu;
+      }
+    }
+    const bool vT = HAS_T && (f & 1), vQ = HAS_QU && (f & 2);
+    double2* o = reinterpret_cast<double2*>(prs + 4 * (int64_t)ipos[j]);
+    o[0] = make_double2(vT ? v.w[0] * dT : 0.0, vQ ? dQ : 0.0);
+    o[1] = make_double2(vQ ? dU : 0.0, 0.0);
+    if (vT) acc[0] += dT;
+    if (vQ) {
+      acc[1] += dq;
+      acc[2] += du;
+    }
+  }
+  dev::wave_sum<3>(acc);
+  if (lane == 0) {
+    const int64_t o = b * v.n_streams * Rp + ri;
+    if (HAS_T) braw[o + v.rowT * Rp] = v.w[0] * acc[0];
+    if (HAS_QU) {
+      braw[o + v.rowQ * Rp] = v.w[1] * acc[1];
+      braw[o + v.rowU * Rp] = v.w[2] * acc[2];
+    }
+  }
+}
+
+// One wavefront per compact pixel: md = M^-1 (sum of its run sums), column ri.
+__global__ void __launch_bounds__(kBlock) k_multi_pixsum(int64_t n_obs, View vc, const int64_t* __restrict__ pstart,
+                                                         const double* __restrict__ prs,
+                                                         const double* __restrict__ Minv4, int Rp, int ri,
+                                                         double* __restrict__ md) {
+  const int lane = lane_id();
+  const int64_t nw = (int64_t)gridDim.x * kWaves;
+  for (int64_t c = (int64_t)blockIdx.x * kWaves + (threadIdx.x >> 6); c < n_obs; c += nw) {
+    const int64_t j0 = pstart[c], j1 = pstart[c + 1];
+    double acc[3] = {0.0, 0.0, 0.0};
+    for (int64_t j = j0 + lane; j < j1; j += 64) {
+      const double2* x = reinterpret_cast<const double2*>(prs + 4 * j);
+      const double2 x0 = x[0], x1 = x[1];
+      acc[0] += x0.x;
+      acc[1] += x0.y;
+      acc[2] += x1.x;
+    }
+    dev::wave_sum<3>(acc);
+    if (lane == 0) {
+      const double2* ip = reinterpret_cast<const double2*>(Minv4 + 4 * c);
+      const double2 i01 = ip[0], i23 = ip[1];
+      const int64_t o = c * vc.n_streams * Rp + ri;
+      if (vc.rowT >= 0) md[o + vc.rowT * Rp] = i01.x * acc[0];
+      if (vc.rowQ >= 0) {
+        md[o + vc.rowQ * Rp] = i01.y * acc[1] + i23.x * acc[2];
+        md[o + vc.rowU * Rp] = i23.x * acc[1] + i23.y * acc[2];
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------- operator
+
+__device__ __forceinline__ bool lane_active(int r, int R, const MultiCtl* ctl) {
+  return r < R && (ctl == nullptr || ctl->done[r] == DONE_RUNNING);
+}
+
+// m = M^-1 A^T W F p per compact pixel (one wavefront per pixel), for every
+// active realization.  p is unweighted; the weights are applied here.
+template <typename RT, bool HAS_T, bool HAS_QU>
+__global__ void __launch_bounds__(kBlock) k_multi_bin(View vc, int R, int Rp, const int64_t* __restrict__ pstart,
+                                                      const int32_t* __restrict__ pb, const int32_t* __restrict__ pn,
+                                                      const RT* __restrict__ pc, const RT* __restrict__ ps,
+                                                      const double* __restrict__ p, const double* __restrict__ Minv4,
+                                                      double* __restrict__ m, const MultiCtl* __restrict__ ctl) {
+  if (ctl && ctl->running == 0) return;
+  const int lane = lane_id();
+  const int r = lane & (Rp - 1);
+  const int slot = lane / Rp;
+  const int slots = 64 / Rp;
+  const bool act = lane_active(r, R, ctl);
+  const int nS = vc.n_streams;
+  const int oT = vc.rowT * Rp, oQ = vc.rowQ * Rp, oU = vc.rowU * Rp;
+  const double w0 = vc.w[0], w1 = vc.w[1], w2 = vc.w[2];
+  const int64_t n_obs = vc.n_pix;
+  const int64_t nw = (int64_t)gridDim.x * kWaves;
+  for (int64_t c = (int64_t)blockIdx.x * kWaves + (threadIdx.x >> 6); c < n_obs; c += nw) {
+    const int64_t j0 = pstart[c], j1 = pstart[c + 1];
+    double acc[3] = {0.0, 0.0, 0.0};
+    constexpr int U = 2;
+    for (int64_t jb = j0 + slot; jb < j1; jb += (int64_t)slots * U) {
+      int32_t bb[U], nn[U];
+      double C[U], S[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int64_t j = jb + (int64_t)slots * u;
+        const bool in = j < j1;
+        bb[u] = in ? pb[j] : -1;
+        nn[u] = (HAS_T && in) ? pn[j] : 0;
+        C[u] = (HAS_QU && in) ? (double)pc[j] : 0.0;
+        S[u] = (HAS_QU && in) ? (double)ps[j] : 0.0;
+      }
+      if (!act) continue;
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        if (bb[u] < 0) continue;
+        const double* pr = p + (int64_t)bb[u] * nS * Rp + r;
+        if (HAS_T) acc[0] += (double)nn[u] * (w0 * pr[oT]);
+        if (HAS_QU) {
+          const double xq = w1 * pr[oQ], xu = w2 * pr[oU];
+          acc[1] += C[u] * xq - S[u] * xu;
+          acc[2] += S[u] * xq + C[u] * xu;
+        }
+      }
+    }
+    dev::lane_group_sum<3>(acc, Rp);
+    if (slot == 0 && act) {
+      const double2* ip = reinterpret_cast<const double2*>(Minv4 + 4 * c);
+      const double2 i01 = ip[0], i23 = ip[1];
+      double* mo = m + c * nS * Rp + r;
+      if (HAS_T) mo[oT] = i01.x * acc[0];
+      if (HAS_QU) {
+        mo[oQ] = i01.y * acc[1] + i23.x * acc[2];
+        mo[oU] = i23.x * acc[1] + i23.y * acc[2];
+      }
+    }
+  }
+}
+
+// Rescan and baseline sums, one wavefront per baseline, each XCD (workgroup
+// i runs on XCD i mod 8) sweeping a contiguous eighth of the baselines.
+//   OPERATOR / CG:  q = w (n_valid p - sum_runs A . m)  (= K p)
+//   RHS:            q = braw - w sum_runs A . m         (= F^T Z d with m = m_d)
+// CG also writes per-workgroup partials [block][3][Rp] of p.q and of the
+// T-projection sums (q_T and p_T over T-valid baselines).
+template <typename RT, bool HAS_T, bool HAS_QU, int MODE>
+__global__ void __launch_bounds__(kBlock) k_multi_unbin(View vc, int R, int Rp, const uint32_t* __restrict__ bstart,
+                                                        const int32_t* __restrict__ tpix,
+                                                        const int32_t* __restrict__ tn, const RT* __restrict__ tc,
+                                                        const RT* __restrict__ ts, const double* __restrict__ m,
+                                                        const int32_t* __restrict__ nvalid,
+                                                        const double* __restrict__ p, const double* __restrict__ braw,
+                                                        double* __restrict__ q, MultiCtl* __restrict__ ctl,
+                                                        double* __restrict__ partials) {
+  __shared__ double lds[kWaves][3][64];
+  if (MODE == UNBIN_CG && ctl->running == 0) return;
+  const int lane = lane_id();
+  const int wave = threadIdx.x >> 6;
+  const int r = lane & (Rp - 1);
+  const int slot = lane / Rp;
+  const int slots = 64 / Rp;
+  const bool act = lane_active(r, R, MODE == UNBIN_CG ? ctl : nullptr);
+  const int nS = vc.n_streams;
+  const int oT = vc.rowT * Rp, oQ = vc.rowQ * Rp, oU = vc.rowU * Rp;
+  const double w0 = vc.w[0], w1 = vc.w[1], w2 = vc.w[2];
+  const int64_t n_b = vc.n_b;
+  const int64_t per = (n_b + 7) / 8;
+  const int64_t x = blockIdx.x & 7, k = blockIdx.x >> 3, nk = gridDim.x >> 3;
+  const int64_t lo = x * per, hi = std::min(n_b, lo + per);
+  double dots[3] = {0.0, 0.0, 0.0};
+  for (int64_t b = lo + k * kWaves + wave; b < hi; b += nk * kWaves) {
+    const int64_t r0 = bstart[b], r1 = bstart[b + 1];
+    double acc[3] = {0.0, 0.0, 0.0};
+    constexpr int U = 2;
+    for (int64_t jb = r0 + slot; jb < r1; jb += (int64_t)slots * U) {
+      int32_t cc[U], nn[U];
+      double C[U], S[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int64_t j = jb + (int64_t)slots * u;
+        const bool in = j < r1;
+        cc[u] = in ? tpix[j] : -1;
+        nn[u] = (HAS_T && in) ? tn[j] : 0;
+        C[u] = (HAS_QU && in) ? (double)tc[j] : 0.0;
+        S[u] = (HAS_QU && in) ? (double)ts[j] : 0.0;
+      }
+      if (!act) continue;
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        if (cc[u] < 0) continue;
+        const double* mr = m + (int64_t)cc[u] * nS * Rp + r;
+        if (HAS_T) acc[0] += (double)nn[u] * mr[oT];
+        if (HAS_QU) {
+          const double mQ = mr[oQ], mU = mr[oU];
+          acc[1] += C[u] * mQ + S[u] * mU;
+          acc[2] += C[u] * mU - S[u] * mQ;
+        }
+      }
+    }
+    dev::lane_group_sum<3>(acc, Rp);
+    if (slot == 0 && act) {
+      const int64_t o = b * nS * Rp + r;
+      if (MODE == UNBIN_RHS) {
+        if (HAS_T) q[o + oT] = braw[o + oT] - w0 * acc[0];
+        if (HAS_QU) {
+          q[o + oQ] = braw[o + oQ] - w1 * acc[1];
+          q[o + oU] = braw[o + oU] - w2 * acc[2];
+        }
+      } else {
+        const double nT = (double)nvalid[b], nQ = (double)nvalid[n_b + b];
+        if (HAS_T) {
+          const double pv = p[o + oT];
+          const double out = w0 * (pv * nT - acc[0]);
+          q[o + oT] = out;
+          dots[0] += pv * out;
+          if (nT > 0.0) {
+            dots[1] += out;
+            dots[2] += pv;
+          }
+        }
+        if (HAS_QU) {
+          const double pq = p[o + oQ], pu = p[o + oU];
+          const double oq = w1 * (pq * nQ - acc[1]);
+          const double ou = w2 * (pu * nQ - acc[2]);
+          q[o + oQ] = oq;
+          q[o + oU] = ou;
+          dots[0] += pq * oq + pu * ou;
+        }
+      }
+    }
+  }
+  if (MODE == UNBIN_CG) {
+    if (slot == 0) {
+#pragma unroll
+      for (int i = 0; i < 3; ++i) lds[wave][i][r] = dots[i];
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < Rp) {
+      const int t = threadIdx.x;
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        double s = lds[0][i][t];
+        for (int w = 1; w < kWaves; ++w) s += lds[w][i][t];
+        partials[((int64_t)blockIdx.x * 3 + i) * Rp + t] = s;
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------- CG pieces
+
+// Sum over threads with equal (thread mod Rp) in fixed order; the result for
+// realization t sits in lds[i][t], t < Rp.
+template <int N>
+__device__ __forceinline__ void block_sum_by_rhs(double (&v)[N], double (*lds)[kBlock], int Rp) {
+  const int t = threadIdx.x;
+#pragma unroll
+  for (int i = 0; i < N; ++i) lds[i][t] = v[i];
+  __syncthreads();
+  for (int h = kBlock / 2; h >= Rp; h >>= 1) {
+    if (t < h) {
+#pragma unroll
+      for (int i = 0; i < N; ++i) lds[i][t] += lds[i][t + h];
+    }
+    __syncthreads();
+  }
+}
+
+// Sum of per-block partials [n_part][N][Rp] per realization, by one
+// workgroup, in fixed order; the result for realization t sits in lds[i][t].
+template <int N>
+__device__ __forceinline__ void sum_partials_by_rhs(const double* __restrict__ part, int n_part, int Rp,
+                                                    double (*lds)[kBlock]) {
+  const int t = threadIdx.x;
+  const int r = t & (Rp - 1), ch = t / Rp, nch = kBlock / Rp;
+  double s[N];
+#pragma unroll
+  for (int i = 0; i < N; ++i) s[i] = 0.0;
+  for (int blk = ch; blk < n_part; blk += nch) {
+#pragma unroll
+    for (int i = 0; i < N; ++i) s[i] += part[((int64_t)blk * N + i) * Rp + r];
+  }
+  block_sum_by_rhs<N>(s, lds, Rp);
+}
+
+__device__ __forceinline__ bool t_valid(const View& v, int row, int64_t b, const double* J) {
+  return row == v.rowT && J[(int64_t)row * v.n_b + b] > 0.0;
+}
+
+// Per block and realization: sum of x over T-valid baselines and their count.
+__global__ void __launch_bounds__(kBlock) k_multi_tsum(View v, int Rp, const double* __restrict__ x,
+                                                       const double* __restrict__ J, double* __restrict__ partials) {
+  __shared__ double lds[2][kBlock];
+  double acc[2] = {0.0, 0.0};
+  if (v.rowT >= 0) {
+    const int nS = v.n_streams;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < v.n_b * Rp;
+         i += (int64_t)gridDim.x * blockDim.x) {
+      const int64_t b = i / Rp;
+      const int r = (int)(i & (Rp - 1));
+      if (J[v.rowT * v.n_b + b] > 0.0) {
+        acc[0] += x[(b * nS + v.rowT) * Rp + r];
+        acc[1] += 1.0;
+      }
+    }
+  }
+  block_sum_by_rhs<2>(acc, lds, Rp);
+  if ((int)threadIdx.x < Rp) {
+    partials[((int64_t)blockIdx.x * 2 + 0) * Rp + threadIdx.x] = lds[0][threadIdx.x];
+    partials[((int64_t)blockIdx.x * 2 + 1) * Rp + threadIdx.x] = lds[1][threadIdx.x];
+  }
+}
+
+// which = 0: mu_b and n_e (start-up); which = 1: mu (canonicalisation).
+__global__ void __launch_bounds__(kBlock) k_multi_tsum_fin(int n_part, int Rp, MultiCtl* __restrict__ ctl,
+                                                           const double* __restrict__ partials, int which) {
+  __shared__ double lds[2][kBlock];
+  sum_partials_by_rhs<2>(partials, n_part, Rp, lds);
+  const int t = threadIdx.x;
+  if (t < Rp) {
+    const double mean = lds[1][t] > 0.0 ? lds[0][t] / lds[1][t] : 0.0;
+    if (which == 0) {
+      ctl->mu_b[t] = mean;
+      if (t == 0) ctl->n_e = lds[1][0];
+    } else {
+      ctl->mu[t] = mean;
+    }
+  }
+}
+
+// b <- P b;  a = 0;  r = b;  z = J r;  p = z;  per-block partials of r.z, b.b.
+__global__ void __launch_bounds__(kBlock) k_multi_init(View v, int R, int Rp, double* __restrict__ b,
+                                                       double* __restrict__ a, double* __restrict__ r,
+                                                       double* __restrict__ z, double* __restrict__ p,
+                                                       const double* __restrict__ J,
+                                                       const MultiCtl* __restrict__ ctl,
+                                                       double* __restrict__ partials) {
+  __shared__ double lds[2][kBlock];
+  const int nS = v.n_streams;
+  const int64_t N = v.n_b * nS * Rp;
+  const int ri = threadIdx.x & (Rp - 1);
+  const bool real = ri < R;
+  const double mu_b = ctl->mu_b[ri];
+  double acc[2] = {0.0, 0.0};
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t rowb = i / Rp;
+    const int row = (int)(rowb % nS);
+    const int64_t bb = rowb / nS;
+    const double Ji = J[(int64_t)row * v.n_b + bb];
+    double bi = real ? b[i] - (t_valid(v, row, bb, J) ? mu_b : 0.0) : 0.0;
+    b[i] = bi;
+    a[i] = 0.0;
+    r[i] = bi;
+    const double zi = Ji * bi;
+    z[i] = zi;
+    p[i] = zi;
+    acc[0] += bi * zi;
+    acc[1] += bi * bi;
+  }
+  block_sum_by_rhs<2>(acc, lds, Rp);
+  if ((int)threadIdx.x < Rp) {
+    partials[((int64_t)blockIdx.x * 2 + 0) * Rp + threadIdx.x] = lds[0][threadIdx.x];
+    partials[((int64_t)blockIdx.x * 2 + 1) * Rp + threadIdx.x] = lds[1][threadIdx.x];
+  }
+}
+
+__global__ void __launch_bounds__(kBlock) k_multi_init_fin(int n_part, int R, int Rp, MultiCtl* __restrict__ ctl,
+                                                           const double* __restrict__ partials, double tol,
+                                                           int max_iter) {
+  __shared__ double lds[2][kBlock];
+  sum_partials_by_rhs<2>(partials, n_part, Rp, lds);
+  const int t = threadIdx.x;
+  if (t < kMaxRhs) {
+    ctl->iter[t] = 0;
+    ctl->alpha[t] = 0.0;
+    ctl->beta[t] = 0.0;
+    ctl->mu[t] = 0.0;
+    ctl->true_norm[t] = 0.0;
+    if (t >= R) {
+      ctl->rz[t] = ctl->b_norm[t] = ctl->r_norm[t] = 0.0;
+      ctl->done[t] = DONE_PAD;
+    } else {
+      const double rz = lds[0][t], bb = lds[1][t];
+      ctl->rz[t] = rz;
+      ctl->b_norm[t] = sqrt(bb);
+      ctl->r_norm[t] = sqrt(bb);
+      if (!isfinite(rz) || !isfinite(bb))
+        ctl->done[t] = DONE_NAN;
+      else if (bb == 0.0)
+        ctl->done[t] = DONE_CONVERGED;
+      else if (max_iter <= 0)
+        ctl->done[t] = DONE_MAXITER;
+      else
+        ctl->done[t] = DONE_RUNNING;
+    }
+  }
+  __syncthreads();
+  if (t == 0) {
+    int run = 0;
+    for (int i = 0; i < R; ++i) run += ctl->done[i] == DONE_RUNNING;
+    ctl->running = run;
+    ctl->tol = tol;
+    ctl->max_iter = max_iter;
+    ctl->n_rhs = R;
+  }
+}
+
+// alpha_r = r.z / (p.K p) with K p projected on the T null space.
+__global__ void __launch_bounds__(kBlock) k_multi_alpha(int n_part, int Rp, MultiCtl* __restrict__ ctl,
+                                                        const double* __restrict__ partials) {
+  if (ctl->running == 0) return;
+  __shared__ double lds[3][kBlock];
+  sum_partials_by_rhs<3>(partials, n_part, Rp, lds);
+  const int t = threadIdx.x;
+  if (t < Rp && ctl->done[t] == DONE_RUNNING) {
+    const double mu = ctl->n_e > 0.0 ? lds[1][t] / ctl->n_e : 0.0;
+    const double pkp = lds[0][t] - mu * lds[2][t];
+    ctl->mu[t] = mu;
+    if (!isfinite(pkp))
+      ctl->done[t] = DONE_NAN;
+    else if (pkp <= 0.0)
+      ctl->done[t] = DONE_BREAKDOWN;
+    else
+      ctl->alpha[t] = ctl->rz[t] / pkp;
+  }
+}
+
+// a += alpha p;  r -= alpha P q;  z = J r;  per-block partials of r.z and r.r.
+__global__ void __launch_bounds__(kBlock) k_multi_update(View v, int Rp, double* __restrict__ a,
+                                                         double* __restrict__ r, double* __restrict__ z,
+                                                         const double* __restrict__ q, const double* __restrict__ p,
+                                                         const double* __restrict__ J, MultiCtl* __restrict__ ctl,
+                                                         double* __restrict__ partials) {
+  if (ctl->running == 0) return;
+  __shared__ double lds[2][kBlock];
+  const int nS = v.n_streams;
+  const int64_t N = v.n_b * nS * Rp;
+  const int ri = threadIdx.x & (Rp - 1);
+  const bool run = ctl->done[ri] == DONE_RUNNING;
+  const double alpha = ctl->alpha[ri], mu = ctl->mu[ri];
+  double acc[2] = {0.0, 0.0};
+  if (run) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (int64_t)gridDim.x * blockDim.x) {
+      const int64_t rowb = i / Rp;
+      const int row = (int)(rowb % nS);
+      const int64_t bb = rowb / nS;
+      const double Ji = J[(int64_t)row * v.n_b + bb];
+      const double qi = q[i] - ((row == v.rowT && Ji > 0.0) ? mu : 0.0);
+      a[i] += alpha * p[i];
+      const double rr = r[i] - alpha * qi;
+      r[i] = rr;
+      const double zz = Ji * rr;
+      z[i] = zz;
+      acc[0] += rr * zz;
+      acc[1] += rr * rr;
+    }
+  }
+  block_sum_by_rhs<2>(acc, lds, Rp);
+  if ((int)threadIdx.x < Rp) {
+    partials[((int64_t)blockIdx.x * 2 + 0) * Rp + threadIdx.x] = lds[0][threadIdx.x];
+    partials[((int64_t)blockIdx.x * 2 + 1) * Rp + threadIdx.x] = lds[1][threadIdx.x];
+  }
+}
+
+// Stopping test per realization and beta = r'.z' / r.z.
+__global__ void __launch_bounds__(kBlock) k_multi_beta(int n_part, int Rp, MultiCtl* __restrict__ ctl,
+                                                       const double* __restrict__ partials) {
+  if (ctl->running == 0) return;
+  __shared__ double lds[2][kBlock];
+  sum_partials_by_rhs<2>(partials, n_part, Rp, lds);
+  const int t = threadIdx.x;
+  if (t < Rp && ctl->done[t] == DONE_RUNNING) {
+    const double rz_new = lds[0][t];
+    const double rn = sqrt(lds[1][t]);
+    const int it = ctl->iter[t] + 1;
+    ctl->iter[t] = it;
+    ctl->r_norm[t] = rn;
+    if (!isfinite(rz_new) || !isfinite(rn))
+      ctl->done[t] = DONE_NAN;
+    else if (rn <= ctl->tol * ctl->b_norm[t])
+      ctl->done[t] = DONE_CONVERGED;
+    else if (it >= ctl->max_iter)
+      ctl->done[t] = DONE_MAXITER;
+    else {
+      ctl->beta[t] = rz_new / ctl->rz[t];
+      ctl->rz[t] = rz_new;
+    }
+  }
+  __syncthreads();
+  if (t == 0) {
+    int run = 0;
+    for (int i = 0; i < ctl->n_rhs; ++i) run += ctl->done[i] == DONE_RUNNING;
+    ctl->running = run;
+  }
+}
+
+__global__ void __launch_bounds__(kBlock) k_multi_p(int64_t N, int Rp, double* __restrict__ p,
+                                                    const double* __restrict__ z, const MultiCtl* __restrict__ ctl) {
+  if (ctl->running == 0) return;
+  const int ri = threadIdx.x & (Rp - 1);
+  if (ctl->done[ri] != DONE_RUNNING) return;
+  const double beta = ctl->beta[ri];
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = z[i] + beta * p[i];
+}
+
+__global__ void __launch_bounds__(kBlock) k_multi_canon_apply(View v, int Rp, double* __restrict__ a,
+                                                              const double* __restrict__ J,
+                                                              const MultiCtl* __restrict__ ctl) {
+  if (v.rowT < 0) return;
+  const int nS = v.n_streams;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < v.n_b * Rp;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t b = i / Rp;
+    const int r = (int)(i & (Rp - 1));
+    const int64_t o = (b * nS + v.rowT) * Rp + r;
+    a[o] = J[v.rowT * v.n_b + b] > 0.0 ? a[o] - ctl->mu[r] : 0.0;
+  }
+}
+
+// Per block and realization, x = b - K a: sum of x^2 and sum of x over T-valid rows.
+__global__ void __launch_bounds__(kBlock) k_multi_resid(View v, int Rp, const double* __restrict__ b,
+                                                        const double* __restrict__ ka, const double* __restrict__ J,
+                                                        double* __restrict__ partials) {
+  __shared__ double lds[2][kBlock];
+  const int nS = v.n_streams;
+  const int64_t N = v.n_b * nS * Rp;
+  double acc[2] = {0.0, 0.0};
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t rowb = i / Rp;
+    const int row = (int)(rowb % nS);
+    const int64_t bb = rowb / nS;
+    const double x = b[i] - ka[i];
+    acc[0] += x * x;
+    if (t_valid(v, row, bb, J)) acc[1] += x;
+  }
+  block_sum_by_rhs<2>(acc, lds, Rp);
+  if ((int)threadIdx.x < Rp) {
+    partials[((int64_t)blockIdx.x * 2 + 0) * Rp + threadIdx.x] = lds[0][threadIdx.x];
+    partials[((int64_t)blockIdx.x * 2 + 1) * Rp + threadIdx.x] = lds[1][threadIdx.x];
+  }
+}
+
+// ||P x||^2 = sum x^2 - n_e mean_T(x)^2.
+__global__ void __launch_bounds__(kBlock) k_multi_resid_fin(int n_part, int Rp, MultiCtl* __restrict__ ctl,
+                                                            const double* __restrict__ partials) {
+  __shared__ double lds[2][kBlock];
+  sum_partials_by_rhs<2>(partials, n_part, Rp, lds);
+  const int t = threadIdx.x;
+  if (t < Rp) {
+    const double n_e = ctl->n_e;
+    const double s2 = lds[0][t] - (n_e > 0.0 ? lds[1][t] * lds[1][t] / n_e : 0.0);
+    ctl->true_norm[t] = sqrt(s2 > 0.0 ? s2 : 0.0);
+  }
+}
+
+__global__ void __launch_bounds__(kBlock) k_multi_extract(View v, int Rp, int ri, const double* __restrict__ x,
+                                                          double* __restrict__ out) {
+  const int nS = v.n_streams;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nS * v.n_b;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t row = i / v.n_b, b = i - row * v.n_b;
+    out[i] = x[(b * nS + row) * Rp + ri];
+  }
+}
+
+__global__ void __launch_bounds__(kBlock) k_multi_scatter(int64_t n_pix, View vc, const int32_t* __restrict__ cid,
+                                                          int Rp, int ri, const double* __restrict__ md,
+                                                          const double* __restrict__ m, double* __restrict__ out3) {
+  const int nS = vc.n_streams;
+  const int rows[3] = {vc.rowT, vc.rowQ, vc.rowU};
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_pix; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t c = cid[i];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      double val = 0.0;
+      if (c >= 0 && rows[k] >= 0) {
+        const int64_t o = (c * nS + rows[k]) * Rp + ri;
+        val = md[o] - (m ? m[o] : 0.0);
+      }
+      out3[3 * i + k] = val;
+    }
+  }
+}
+
+// ---------------------------------------------------------------- dispatch
+
+template <typename T>
+struct type_tag {
+  using type = T;
+};
+template <typename F>
+void by_float(bool f32, F&& f) {
+  if (f32)
+    f(type_tag<float>{});
+  else
+    f(type_tag<double>{});
+}
+template <typename F>
+void by_streams(const View& v, F&& f) {
+  if (v.rowT >= 0 && v.rowQ >= 0)
+    f(std::true_type{}, std::true_type{});
+  else if (v.rowQ >= 0)
+    f(std::false_type{}, std::true_type{});
+  else
+    f(std::true_type{}, std::false_type{});
+}
+
+unsigned grid_for(int64_t n, int64_t per_block, int64_t cap) {
+  int64_t g = (n + per_block - 1) / per_block;
+  return (unsigned)std::max<int64_t>(1, std::min(g, cap));
+}
+
+constexpr int kTsumBlocks = 256;
+
+}  // namespace
+
+int multi_padded(int R) {
+  int Rp = 1;
+  while (Rp < R) Rp <<= 1;
+  return Rp;
+}
+
+hipError_t launch_run_positions(const Runs& W, uint32_t* ipos, hipStream_t st) {
+  hipLaunchKernelGGL(k_run_positions, dim3(grid_for(W.n_obs, kWaves, 16384)), dim3(kBlock), 0, st, W.n_obs, W.order,
+                     W.seg, W.rperm, W.pstart, ipos);
+  return hipGetLastError();
+}
+
+hipError_t launch_multi_tod(const View& vc, int psi_f32, const void* tod, int tod_f32, const Runs& W,
+                            const uint32_t* ipos, const uint8_t* valid, int Rp, int ri, double* prs, double* braw,
+                            hipStream_t st) {
+  const unsigned g = grid_for(vc.n_b, kWaves, INT32_MAX);
+  by_float(psi_f32, [&](auto pt) {
+    using PT = typename decltype(pt)::type;
+    by_float(tod_f32, [&](auto tt) {
+      using TT = typename decltype(tt)::type;
+      by_streams(vc, [&](auto T, auto Q) {
+        hipLaunchKernelGGL((k_multi_tod<PT, TT, decltype(T)::value, decltype(Q)::value>), dim3(g), dim3(kBlock), 0,
+                           st, vc, static_cast<const TT*>(tod), W.bstart, W.t0, W.tpix, W.tn, ipos, valid, Rp, ri,
+                           prs, braw);
+      });
+    });
+  });
+  return hipGetLastError();
+}
+
+hipError_t launch_multi_pixsum(int64_t n_obs, const View& vc, const Runs& W, const double* prs, const double* Minv4,
+                               int Rp, int ri, double* md, hipStream_t st) {
+  hipLaunchKernelGGL(k_multi_pixsum, dim3(grid_for(n_obs, kWaves, 16384)), dim3(kBlock), 0, st, n_obs, vc, W.pstart,
+                     prs, Minv4, Rp, ri, md);
+  return hipGetLastError();
+}
+
+hipError_t launch_multi_bin(const View& vc, const Runs& W, const Multi& mu, const double* p, const double* Minv4,
+                            double* m, const MultiCtl* ctl, hipStream_t st) {
+  const unsigned g = grid_for(vc.n_pix, kWaves, 16384);
+  by_float(W.f32, [&](auto rt) {
+    using RT = typename decltype(rt)::type;
+    by_streams(vc, [&](auto T, auto Q) {
+      hipLaunchKernelGGL((k_multi_bin<RT, decltype(T)::value, decltype(Q)::value>), dim3(g), dim3(kBlock), 0, st,
+                         vc, mu.R, mu.Rp, W.pstart, W.pb, W.pn, static_cast<const RT*>(W.pc),
+                         static_cast<const RT*>(W.ps), p, Minv4, m, ctl);
+    });
+  });
+  return hipGetLastError();
+}
+
+int multi_unbin_blocks(const View& vc) {
+  const int64_t per = (vc.n_b + 7) / 8;
+  const int64_t g = std::max<int64_t>(1, std::min<int64_t>((per + kWaves - 1) / kWaves, 256));
+  return (int)(8 * g);
+}
+
+hipError_t launch_multi_unbin(const View& vc, const Runs& W, const Multi& mu, int mode, const double* m,
+                              const int32_t* nvalid, const double* p, const double* braw, double* q, MultiCtl* ctl,
+                              double* partials, hipStream_t st) {
+  const unsigned g = (unsigned)multi_unbin_blocks(vc);
+  by_float(W.f32, [&](auto rt) {
+    using RT = typename decltype(rt)::type;
+    by_streams(vc, [&](auto T, auto Q) {
+      constexpr bool HT = decltype(T)::value, HQ = decltype(Q)::value;
+      auto launch = [&](auto kern) {
+        hipLaunchKernelGGL(kern, dim3(g), dim3(kBlock), 0, st, vc, mu.R, mu.Rp, W.bstart, W.tpix, W.tn,
+                           static_cast<const RT*>(W.tc), static_cast<const RT*>(W.ts), m, nvalid, p, braw, q, ctl,
+                           partials);
+      };
+      if (mode == UNBIN_CG)
+        launch(k_multi_unbin<RT, HT, HQ, UNBIN_CG>);
+      else if (mode == UNBIN_RHS)
+        launch(k_multi_unbin<RT, HT, HQ, UNBIN_RHS>);
+      else
+        launch(k_multi_unbin<RT, HT, HQ, UNBIN_OPERATOR>);
+    });
+  });
+  return hipGetLastError();
+}
+
+int multi_update_blocks(const View& v, const Multi& mu) {
+  return (int)grid_for((int64_t)v.n_b * v.n_streams * mu.Rp, kBlock, 1024);
+}
+
+hipError_t launch_multi_start(const View& v, const Multi& mu, double* b, double* a, double* r, double* z, double* p,
+                              const double* J, MultiCtl* ctl, double* partials, double tol, int max_iter,
+                              hipStream_t st) {
+  const unsigned gt = grid_for((int64_t)v.n_b * mu.Rp, kBlock, kTsumBlocks);
+  hipLaunchKernelGGL(k_multi_tsum, dim3(gt), dim3(kBlock), 0, st, v, mu.Rp, b, J, partials);
+  hipLaunchKernelGGL(k_multi_tsum_fin, dim3(1), dim3(kBlock), 0, st, (int)gt, mu.Rp, ctl, partials, 0);
+  const unsigned gu = (unsigned)multi_update_blocks(v, mu);
+  hipLaunchKernelGGL(k_multi_init, dim3(gu), dim3(kBlock), 0, st, v, mu.R, mu.Rp, b, a, r, z, p, J, ctl, partials);
+  hipLaunchKernelGGL(k_multi_init_fin, dim3(1), dim3(kBlock), 0, st, (int)gu, mu.R, mu.Rp, ctl, partials, tol,
+                     max_iter);
+  return hipGetLastError();
+}
+
+hipError_t launch_multi_alpha(const View& vc, const Multi& mu, MultiCtl* ctl, const double* partials,
+                              hipStream_t st) {
+  hipLaunchKernelGGL(k_multi_alpha, dim3(1), dim3(kBlock), 0, st, multi_unbin_blocks(vc), mu.Rp, ctl, partials);
+  return hipGetLastError();
+}
+
+hipError_t launch_multi_update(const View& v, const Multi& mu, double* a, double* r, double* z, const double* q,
+                               const double* p, const double* J, MultiCtl* ctl, double* partials, hipStream_t st) {
+  hipLaunchKernelGGL(k_multi_update, dim3(multi_update_blocks(v, mu)), dim3(kBlock), 0, st, v, mu.Rp, a, r, z, q, p,
+                     J, ctl, partials);
+  return hipGetLastError();
+}
+
+hipError_t launch_multi_beta(const View& v, const Multi& mu, MultiCtl* ctl, const double* partials, hipStream_t st) {
+  hipLaunchKernelGGL(k_multi_beta, dim3(1), dim3(kBlock), 0, st, multi_update_blocks(v, mu), mu.Rp, ctl, partials);
+  return hipGetLastError();
+}
+
+hipError_t launch_multi_p(const View& v, const Multi& mu, double* p, const double* z, const MultiCtl* ctl,
+                          hipStream_t st) {
+  const int64_t N = (int64_t)v.n_b * v.n_streams * mu.Rp;
+  hipLaunchKernelGGL(k_multi_p, dim3(grid_for(N, kBlock, 2048)), dim3(kBlock), 0, st, N, mu.Rp, p, z, ctl);
+  return hipGetLastError();
+}
+
+hipError_t launch_multi_canonicalise(const View& v, const Multi& mu, double* a, const double* J, MultiCtl* ctl,
+                                     double* partials, hipStream_t st) {
+  const unsigned gt = grid_for((int64_t)v.n_b * mu.Rp, kBlock, kTsumBlocks);
+  hipLaunchKernelGGL(k_multi_tsum, dim3(gt), dim3(kBlock), 0, st, v, mu.Rp, a, J, partials);
+  hipLaunchKernelGGL(k_multi_tsum_fin, dim3(1), dim3(kBlock), 0, st, (int)gt, mu.Rp, ctl, partials, 1);
+  hipLaunchKernelGGL(k_multi_canon_apply, dim3(gt), dim3(kBlock), 0, st, v, mu.Rp, a, J, ctl);
+  return hipGetLastError();
+}
+
+hipError_t launch_multi_resid(const View& v, const Multi& mu, const double* b, const double* ka, const double* J,
+                              MultiCtl* ctl, double* partials, hipStream_t st) {
+  const unsigned g = (unsigned)multi_update_blocks(v, mu);
+  hipLaunchKernelGGL(k_multi_resid, dim3(g), dim3(kBlock), 0, st, v, mu.Rp, b, ka, J, partials);
+  hipLaunchKernelGGL(k_multi_resid_fin, dim3(1), dim3(kBlock), 0, st, (int)g, mu.Rp, ctl, partials);
+  return hipGetLastError();
+}
+
+hipError_t launch_multi_extract(const View& v, const Multi& mu, int ri, const double* x, double* out,
+                                hipStream_t st) {
+  hipLaunchKernelGGL(k_multi_extract, dim3(grid_for((int64_t)v.n_b * v.n_streams, kBlock, 4096)), dim3(kBlock), 0,
+                     st, v, mu.Rp, ri, x, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_multi_scatter(const View& full, const View& vc, const int32_t* cid, const Multi& mu, int ri,
+                                const double* md, const double* m, double* out3, hipStream_t st) {
+  hipLaunchKernelGGL(k_multi_scatter, dim3(grid_for(full.n_pix, kBlock, 8192)), dim3(kBlock), 0, st, full.n_pix, vc,
+                     cid, mu.Rp, ri, md, m, out3);
+  return hipGetLastError();
+}
+
+}  // namespace dst

@@ -29,7 +29,7 @@ DST_BIN_USE_TOD, DST_BIN_MAP = 1, 2
 DST_SOLVE_NO_CANON, DST_SOLVE_PROFILE, DST_SOLVE_NO_GRAPH, DST_SOLVE_PER_SAMPLE = 1, 2, 4, 8
 
 EXPORTS = ("dst_version", "dst_create", "dst_destroy", "dst_last_error", "dst_pixel_setup", "dst_bin", "dst_unbin",
-           "dst_baseline_reduce", "dst_residual", "dst_apply_operator", "dst_solve")
+           "dst_baseline_reduce", "dst_residual", "dst_apply_operator", "dst_solve", "dst_solve_batched")
 
 
 class dst_problem(ctypes.Structure):
@@ -89,6 +89,8 @@ def library(path: str = LIB_PATH) -> ctypes.CDLL:
         "dst_apply_operator": ([vp, P, vp, vp, vp], i32),
         "dst_solve": ([vp, P, ctypes.POINTER(dst_solve_opts), vp, vp, vp, vp, ctypes.POINTER(dst_solve_info), vp],
                       i32),
+        "dst_solve_batched": ([vp, i32, P, ctypes.POINTER(dst_solve_opts), vp, vp, vp, vp,
+                               ctypes.POINTER(dst_solve_info), vp], i32),
     }
     for name, (argtypes, restype) in sig.items():
         fn = getattr(lib, name)
@@ -293,3 +295,53 @@ def dst_solve(ctx: Context, prob: Problem, tol: float = 1e-10, max_iter: int = 1
     out["n_valid_samples"] = tuple(info.n_valid_samples)
     out.update(status=rc, baselines=a, destriped_map=m, binned_map=mb, hits=hits)
     return out
+
+
+def _info_dict(info) -> dict:
+    out = {k: getattr(info, k) for k, _ in dst_solve_info._fields_}
+    out["n_valid_pix"] = tuple(info.n_valid_pix)
+    out["n_valid_samples"] = tuple(info.n_valid_samples)
+    return out
+
+
+def dst_solve_batched(ctx: Context, probs, tol: float = 1e-10, max_iter: int = 1000, flags: int = 0,
+                      check_every: int = 0, maps: bool = True, allow_noconv: bool = True):
+    """Destripe a list of problems in one call; problems sharing pix/psi/weights are solved together.
+
+    Returns (status, [dict per problem]) with the keys of ``dst_solve``'s result.
+    """
+    import torch
+    n = len(probs)
+    structs = (dst_problem * n)(*[p.c_struct() for p in probs])
+    outs = []
+    for p in probs:
+        dev = p.pix.device
+        outs.append(dict(
+            baselines=_empty((p.n_streams, p.n_baselines), torch.float64, dev),
+            destriped_map=_empty((p.n_pix, 3), torch.float64, dev) if maps else None,
+            binned_map=_empty((p.n_pix, 3), torch.float64, dev) if maps else None,
+            hits=_empty((p.n_pix,), torch.int32, dev)))
+
+    def ptrs(key):
+        if not maps and key in ("destriped_map", "binned_map"):
+            return None
+        return (ctypes.c_void_p * n)(*[o[key].data_ptr() for o in outs])
+
+    opts = dst_solve_opts()
+    opts.tol = tol
+    opts.max_iter = max_iter
+    opts.check_every = check_every
+    opts.flags = flags
+    opts.reserved = 0
+    opts.a0 = None
+    infos = (dst_solve_info * n)()
+    allow = (DST_OK, DST_ENOCONV) if allow_noconv else (DST_OK,)
+    b, m, mb, h = ptrs("baselines"), ptrs("destriped_map"), ptrs("binned_map"), ptrs("hits")
+    rc = ctx.check(ctx.lib.dst_solve_batched(ctx.handle, n, structs, ctypes.byref(opts), b, m, mb, h, infos,
+                                             _stream()), allow)
+    res = []
+    for o, info in zip(outs, infos):
+        d = _info_dict(info)
+        d.update(o)
+        res.append(d)
+    return rc, res
