@@ -16,6 +16,12 @@ Workloads (seeded synthetic inputs, see ``synth``):
   0: 6 h = 1,080,000 samples at N_side 64, same scan and noise, FP64.
   2: workload 1 with FP32 timelines and angles (FP64 accumulation and CG).
 
+With workload 1 the line also carries the FP32 mixed-precision form and the
+batched Monte Carlo form (``dst_solve_batched``): 32 noise realizations
+(white 1 mK + 1/f, f_k 50 mHz, alpha 1.7, drawn on the GPU) of the same sky
+over the shared 30-day pointing, FP32 timelines and angles, solved together;
+its throughput is realizations x samples x CG-iterations per second.
+
 Prints one JSON line on stdout; progress goes to stderr.
 """
 from __future__ import annotations
@@ -70,29 +76,101 @@ def algorithmic_bytes(n_t: int, n_obs: int, n_b: int, s_psi: int, n_runs: int = 
     return out
 
 
-def cpu_baseline(p, seconds_target: float = 20.0) -> dict:
-    """The oracle's operator on the first day of the workload, single-threaded NumPy."""
+def cpu_baseline(p, seconds_target: float = 15.0) -> dict:
+    """The oracle's operator on the first day of the workload, NumPy FP64 on one host thread."""
     import numpy as np
+    from threadpoolctl import threadpool_limits
 
     from oracle import destripe as O
 
     n = min(p.n_samples, 4_320_000)
     sl = slice(0, n)
     psi = None if p.psi is None else np.asarray(p.psi[sl], dtype=np.float64)
-    st = O.prepare(p.pix[sl], psi, p.n_pix, p.baseline_length, p.streams, p.weights)
-    v = np.random.default_rng(0).standard_normal((3, st.pt.n_b))
-    iters = 0
-    t0 = time.perf_counter()
-    while True:
-        O.apply_K(st, v)
-        iters += 1
-        el = time.perf_counter() - t0
-        if el > seconds_target or iters >= 8:
-            break
+    with threadpool_limits(limits=1):
+        st = O.prepare(p.pix[sl], psi, p.n_pix, p.baseline_length, p.streams, p.weights)
+        v = np.random.default_rng(0).standard_normal((3, st.pt.n_b))
+        iters = 0
+        t0 = time.perf_counter()
+        while True:
+            O.apply_K(st, v)
+            iters += 1
+            el = time.perf_counter() - t0
+            if el > seconds_target or iters >= 400:
+                break
     return {"value": n * iters / el, "unit": "samples*CG-iters/s", "cores": 1, "kind": "oracle",
             "sample": (f"first {n:,} samples (1 day) of the same workload; {iters} applications of the oracle's "
-                       f"K = F^T Z F (one CG iteration each), NumPy FP64 single-threaded, after its setup; "
+                       f"K = F^T Z F (one CG iteration each), NumPy FP64 on one thread, after its setup; "
                        f"{el:.1f} s")}
+
+
+def batched_form(ctx, p, dp, n_real: int, tol: float, steps: int, warmup: int, plain_value: float) -> dict:
+    """Monte Carlo batch: n_real realizations sharing dp's pointing, FP32 timelines, one batched solve."""
+    import numpy as np
+    import torch
+
+    from paper_1309_5609_amd import dst
+    from synth import signal_timelines
+    from synth.noise import one_over_f_torch
+
+    n = p.n_samples
+    sigma, fk, alpha = 1e-3, 0.05, 1.7
+    t = time.perf_counter()
+    sig = np.zeros((3, n))
+    signal_timelines(p.sky, p.pix, p.psi, "TQU", sig)
+    sig_d = torch.from_numpy(sig).to("cuda")
+    del sig
+    tods, tod0 = [], torch.empty((3, n), dtype=torch.float64, device="cuda")
+    for r in range(n_real):
+        x32 = torch.empty((3, n), dtype=torch.float32, device="cuda")
+        for k in range(3):
+            g = torch.Generator(device="cuda")
+            g.manual_seed(1309_5609_000 + 3 * r + k)
+            x = sig_d[k] + one_over_f_torch(g, n, 50.0, sigma, fk, alpha)
+            x32[k] = x.float()
+            if r == 0:
+                tod0[k] = x32[k].double()
+            del x
+        tods.append(x32)
+    del sig_d
+    torch.cuda.synchronize()
+    log(f"batched form: {n_real} realizations drawn in {time.perf_counter() - t:.1f} s")
+    psi32 = dp.psi.float()
+    probs = [dst.Problem(dp.pix, psi32, x, dp.n_pix, dp.baseline_length, dp.streams, dp.weights) for x in tods]
+    for _ in range(max(warmup, 1)):
+        dst.dst_solve_batched(ctx, probs, tol=tol, max_iter=2000, maps=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = None
+    its = 0
+    for _ in range(steps):
+        _, res = dst.dst_solve_batched(ctx, probs, tol=tol, max_iter=2000)
+        its += sum(r["iterations"] for r in res)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    value = n * its / wall
+    _, prof = dst.dst_solve_batched(ctx, probs, tol=tol, max_iter=2000, flags=dst.DST_SOLVE_PROFILE, maps=False)
+    # equal map accuracy: realization 0 in FP64 (the FP32 timelines promoted) by the plain FP64 solve
+    ref = dst.dst_solve(ctx, dst.Problem(dp.pix, dp.psi, tod0, dp.n_pix, dp.baseline_length, dp.streams,
+                                         dp.weights), tol=tol, max_iter=2000)
+    obs = ref["hits"].cpu().numpy() > 0
+    m64 = ref["destriped_map"].cpu().numpy()[obs]
+    m32 = res[0]["destriped_map"].cpu().numpy()[obs]
+    sky = p.sky[obs]
+    ratio = [float(np.sqrt(np.mean((m32[:, c] - sky[:, c]) ** 2)) / np.sqrt(np.mean((m64[:, c] - sky[:, c]) ** 2)))
+             for c in range(3)]
+    out = {"value": value, "unit": "realizations*samples*CG-iters/s", "n_realizations": n_real,
+           "ms_per_solve": wall * 1e3 / steps, "setup_ms": res[0]["t_setup_ms"],
+           "iter_ms": res[0]["t_iter_ms"], "iterations": [r["iterations"] for r in res],
+           "kernel_ms": {k: prof[0][f"t_{k}_ms"] for k in ("bin", "unbin", "update")},
+           "vs_plain_fp64": value / plain_value,
+           "map_rms_error_ratio_vs_fp64": ratio,
+           "dtype": "f32 timelines and angles, f64 accumulation / inverse / CG",
+           "inputs": ("sky signal of the 30-day workload + per-realization white 1 mK and 1/f noise "
+                      "(f_k 50 mHz, alpha 1.7) drawn on the GPU by FFT filtering")}
+    del probs, tods, tod0, res, prof, ref
+    torch.cuda.empty_cache()
+    log(f"batched form: {value:.3e} realizations*samples*iters/s ({out['vs_plain_fp64']:.2f}x plain FP64)")
+    return out
 
 
 def main() -> int:
@@ -104,6 +182,7 @@ def main() -> int:
     ap.add_argument("--fknee", type=float, default=0.05)
     ap.add_argument("--tol", type=float, default=1e-10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--realizations", type=int, default=32, help="batch size of the Monte Carlo form (0: skip)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a 1 GiB device copy (reference kernel for HBM counters)")
     args = ap.parse_args()
@@ -188,6 +267,10 @@ def main() -> int:
         del dp32
         log(f"mixed form: {mixed['value']:.3e} samples*iters/s")
 
+    batched = None
+    if args.workload == 1 and args.realizations > 0:
+        batched = batched_form(ctx, p, dp, args.realizations, args.tol, args.steps, args.warmup, value)
+
     # the per-sample form of the same solve, for comparison with the per-sample byte model
     log("per-sample form: one profiled solve")
     ps = dst.dst_solve(ctx, dp, tol=args.tol, max_iter=2000,
@@ -222,6 +305,7 @@ def main() -> int:
                             "dominant": ps_dom, "achieved_GBs": ps_ach, "frac": ps_ach / HBM_PEAK_GBS},
         "n_runs": n_runs,
         "mixed_form": mixed,
+        "batched_form": batched,
         "iterations_per_solve": r0["iterations"],
         "iter_ms": iter_ms,
         "iteration_throughput": p.n_samples / (iter_ms * 1e-3),

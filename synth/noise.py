@@ -50,3 +50,25 @@ def segmented(seed_words, n: int, segment: int, sample_rate_hz: float, sigma: fl
         rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence(list(seed_words) + [j])))
         out[s0:s1] = one_over_f(rng, s1 - s0, sample_rate_hz, sigma, fknee_hz, alpha)
     return out
+
+
+def one_over_f_torch(gen, n: int, sample_rate_hz: float, sigma: float, fknee_hz: float, alpha: float,
+                     device="cuda"):
+    """``one_over_f`` on a torch device (same spectrum, torch's generator ``gen``).
+
+    Used where many long realizations are needed at once (the batched Monte
+    Carlo benchmark); the draws differ from the NumPy generator's, the
+    recipe and spectrum are the same.  Returns float64 on ``device``.
+    """
+    import torch
+    w = torch.randn(n, generator=gen, dtype=torch.float64, device=device) * sigma
+    if fknee_hz <= 0.0 or n < 2:
+        return w
+    spec = torch.fft.rfft(w)
+    del w
+    f = torch.fft.rfftfreq(n, d=1.0 / sample_rate_hz, dtype=torch.float64, device=device)
+    gain = torch.ones_like(f)
+    gain[1:] = torch.sqrt(1.0 + (fknee_hz / f[1:]) ** alpha)
+    spec *= gain
+    del gain, f
+    return torch.fft.irfft(spec, n=n)

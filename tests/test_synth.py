@@ -120,3 +120,23 @@ def test_problem_reproducible_and_signal_only():
     assert np.allclose(s.tod[0], sky[:, 0], rtol=0, atol=1e-18)
     assert np.allclose(s.tod[1], sky[:, 1] * c + sky[:, 2] * sn, rtol=0, atol=1e-18)
     assert np.allclose(s.tod[2], -sky[:, 1] * sn + sky[:, 2] * c, rtol=0, atol=1e-18)
+
+
+def test_one_over_f_torch_spectrum():
+    """The torch generator follows the same spectrum: band powers / (sigma^2 (1 + (f_k/f)^alpha)) near 1."""
+    import torch
+    from synth.noise import one_over_f_torch
+    n, fs, sigma, fk, alpha = 2 ** 18, 50.0, 1e-3, 0.5, 1.7
+    acc = np.zeros(n // 2 + 1)
+    for s in range(8):
+        g = torch.Generator(device="cpu")
+        g.manual_seed(100 + s)
+        x = one_over_f_torch(g, n, fs, sigma, fk, alpha, device="cpu").numpy()
+        acc += np.abs(np.fft.rfft(x)) ** 2 / n
+    acc /= 8
+    f = np.fft.rfftfreq(n, 1.0 / fs)
+    model = sigma ** 2 * (1.0 + (fk / f[1:]) ** alpha)
+    ratio = acc[1:] / model
+    for lo, hi in ((0.01, 0.1), (0.1, 1.0), (1.0, 10.0), (10.0, 25.0)):
+        band = (f[1:] >= lo) & (f[1:] < hi)
+        assert abs(ratio[band].mean() - 1.0) < 0.1, (lo, hi, ratio[band].mean())
