@@ -38,6 +38,28 @@ if ROOT not in sys.path:
 
 METRIC = "samples x CG-iters/s per GPU (FP64 plain vs FP32-mixed batched); HBM GB/s % of peak"
 HBM_PEAK_GBS = 8000.0
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "runs_30day_nside256_hbm_traffic.md")
+RUN_KERNELS_SRC = os.path.join(ROOT, "paper_1309_5609_amd", "csrc", "dst_runs.hip")
+
+
+def measured_traffic(kernel: str):
+    """HBM bytes per dispatch of ``kernel`` from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE summary.
+
+    None when the summary is missing, has no row for the kernel, or was taken
+    on a different kernel source than the one built now.
+    """
+    import hashlib
+    try:
+        text = open(TRAFFIC_PROFILE).read()
+        sha = hashlib.sha256(open(RUN_KERNELS_SRC, "rb").read()).hexdigest()
+    except OSError:
+        return None
+    if f"sha256 {sha}" not in text:
+        return None
+    for line in text.splitlines():
+        if line.startswith(f"| `{kernel}` |"):
+            return float(line.split("|")[5])
+    return None
 
 
 def log(msg: str) -> None:
@@ -241,6 +263,9 @@ def main() -> int:
     k_ms = {k: float(np.mean([r[f"t_{k}_ms"] for r in runs])) for k in ("bin", "apply", "unbin", "update")}
     dom = max(("bin", "unbin"), key=lambda k: k_ms[k])
     dom_bytes = algo[f"{dom}_runs"]
+    rt = "float" if args.workload == 2 else "double"
+    dom_kernel = {"bin": f"k_bin_runs<{rt}, true, true, 32>", "unbin": f"k_unbin_runs<{rt}, true, true, true, 1>"}[dom]
+    traffic = measured_traffic(dom_kernel)
     achieved = dom_bytes / (k_ms[dom] * 1e-3) / 1e9
     iter_ms = float(np.mean([r["t_iter_ms"] for r in runs]))
     b_iter = algo["bin_samples"] + algo["unbin_samples"]
@@ -295,8 +320,8 @@ def main() -> int:
         "config": {"workload": workload_name(args.workload, args.fknee), "n_samples": p.n_samples,
                    "n_pix": p.n_pix, "baseline_length": p.baseline_length, "n_baselines": p.n_baselines,
                    "streams": p.streams, "tol": args.tol, "parallelism": "1 GPU"},
-        "roofline": {"bound": "hbm", "kernel": f"{dom}_runs", "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+        "roofline": {"bound": "hbm", "kernel": dom_kernel, "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "algorithmic_bytes_per_launch": dom_bytes, "avg_launch_ms": k_ms[dom]},
         "per_sample_model": {"bytes_per_iteration": b_iter,
                              "equivalent_GBs": b_iter / (iter_ms * 1e-3) / 1e9,

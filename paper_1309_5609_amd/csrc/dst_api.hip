@@ -9,6 +9,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <algorithm>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <unordered_map>
@@ -35,6 +36,8 @@ struct dst_ctx {
   int* err_host = nullptr;    // pinned mirror of the device error flag
   dst::MultiCtl* mctl_host = nullptr;  // pinned mirror of the batched CG state
   hipStream_t cap = nullptr;  // private stream on which iteration graphs are captured
+  int unbin_wpb = 1;          // launch shape of the run rescan (wavefronts per baseline)
+  int bin_lpp = 32;           // launch shape of the run binning (lanes per pixel)
 };
 
 namespace {
@@ -411,7 +414,7 @@ int build_plan(dst_ctx* ctx, const dst_problem* prob, Plan& P, const void* tod, 
 int plan_bin(dst_ctx* ctx, Plan& P, const CgCtl* gate, hipStream_t st) {
   Setup& S = P.S;
   if (P.runs)
-    HIP_TRY(dst::launch_bin_runs(S.v, P.W, P.pw4, S.Minv4, S.valid, P.m4, gate, st));
+    HIP_TRY(dst::launch_bin_runs(S.v, P.W, P.pw4, S.Minv4, S.valid, P.m4, gate, ctx->bin_lpp, st));
   else
     HIP_TRY(dst::launch_bin_pixel(S.v, S.psi_f32, P.T, P.pw4, S.Minv4, S.valid, P.m4, gate, st));
   return DST_OK;
@@ -420,7 +423,7 @@ int plan_bin(dst_ctx* ctx, Plan& P, const CgCtl* gate, hipStream_t st) {
 int plan_unbin(dst_ctx* ctx, Plan& P, const double* p, double* q, CgCtl* ctl, double* partials, hipStream_t st) {
   Setup& S = P.S;
   if (P.runs)
-    HIP_TRY(dst::launch_unbin_runs(S.v, P.W, P.m4, S.nvalid, p, q, ctl, partials, st));
+    HIP_TRY(dst::launch_unbin_runs(S.v, P.W, P.m4, S.nvalid, p, q, ctl, partials, ctx->unbin_wpb, st));
   else
     HIP_TRY(dst::launch_unbin_cg(S.v, S.psi_f32, P.m4, S.nvalid, p, q, ctl, partials, st));
   return DST_OK;
@@ -700,6 +703,8 @@ int dst_create(dst_ctx** out, int device) {
   dst_ctx* ctx = new (std::nothrow) dst_ctx();
   if (!ctx) return DST_ENOMEM;
   ctx->device = device;
+  if (const char* e = std::getenv("DST_UNBIN_WPB")) ctx->unbin_wpb = std::atoi(e);
+  if (const char* e = std::getenv("DST_BIN_LPP")) ctx->bin_lpp = std::atoi(e);
   DeviceGuard g(device);
   if (hipHostMalloc(reinterpret_cast<void**>(&ctx->ctl_host), sizeof(CgCtl), hipHostMallocDefault) != hipSuccess ||
       hipHostMalloc(reinterpret_cast<void**>(&ctx->err_host), sizeof(int), hipHostMallocDefault) != hipSuccess ||

@@ -81,10 +81,12 @@ hipError_t runs_build(const View& v, int psi_f32, const void* tod, int tod_f32, 
 hipError_t launch_rhs_runs(const View& vc, const Runs& W, const void* tod, const double* md4, const uint8_t* valid,
                            int32_t* nvalid, double* J, double* b, hipStream_t st);
 // m = M^-1 A^T W F p (pw4 = interleaved w .* p).
+// lpp: lanes per pixel (64, 32 or 16).
 hipError_t launch_bin_runs(const View& vc, const Runs& W, const double* pw4, const double* Minv4,
-                           const uint8_t* valid, double* m4, const CgCtl* gate, hipStream_t st);
+                           const uint8_t* valid, double* m4, const CgCtl* gate, int lpp, hipStream_t st);
 // q = K p; with ctl the per-baseline CG partials (finished by launch_cg_alpha).
+// wpb: wavefronts per baseline (1, 2 or 4).
 hipError_t launch_unbin_runs(const View& vc, const Runs& W, const double* m4, const int32_t* nvalid, const double* p,
-                             double* q, CgCtl* ctl, double* partials, hipStream_t st);
+                             double* q, CgCtl* ctl, double* partials, int wpb, hipStream_t st);
 
 }  // namespace dst

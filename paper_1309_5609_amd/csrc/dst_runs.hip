@@ -400,9 +400,10 @@ __global__ void __launch_bounds__(kBlock) k_rhs_runs(View v, const uint32_t* __r
 
 // ---------------------------------------------------------------- iteration kernels
 
-// m = M^-1 A^T W F p per compact pixel from its pixel-order runs (one
-// wavefront per pixel).  pw4[b] = (w_T p_T, w_q p_q, w_u p_u, 0).
-template <typename RT, bool HAS_T, bool HAS_QU>
+// m = M^-1 A^T W F p per compact pixel from its pixel-order runs.  LPP lanes
+// work on one pixel (64 / LPP pixels per wavefront, each with its own chain of
+// dependent loads in flight); pw4[b] = (w_T p_T, w_q p_q, w_u p_u, 0).
+template <typename RT, bool HAS_T, bool HAS_QU, int LPP>
 __global__ void __launch_bounds__(kBlock) k_bin_runs(int64_t n_obs, const int64_t* __restrict__ pstart,
                                                      const int32_t* __restrict__ pb, const int32_t* __restrict__ pn,
                                                      const RT* __restrict__ pc, const RT* __restrict__ ps,
@@ -411,19 +412,26 @@ __global__ void __launch_bounds__(kBlock) k_bin_runs(int64_t n_obs, const int64_
                                                      const uint8_t* __restrict__ valid, double* __restrict__ m4,
                                                      const CgCtl* __restrict__ gate) {
   if (gate && gate->done) return;
+  constexpr int PPW = 64 / LPP;
+  constexpr int U = LPP >= 64 ? 2 : (LPP == 32 ? 4 : 8);
   const int lane = lane_id();
-  const int64_t nw = (int64_t)gridDim.x * kWaves;
-  for (int64_t c = (int64_t)blockIdx.x * kWaves + (threadIdx.x >> 6); c < n_obs; c += nw) {
-    if (valid[c] == 0) continue;  // m stays 0 on invalid pixels
-    const int64_t j0 = pstart[c], j1 = pstart[c + 1];
+  const int grp = lane / LPP, sub = lane % LPP;
+  const int64_t step = (int64_t)gridDim.x * kWaves * PPW;
+  for (int64_t cb = ((int64_t)blockIdx.x * kWaves + (threadIdx.x >> 6)) * PPW; cb < n_obs; cb += step) {
+    const int64_t c = cb + grp;
+    const bool have = c < n_obs && valid[c] != 0;  // m stays 0 on invalid pixels
+    int64_t j0 = 0, j1 = 0;
+    if (have) {
+      j0 = pstart[c];
+      j1 = pstart[c + 1];
+    }
     double acc[3] = {0.0, 0.0, 0.0};
-    constexpr int U = 2;
-    for (int64_t jb = j0 + lane; jb < j1; jb += 64 * U) {
+    for (int64_t jb = j0 + sub; jb < j1; jb += LPP * U) {
       int32_t bb[U], nn[U];
       double cc[U], ss[U];
 #pragma unroll
       for (int u = 0; u < U; ++u) {
-        const int64_t j = jb + 64 * u;
+        const int64_t j = jb + LPP * u;
         const bool in = j < j1;
         bb[u] = in ? pb[j] : -1;
         nn[u] = (HAS_T && in) ? pn[j] : 0;
@@ -443,8 +451,12 @@ __global__ void __launch_bounds__(kBlock) k_bin_runs(int64_t n_obs, const int64_
         }
       }
     }
-    wave_sum<3>(acc);
-    if (lane == 0) {
+#pragma unroll
+    for (int off = LPP / 2; off > 0; off >>= 1) {
+#pragma unroll
+      for (int i = 0; i < 3; ++i) acc[i] += __shfl_xor(acc[i], off, 64);
+    }
+    if (have && sub == 0) {
       const double2* ip = reinterpret_cast<const double2*>(Minv4 + 4 * c);
       const double2 i01 = ip[0], i23 = ip[1];
       double2* mp = reinterpret_cast<double2*>(m4 + 4 * c);
@@ -454,57 +466,80 @@ __global__ void __launch_bounds__(kBlock) k_bin_runs(int64_t n_obs, const int64_
   }
 }
 
-// q = K p = F^T W (F p - A m) per baseline from its time-order runs: one
-// wavefront per baseline, four baselines per workgroup, consecutive groups
-// on one XCD; m is zero on invalid blocks.  With CG: per-baseline partials of
-// p.q and of the T-projection sums.
-template <typename RT, bool HAS_T, bool HAS_QU, bool CG>
-__global__ void __launch_bounds__(kBlock) k_unbin_runs(View v, const uint32_t* __restrict__ bstart,
+// q = K p = F^T W (F p - A m) per baseline from its time-order runs.  WPB
+// wavefronts share one baseline (4 / WPB baselines per workgroup); consecutive
+// workgroups run on one XCD and take consecutive baselines, so fewer
+// baselines in flight per XCD (larger WPB) keep the map values they gather
+// in that XCD's L2.  m is zero on invalid blocks.  With CG: per-baseline
+// partials of p.q and of the T-projection sums.
+template <typename RT, bool HAS_T, bool HAS_QU, bool CG, int WPB>
+__global__ void __launch_bounds__(WPB > 4 ? 64 * WPB : kBlock) k_unbin_runs(View v, const uint32_t* __restrict__ bstart,
                                                        const int32_t* __restrict__ rpix,
                                                        const int32_t* __restrict__ rn, const RT* __restrict__ rc,
                                                        const RT* __restrict__ rs, const double* __restrict__ m4,
                                                        const int32_t* __restrict__ nvalid,
                                                        const double* __restrict__ p, double* __restrict__ q,
                                                        CgCtl* __restrict__ ctl, double* __restrict__ partials) {
+  constexpr int NW = WPB > 4 ? WPB : kWaves;  // wavefronts per workgroup
+  constexpr int BPB = NW / WPB;              // baselines per workgroup
+  __shared__ double lds[NW][3];
   if (CG && ctl->done) return;
   const int lane = lane_id();
+  const int wave = threadIdx.x >> 6;
   const int64_t n_b = v.n_b;
-  const int64_t n_g = (n_b + kWaves - 1) / kWaves;
+  const int64_t n_g = (n_b + BPB - 1) / BPB;
   const int64_t per = (n_g + 7) / 8;
   const int64_t i = blockIdx.x;
   const int64_t g = (i & 7) * per + (i >> 3);
-  const int64_t b = g * kWaves + (threadIdx.x >> 6);
-  if (g >= n_g || b >= n_b) return;
-  const int64_t r0 = bstart[b], r1 = bstart[b + 1];
+  if (g >= n_g) return;  // whole workgroup
+  const int64_t b = g * BPB + wave / WPB;
+  const int sub = wave % WPB;
   double acc[3] = {0.0, 0.0, 0.0};
-  constexpr int U = 4;
-  for (int64_t rb = r0 + lane; rb < r1; rb += 64 * U) {
-    int32_t cc_[U], nn[U];
-    double C[U], S[U];
+  if (b < n_b) {
+    const int64_t r0 = bstart[b], r1 = bstart[b + 1];
+    constexpr int U = 4;
+    for (int64_t rb = r0 + sub * 64 + lane; rb < r1; rb += 64 * WPB * U) {
+      int32_t cc_[U], nn[U];
+      double C[U], S[U];
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int64_t r = rb + 64 * u;
-      const bool in = r < r1;
-      cc_[u] = in ? rpix[r] : -1;
-      nn[u] = (HAS_T && in) ? rn[r] : 0;
-      C[u] = (HAS_QU && in) ? (double)rc[r] : 0.0;
-      S[u] = (HAS_QU && in) ? (double)rs[r] : 0.0;
-    }
+      for (int u = 0; u < U; ++u) {
+        const int64_t r = rb + 64 * WPB * u;
+        const bool in = r < r1;
+        cc_[u] = in ? rpix[r] : -1;
+        nn[u] = (HAS_T && in) ? rn[r] : 0;
+        C[u] = (HAS_QU && in) ? (double)rc[r] : 0.0;
+        S[u] = (HAS_QU && in) ? (double)rs[r] : 0.0;
+      }
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-      if (cc_[u] < 0) continue;
-      const double2* mp = reinterpret_cast<const double2*>(m4 + 4 * (int64_t)cc_[u]);
-      const double2 m01 = mp[0];
-      if (HAS_T) acc[0] += (double)nn[u] * m01.x;
-      if (HAS_QU) {
-        const double mU = mp[1].x;
-        acc[1] += C[u] * m01.y + S[u] * mU;
-        acc[2] += C[u] * mU - S[u] * m01.y;
+      for (int u = 0; u < U; ++u) {
+        if (cc_[u] < 0) continue;
+        const double2* mp = reinterpret_cast<const double2*>(m4 + 4 * (int64_t)cc_[u]);
+        const double2 m01 = mp[0];
+        if (HAS_T) acc[0] += (double)nn[u] * m01.x;
+        if (HAS_QU) {
+          const double mU = mp[1].x;
+          acc[1] += C[u] * m01.y + S[u] * mU;
+          acc[2] += C[u] * mU - S[u] * m01.y;
+        }
       }
     }
   }
   wave_sum<3>(acc);
-  if (lane == 0) {
+  if (WPB > 1) {
+    if (lane == 0) {
+      lds[wave][0] = acc[0];
+      lds[wave][1] = acc[1];
+      lds[wave][2] = acc[2];
+    }
+    __syncthreads();
+    if (sub != 0) return;
+    for (int w = 1; w < WPB; ++w) {
+      acc[0] += lds[wave + w][0];
+      acc[1] += lds[wave + w][1];
+      acc[2] += lds[wave + w][2];
+    }
+  }
+  if (lane == 0 && b < n_b) {
     const int nT = nvalid[b], nQ = nvalid[n_b + b];
     double pq = 0.0, eq = 0.0, ep = 0.0;
     if (HAS_T) {
@@ -720,31 +755,56 @@ hipError_t launch_rhs_runs(const View& vc, const Runs& W, const void* tod, const
 }
 
 hipError_t launch_bin_runs(const View& vc, const Runs& W, const double* pw4, const double* Minv4,
-                           const uint8_t* valid, double* m4, const CgCtl* gate, hipStream_t st) {
-  if (W.n_obs == 0) return hipSuccess;
-  const unsigned g = grid_for(W.n_obs, kWaves, 16384);
+                           const uint8_t* valid, double* m4, const CgCtl* gate, int lpp, hipStream_t st) {
+  if (lpp != 64 && lpp != 32 && lpp != 16) lpp = 64;
+  const int64_t ppb = kWaves * (64 / lpp);
+  const unsigned g = (unsigned)std::max<int64_t>(1, std::min<int64_t>((W.n_obs + ppb - 1) / ppb, 16384));
   by_float(W.f32, [&](auto rt) {
     using RT = typename decltype(rt)::type;
     by_streams(vc, [&](auto T, auto Q) {
-      hipLaunchKernelGGL((k_bin_runs<RT, decltype(T)::value, decltype(Q)::value>), dim3(g), dim3(kBlock), 0, st,
-                         W.n_obs, W.pstart, W.pb, W.pn, static_cast<const RT*>(W.pc), static_cast<const RT*>(W.ps),
-                         pw4, Minv4, valid, m4, gate);
+      constexpr bool HT = decltype(T)::value, HQ = decltype(Q)::value;
+      auto launch = [&](auto kern) {
+        hipLaunchKernelGGL(kern, dim3(g), dim3(kBlock), 0, st, W.n_obs, W.pstart, W.pb, W.pn,
+                           static_cast<const RT*>(W.pc), static_cast<const RT*>(W.ps), pw4, Minv4, valid, m4, gate);
+      };
+      if (lpp == 16)
+        launch(k_bin_runs<RT, HT, HQ, 16>);
+      else if (lpp == 32)
+        launch(k_bin_runs<RT, HT, HQ, 32>);
+      else
+        launch(k_bin_runs<RT, HT, HQ, 64>);
     });
   });
   return hipGetLastError();
 }
 
 hipError_t launch_unbin_runs(const View& vc, const Runs& W, const double* m4, const int32_t* nvalid, const double* p,
-                             double* q, CgCtl* ctl, double* partials, hipStream_t st) {
-  const int64_t n_g = (vc.n_b + kWaves - 1) / kWaves;
+                             double* q, CgCtl* ctl, double* partials, int wpb, hipStream_t st) {
+  if (wpb != 1 && wpb != 2 && wpb != 4 && wpb != 8 && wpb != 16) wpb = 1;
+  const int64_t bpb = wpb > 4 ? 1 : kWaves / wpb;
+  const unsigned nt = wpb > 4 ? 64 * wpb : kBlock;
+  const int64_t n_g = (vc.n_b + bpb - 1) / bpb;
   const unsigned g = (unsigned)(8 * ((n_g + 7) / 8));
   by_float(W.f32, [&](auto rt) {
     using RT = typename decltype(rt)::type;
     by_streams(vc, [&](auto T, auto Q) {
       by_bool(ctl != nullptr, [&](auto CG) {
-        hipLaunchKernelGGL((k_unbin_runs<RT, decltype(T)::value, decltype(Q)::value, decltype(CG)::value>), dim3(g),
-                           dim3(kBlock), 0, st, vc, W.bstart, W.tpix, W.tn, static_cast<const RT*>(W.tc),
-                           static_cast<const RT*>(W.ts), m4, nvalid, p, q, ctl, partials);
+        constexpr bool HT = decltype(T)::value, HQ = decltype(Q)::value, C = decltype(CG)::value;
+        auto launch = [&](auto kern) {
+          hipLaunchKernelGGL(kern, dim3(g), dim3(nt), 0, st, vc, W.bstart, W.tpix, W.tn,
+                             static_cast<const RT*>(W.tc), static_cast<const RT*>(W.ts), m4, nvalid, p, q, ctl,
+                             partials);
+        };
+        if (wpb == 16)
+          launch(k_unbin_runs<RT, HT, HQ, C, 16>);
+        else if (wpb == 8)
+          launch(k_unbin_runs<RT, HT, HQ, C, 8>);
+        else if (wpb == 4)
+          launch(k_unbin_runs<RT, HT, HQ, C, 4>);
+        else if (wpb == 2)
+          launch(k_unbin_runs<RT, HT, HQ, C, 2>);
+        else
+          launch(k_unbin_runs<RT, HT, HQ, C, 1>);
       });
     });
   });
