@@ -199,6 +199,37 @@ typedef struct {
 int dst_solve(dst_ctx* ctx, const dst_problem* prob, const dst_solve_opts* opts, double* baselines_out,
               double* map_out, double* binned_out, int32_t* hits_out, dst_solve_info* info, void* stream);
 
+/* Scan strategy of a spinning ground telescope (input synthesis on the GPU).
+ * The telescope turns about the vertical at constant elevation; sample i is
+ * taken at t = i / sample_rate_hz, azimuth az0 + 2 pi t / spin_period_s, local
+ * sidereal time lst0 + 2 pi t / sidereal_day_s.  The alt-az -> equatorial
+ * transform gives declination, hour angle H and parallactic angle q; the
+ * sample's direction is (colatitude 90 deg - dec, RA = LST - H) and its
+ * polarisation angle psi = q + psi0 (the parallactic-angle footnote of the
+ * Algorithm section). */
+typedef struct {
+  double sample_rate_hz;  /* > 0 */
+  double spin_period_s;   /* > 0; sample_rate_hz * spin_period_s must be a whole number <= 2^24 */
+  double elevation_deg;
+  double latitude_deg;    /* in (-90, 90) */
+  double az0_deg;
+  double lst0_rad;
+  double psi0_deg;
+  double sidereal_day_s;  /* > 0 */
+} dst_scan;
+
+/* Pointing of samples start .. start + n_samples - 1 of the scan:
+ *   pix_out [n_samples] int32   HEALPix RING index at resolution nside
+ *   psi_out [n_samples] f64 or f32 (psi_dtype) polarisation angle, or NULL
+ * nside in [1, 8192]; start >= 0 and start + n_samples <= 2^53.  The
+ * per-period angles are tabulated on the host with the C library's sin, cos,
+ * tan, asin and atan2; every per-sample step is a correctly rounded FP64
+ * operation in a fixed order, so a host implementation evaluating the same
+ * expressions reproduces the pixels bit for bit.  Stream-ordered; the call
+ * waits for its stream before returning. */
+int dst_pointing_expand(dst_ctx* ctx, const dst_scan* scan, int64_t nside, int64_t start, int64_t n_samples,
+                        int32_t* pix_out, void* psi_out, int32_t psi_dtype, void* stream);
+
 /* Destripe several problems in one call.
  *
  * Problems that share the operator K of Eq. 13 -- the same pix and psi

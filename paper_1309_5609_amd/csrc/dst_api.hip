@@ -1091,4 +1091,38 @@ int dst_solve_batched(dst_ctx* ctx, int32_t n_problems, const dst_problem* probl
   return status;
 }
 
+int dst_pointing_expand(dst_ctx* ctx, const dst_scan* scan, int64_t nside, int64_t start, int64_t n_samples,
+                        int32_t* pix_out, void* psi_out, int32_t psi_dtype, void* stream) {
+  if (!ctx) return DST_EINVAL;
+  if (!scan) return fail(ctx, DST_EINVAL, "scan is NULL");
+  if (!pix_out) return fail(ctx, DST_EINVAL, "pix_out is NULL");
+  if (nside < 1 || nside > 8192) return fail(ctx, DST_EINVAL, "nside must be in [1, 8192] (got %lld)", (long long)nside);
+  if (n_samples < 1 || start < 0 || start > ((int64_t)1 << 53) - n_samples)
+    return fail(ctx, DST_EINVAL, "need n_samples >= 1, start >= 0 and start + n_samples <= 2^53");
+  if (psi_out && !is_dtype(psi_dtype)) return fail(ctx, DST_EINVAL, "psi_dtype must be DST_F32 or DST_F64");
+  const dst_scan& s = *scan;
+  const double vals[8] = {s.sample_rate_hz, s.spin_period_s, s.elevation_deg, s.latitude_deg,
+                          s.az0_deg,        s.lst0_rad,      s.psi0_deg,      s.sidereal_day_s};
+  for (double x : vals)
+    if (!std::isfinite(x)) return fail(ctx, DST_EINVAL, "scan parameters must be finite");
+  if (!(s.sample_rate_hz > 0.0) || !(s.spin_period_s > 0.0) || !(s.sidereal_day_s > 0.0))
+    return fail(ctx, DST_EINVAL, "sample rate, spin period and sidereal day must be > 0");
+  if (!(std::fabs(s.latitude_deg) < 90.0)) return fail(ctx, DST_EINVAL, "latitude must be in (-90, 90) degrees");
+  const double per = s.sample_rate_hz * s.spin_period_s;
+  if (!(per >= 1.0 && per <= (double)(1 << 24)) || std::fabs(per - std::nearbyint(per)) > 1e-9)
+    return fail(ctx, DST_EINVAL, "a spin period must hold a whole number of samples in [1, 2^24]");
+  const int64_t n_per = (int64_t)std::nearbyint(per);
+  ctx->err.clear();
+  DeviceGuard g(ctx->device);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  std::vector<double> tab;
+  dst::scan_period_table(s, n_per, tab);
+  double* dtab = nullptr;
+  DST_TRY(ws(ctx, "scan_tab", tab.size(), &dtab));
+  HIP_TRY(hipMemcpyAsync(dtab, tab.data(), tab.size() * sizeof(double), hipMemcpyHostToDevice, st));
+  HIP_TRY(dst::launch_expand(nside, start, n_samples, n_per, s, dtab, pix_out, psi_out, psi_dtype == DST_F32, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  return DST_OK;
+}
+
 }  // extern "C"

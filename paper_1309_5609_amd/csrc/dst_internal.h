@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <vector>
 
 #include "dst.h"
 
@@ -86,5 +87,11 @@ hipError_t launch_residual_norm(const View& v, const double* b, const double* ka
 // Copy kernel layout [n_pix][4] -> user [n_pix][3]
 hipError_t launch_fill(double* x, int64_t n, double value, hipStream_t st);
 hipError_t launch_fill_u32(uint32_t* x, int64_t n, uint32_t value, hipStream_t st);
+
+// ---- pointing expansion (dst_pointing.hip) ---------------------------------
+// [3][n_per] table of one spin period: hour angle, cos(colatitude), psi.
+void scan_period_table(const dst_scan& s, int64_t n_per, std::vector<double>& tab);
+hipError_t launch_expand(int64_t nside, int64_t start, int64_t n, int64_t n_per, const dst_scan& s, const double* tab,
+                         int32_t* pix, void* psi, int psi_f32, hipStream_t st);
 
 }  // namespace dst

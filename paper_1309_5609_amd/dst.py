@@ -29,7 +29,8 @@ DST_BIN_USE_TOD, DST_BIN_MAP = 1, 2
 DST_SOLVE_NO_CANON, DST_SOLVE_PROFILE, DST_SOLVE_NO_GRAPH, DST_SOLVE_PER_SAMPLE = 1, 2, 4, 8
 
 EXPORTS = ("dst_version", "dst_create", "dst_destroy", "dst_last_error", "dst_pixel_setup", "dst_bin", "dst_unbin",
-           "dst_baseline_reduce", "dst_residual", "dst_apply_operator", "dst_solve", "dst_solve_batched")
+           "dst_baseline_reduce", "dst_residual", "dst_apply_operator", "dst_solve", "dst_solve_batched",
+           "dst_pointing_expand")
 
 
 class dst_problem(ctypes.Structure):
@@ -51,6 +52,14 @@ class dst_solve_info(ctypes.Structure):
                 ("t_setup_ms", ctypes.c_double), ("t_iter_ms", ctypes.c_double), ("t_total_ms", ctypes.c_double),
                 ("t_bin_ms", ctypes.c_double), ("t_apply_ms", ctypes.c_double), ("t_unbin_ms", ctypes.c_double),
                 ("t_update_ms", ctypes.c_double), ("n_runs", ctypes.c_int64)]
+
+
+SCAN_FIELDS = ("sample_rate_hz", "spin_period_s", "elevation_deg", "latitude_deg", "az0_deg", "lst0_rad",
+               "psi0_deg", "sidereal_day_s")
+
+
+class dst_scan(ctypes.Structure):
+    _fields_ = [(name, ctypes.c_double) for name in SCAN_FIELDS]
 
 
 class DstError(RuntimeError):
@@ -91,6 +100,7 @@ def library(path: str = LIB_PATH) -> ctypes.CDLL:
                       i32),
         "dst_solve_batched": ([vp, i32, P, ctypes.POINTER(dst_solve_opts), vp, vp, vp, vp,
                                ctypes.POINTER(dst_solve_info), vp], i32),
+        "dst_pointing_expand": ([vp, ctypes.POINTER(dst_scan), i64, i64, i64, vp, vp, i32, vp], i32),
     }
     for name, (argtypes, restype) in sig.items():
         fn = getattr(lib, name)
@@ -345,3 +355,22 @@ def dst_solve_batched(ctx: Context, probs, tol: float = 1e-10, max_iter: int = 1
         d.update(o)
         res.append(d)
     return rc, res
+
+
+def dst_pointing_expand(ctx: Context, spec, nside: int, n_samples: int, start: int = 0, psi_dtype=None,
+                        with_psi: bool = True, device="cuda:0"):
+    """Pointing of samples start .. start + n_samples - 1 of a scan, computed on the GPU.
+
+    ``spec`` is any object with the ``dst_scan`` field names (``synth.ScanSpec``).
+    Returns (pix int32 [n], psi [n] float64 / float32 or None).
+    """
+    import torch
+    sc = dst_scan(*[float(getattr(spec, f)) for f in SCAN_FIELDS])
+    pix = _empty((n_samples,), torch.int32, device)
+    dt = torch.float32 if psi_dtype in ("float32", torch.float32) or getattr(psi_dtype, "__name__", "") == "float32" \
+        else torch.float64
+    psi = _empty((n_samples,), dt, device) if with_psi else None
+    code = DST_F32 if dt == torch.float32 else DST_F64
+    ctx.check(ctx.lib.dst_pointing_expand(ctx.handle, ctypes.byref(sc), int(nside), int(start), int(n_samples),
+                                          _ptr(pix), _ptr(psi), code, _stream()))
+    return pix, psi

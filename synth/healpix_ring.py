@@ -45,10 +45,14 @@ def ang2pix_ring(nside: int, theta, phi) -> np.ndarray:
     ``theta`` is the colatitude in [0, pi] and ``phi`` the longitude (any real
     value, taken modulo 2 pi), both in radians, float64 arrays of one shape.
     """
+    return ang2pix_ring_z(nside, np.cos(np.asarray(theta, dtype=np.float64)), phi)
+
+
+def ang2pix_ring_z(nside: int, z, phi) -> np.ndarray:
+    """``ang2pix_ring`` from ``z = cos(theta)`` directly."""
     n = int(nside)
-    theta = np.asarray(theta, dtype=np.float64)
+    z = np.asarray(z, dtype=np.float64)
     phi = np.asarray(phi, dtype=np.float64)
-    z = np.cos(theta)
     za = np.abs(z)
     twopi = 2.0 * np.pi
     ph = np.mod(phi, twopi)

@@ -24,13 +24,14 @@ holds no step of the destriping method.
 """
 from __future__ import annotations
 
+import math
 import os
 from concurrent.futures import ThreadPoolExecutor
 from dataclasses import dataclass
 
 import numpy as np
 
-from .healpix_ring import ang2pix_ring
+from .healpix_ring import ang2pix_ring_z
 
 SIDEREAL_DAY_S = 86164.0905
 
@@ -51,18 +52,32 @@ def one_period(spec: ScanSpec, n_period: int):
     """Declination, hour angle and polarisation angle over one spin period.
 
     Returns ``(dec, hour_angle, psi)`` float64 arrays of length ``n_period``
-    for samples ``i = 0..n_period-1`` at ``t = i / sample_rate``.
+    for samples ``i = 0..n_period-1`` at ``t = i / sample_rate``.  Evaluated
+    element by element with the C library's functions (``math``), in the
+    order written, so that any consumer calling the same library on the same
+    expressions gets the same bits (the table is only ``n_period`` long).
     """
-    t = np.arange(n_period, dtype=np.float64) / spec.sample_rate_hz
-    az = np.deg2rad(spec.az0_deg) + 2.0 * np.pi * t / spec.spin_period_s
-    el = np.deg2rad(spec.elevation_deg)
-    lat = np.deg2rad(spec.latitude_deg)
-    sin_dec = np.sin(el) * np.sin(lat) + np.cos(el) * np.cos(lat) * np.cos(az)
-    dec = np.arcsin(np.clip(sin_dec, -1.0, 1.0))
-    ha = np.arctan2(-np.sin(az) * np.cos(el), np.cos(lat) * np.sin(el) - np.sin(lat) * np.cos(el) * np.cos(az))
-    q = np.arctan2(np.sin(ha), np.tan(lat) * np.cos(dec) - np.sin(dec) * np.cos(ha))
-    psi = q + np.deg2rad(spec.psi0_deg)
+    el = math.radians(spec.elevation_deg)
+    lat = math.radians(spec.latitude_deg)
+    az0 = math.radians(spec.az0_deg)
+    psi0 = math.radians(spec.psi0_deg)
+    dec = np.empty(n_period)
+    ha = np.empty(n_period)
+    psi = np.empty(n_period)
+    for i in range(n_period):
+        t = float(i) / spec.sample_rate_hz
+        az = az0 + 2.0 * math.pi * t / spec.spin_period_s
+        sin_dec = math.sin(el) * math.sin(lat) + math.cos(el) * math.cos(lat) * math.cos(az)
+        d = math.asin(min(1.0, max(-1.0, sin_dec)))
+        h = math.atan2(-math.sin(az) * math.cos(el), math.cos(lat) * math.sin(el) - math.sin(lat) * math.cos(el) * math.cos(az))
+        q = math.atan2(math.sin(h), math.tan(lat) * math.cos(d) - math.sin(d) * math.cos(h))
+        dec[i], ha[i], psi[i] = d, h, q + psi0
     return dec, ha, psi
+
+
+def period_z(dec: np.ndarray) -> np.ndarray:
+    """cos(colatitude) of each table entry, element by element with ``math``."""
+    return np.array([math.cos(0.5 * math.pi - d) for d in dec])
 
 
 def samples_per_period(spec: ScanSpec) -> int:
@@ -80,7 +95,7 @@ def pointing(spec: ScanSpec, nside: int, n_samples: int, start: int = 0, chunk: 
     """
     n_per = samples_per_period(spec)
     dec, ha, psi_per = one_period(spec, n_per)
-    theta_per = 0.5 * np.pi - dec
+    z_per = period_z(dec)
     pix = np.empty(n_samples, dtype=np.int32)
     psi = np.empty(n_samples, dtype=np.float64)
 
@@ -91,7 +106,7 @@ def pointing(spec: ScanSpec, nside: int, n_samples: int, start: int = 0, chunk: 
         t = idx.astype(np.float64) / spec.sample_rate_hz
         lst = spec.lst0_rad + 2.0 * np.pi * t / spec.sidereal_day_s
         ra = lst - ha[ph]
-        pix[c0:c1] = ang2pix_ring(nside, theta_per[ph], ra).astype(np.int32)
+        pix[c0:c1] = ang2pix_ring_z(nside, z_per[ph], ra).astype(np.int32)
         psi[c0:c1] = psi_per[ph]
 
     starts = list(range(0, n_samples, chunk))

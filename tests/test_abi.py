@@ -40,6 +40,7 @@ def test_struct_layouts():
     assert dst.dst_problem.pix.offset == 40 and dst.dst_problem.weight.offset == 64
     assert ctypes.sizeof(dst.dst_solve_opts) == 32 and dst.dst_solve_opts.a0.offset == 24
     assert ctypes.sizeof(dst.dst_solve_info) == 128
+    assert ctypes.sizeof(dst.dst_scan) == 64
 
 
 def test_layouts_agree_with_the_c_compiler(tmp_path):
@@ -47,11 +48,13 @@ def test_layouts_agree_with_the_c_compiler(tmp_path):
     src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "dst.h"\n'
                    'int main(void){printf("%zu %zu %zu %zu %zu %zu\\n", sizeof(dst_problem),'
                    ' offsetof(dst_problem, pix), offsetof(dst_problem, weight), sizeof(dst_solve_opts),'
-                   ' offsetof(dst_solve_opts, a0), sizeof(dst_solve_info)); return 0;}\n')
+                   ' offsetof(dst_solve_opts, a0), sizeof(dst_solve_info)); printf("%zu %zu\\n", sizeof(dst_scan),'
+                   ' offsetof(dst_scan, sidereal_day_s)); return 0;}\n')
     exe = tmp_path / "layout"
     subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
     got = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()
-    assert got == ["96", "40", "64", "32", "24", "128"]
+    assert got == ["96", "40", "64", "32", "24", "128", "64", "56"]
+    assert dst.dst_scan.sidereal_day_s.offset == 56
 
 
 def test_no_device_is_reported_not_crashed():
