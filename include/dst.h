@@ -230,6 +230,23 @@ typedef struct {
 int dst_pointing_expand(dst_ctx* ctx, const dst_scan* scan, int64_t nside, int64_t start, int64_t n_samples,
                         int32_t* pix_out, void* psi_out, int32_t psi_dtype, void* stream);
 
+/* White + 1/f noise on the GPU (Eq. 1: P(f) = sigma^2 (1 + (f_k / f)^alpha)).
+ * Timeline of n_samples made of segments of `segment` samples (a power of two
+ * in [4, 2^26]; the last segment is drawn at full length and cut).  Segment j
+ * is sigma times unit normals -- Box-Muller on Philox4x64-10 words, block b of
+ * the segment from counter (b, j, 0, 0) and key (seed, stream_id), the four
+ * words of a block giving samples 4b .. 4b+3 -- filtered by
+ * sqrt(1 + (f_k / |f|)^alpha) in the Fourier domain of the segment with the
+ * zero-frequency bin kept (fknee_hz = 0: white noise).
+ *   out [n_samples] of out_dtype (DST_F32 or DST_F64); with flags
+ *       DST_NOISE_ACCUMULATE the noise is added to what out holds.
+ * Stream-ordered; the call waits for its stream before returning.  Work
+ * memory: two buffers of up to 256 MiB in the context. */
+enum { DST_NOISE_ACCUMULATE = 1u };
+int dst_noise_generate(dst_ctx* ctx, uint64_t seed, uint64_t stream_id, int64_t n_samples, int64_t segment,
+                       double sample_rate_hz, double sigma, double fknee_hz, double alpha, void* out,
+                       int32_t out_dtype, uint32_t flags, void* stream);
+
 /* Destripe several problems in one call.
  *
  * Problems that share the operator K of Eq. 13 -- the same pix and psi

@@ -1125,4 +1125,31 @@ int dst_pointing_expand(dst_ctx* ctx, const dst_scan* scan, int64_t nside, int64
   return DST_OK;
 }
 
+int dst_noise_generate(dst_ctx* ctx, uint64_t seed, uint64_t stream_id, int64_t n_samples, int64_t segment,
+                       double sample_rate_hz, double sigma, double fknee_hz, double alpha, void* out,
+                       int32_t out_dtype, uint32_t flags, void* stream) {
+  if (!ctx) return DST_EINVAL;
+  if (!out) return fail(ctx, DST_EINVAL, "out is NULL");
+  if (!is_dtype(out_dtype)) return fail(ctx, DST_EINVAL, "out_dtype must be DST_F32 or DST_F64");
+  if (n_samples < 1) return fail(ctx, DST_EINVAL, "n_samples must be >= 1");
+  if (segment < 4 || segment > ((int64_t)1 << 26) || (segment & (segment - 1)))
+    return fail(ctx, DST_EINVAL, "segment must be a power of two in [4, 2^26] (got %lld)", (long long)segment);
+  if (!(sample_rate_hz > 0.0) || !std::isfinite(sample_rate_hz)) return fail(ctx, DST_EINVAL, "sample rate must be > 0");
+  if (!(sigma >= 0.0) || !std::isfinite(sigma)) return fail(ctx, DST_EINVAL, "sigma must be >= 0 and finite");
+  if (!(fknee_hz >= 0.0) || !std::isfinite(fknee_hz)) return fail(ctx, DST_EINVAL, "fknee must be >= 0 and finite");
+  if (!std::isfinite(alpha)) return fail(ctx, DST_EINVAL, "alpha must be finite");
+  if (flags & ~(uint32_t)DST_NOISE_ACCUMULATE) return fail(ctx, DST_EINVAL, "unknown flags %u", flags);
+  ctx->err.clear();
+  DeviceGuard g(ctx->device);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const size_t nbuf = (size_t)dst::noise_pairs_per_chunk(segment) * (size_t)segment;
+  double2 *b0 = nullptr, *b1 = nullptr;
+  DST_TRY(ws(ctx, "noise_b0", nbuf, &b0));
+  DST_TRY(ws(ctx, "noise_b1", nbuf, &b1));
+  HIP_TRY(dst::launch_noise(seed, stream_id, n_samples, segment, sample_rate_hz, sigma, fknee_hz, alpha, out,
+                            out_dtype == DST_F32, (flags & DST_NOISE_ACCUMULATE) ? 1 : 0, b0, b1, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  return DST_OK;
+}
+
 }  // extern "C"

@@ -94,4 +94,11 @@ void scan_period_table(const dst_scan& s, int64_t n_per, std::vector<double>& ta
 hipError_t launch_expand(int64_t nside, int64_t start, int64_t n, int64_t n_per, const dst_scan& s, const double* tab,
                          int32_t* pix, void* psi, int psi_f32, hipStream_t st);
 
+// ---- Monte Carlo noise (dst_noise.hip) -------------------------------------
+int64_t noise_pairs_per_chunk(int64_t S);
+// buf0, buf1: noise_pairs_per_chunk(S) * S complex values each.
+hipError_t launch_noise(uint64_t seed, uint64_t stream, int64_t n, int64_t S, double rate, double sigma, double fknee,
+                        double alpha, void* out, int out_f32, int accumulate, double2* buf0, double2* buf1,
+                        hipStream_t st);
+
 }  // namespace dst

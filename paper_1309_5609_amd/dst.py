@@ -27,10 +27,11 @@ STREAMS = {"T": 1, "QU": 6, "TQU": 7}
 N_STREAMS = {"T": 1, "QU": 2, "TQU": 3}
 DST_BIN_USE_TOD, DST_BIN_MAP = 1, 2
 DST_SOLVE_NO_CANON, DST_SOLVE_PROFILE, DST_SOLVE_NO_GRAPH, DST_SOLVE_PER_SAMPLE = 1, 2, 4, 8
+DST_NOISE_ACCUMULATE = 1
 
 EXPORTS = ("dst_version", "dst_create", "dst_destroy", "dst_last_error", "dst_pixel_setup", "dst_bin", "dst_unbin",
            "dst_baseline_reduce", "dst_residual", "dst_apply_operator", "dst_solve", "dst_solve_batched",
-           "dst_pointing_expand")
+           "dst_pointing_expand", "dst_noise_generate")
 
 
 class dst_problem(ctypes.Structure):
@@ -101,6 +102,8 @@ def library(path: str = LIB_PATH) -> ctypes.CDLL:
         "dst_solve_batched": ([vp, i32, P, ctypes.POINTER(dst_solve_opts), vp, vp, vp, vp,
                                ctypes.POINTER(dst_solve_info), vp], i32),
         "dst_pointing_expand": ([vp, ctypes.POINTER(dst_scan), i64, i64, i64, vp, vp, i32, vp], i32),
+        "dst_noise_generate": ([vp, ctypes.c_uint64, ctypes.c_uint64, i64, i64, dbl, dbl, dbl, dbl, vp, i32, u32, vp],
+                               i32),
     }
     for name, (argtypes, restype) in sig.items():
         fn = getattr(lib, name)
@@ -374,3 +377,17 @@ def dst_pointing_expand(ctx: Context, spec, nside: int, n_samples: int, start: i
     ctx.check(ctx.lib.dst_pointing_expand(ctx.handle, ctypes.byref(sc), int(nside), int(start), int(n_samples),
                                           _ptr(pix), _ptr(psi), code, _stream()))
     return pix, psi
+
+
+def dst_noise_generate(ctx: Context, seed: int, stream_id: int, n_samples: int, segment: int,
+                       sample_rate_hz: float, sigma: float, fknee_hz: float, alpha: float, out=None,
+                       dtype=None, accumulate: bool = False, device="cuda:0"):
+    """White + 1/f noise timeline on the GPU (into ``out`` when given; added to it with ``accumulate``)."""
+    import torch
+    if out is None:
+        out = torch.zeros((n_samples,), dtype=dtype or torch.float64, device=device)
+    code = DST_F32 if out.dtype == torch.float32 else DST_F64
+    ctx.check(ctx.lib.dst_noise_generate(ctx.handle, int(seed), int(stream_id), int(n_samples), int(segment),
+                                         float(sample_rate_hz), float(sigma), float(fknee_hz), float(alpha),
+                                         _ptr(out), code, DST_NOISE_ACCUMULATE if accumulate else 0, _stream()))
+    return out
