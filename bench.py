@@ -195,6 +195,77 @@ def batched_form(ctx, p, dp, n_real: int, tol: float, steps: int, warmup: int, p
     return out
 
 
+# Uneven survey batch (config 4): 8 polarimeter channels of 3 .. 30 days plus a
+# 12-month intensity-only stream at N_side 512, FP32 timelines and angles.
+# Per channel: days, baseline length, f_k (Hz), alpha, spin-axis phase.
+UNEVEN_CHANNELS = [(3, 1500, 0.010, 1.0), (5, 2000, 0.015, 1.15), (7, 2500, 0.022, 1.3), (10, 3000, 0.033, 1.45),
+                   (14, 3500, 0.050, 1.6), (20, 4000, 0.075, 1.75), (25, 5000, 0.110, 1.9), (30, 6000, 0.200, 2.0)]
+UNEVEN_T_STREAM = (365, 6000, 0.010, 1.0)
+
+
+def uneven_form(ctx, tol: float, steps: int, warmup: int) -> dict:
+    """Config 4, generated on the GPU by the library (pointing expansion, sky scan, noise) and solved by
+    dst_solve_batched (channels share no pointing, so they are solved one after another, autotuned)."""
+    import numpy as np
+    import torch
+
+    from paper_1309_5609_amd import dst
+    from synth import ScanSpec, gaussian_sky
+
+    nside, rate, sigma = 512, 50.0, 1e-3
+    n_pix = 12 * nside * nside
+    t = time.perf_counter()
+    sky = torch.from_numpy(gaussian_sky(n_pix, 4)).to("cuda")
+    w = 1.0 / (sigma * sigma)
+    probs, desc = [], []
+    specs = [(c, days, L, fk, al, "TQU") for c, (days, L, fk, al) in enumerate(UNEVEN_CHANNELS)]
+    specs.append((len(UNEVEN_CHANNELS),) + UNEVEN_T_STREAM + ("T",))
+    for c, days, L, fk, al, streams in specs:
+        n = int(days * 86400 * rate)
+        scan = ScanSpec(sample_rate_hz=rate, az0_deg=37.0 * c, psi0_deg=22.5 * c)
+        pix, psi = dst.dst_pointing_expand(ctx, scan, nside, n, psi_dtype=torch.float32)
+        rows = 1 if streams == "T" else 3
+        head = dst.Problem(pix, psi if streams != "T" else None, None, n_pix, L, streams, (w, w, w))
+        sig = dst.dst_unbin(ctx, head, sky)              # A m_sky per stream, FP64
+        tod = sig.float()
+        del sig
+        for k in range(rows):
+            dst.dst_noise_generate(ctx, 4000 + c, k, n, 1 << 22, rate, sigma, fk, al, out=tod[k], accumulate=True)
+        probs.append(dst.Problem(pix, psi if streams != "T" else None, tod, n_pix, L, streams, (w, w, w)))
+        desc.append({"days": days, "n_samples": n, "baseline_length": L, "fknee_hz": fk, "alpha": al,
+                     "streams": streams})
+        if streams == "T":
+            del psi
+    torch.cuda.synchronize()
+    gen_s = time.perf_counter() - t
+    log(f"uneven batch: {len(probs)} problems, {sum(d['n_samples'] for d in desc):,} samples drawn on the GPU "
+        f"in {gen_s:.1f} s")
+    flags = dst.DST_SOLVE_AUTOTUNE
+    for _ in range(max(warmup, 1)):
+        dst.dst_solve_batched(ctx, probs, tol=tol, max_iter=3000, flags=flags, maps=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = None
+    work = 0
+    for _ in range(steps):
+        _, res = dst.dst_solve_batched(ctx, probs, tol=tol, max_iter=3000, flags=flags, maps=False)
+        work += sum(d["n_samples"] * r["iterations"] for d, r in zip(desc, res))
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    for d, r in zip(desc, res):
+        d.update(iterations=r["iterations"], converged=r["converged"], setup_ms=r["t_setup_ms"],
+                 iter_ms=r["t_iter_ms"], total_ms=r["t_total_ms"], n_runs=r["n_runs"])
+    out = {"value": work / wall, "unit": "samples*CG-iters/s", "ms_per_step": wall * 1e3 / steps,
+           "n_problems": len(probs), "total_samples": sum(d["n_samples"] for d in desc), "nside": nside,
+           "dtype": "f32 timelines and angles, f64 accumulation / inverse / CG", "problems": desc,
+           "inputs": ("pointing expanded on the GPU (dst_pointing_expand), Gaussian sky (I 1 mK, Q/U 0.1 mK) scanned "
+                      "by dst_unbin, white 1 mK + 1/f noise by dst_noise_generate (segments of 2^22 samples)")}
+    del probs, res, sky
+    torch.cuda.empty_cache()
+    log(f"uneven batch: {out['value']:.3e} samples*iters/s, {out['ms_per_step']:.0f} ms per batch")
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -205,6 +276,7 @@ def main() -> int:
     ap.add_argument("--tol", type=float, default=1e-10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--realizations", type=int, default=32, help="batch size of the Monte Carlo form (0: skip)")
+    ap.add_argument("--no-uneven", action="store_true", help="skip the uneven survey batch (N_side 512)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a 1 GiB device copy (reference kernel for HBM counters)")
     args = ap.parse_args()
@@ -295,6 +367,9 @@ def main() -> int:
     batched = None
     if args.workload == 1 and args.realizations > 0:
         batched = batched_form(ctx, p, dp, args.realizations, args.tol, args.steps, args.warmup, value)
+    uneven = None
+    if args.workload == 1 and not args.no_uneven:
+        uneven = uneven_form(ctx, args.tol, max(1, args.steps // 3), args.warmup)
 
     # the per-sample form of the same solve, for comparison with the per-sample byte model
     log("per-sample form: one profiled solve")
@@ -331,6 +406,7 @@ def main() -> int:
         "n_runs": n_runs,
         "mixed_form": mixed,
         "batched_form": batched,
+        "uneven_form": uneven,
         "iterations_per_solve": r0["iterations"],
         "iter_ms": iter_ms,
         "iteration_throughput": p.n_samples / (iter_ms * 1e-3),

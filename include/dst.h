@@ -159,8 +159,11 @@ enum {
   DST_SOLVE_NO_CANON = 1u,    /* return the raw CG iterate (skip the T mean removal) */
   DST_SOLVE_PROFILE = 2u,     /* time each kernel class with HIP events (into info) */
   DST_SOLVE_NO_GRAPH = 4u,    /* launch iterations one by one instead of a captured graph */
-  DST_SOLVE_PER_SAMPLE = 8u   /* iterate on per-sample pointing (recomputing cos 2psi, sin 2psi)
+  DST_SOLVE_PER_SAMPLE = 8u,  /* iterate on per-sample pointing (recomputing cos 2psi, sin 2psi)
                                  instead of the default run-compressed pointing */
+  DST_SOLVE_AUTOTUNE = 16u    /* time the launch shapes of the run-form binning and rescan on this
+                                 problem once (a few operator applications) and use the fastest;
+                                 the choice is kept in the context per problem shape */
 };
 typedef struct {
   double tol;               /* stop when ||r||_2 <= tol ||b||_2 (recurrence residual) */

@@ -12,6 +12,8 @@
 #include <cstdlib>
 #include <cstring>
 #include <string>
+#include <map>
+#include <tuple>
 #include <unordered_map>
 #include <vector>
 
@@ -38,6 +40,8 @@ struct dst_ctx {
   hipStream_t cap = nullptr;  // private stream on which iteration graphs are captured
   int unbin_wpb = 1;          // launch shape of the run rescan (wavefronts per baseline)
   int bin_lpp = 32;           // launch shape of the run binning (lanes per pixel)
+  // launch shapes chosen by the autotuner, per problem shape
+  std::map<std::tuple<int64_t, int64_t, int, int>, std::pair<int, int>> tuned;
 };
 
 namespace {
@@ -257,6 +261,8 @@ struct Plan {
   dst::Runs W;            // run form
   double* m4 = nullptr;   // per-iteration map (zero on invalid pixels)
   double* pw4 = nullptr;  // weighted interleaved baseline vector
+  int lpp = 32;           // launch shapes of the run binning and rescan
+  int wpb = 1;
   const int32_t* cid() const { return runs ? W.cid : T.cid; }
 };
 
@@ -405,6 +411,8 @@ int build_sample_plan(dst_ctx* ctx, const dst_problem* prob, Plan& P, const void
 
 int build_plan(dst_ctx* ctx, const dst_problem* prob, Plan& P, const void* tod, double** sd4, double** md4,
                double* b, hipStream_t st) {
+  P.lpp = ctx->bin_lpp;
+  P.wpb = ctx->unbin_wpb;
   return P.runs ? build_runs_plan(ctx, prob, P, tod, sd4, md4, b, st)
                 : build_sample_plan(ctx, prob, P, tod, sd4, md4, b, st);
 }
@@ -414,7 +422,7 @@ int build_plan(dst_ctx* ctx, const dst_problem* prob, Plan& P, const void* tod, 
 int plan_bin(dst_ctx* ctx, Plan& P, const CgCtl* gate, hipStream_t st) {
   Setup& S = P.S;
   if (P.runs)
-    HIP_TRY(dst::launch_bin_runs(S.v, P.W, P.pw4, S.Minv4, S.valid, P.m4, gate, ctx->bin_lpp, st));
+    HIP_TRY(dst::launch_bin_runs(S.v, P.W, P.pw4, S.Minv4, S.valid, P.m4, gate, P.lpp, st));
   else
     HIP_TRY(dst::launch_bin_pixel(S.v, S.psi_f32, P.T, P.pw4, S.Minv4, S.valid, P.m4, gate, st));
   return DST_OK;
@@ -423,7 +431,7 @@ int plan_bin(dst_ctx* ctx, Plan& P, const CgCtl* gate, hipStream_t st) {
 int plan_unbin(dst_ctx* ctx, Plan& P, const double* p, double* q, CgCtl* ctl, double* partials, hipStream_t st) {
   Setup& S = P.S;
   if (P.runs)
-    HIP_TRY(dst::launch_unbin_runs(S.v, P.W, P.m4, S.nvalid, p, q, ctl, partials, ctx->unbin_wpb, st));
+    HIP_TRY(dst::launch_unbin_runs(S.v, P.W, P.m4, S.nvalid, p, q, ctl, partials, P.wpb, st));
   else
     HIP_TRY(dst::launch_unbin_cg(S.v, S.psi_f32, P.m4, S.nvalid, p, q, ctl, partials, st));
   return DST_OK;
@@ -689,6 +697,67 @@ int solve_group(dst_ctx* ctx, const dst_problem* problems, const std::vector<int
   return DST_OK;
 }
 
+// Autotuner: times every launch shape of the run binning and rescan on the
+// problem itself (operator mode, best of two launches each) and keeps the
+// fastest for this problem shape in the context.  p: any baseline vector;
+// scratch: [n_streams][n_b] written by the rescan.
+int autotune(dst_ctx* ctx, Plan& P, const double* p, double* scratch, hipStream_t st) {
+  if (!P.runs) return DST_OK;
+  Setup& S = P.S;
+  const auto key = std::make_tuple(P.W.n_obs, S.v.n_b, S.v.n_streams, (int)P.W.f32);
+  auto it = ctx->tuned.find(key);
+  if (it == ctx->tuned.end()) {
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    struct Ev {
+      hipEvent_t a, b;
+      ~Ev() {
+        (void)hipEventDestroy(a);
+        (void)hipEventDestroy(b);
+      }
+    } ev{e0, e1};
+    auto time_of = [&](auto launch) -> float {
+      float best = 1e30f;
+      for (int rep = 0; rep < 2; ++rep) {
+        if (hipEventRecord(e0, st) != hipSuccess || launch() != hipSuccess || hipEventRecord(e1, st) != hipSuccess ||
+            hipEventSynchronize(e1) != hipSuccess)
+          return -1.0f;
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) return -1.0f;
+        best = std::min(best, ms);
+      }
+      return best;
+    };
+    int best_lpp = P.lpp, best_wpb = P.wpb;
+    float tb = 1e30f, tu = 1e30f;
+    for (int lpp : {64, 32, 16}) {
+      const float t = time_of([&] {
+        return dst::launch_bin_runs(S.v, P.W, P.pw4, S.Minv4, S.valid, P.m4, nullptr, lpp, st);
+      });
+      if (t < 0.f) return fail(ctx, DST_EHIP, "autotuner: a bin launch failed");
+      if (t < tb) {
+        tb = t;
+        best_lpp = lpp;
+      }
+    }
+    for (int wpb : {1, 2, 4, 8}) {
+      const float t = time_of([&] {
+        return dst::launch_unbin_runs(S.v, P.W, P.m4, S.nvalid, p, scratch, nullptr, nullptr, wpb, st);
+      });
+      if (t < 0.f) return fail(ctx, DST_EHIP, "autotuner: a rescan launch failed");
+      if (t < tu) {
+        tu = t;
+        best_wpb = wpb;
+      }
+    }
+    it = ctx->tuned.emplace(key, std::make_pair(best_lpp, best_wpb)).first;
+  }
+  P.lpp = it->second.first;
+  P.wpb = it->second.second;
+  return DST_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -845,7 +914,8 @@ int dst_solve(dst_ctx* ctx, const dst_problem* prob, const dst_solve_opts* opts_
   dst_solve_opts opts{};
   if (opts_in) opts = *opts_in;
   if (opts.reserved != 0) return fail(ctx, DST_EINVAL, "opts.reserved must be 0");
-  const uint32_t known = DST_SOLVE_NO_CANON | DST_SOLVE_PROFILE | DST_SOLVE_NO_GRAPH | DST_SOLVE_PER_SAMPLE;
+  const uint32_t known =
+      DST_SOLVE_NO_CANON | DST_SOLVE_PROFILE | DST_SOLVE_NO_GRAPH | DST_SOLVE_PER_SAMPLE | DST_SOLVE_AUTOTUNE;
   if (opts.flags & ~known) return fail(ctx, DST_EINVAL, "unknown solve flags %u", opts.flags);
   if (!(opts.tol > 0.0)) opts.tol = 1e-10;
   if (!std::isfinite(opts.tol)) return fail(ctx, DST_EINVAL, "tol must be finite");
@@ -898,6 +968,7 @@ int dst_solve(dst_ctx* ctx, const dst_problem* prob, const dst_solve_opts* opts_
   }
   HIP_TRY(dst::launch_cg_start(v, b, ka_ptr, opts.a0, a, r, z, p, S.J, ctl, partials, opts.tol, opts.max_iter, st));
   HIP_TRY(dst::launch_p_update4(v, p, nullptr, P.pw4, nullptr, 0, st));
+  if (opts.flags & DST_SOLVE_AUTOTUNE) DST_TRY(autotune(ctx, P, p, ka, st));
   HIP_TRY(hipEventRecord(ev[1], st));
   HIP_TRY(hipMemcpyAsync(ctx->ctl_host, ctl, sizeof(CgCtl), hipMemcpyDeviceToHost, st));
   DST_TRY(finish(ctx, &S, st));
@@ -1040,7 +1111,7 @@ int dst_solve_batched(dst_ctx* ctx, int32_t n_problems, const dst_problem* probl
   if (opts_in) opts = *opts_in;
   if (opts.reserved != 0) return fail(ctx, DST_EINVAL, "opts.reserved must be 0");
   if (opts.a0) return fail(ctx, DST_EINVAL, "opts.a0 is not supported by the batched solve");
-  const uint32_t known = DST_SOLVE_NO_CANON | DST_SOLVE_PROFILE | DST_SOLVE_NO_GRAPH;
+  const uint32_t known = DST_SOLVE_NO_CANON | DST_SOLVE_PROFILE | DST_SOLVE_NO_GRAPH | DST_SOLVE_AUTOTUNE;
   if (opts.flags & ~known) return fail(ctx, DST_EINVAL, "unknown or unsupported solve flags %u", opts.flags);
   if (!(opts.tol > 0.0)) opts.tol = 1e-10;
   if (!std::isfinite(opts.tol)) return fail(ctx, DST_EINVAL, "tol must be finite");

@@ -27,6 +27,7 @@ STREAMS = {"T": 1, "QU": 6, "TQU": 7}
 N_STREAMS = {"T": 1, "QU": 2, "TQU": 3}
 DST_BIN_USE_TOD, DST_BIN_MAP = 1, 2
 DST_SOLVE_NO_CANON, DST_SOLVE_PROFILE, DST_SOLVE_NO_GRAPH, DST_SOLVE_PER_SAMPLE = 1, 2, 4, 8
+DST_SOLVE_AUTOTUNE = 16
 DST_NOISE_ACCUMULATE = 1
 
 EXPORTS = ("dst_version", "dst_create", "dst_destroy", "dst_last_error", "dst_pixel_setup", "dst_bin", "dst_unbin",

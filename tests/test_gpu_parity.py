@@ -234,3 +234,15 @@ def test_errors(ctx):
     with pytest.raises(dst.DstError) as e:
         dst.dst_solve(ctx, q)
     assert e.value.code == -5
+
+
+def test_autotuned_solve_matches(ctx):
+    """The autotuner only changes launch shapes: same iterations (within one), same solution."""
+    from paper_1309_5609_amd import dst
+    p = toy(n_samples=30000, nside=16)
+    d = dev(p)
+    ref = dst.dst_solve(ctx, d, tol=1e-12)
+    for _ in range(2):  # tuning run, then a run from the context's cache
+        out = dst.dst_solve(ctx, d, tol=1e-12, flags=dst.DST_SOLVE_AUTOTUNE)
+        assert abs(out["iterations"] - ref["iterations"]) <= 1
+        assert rel(out["baselines"].cpu().numpy(), ref["baselines"].cpu().numpy()) < 1e-9
