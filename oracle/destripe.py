@@ -345,6 +345,94 @@ def pcg(st: Setup, b3: np.ndarray, tol: float, max_iter: int, a0=None) -> PCGRes
     return PCGResult(a, it, converged, rel, true, hist)
 
 
+@dataclass
+class GMRESResult:
+    a: np.ndarray
+    iterations: int
+    converged: bool
+    rel_residual: float  # the least-squares residual estimate at exit
+    true_rel_residual: float
+    history: list
+
+
+def gmres_core(op, b, M, tol: float, restart: int, max_iter: int, x0=None):
+    """Restarted GMRES(m) (Saad & Schultz 1986) for ``op(x) = b`` with right preconditioner ``diag(M)``.
+
+    Each cycle: Arnoldi with modified Gram-Schmidt on ``op(M v)`` builds an
+    orthonormal basis ``V`` and the Hessenberg matrix ``H``; Givens rotations
+    triangularise ``H`` column by column, so ``|g[j+1]|`` is the residual norm of
+    the minimiser of ``||beta e1 - H y||`` over the current Krylov space; after
+    ``restart`` steps, convergence, or ``max_iter``, ``x += M (V y)`` and the
+    next cycle starts from the new residual.  Returns
+    ``(x, iterations, converged, estimate, history)`` with the estimate and
+    history relative to ``||b||``.
+    """
+    b = np.asarray(b, dtype=np.float64)
+    bnorm = float(np.linalg.norm(b))
+    x = np.zeros_like(b) if x0 is None else np.array(x0, dtype=np.float64)
+    if bnorm == 0.0:
+        return x, 0, True, 0.0, []
+    r = b - op(x) if x0 is not None else b.copy()
+    beta = float(np.linalg.norm(r))
+    rel = beta / bnorm
+    it, hist = 0, []
+    while rel > tol and it < max_iter and beta > 0.0:
+        m = int(restart)
+        V = [r / beta]
+        H = np.zeros((m + 1, m))
+        cs, sn = np.zeros(m), np.zeros(m)
+        g = np.zeros(m + 1)
+        g[0] = beta
+        k = 0
+        for j in range(m):
+            w = op(M * V[j])
+            for i in range(j + 1):
+                H[i, j] = float(np.sum(w * V[i]))
+                w = w - H[i, j] * V[i]
+            hn = float(np.linalg.norm(w))
+            H[j + 1, j] = hn
+            for i in range(j):
+                t = cs[i] * H[i, j] + sn[i] * H[i + 1, j]
+                H[i + 1, j] = -sn[i] * H[i, j] + cs[i] * H[i + 1, j]
+                H[i, j] = t
+            den = float(np.hypot(H[j, j], H[j + 1, j]))
+            cs[j], sn[j] = H[j, j] / den, H[j + 1, j] / den
+            H[j, j], H[j + 1, j] = den, 0.0
+            g[j + 1] = -sn[j] * g[j]
+            g[j] = cs[j] * g[j]
+            it += 1
+            k = j + 1
+            rel = abs(g[j + 1]) / bnorm
+            hist.append(rel)
+            if rel <= tol or it >= max_iter or hn == 0.0:
+                break
+            V.append(w / hn)
+        y = np.zeros(k)
+        for i in range(k - 1, -1, -1):  # back substitution on the triangularised H
+            y[i] = (g[i] - np.dot(H[i, i + 1:k], y[i + 1:k])) / H[i, i]
+        x = x + M * sum(y[i] * V[i] for i in range(k))
+        r = b - op(x)
+        beta = float(np.linalg.norm(r))
+    return x, it, rel <= tol, rel, hist
+
+
+def gmres(st: Setup, b3: np.ndarray, tol: float, max_iter: int, restart: int = 50, a0=None) -> GMRESResult:
+    """Eq. 13 by restarted GMRES with the Jacobi diagonal as right preconditioner.
+
+    Works on the same projected operator as ``pcg`` (the T null vectors
+    removed from ``b`` and from every ``K v``).
+    """
+    J = jacobi(st)
+    proj = null_projector(st)
+    b3 = proj(b3)
+    bnorm = float(np.sqrt(np.sum(b3 * b3)))
+    if bnorm == 0.0:
+        return GMRESResult(np.zeros_like(b3), 0, True, 0.0, 0.0, [])
+    a, it, conv, rel, hist = gmres_core(lambda x: proj(apply_K(st, x)), b3, J, tol, restart, max_iter, a0)
+    true = float(np.sqrt(np.sum((b3 - apply_K(st, a)) ** 2))) / bnorm
+    return GMRESResult(a, it, conv, rel, true, hist)
+
+
 def null_projector(st: Setup):
     """Orthogonal projector removing the T null vectors (one per component)."""
     if st.pt.rows[0] is None:
@@ -418,13 +506,16 @@ class Solution:
 
 
 def solve(pix, psi, tod, n_pix: int, L: int, streams: str, weights, tol: float = 1e-10,
-          max_iter: int = 1000, rcond_cut: float = 1e-3) -> Solution:
-    """Full destriping of one channel: hits, binned map, baselines, destriped map."""
+          max_iter: int = 1000, rcond_cut: float = 1e-3, solver: str = "pcg", restart: int = 50) -> Solution:
+    """Full destriping of one channel: hits, binned map, baselines, destriped map.
+
+    ``solver``: "pcg" (default) or "gmres" (restarted every ``restart`` steps).
+    """
     pt = make_pointing(pix, psi, n_pix, L, streams, weights, rcond_cut)
     st = setup(pt)
     d3 = _full(pt, tod)
     b = rhs(st, d3)
-    res = pcg(st, b, tol, max_iter)
+    res = pcg(st, b, tol, max_iter) if solver == "pcg" else gmres(st, b, tol, max_iter, restart)
     a = canonicalise(st, res.a)
     binned = map_from(st, d3)
     destriped = map_from(st, d3 - expand(pt, a))
