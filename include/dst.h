@@ -161,16 +161,20 @@ enum {
   DST_SOLVE_NO_GRAPH = 4u,    /* launch iterations one by one instead of a captured graph */
   DST_SOLVE_PER_SAMPLE = 8u,  /* iterate on per-sample pointing (recomputing cos 2psi, sin 2psi)
                                  instead of the default run-compressed pointing */
-  DST_SOLVE_AUTOTUNE = 16u    /* time the launch shapes of the run-form binning and rescan on this
+  DST_SOLVE_AUTOTUNE = 16u,   /* time the launch shapes of the run-form binning and rescan on this
                                  problem once (a few operator applications) and use the fastest;
                                  the choice is kept in the context per problem shape */
+  DST_SOLVE_GMRES = 32u       /* restarted GMRES (Saad & Schultz 1986, the solver of the paper's
+                                 implementation) with the same Jacobi diagonal as right
+                                 preconditioner, instead of PCG; tol applies to the GMRES
+                                 residual estimate ||b - K a|| / ||b|| */
 };
 typedef struct {
   double tol;               /* stop when ||r||_2 <= tol ||b||_2 (recurrence residual) */
   int32_t max_iter;
   int32_t check_every;      /* iterations per host convergence check (<= 0: automatic) */
   uint32_t flags;
-  int32_t reserved;
+  int32_t restart;          /* GMRES restart length in [1, 126] (0: 50); must be 0 without DST_SOLVE_GMRES */
   const double* a0;         /* device [n_streams][n_b] initial guess, or NULL for 0 */
 } dst_solve_opts;
 

@@ -15,7 +15,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libdst.so")
-SOURCES = ["dst_kernels.hip", "dst_pixel.hip", "dst_runs.hip", "dst_multi.hip", "dst_pointing.hip", "dst_noise.hip", "dst_api.hip"]
+SOURCES = ["dst_kernels.hip", "dst_pixel.hip", "dst_runs.hip", "dst_multi.hip", "dst_pointing.hip", "dst_noise.hip", "dst_gmres.hip", "dst_api.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",

@@ -697,6 +697,120 @@ int solve_group(dst_ctx* ctx, const dst_problem* problems, const std::vector<int
   return DST_OK;
 }
 
+// Restarted GMRES on K a = b (Eq. 13), right-preconditioned by the Jacobi
+// diagonal J, with the same T null-space projection as the PCG (b and every
+// K v lose their mean over T-valid baselines).  Arnoldi by classical
+// Gram-Schmidt with one reorthogonalisation (two batched dot / combine
+// passes); Givens rotations and the triangular solve on the host.  On entry
+// b is projected, a holds a0 (or 0), r = b - P K a0 and ctl_host the start-up
+// scalars (b_norm, r_norm, n_e).  q is scratch.  *fin receives iterations,
+// stop code and the residual estimate for the common exit path.
+int gmres_loop(dst_ctx* ctx, Plan& P, const View& v, const double* b, double* a, double* r, double* q,
+               const dst_solve_opts& opts, CgCtl* fin, hipStream_t st) {
+  Setup& S = P.S;
+  const int64_t N = (int64_t)v.n_streams * v.n_b;
+  const int m = opts.restart > 0 ? opts.restart : 50;
+  const CgCtl h0 = *ctx->ctl_host;
+  const double bnorm = h0.b_norm, n_e = h0.n_e;
+  double *V, *z, *part, *dots;
+  DST_TRY(ws(ctx, "gm_V", (size_t)(m + 2) * N, &V));  // slot 0: T mask e; slots 1..m+1: basis
+  DST_TRY(ws(ctx, "gm_z", N, &z));
+  DST_TRY(ws(ctx, "gm_part", (size_t)(m + 2) * dst::gmres_dot_blocks(N), &part));
+  DST_TRY(ws(ctx, "gm_dots", m + 2, &dots));
+  double* e = V;
+  auto slot = [&](int i) { return V + (int64_t)(i + 1) * N; };  // basis vector i
+  HIP_TRY(dst::launch_tmask(v, S.J, e, st));
+  std::vector<double> hd(m + 2);
+  auto dot_with = [&](const double* base, int k, const double* w) -> int {
+    HIP_TRY(dst::launch_dots(base, N, k, w, N, part, dots, st));
+    HIP_TRY(hipMemcpyAsync(hd.data(), dots, k * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    return DST_OK;
+  };
+  int it = 0;
+  double rel = bnorm > 0.0 ? h0.r_norm / bnorm : 0.0;
+  double beta = h0.r_norm;
+  bool broke = false;
+  std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), y(m);
+  auto Hij = [&](int i, int j) -> double& { return H[(size_t)i * m + j]; };
+  if (bnorm > 0.0 && beta > 0.0 && rel > opts.tol && opts.max_iter > 0) {
+    HIP_TRY(dst::launch_scale(r, 1.0 / beta, nullptr, slot(0), N, st));
+  }
+  while (bnorm > 0.0 && beta > 0.0 && rel > opts.tol && it < opts.max_iter && !broke) {
+    std::fill(H.begin(), H.end(), 0.0);
+    std::fill(g.begin(), g.end(), 0.0);
+    g[0] = beta;
+    int k = 0;
+    for (int j = 0; j < m; ++j) {
+      // w = P K J v_j
+      HIP_TRY(dst::launch_scale(slot(j), 0.0, S.J, z, N, st));
+      DST_TRY(plan_operator(ctx, P, z, q, st));
+      DST_TRY(dot_with(V, j + 2, q));  // e.w, v_0.w .. v_j.w
+      dst::GmresCoef c{};
+      c.c[0] = n_e > 0.0 ? hd[0] / n_e : 0.0;
+      for (int i = 0; i <= j; ++i) {
+        c.c[i + 1] = hd[i + 1];
+        Hij(i, j) = hd[i + 1];
+      }
+      HIP_TRY(dst::launch_combine(q, V, N, j + 2, c, N, st));
+      DST_TRY(dot_with(slot(0), j + 1, q));  // reorthogonalisation
+      dst::GmresCoef c2{};
+      for (int i = 0; i <= j; ++i) {
+        c2.c[i] = hd[i];
+        Hij(i, j) += hd[i];
+      }
+      HIP_TRY(dst::launch_combine(q, slot(0), N, j + 1, c2, N, st));
+      DST_TRY(dot_with(q, 1, q));
+      const double hn = std::sqrt(std::max(hd[0], 0.0));
+      Hij(j + 1, j) = hn;
+      for (int i = 0; i < j; ++i) {
+        const double t = cs[i] * Hij(i, j) + sn[i] * Hij(i + 1, j);
+        Hij(i + 1, j) = -sn[i] * Hij(i, j) + cs[i] * Hij(i + 1, j);
+        Hij(i, j) = t;
+      }
+      const double den = std::hypot(Hij(j, j), Hij(j + 1, j));
+      if (!(den > 0.0) || !std::isfinite(den)) {
+        broke = true;
+        break;
+      }
+      cs[j] = Hij(j, j) / den;
+      sn[j] = Hij(j + 1, j) / den;
+      Hij(j, j) = den;
+      Hij(j + 1, j) = 0.0;
+      g[j + 1] = -sn[j] * g[j];
+      g[j] = cs[j] * g[j];
+      ++it;
+      k = j + 1;
+      rel = std::fabs(g[j + 1]) / bnorm;
+      if (rel <= opts.tol || it >= opts.max_iter || hn == 0.0) break;
+      HIP_TRY(dst::launch_scale(q, 1.0 / hn, nullptr, slot(j + 1), N, st));
+    }
+    if (k == 0) break;
+    for (int i = k - 1; i >= 0; --i) {
+      double sum = g[i];
+      for (int l = i + 1; l < k; ++l) sum -= Hij(i, l) * y[l];
+      y[i] = sum / Hij(i, i);
+    }
+    dst::GmresCoef yc{};
+    for (int i = 0; i < k; ++i) yc.c[i] = y[i];
+    HIP_TRY(dst::launch_xupdate(a, S.J, slot(0), N, k, yc, N, st));
+    if (rel <= opts.tol || it >= opts.max_iter || broke) break;
+    // restart from r = b - P K a
+    DST_TRY(plan_operator(ctx, P, a, q, st));
+    DST_TRY(dot_with(e, 1, q));
+    const double mu = n_e > 0.0 ? hd[0] / n_e : 0.0;
+    HIP_TRY(dst::launch_restart_resid(b, q, mu, e, r, N, st));
+    DST_TRY(dot_with(r, 1, r));
+    beta = std::sqrt(std::max(hd[0], 0.0));
+    if (beta > 0.0) HIP_TRY(dst::launch_scale(r, 1.0 / beta, nullptr, slot(0), N, st));
+  }
+  *fin = h0;
+  fin->iter = it;
+  fin->r_norm = rel * bnorm;
+  fin->done = !std::isfinite(rel) ? dst::DONE_NAN : (rel <= opts.tol ? dst::DONE_CONVERGED : dst::DONE_MAXITER);
+  return DST_OK;
+}
+
 // Autotuner: times every launch shape of the run binning and rescan on the
 // problem itself (operator mode, best of two launches each) and keeps the
 // fastest for this problem shape in the context.  p: any baseline vector;
@@ -913,9 +1027,12 @@ int dst_solve(dst_ctx* ctx, const dst_problem* prob, const dst_solve_opts* opts_
   if (!baselines_out) return fail(ctx, DST_EINVAL, "baselines_out is NULL");
   dst_solve_opts opts{};
   if (opts_in) opts = *opts_in;
-  if (opts.reserved != 0) return fail(ctx, DST_EINVAL, "opts.reserved must be 0");
-  const uint32_t known =
-      DST_SOLVE_NO_CANON | DST_SOLVE_PROFILE | DST_SOLVE_NO_GRAPH | DST_SOLVE_PER_SAMPLE | DST_SOLVE_AUTOTUNE;
+  const uint32_t known = DST_SOLVE_NO_CANON | DST_SOLVE_PROFILE | DST_SOLVE_NO_GRAPH | DST_SOLVE_PER_SAMPLE |
+                         DST_SOLVE_AUTOTUNE | DST_SOLVE_GMRES;
+  const bool use_gmres = opts.flags & DST_SOLVE_GMRES;
+  if (!use_gmres && opts.restart != 0) return fail(ctx, DST_EINVAL, "opts.restart is for DST_SOLVE_GMRES only");
+  if (opts.restart < 0 || opts.restart > dst::kMaxKrylov - 2)
+    return fail(ctx, DST_EINVAL, "opts.restart must be in [0, %d]", dst::kMaxKrylov - 2);
   if (opts.flags & ~known) return fail(ctx, DST_EINVAL, "unknown solve flags %u", opts.flags);
   if (!(opts.tol > 0.0)) opts.tol = 1e-10;
   if (!std::isfinite(opts.tol)) return fail(ctx, DST_EINVAL, "tol must be finite");
@@ -1015,6 +1132,13 @@ int dst_solve(dst_ctx* ctx, const dst_problem* prob, const dst_solve_opts* opts_
     return DST_OK;
   };
 
+  CgCtl fin{};
+  if (use_gmres) {
+    // restarted GMRES from the projected residual of the start-up
+    HIP_TRY(hipEventRecord(ev[2], st));
+    DST_TRY(gmres_loop(ctx, P, v, b, a, r, q, opts, &fin, st));
+    HIP_TRY(hipEventRecord(ev[3], st));
+  } else {
   // batches of check_every iterations, replayed from one captured graph
   // unless profiling or asked not to
   CgCtl& h = *ctx->ctl_host;
@@ -1036,7 +1160,8 @@ int dst_solve(dst_ctx* ctx, const dst_problem* prob, const dst_solve_opts* opts_
     HIP_TRY(hipStreamSynchronize(st));
   }
   HIP_TRY(hipEventRecord(ev[3], st));
-  const CgCtl fin = h;
+  fin = h;
+  }
 
   // canonical baselines, true residual, maps (destriped = m_d - M^-1 A^T W F a)
   if (!(opts.flags & DST_SOLVE_NO_CANON)) HIP_TRY(dst::launch_canonicalise(v, a, S.J, partials, ctl, st));
@@ -1109,7 +1234,7 @@ int dst_solve_batched(dst_ctx* ctx, int32_t n_problems, const dst_problem* probl
   if (!baselines_out) return fail(ctx, DST_EINVAL, "baselines_out is NULL");
   dst_solve_opts opts{};
   if (opts_in) opts = *opts_in;
-  if (opts.reserved != 0) return fail(ctx, DST_EINVAL, "opts.reserved must be 0");
+  if (opts.restart != 0) return fail(ctx, DST_EINVAL, "opts.restart must be 0 in the batched solve");
   if (opts.a0) return fail(ctx, DST_EINVAL, "opts.a0 is not supported by the batched solve");
   const uint32_t known = DST_SOLVE_NO_CANON | DST_SOLVE_PROFILE | DST_SOLVE_NO_GRAPH | DST_SOLVE_AUTOTUNE;
   if (opts.flags & ~known) return fail(ctx, DST_EINVAL, "unknown or unsupported solve flags %u", opts.flags);

@@ -101,4 +101,22 @@ hipError_t launch_noise(uint64_t seed, uint64_t stream, int64_t n, int64_t S, do
                         double alpha, void* out, int out_f32, int accumulate, double2* buf0, double2* buf1,
                         hipStream_t st);
 
+// ---- restarted GMRES vector kernels (dst_gmres.hip) ------------------------
+constexpr int kMaxKrylov = 128;  // basis vectors + the T mask in one dot / combine launch
+struct GmresCoef {
+  double c[kMaxKrylov];
+};
+int gmres_dot_blocks(int64_t N);
+hipError_t launch_tmask(const View& v, const double* J, double* e, hipStream_t st);
+// out[i] = V_i . w for i < k (V_i = V + i ldv); partial: k * gmres_dot_blocks(N) doubles.
+hipError_t launch_dots(const double* V, int64_t ldv, int k, const double* w, int64_t N, double* partial, double* out,
+                       hipStream_t st);
+hipError_t launch_combine(double* w, const double* V, int64_t ldv, int k, const GmresCoef& c, int64_t N,
+                          hipStream_t st);
+hipError_t launch_scale(const double* w, double s, const double* J, double* out, int64_t N, hipStream_t st);
+hipError_t launch_xupdate(double* x, const double* J, const double* V, int64_t ldv, int k, const GmresCoef& y,
+                          int64_t N, hipStream_t st);
+hipError_t launch_restart_resid(const double* b, const double* q, double mu, const double* e, double* r, int64_t N,
+                                hipStream_t st);
+
 }  // namespace dst

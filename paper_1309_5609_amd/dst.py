@@ -28,6 +28,7 @@ N_STREAMS = {"T": 1, "QU": 2, "TQU": 3}
 DST_BIN_USE_TOD, DST_BIN_MAP = 1, 2
 DST_SOLVE_NO_CANON, DST_SOLVE_PROFILE, DST_SOLVE_NO_GRAPH, DST_SOLVE_PER_SAMPLE = 1, 2, 4, 8
 DST_SOLVE_AUTOTUNE = 16
+DST_SOLVE_GMRES = 32
 DST_NOISE_ACCUMULATE = 1
 
 EXPORTS = ("dst_version", "dst_create", "dst_destroy", "dst_last_error", "dst_pixel_setup", "dst_bin", "dst_unbin",
@@ -44,7 +45,7 @@ class dst_problem(ctypes.Structure):
 
 class dst_solve_opts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("max_iter", ctypes.c_int32), ("check_every", ctypes.c_int32),
-                ("flags", ctypes.c_uint32), ("reserved", ctypes.c_int32), ("a0", ctypes.c_void_p)]
+                ("flags", ctypes.c_uint32), ("restart", ctypes.c_int32), ("a0", ctypes.c_void_p)]
 
 
 class dst_solve_info(ctypes.Structure):
@@ -284,7 +285,7 @@ def dst_apply_operator(ctx: Context, prob: Problem, v):
 
 
 def dst_solve(ctx: Context, prob: Problem, tol: float = 1e-10, max_iter: int = 1000, a0=None, flags: int = 0,
-              check_every: int = 0, maps: bool = True, allow_noconv: bool = True) -> dict:
+              check_every: int = 0, maps: bool = True, allow_noconv: bool = True, restart: int = 0) -> dict:
     """Destripe: baselines, destriped and binned maps, hits and solver info."""
     import torch
     dev = prob.pix.device
@@ -297,7 +298,7 @@ def dst_solve(ctx: Context, prob: Problem, tol: float = 1e-10, max_iter: int = 1
     opts.max_iter = max_iter
     opts.check_every = check_every
     opts.flags = flags
-    opts.reserved = 0
+    opts.restart = restart
     opts.a0 = None if a0 is None else a0.data_ptr()
     info = dst_solve_info()
     s = prob.c_struct()
@@ -346,7 +347,7 @@ def dst_solve_batched(ctx: Context, probs, tol: float = 1e-10, max_iter: int = 1
     opts.max_iter = max_iter
     opts.check_every = check_every
     opts.flags = flags
-    opts.reserved = 0
+    opts.restart = 0
     opts.a0 = None
     infos = (dst_solve_info * n)()
     allow = (DST_OK, DST_ENOCONV) if allow_noconv else (DST_OK,)
