@@ -22,7 +22,7 @@ from __future__ import annotations
 import numpy as np
 import scipy.sparse as sp
 
-_ROWS = {"TQU": (0, 1, 2), "QU": (1, 2), "T": (0,)}
+_ROWS = {"TQU": (0, 1, 2), "QU": (1, 2), "T": (0,), "IQU": (0,)}
 
 
 def _entries(pix, psi, n_pix, streams, weights, rcond_cut):
@@ -38,7 +38,10 @@ def _entries(pix, psi, n_pix, streams, weights, rcond_cut):
     ts, ks, rs, As = [], [], [], []
     for row, k in enumerate(present):
         A = np.zeros((n_t, 3))
-        if k == 0:
+        if streams == "IQU":  # radiometer row (1, cos 2psi, sin 2psi)
+            ang = 2.0 * np.asarray(psi, dtype=np.float64)
+            A[:, 0], A[:, 1], A[:, 2] = 1.0, np.cos(ang), np.sin(ang)
+        elif k == 0:
             A[:, 0] = 1.0
         else:
             ang = 2.0 * np.asarray(psi, dtype=np.float64)
@@ -70,6 +73,12 @@ def _entries(pix, psi, n_pix, streams, weights, rcond_cut):
         for q in obs:
             ev = np.linalg.eigvalsh(M[q, 1:, 1:])
             okQU[q] = ev[0] > 0 and ev[0] / ev[1] >= rcond_cut
+    if streams == "IQU":
+        okT = np.zeros(n_pix, dtype=bool)
+        for q in np.nonzero(hits > 0)[0]:
+            ev = np.linalg.eigvalsh(M[q])
+            okT[q] = ev[0] > 0 and ev[0] / ev[2] >= rcond_cut
+        okQU = okT.copy()
     pp = np.where(good, p, 0)
     ok = good & np.where(k == 0, okT[pp], okQU[pp])
     return dict(t=t, k=k, row=row, p=p, A=A, w=w, ok=ok, present=present, M=M, okT=okT, okQU=okQU)

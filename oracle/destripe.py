@@ -33,6 +33,12 @@ the design notes):
   reduce exactly to the paper's unweighted form.
 * The T stream is solved in the same system; the per-pixel matrix is block
   diagonal (T | QU), so this equals destriping T separately.
+* Streams "IQU": one polarisation-sensitive radiometer stream with row
+  ``A = (1, cos 2psi, sin 2psi)`` (the remark after Eqs. 10-11 that such a
+  detector needs the full 3x3 per-pixel inverse); its block is valid when
+  ``lambda_min > 0`` and ``lambda_min / lambda_max >= rcond_cut`` over all
+  three eigenvalues.  A constant offset on its baselines is again a null
+  vector (it equals a constant I map), handled like the T stream's.
 * A block is valid when T: ``h_p > 0``; QU: ``lambda_min > 0`` and
   ``lambda_min / lambda_max >= rcond_cut``.  Samples on invalid blocks are
   dropped from that stream (both from binning and from ``F^T``).
@@ -59,7 +65,7 @@ import numpy as np
 import scipy.sparse as sp
 from scipy.sparse.csgraph import connected_components
 
-ROWS = {"TQU": (0, 1, 2), "QU": (1, 2), "T": (0,)}
+ROWS = {"TQU": (0, 1, 2), "QU": (1, 2), "T": (0,), "IQU": (0,)}
 
 
 def n_baselines(n_t: int, L: int) -> int:
@@ -106,6 +112,11 @@ def make_pointing(pix, psi, n_pix: int, L: int, streams: str, weights, rcond_cut
     for k in present:
         w[k] = float(weights[k])
     rows = [None, None, None]
+    if streams == "IQU":
+        # one polarisation-sensitive radiometer stream: A = (1, cos 2psi, sin 2psi)
+        two = 2.0 * np.asarray(psi, dtype=np.float64)
+        rows[0] = (np.ones(n_t), np.cos(two), np.sin(two))
+        return Pointing(pix, int(n_pix), int(L), streams, w, rows, float(rcond_cut))
     if 0 in present:
         one = np.ones(n_t)
         zero = np.zeros(n_t)
@@ -150,6 +161,16 @@ def block_inverse(pt: Pointing, M: np.ndarray, hits: np.ndarray):
     Minv = np.zeros((n, 3, 3))
     valid_T = np.zeros(n, dtype=bool)
     valid_QU = np.zeros(n, dtype=bool)
+    if pt.streams == "IQU":
+        # the full 3x3 block: valid when lambda_min > 0 and lambda_min / lambda_max >= rcond_cut
+        lam = np.linalg.eigvalsh(M)
+        lmin, lmax = lam[:, 0], lam[:, 2]
+        with np.errstate(divide="ignore", invalid="ignore"):
+            rc = np.where(lmax > 0, lmin / lmax, 0.0)
+        valid = (hits > 0) & (lmin > 0) & (rc >= pt.rcond_cut)
+        if np.any(valid):
+            Minv[valid] = np.linalg.inv(M[valid])
+        return Minv, valid, valid.copy()
     if pt.rows[0] is not None:
         valid_T = hits > 0
         Minv[valid_T, 0, 0] = 1.0 / M[valid_T, 0, 0]

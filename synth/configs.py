@@ -43,8 +43,9 @@ from .healpix_ring import nside2npix
 from .noise import segmented
 from .scan import ScanSpec, pointing
 
-STREAM_INDEX = {"T": 0, "q": 1, "u": 2}
-STREAM_SETS = {"TQU": ("T", "q", "u"), "QU": ("q", "u"), "T": ("T",)}
+# "r": one stream of a polarisation-sensitive radiometer, d = I + Q cos 2psi + U sin 2psi
+STREAM_INDEX = {"T": 0, "q": 1, "u": 2, "r": 0}
+STREAM_SETS = {"TQU": ("T", "q", "u"), "QU": ("q", "u"), "T": ("T",), "IQU": ("r",)}
 
 DAY_S = 86400.0
 
@@ -109,6 +110,8 @@ def signal_timelines(sky: np.ndarray, pix: np.ndarray, psi, streams: str, out: n
         for row, name in enumerate(names):
             if name == "T":
                 sig = sky[pp, 0]
+            elif name == "r":
+                sig = sky[pp, 0] + sky[pp, 1] * c + sky[pp, 2] * s
             elif name == "q":
                 sig = sky[pp, 1] * c + sky[pp, 2] * s
             else:

@@ -109,7 +109,7 @@ def test_signal_only_map_equals_sky():
 
 # --------------------------------------------------------------------------- operator pins
 
-@pytest.mark.parametrize("variant", ["plain", "masked", "ragged", "unequal", "QU", "T"])
+@pytest.mark.parametrize("variant", ["plain", "masked", "ragged", "unequal", "QU", "T", "IQU"])
 def test_operator_matches_dense(variant):
     kw = {}
     if variant == "masked":
@@ -118,15 +118,13 @@ def test_operator_matches_dense(variant):
         kw["n_samples"] = 1457
     if variant == "unequal":
         kw["weights"] = (2.0, 5.0, 0.7)
-    if variant in ("QU", "T"):
+    if variant in ("QU", "T", "IQU"):
         kw["streams"] = variant
     p = tiny(**kw)
     st = O.prepare(p.pix, p.psi, p.n_pix, p.baseline_length, p.streams, p.weights)
     K, b, a = D.eliminated(*args(p))
     rng = np.random.default_rng(3)
-    v = rng.standard_normal((len(p.streams) if p.streams != "TQU" else 3, p.n_baselines))
-    if p.streams == "QU":
-        v = rng.standard_normal((2, p.n_baselines))
+    v = rng.standard_normal((len(O.ROWS[p.streams]), p.n_baselines))
     Kv = O.K_compact(st, v)
     assert rel(Kv.ravel(), K @ v.ravel()) < 1e-12
     assert rel(O.rhs_compact(st, p.tod).ravel(), b) < 1e-12
@@ -165,7 +163,7 @@ def test_dense_K_psd_and_null_space():
 
 # --------------------------------------------------------------------------- solve pins
 
-@pytest.mark.parametrize("variant", ["plain", "masked", "ragged", "unequal", "QU", "T"])
+@pytest.mark.parametrize("variant", ["plain", "masked", "ragged", "unequal", "QU", "T", "IQU"])
 def test_solve_matches_dense_and_joint(variant):
     kw = {}
     if variant == "masked":
@@ -174,7 +172,7 @@ def test_solve_matches_dense_and_joint(variant):
         kw["n_samples"] = 1457
     if variant == "unequal":
         kw["weights"] = (2.0, 5.0, 0.7)
-    if variant in ("QU", "T"):
+    if variant in ("QU", "T", "IQU"):
         kw["streams"] = variant
     p = tiny(**kw)
     sol = O.solve(*args(p), tol=1e-14, max_iter=2000)
@@ -299,3 +297,38 @@ def test_planted_transposed_binning_is_caught(monkeypatch):
         return pt
 
     assert _mutated_K_error(monkeypatch, lambda mp: mp.setattr(O, "make_pointing", bad)) > 1e-3
+
+
+# --------------------------------------------------------------------------- radiometer rows
+
+def test_iqu_block_cut_bites():
+    """A pixel seen at only two angles has a rank-2 3x3 block: it is cut and its samples leave the stream."""
+    pix = np.array([0, 0, 0, 0, 1, 1, 1, 1, 1, 1])
+    psi = np.array([0.0, 0.3, 0.0, 0.3, 0.0, 0.4, 0.9, 1.3, 0.2, 0.7])
+    st = O.prepare(pix, psi, 2, 5, "IQU", (4.0, 0.0, 0.0))
+    assert not st.valid_T[0] and st.valid_T[1]
+    assert np.array_equal(st.v[0], [0, 0, 0, 0, 1, 1, 1, 1, 1, 1])
+    # brute-force block of pixel 1 and its eigenvalue ratio
+    M = np.zeros((3, 3))
+    for t in range(4, 10):
+        a = np.array([1.0, np.cos(2 * psi[t]), np.sin(2 * psi[t])])
+        M += 4.0 * np.outer(a, a)
+    assert np.allclose(st.M[1], M, rtol=0, atol=1e-13)
+    assert np.allclose(st.Minv[1] @ M, np.eye(3), atol=1e-12)
+    lam = np.linalg.eigvalsh(st.M[0])
+    assert lam[0] <= 1e-12 * lam[-1]
+    # a cut that rejects pixel 1 as well
+    lam1 = np.linalg.eigvalsh(M)
+    st2 = O.prepare(pix, psi, 2, 5, "IQU", (4.0, 0.0, 0.0), rcond_cut=1.01 * lam1[0] / lam1[-1])
+    assert not st2.valid_T.any()
+
+
+def test_iqu_signal_only_map_and_null_baselines():
+    p = toy(streams="IQU", noise=False, n_samples=20000, L=400)
+    st = O.prepare(p.pix, p.psi, p.n_pix, p.baseline_length, p.streams, p.weights)
+    m = O.map_compact(st, p.tod)
+    ok = st.valid_T
+    assert ok.sum() > 20 and (~ok & (st.hits > 0)).sum() > 20  # the cut keeps some pixels and drops others
+    assert rel(m[ok], p.sky[ok]) < 1e-12
+    sol = O.solve(*args(p), tol=1e-12)
+    assert np.max(np.abs(sol.baselines)) <= 1e-12 * np.sqrt(np.mean(p.tod ** 2))
