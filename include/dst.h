@@ -74,8 +74,14 @@ typedef enum {
 typedef enum { DST_F32 = 1, DST_F64 = 2 } dst_dtype;
 
 /* Stream sets.  q and u always come together (the two channels of a
- * polarimeter, Algorithm section). */
-enum { DST_T = 1u, DST_Q = 2u, DST_U = 4u, DST_QU = 6u, DST_TQU = 7u };
+ * polarimeter, Algorithm section).  DST_IQU is one stream of a
+ * polarisation-sensitive radiometer, d = I + Q cos 2psi + U sin 2psi, whose
+ * pixels need the full 3x3 block (the remark after Eqs. 10-11); it is weighted
+ * by weight[0] and its block cut by rcond_cut over all three eigenvalues.
+ * DST_IQU is accepted by dst_solve (run form), dst_apply_operator and
+ * dst_solve_batched (each such problem on its own); the other entry points
+ * and DST_SOLVE_PER_SAMPLE return DST_EINVAL for it. */
+enum { DST_T = 1u, DST_Q = 2u, DST_U = 4u, DST_QU = 6u, DST_TQU = 7u, DST_IQU = 8u };
 
 typedef struct dst_ctx dst_ctx;
 
@@ -84,7 +90,7 @@ typedef struct {
   int64_t n_samples;       /* n_t >= 1 */
   int64_t n_pix;           /* pixels of the map, >= 1 (12 nside^2 for HEALPix) */
   int64_t baseline_length; /* L >= 1 samples; the last baseline may be shorter */
-  uint32_t streams;        /* DST_T, DST_QU or DST_TQU */
+  uint32_t streams;        /* DST_T, DST_QU, DST_TQU or DST_IQU */
   int32_t tod_dtype;       /* dst_dtype of `tod` */
   int32_t psi_dtype;       /* dst_dtype of `psi` (ignored for DST_T) */
   int32_t reserved;        /* must be 0 */
@@ -93,7 +99,7 @@ typedef struct {
   const void* tod;         /* device [n_streams][n_samples]; calibrated timelines in K (may be NULL
                               where a call states it is not read) */
   double weight[3];        /* w_T, w_q, w_u > 0 and finite (entries of absent streams ignored) */
-  double rcond_cut;        /* QU-block eigenvalue-ratio cut in [0, 1) */
+  double rcond_cut;        /* eigenvalue-ratio cut of the QU block (IQU: of the 3x3 block) in [0, 1) */
 } dst_problem;
 
 /* Library ABI version (DST_ABI_VERSION of the build). */

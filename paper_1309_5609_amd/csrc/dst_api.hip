@@ -112,6 +112,7 @@ int ws(dst_ctx* ctx, const char* name, size_t count, T** out) {
 
 int stream_rows(uint32_t streams, View& v) {
   v.rowT = v.rowQ = v.rowU = -1;
+  v.iqu = 0;
   switch (streams) {
     case DST_T:
       v.rowT = 0;
@@ -127,6 +128,11 @@ int stream_rows(uint32_t streams, View& v) {
       v.rowQ = 1;
       v.rowU = 2;
       v.n_streams = 3;
+      return 0;
+    case DST_IQU:
+      v.rowT = 0;
+      v.n_streams = 1;
+      v.iqu = 1;
       return 0;
     default:
       return -1;
@@ -147,10 +153,10 @@ int check_problem(dst_ctx* ctx, const dst_problem* prob, bool need_tod, View& v)
     return fail(ctx, DST_EINVAL, "baseline_length must be in [1, 2^31) (got %lld)",
                 (long long)prob->baseline_length);
   if (stream_rows(prob->streams, v) != 0)
-    return fail(ctx, DST_EINVAL, "streams must be DST_T, DST_QU or DST_TQU (got %u)", prob->streams);
+    return fail(ctx, DST_EINVAL, "streams must be DST_T, DST_QU, DST_TQU or DST_IQU (got %u)", prob->streams);
   if (!prob->pix) return fail(ctx, DST_EINVAL, "pix is NULL");
-  if (v.rowQ >= 0) {
-    if (!prob->psi) return fail(ctx, DST_EINVAL, "psi is NULL but q/u streams are present");
+  if (v.rowQ >= 0 || v.iqu) {
+    if (!prob->psi) return fail(ctx, DST_EINVAL, "psi is NULL but the streams need the angle");
     if (!is_dtype(prob->psi_dtype)) return fail(ctx, DST_EINVAL, "psi_dtype must be DST_F32 or DST_F64");
   }
   if (need_tod) {
@@ -306,7 +312,7 @@ int build_runs_plan(dst_ctx* ctx, const dst_problem* prob, Plan& P, const void* 
   DST_TRY(ws(ctx, "r_tpix", R, &W.tpix));
   DST_TRY(ws(ctx, "r_tn", R, &W.tn));
   // FP32 angles (mixed precision): run sums of cos 2psi, sin 2psi kept in FP32
-  W.f32 = S.psi_f32 && v.rowQ >= 0;
+  W.f32 = S.psi_f32 && (v.rowQ >= 0 || v.iqu);
   const size_t rsz = W.f32 ? sizeof(float) : sizeof(double);
   DST_TRY(ws_get(ctx, "r_tc", R * rsz, &W.tc));
   DST_TRY(ws_get(ctx, "r_ts", R * rsz, &W.ts));
@@ -322,7 +328,7 @@ int build_runs_plan(dst_ctx* ctx, const dst_problem* prob, Plan& P, const void* 
   DST_TRY(ws_get(ctx, "r_ps", R * rsz, &W.ps));
   // per-pixel arrays sized for every pixel (the observed count is known later)
   DST_TRY(ws(ctx, "hits", v.n_pix, &S.hits));
-  DST_TRY(ws(ctx, "Minv4", 4 * v.n_pix, &S.Minv4));
+  DST_TRY(ws(ctx, "Minv4", (v.iqu ? 8 : 4) * (size_t)v.n_pix, &S.Minv4));  // IQU: 6 entries of a 3x3 inverse
   DST_TRY(ws(ctx, "valid", v.n_pix, &S.valid));
   DST_TRY(ws(ctx, "m4", 4 * v.n_pix, &P.m4));
   DST_TRY(ws(ctx, "pw4", 4 * v.n_b, &P.pw4));
@@ -514,6 +520,7 @@ int worse(int a, int b) {
 }
 
 bool same_operator(const dst_problem& a, const dst_problem& b) {
+  if (a.streams == DST_IQU || b.streams == DST_IQU) return false;  // the batched kernels have no IQU rows
   return a.pix == b.pix && a.psi == b.psi && a.n_samples == b.n_samples && a.n_pix == b.n_pix &&
          a.baseline_length == b.baseline_length && a.streams == b.streams && a.psi_dtype == b.psi_dtype &&
          a.weight[0] == b.weight[0] && a.weight[1] == b.weight[1] && a.weight[2] == b.weight[2] &&
@@ -921,6 +928,7 @@ int dst_pixel_setup(dst_ctx* ctx, const dst_problem* prob, int32_t* hits_out, do
                     void* stream) {
   View v{};
   DST_TRY(check_problem(ctx, prob, false, v));
+  if (v.iqu) return fail(ctx, DST_EINVAL, "DST_IQU streams are not supported by this entry point");
   ctx->err.clear();
   DeviceGuard g(ctx->device);
   hipStream_t st = static_cast<hipStream_t>(stream);
@@ -937,6 +945,7 @@ int dst_bin(dst_ctx* ctx, const dst_problem* prob, const double* baselines, uint
   View v{};
   const bool use_tod = flags & DST_BIN_USE_TOD;
   DST_TRY(check_problem(ctx, prob, use_tod, v));
+  if (v.iqu) return fail(ctx, DST_EINVAL, "DST_IQU streams are not supported by this entry point");
   if (!map_out) return fail(ctx, DST_EINVAL, "map_out is NULL");
   if (flags & ~(uint32_t)(DST_BIN_USE_TOD | DST_BIN_MAP)) return fail(ctx, DST_EINVAL, "unknown flags %u", flags);
   ctx->err.clear();
@@ -964,6 +973,7 @@ int dst_bin(dst_ctx* ctx, const dst_problem* prob, const double* baselines, uint
 int dst_unbin(dst_ctx* ctx, const dst_problem* prob, const double* map, double* tod_out, void* stream) {
   View v{};
   DST_TRY(check_problem(ctx, prob, false, v));
+  if (v.iqu) return fail(ctx, DST_EINVAL, "DST_IQU streams are not supported by this entry point");
   if (!map || !tod_out) return fail(ctx, DST_EINVAL, "map and tod_out must not be NULL");
   ctx->err.clear();
   DeviceGuard g(ctx->device);
@@ -979,6 +989,7 @@ int dst_unbin(dst_ctx* ctx, const dst_problem* prob, const double* map, double* 
 int dst_baseline_reduce(dst_ctx* ctx, const dst_problem* prob, const void* x, double* out, void* stream) {
   View v{};
   DST_TRY(check_problem(ctx, prob, false, v));
+  if (v.iqu) return fail(ctx, DST_EINVAL, "DST_IQU streams are not supported by this entry point");
   if (!x || !out) return fail(ctx, DST_EINVAL, "x and out must not be NULL");
   if (!is_dtype(prob->tod_dtype)) return fail(ctx, DST_EINVAL, "tod_dtype must be DST_F32 or DST_F64");
   ctx->err.clear();
@@ -994,6 +1005,7 @@ int dst_baseline_reduce(dst_ctx* ctx, const dst_problem* prob, const void* x, do
 int dst_residual(dst_ctx* ctx, const dst_problem* prob, const double* a, double* out, void* stream) {
   View v{};
   DST_TRY(check_problem(ctx, prob, false, v));
+  if (v.iqu) return fail(ctx, DST_EINVAL, "DST_IQU streams are not supported by this entry point");
   if (prob->tod && !is_dtype(prob->tod_dtype)) return fail(ctx, DST_EINVAL, "tod_dtype must be DST_F32 or DST_F64");
   if (!out) return fail(ctx, DST_EINVAL, "out is NULL");
   ctx->err.clear();
@@ -1031,6 +1043,8 @@ int dst_solve(dst_ctx* ctx, const dst_problem* prob, const dst_solve_opts* opts_
                          DST_SOLVE_AUTOTUNE | DST_SOLVE_GMRES;
   const bool use_gmres = opts.flags & DST_SOLVE_GMRES;
   if (!use_gmres && opts.restart != 0) return fail(ctx, DST_EINVAL, "opts.restart is for DST_SOLVE_GMRES only");
+  if (v.iqu && (opts.flags & DST_SOLVE_PER_SAMPLE))
+    return fail(ctx, DST_EINVAL, "DST_IQU streams need the run form (no DST_SOLVE_PER_SAMPLE)");
   if (opts.restart < 0 || opts.restart > dst::kMaxKrylov - 2)
     return fail(ctx, DST_EINVAL, "opts.restart must be in [0, %d]", dst::kMaxKrylov - 2);
   if (opts.flags & ~known) return fail(ctx, DST_EINVAL, "unknown solve flags %u", opts.flags);

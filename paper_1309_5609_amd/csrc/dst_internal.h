@@ -21,6 +21,7 @@ struct View {
   int64_t n_b;
   double w[3];  // T, q, u
   int rowT, rowQ, rowU, n_streams;
+  int iqu;      // 1: one radiometer stream (row 0) with pointing row (1, cos 2psi, sin 2psi)
 };
 
 // CG scalars and reduction scratch, resident in device memory.

@@ -70,6 +70,28 @@ __device__ __forceinline__ void block_sum(T (&v)[N], T* lds) {
   __syncthreads();
 }
 
+// Smallest and largest eigenvalue of the symmetric 3x3 matrix
+// [[a00, a01, a02], [a01, a11, a12], [a02, a12, a22]] by the trigonometric
+// form of the roots of its characteristic cubic (Smith 1961).
+__device__ __forceinline__ void sym3_eig_range(double a00, double a01, double a02, double a11, double a12,
+                                               double a22, double& lmin, double& lmax) {
+  const double p1 = a01 * a01 + a02 * a02 + a12 * a12;
+  const double q = (a00 + a11 + a22) / 3.0;
+  const double b00 = a00 - q, b11 = a11 - q, b22 = a22 - q;
+  const double p2 = b00 * b00 + b11 * b11 + b22 * b22 + 2.0 * p1;
+  if (!(p2 > 0.0)) {  // a multiple of the identity
+    lmin = lmax = q;
+    return;
+  }
+  const double pp = sqrt(p2 / 6.0);
+  const double detb = b00 * (b11 * b22 - a12 * a12) - a01 * (a01 * b22 - a12 * a02) + a02 * (a01 * a12 - b11 * a02);
+  double r = detb / (2.0 * pp * pp * pp);
+  r = r < -1.0 ? -1.0 : (r > 1.0 ? 1.0 : r);
+  const double phi = acos(r) / 3.0;
+  lmax = q + 2.0 * pp * cos(phi);
+  lmin = q + 2.0 * pp * cos(phi + 2.0943951023931957);  // + 2 pi / 3
+}
+
 // Workgroup i runs on XCD i mod 8; give each XCD a contiguous range of
 // baselines.  Returns -1 for padding groups.
 __device__ __forceinline__ int64_t xcd_baseline(int64_t n_b) {
@@ -128,7 +150,7 @@ __global__ void __launch_bounds__(kBlock) k_run_starts(const uint32_t* __restric
 // length, C, S, and the sums of d_T, d_q, d_u); a 64-byte record per run
 // feeds the per-pixel setup, which reads it in pixel order with one aligned
 // access.  Samples are summed in time order.
-template <typename PT, typename TT, typename RT, bool HAS_T, bool HAS_QU, bool TOD>
+template <typename PT, typename TT, typename RT, bool HAS_T, bool HAS_QU, bool IQU, bool TOD>
 __global__ void __launch_bounds__(kBlock) k_run_build(View v, const TT* __restrict__ tod,
                                                       const uint32_t* __restrict__ t0, int64_t R,
                                                       int32_t* __restrict__ rpix, int32_t* __restrict__ rn,
@@ -145,14 +167,21 @@ __global__ void __launch_bounds__(kBlock) k_run_build(View v, const TT* __restri
     int64_t t = ts;
     for (; t < tend && v.pix[t] == p; ++t) {
       double c = 1.0, s = 0.0;
-      if (HAS_QU) {
+      if (HAS_QU || IQU) {
         rot2((double)psi[t], c, s);
         C += c;
         S += s;
         cc += c * c;
         cs += c * s;
       }
-      if (TOD) {
+      if (TOD && IQU) {
+        // radiometer row (1, c, s): sums of d and of the weighted c d, s d
+        const double x = (double)tod[v.rowT * n_t + t];
+        const double wx = v.w[0] * x;
+        dT += x;
+        dQ += c * wx;
+        dU += s * wx;
+      } else if (TOD) {
         if (HAS_T) dT += (double)tod[v.rowT * n_t + t];
         if (HAS_QU) {
           const double xq = (double)tod[v.rowQ * n_t + t];
@@ -168,7 +197,7 @@ __global__ void __launch_bounds__(kBlock) k_run_build(View v, const TT* __restri
     const int32_t n = (int32_t)(t - ts);
     rpix[r] = p;
     rn[r] = n;
-    if (HAS_QU) {
+    if (HAS_QU || IQU) {
       rc[r] = (RT)C;
       rs[r] = (RT)S;
     }
@@ -241,7 +270,7 @@ __global__ void __launch_bounds__(kBlock) k_compact(const uint32_t* __restrict__
 // the pixel) -> the pixel-order run arrays; hits, weight blocks, inverse,
 // validity; with TOD the sum map and binned map.  The sum of sin^2 2psi over
 // a run is its length minus the sum of cos^2 2psi.
-template <typename RT, bool HAS_T, bool HAS_QU, bool TOD>
+template <typename RT, bool HAS_T, bool HAS_QU, bool IQU, bool TOD>
 __global__ void __launch_bounds__(kBlock) k_pixels_from_runs(
     View v, int64_t n_obs, const uint32_t* __restrict__ order, const int64_t* __restrict__ seg,
     const uint32_t* __restrict__ rperm, const RunRecord* __restrict__ rec, double rcond_cut,
@@ -257,18 +286,25 @@ __global__ void __launch_bounds__(kBlock) k_pixels_from_runs(
     const uint32_t p = order[c];
     const int64_t j0 = seg[2 * (int64_t)p], j1 = seg[2 * (int64_t)p + 1];
     const int64_t d0 = pstart[c];
-    double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};  // h, cc, cs, dT, dQ, dU
+    constexpr int NA = IQU ? 8 : 6;
+    double acc[NA];  // h, cc, cs, dT, dQ, dU (and C, S for the radiometer block)
+#pragma unroll
+    for (int i = 0; i < NA; ++i) acc[i] = 0.0;
     for (int64_t j = j0 + lane; j < j1; j += 64) {
       const RunRecord x = rec[rperm[j]];
       const int64_t d = d0 + (j - j0);
       pb[d] = x.b;
       pn[d] = x.n;
       acc[0] += (double)x.n;
-      if (HAS_QU) {
+      if (HAS_QU || IQU) {
         pc[d] = (RT)x.C;
         ps[d] = (RT)x.S;
         acc[1] += x.cc;
         acc[2] += x.cs;
+      }
+      if (IQU) {
+        acc[NA - 2] += x.C;
+        acc[NA - 1] += x.S;
       }
       if (TOD) {
         acc[3] += x.dT;
@@ -276,8 +312,56 @@ __global__ void __launch_bounds__(kBlock) k_pixels_from_runs(
         acc[5] += x.dU;
       }
     }
-    wave_sum<6>(acc);
-    if (lane == 0) {
+    wave_sum<NA>(acc);
+    if (IQU && lane == 0) {
+      // full 3x3 block w [[h, C, S], [C, cc, cs], [S, cs, ss]] of the radiometer row
+      const int64_t h = (int64_t)acc[0];
+      const double w = v.w[0];
+      const double a00 = w * acc[0], a01 = w * acc[NA - 2], a02 = w * acc[NA - 1];
+      const double a11 = w * acc[1], a12 = w * acc[2], a22 = w * (acc[0] - acc[1]);
+      double inv[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+      uint8_t f = 0;
+      if (h > 0) {
+        double lmin, lmax;
+        sym3_eig_range(a00, a01, a02, a11, a12, a22, lmin, lmax);
+        if (lmax > 0.0 && lmin > 0.0 && lmin >= rcond_cut * lmax) {
+          const double c00 = a11 * a22 - a12 * a12, c01 = a02 * a12 - a01 * a22, c02 = a01 * a12 - a02 * a11;
+          const double c11 = a00 * a22 - a02 * a02, c12 = a01 * a02 - a00 * a12, c22 = a00 * a11 - a01 * a01;
+          const double det = a00 * c00 + a01 * c01 + a02 * c02;
+          if (det > 0.0) {
+            f = 3;
+            inv[0] = c00 / det;
+            inv[1] = c01 / det;
+            inv[2] = c02 / det;
+            inv[3] = c11 / det;
+            inv[4] = c12 / det;
+            inv[5] = c22 / det;
+          }
+        }
+      }
+      hits[c] = (int32_t)h;
+      double2* mi = reinterpret_cast<double2*>(Minv4 + 8 * c);
+      mi[0] = make_double2(inv[0], inv[1]);
+      mi[1] = make_double2(inv[2], inv[3]);
+      mi[2] = make_double2(inv[4], inv[5]);
+      mi[3] = make_double2(0.0, 0.0);
+      valid[c] = f;
+      double2* mz = reinterpret_cast<double2*>(m4_zero + 4 * c);
+      mz[0] = make_double2(0.0, 0.0);
+      mz[1] = make_double2(0.0, 0.0);
+      if (TOD) {
+        const double sI = f ? w * acc[3] : 0.0, sQ = f ? acc[4] : 0.0, sU = f ? acc[5] : 0.0;
+        double2* sp = reinterpret_cast<double2*>(sd4 + 4 * c);
+        sp[0] = make_double2(sI, sQ);
+        sp[1] = make_double2(sU, 0.0);
+        double2* mp = reinterpret_cast<double2*>(md4 + 4 * c);
+        mp[0] = make_double2(inv[0] * sI + inv[1] * sQ + inv[2] * sU, inv[1] * sI + inv[3] * sQ + inv[4] * sU);
+        mp[1] = make_double2(inv[2] * sI + inv[4] * sQ + inv[5] * sU, 0.0);
+      }
+      cnt[0] += f ? 1 : 0;
+      cnt[2] += f ? (unsigned long long)h : 0ull;
+    }
+    if (!IQU && lane == 0) {
       const int64_t h = (int64_t)acc[0];
       double inv[4] = {0.0, 0.0, 0.0, 0.0};
       uint8_t f = 0;
@@ -345,7 +429,7 @@ __global__ void __launch_bounds__(kBlock) k_runs_to_compact(int64_t R, const int
 
 // Per baseline (time-order runs): n_valid, the Jacobi diagonal and with TOD
 //   b_k = w_k sum_{runs, valid_k} (sum of d_k over the run - A-weighted m_d).
-template <typename RT, bool HAS_T, bool HAS_QU, bool TOD>
+template <typename RT, bool HAS_T, bool HAS_QU, bool IQU, bool TOD>
 __global__ void __launch_bounds__(kBlock) k_rhs_runs(View v, const uint32_t* __restrict__ bstart,
                                                      const int32_t* __restrict__ rpix, const int32_t* __restrict__ rn,
                                                      const RT* __restrict__ rc, const RT* __restrict__ rs,
@@ -364,7 +448,13 @@ __global__ void __launch_bounds__(kBlock) k_rhs_runs(View v, const uint32_t* __r
     const double n = (double)rn[r];
     const double* m = raw + 3 * r;
     const double2* mp = reinterpret_cast<const double2*>(md4 + 4 * (int64_t)c);
-    if (HAS_T && (f & 1)) {
+    if (IQU && (f & 1)) {
+      acc[3] += n;
+      if (TOD) {
+        const double C = (double)rc[r], S = (double)rs[r];
+        acc[0] += m[0] - (n * mp[0].x + C * mp[0].y + S * mp[1].x);
+      }
+    } else if (HAS_T && (f & 1)) {
       acc[3] += n;
       if (TOD) acc[0] += m[0] - n * mp[0].x;
     }
@@ -403,7 +493,7 @@ __global__ void __launch_bounds__(kBlock) k_rhs_runs(View v, const uint32_t* __r
 // m = M^-1 A^T W F p per compact pixel from its pixel-order runs.  LPP lanes
 // work on one pixel (64 / LPP pixels per wavefront, each with its own chain of
 // dependent loads in flight); pw4[b] = (w_T p_T, w_q p_q, w_u p_u, 0).
-template <typename RT, bool HAS_T, bool HAS_QU, int LPP>
+template <typename RT, bool HAS_T, bool HAS_QU, bool IQU, int LPP>
 __global__ void __launch_bounds__(kBlock) k_bin_runs(int64_t n_obs, const int64_t* __restrict__ pstart,
                                                      const int32_t* __restrict__ pb, const int32_t* __restrict__ pn,
                                                      const RT* __restrict__ pc, const RT* __restrict__ ps,
@@ -435,14 +525,20 @@ __global__ void __launch_bounds__(kBlock) k_bin_runs(int64_t n_obs, const int64_
         const bool in = j < j1;
         bb[u] = in ? pb[j] : -1;
         nn[u] = (HAS_T && in) ? pn[j] : 0;
-        cc[u] = (HAS_QU && in) ? (double)pc[j] : 0.0;
-        ss[u] = (HAS_QU && in) ? (double)ps[j] : 0.0;
+        cc[u] = ((HAS_QU || IQU) && in) ? (double)pc[j] : 0.0;
+        ss[u] = ((HAS_QU || IQU) && in) ? (double)ps[j] : 0.0;
       }
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         if (bb[u] < 0) continue;
         const double2* q0 = reinterpret_cast<const double2*>(pw4 + 4 * (int64_t)bb[u]);
         const double2 x0 = q0[0];
+        if (IQU) {
+          acc[0] += (double)nn[u] * x0.x;
+          acc[1] += cc[u] * x0.x;
+          acc[2] += ss[u] * x0.x;
+          continue;
+        }
         if (HAS_T) acc[0] += (double)nn[u] * x0.x;
         if (HAS_QU) {
           const double u0 = q0[1].x;
@@ -456,7 +552,15 @@ __global__ void __launch_bounds__(kBlock) k_bin_runs(int64_t n_obs, const int64_
 #pragma unroll
       for (int i = 0; i < 3; ++i) acc[i] += __shfl_xor(acc[i], off, 64);
     }
-    if (have && sub == 0) {
+    if (IQU && have && sub == 0) {
+      const double2* ip = reinterpret_cast<const double2*>(Minv4 + 8 * c);
+      const double2 i01 = ip[0], i23 = ip[1], i45 = ip[2];  // (00, 01), (02, 11), (12, 22)
+      double2* mp = reinterpret_cast<double2*>(m4 + 4 * c);
+      mp[0] = make_double2(i01.x * acc[0] + i01.y * acc[1] + i23.x * acc[2],
+                           i01.y * acc[0] + i23.y * acc[1] + i45.x * acc[2]);
+      mp[1] = make_double2(i23.x * acc[0] + i45.x * acc[1] + i45.y * acc[2], 0.0);
+    }
+    if (!IQU && have && sub == 0) {
       const double2* ip = reinterpret_cast<const double2*>(Minv4 + 4 * c);
       const double2 i01 = ip[0], i23 = ip[1];
       double2* mp = reinterpret_cast<double2*>(m4 + 4 * c);
@@ -472,7 +576,7 @@ __global__ void __launch_bounds__(kBlock) k_bin_runs(int64_t n_obs, const int64_
 // baselines in flight per XCD (larger WPB) keep the map values they gather
 // in that XCD's L2.  m is zero on invalid blocks.  With CG: per-baseline
 // partials of p.q and of the T-projection sums.
-template <typename RT, bool HAS_T, bool HAS_QU, bool CG, int WPB>
+template <typename RT, bool HAS_T, bool HAS_QU, bool IQU, bool CG, int WPB>
 __global__ void __launch_bounds__(WPB > 4 ? 64 * WPB : kBlock) k_unbin_runs(View v, const uint32_t* __restrict__ bstart,
                                                        const int32_t* __restrict__ rpix,
                                                        const int32_t* __restrict__ rn, const RT* __restrict__ rc,
@@ -507,14 +611,18 @@ __global__ void __launch_bounds__(WPB > 4 ? 64 * WPB : kBlock) k_unbin_runs(View
         const bool in = r < r1;
         cc_[u] = in ? rpix[r] : -1;
         nn[u] = (HAS_T && in) ? rn[r] : 0;
-        C[u] = (HAS_QU && in) ? (double)rc[r] : 0.0;
-        S[u] = (HAS_QU && in) ? (double)rs[r] : 0.0;
+        C[u] = ((HAS_QU || IQU) && in) ? (double)rc[r] : 0.0;
+        S[u] = ((HAS_QU || IQU) && in) ? (double)rs[r] : 0.0;
       }
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         if (cc_[u] < 0) continue;
         const double2* mp = reinterpret_cast<const double2*>(m4 + 4 * (int64_t)cc_[u]);
         const double2 m01 = mp[0];
+        if (IQU) {
+          acc[0] += (double)nn[u] * m01.x + C[u] * m01.y + S[u] * mp[1].x;
+          continue;
+        }
         if (HAS_T) acc[0] += (double)nn[u] * m01.x;
         if (HAS_QU) {
           const double mU = mp[1].x;
@@ -636,12 +744,14 @@ static void by_float(bool f32, F&& f) {
 }
 template <typename F>
 static void by_streams(const View& v, F&& f) {
-  if (v.rowT >= 0 && v.rowQ >= 0)
-    f(std::true_type{}, std::true_type{});
+  if (v.iqu)
+    f(std::true_type{}, std::false_type{}, std::true_type{});
+  else if (v.rowT >= 0 && v.rowQ >= 0)
+    f(std::true_type{}, std::true_type{}, std::false_type{});
   else if (v.rowQ >= 0)
-    f(std::false_type{}, std::true_type{});
+    f(std::false_type{}, std::true_type{}, std::false_type{});
   else
-    f(std::true_type{}, std::false_type{});
+    f(std::true_type{}, std::false_type{}, std::false_type{});
 }
 template <typename F>
 static void by_bool(bool b, F&& f) {
@@ -660,7 +770,7 @@ hipError_t runs_build(const View& v, int psi_f32, const void* tod, int tod_f32, 
   hipLaunchKernelGGL(k_run_starts, dim3(g), dim3(kBlock), 0, st, W.head, W.hidx, n_t, v.L, v.n_b, W.t0, W.bstart);
   DST_CHECK(hipGetLastError());
   // 2. run records and setup moments (time order)
-  const bool pf = psi_f32 && v.rowQ >= 0;
+  const bool pf = psi_f32 && (v.rowQ >= 0 || v.iqu);
   const unsigned grb = grid_for(R, kBlock, 16384);
   by_float(pf, [&](auto pt) {
     using PT = typename decltype(pt)::type;
@@ -668,9 +778,10 @@ hipError_t runs_build(const View& v, int psi_f32, const void* tod, int tod_f32, 
       using TT = typename decltype(tt)::type;
       by_float(W.f32, [&](auto rt) {
         using RT = typename decltype(rt)::type;
-        by_streams(v, [&](auto T, auto Q) {
+        by_streams(v, [&](auto T, auto Q, auto I) {
           by_bool(tod != nullptr, [&](auto D) {
-            hipLaunchKernelGGL((k_run_build<PT, TT, RT, decltype(T)::value, decltype(Q)::value, decltype(D)::value>),
+            hipLaunchKernelGGL((k_run_build<PT, TT, RT, decltype(T)::value, decltype(Q)::value, decltype(I)::value,
+                                            decltype(D)::value>),
                                dim3(grb), dim3(kBlock), 0, st, v, static_cast<const TT*>(tod), W.t0, W.R, W.tpix, W.tn,
                                static_cast<RT*>(W.tc), static_cast<RT*>(W.ts), W.raw, W.rec);
           });
@@ -722,9 +833,10 @@ hipError_t runs_build(const View& v, int psi_f32, const void* tod, int tod_f32, 
     const unsigned gw = grid_for(W.n_obs, kWaves, 4096);
     by_float(W.f32, [&](auto rt) {
       using RT = typename decltype(rt)::type;
-      by_streams(v, [&](auto T, auto Q) {
+      by_streams(v, [&](auto T, auto Q, auto I) {
         by_bool(tod != nullptr, [&](auto D) {
-          hipLaunchKernelGGL((k_pixels_from_runs<RT, decltype(T)::value, decltype(Q)::value, decltype(D)::value>),
+          hipLaunchKernelGGL((k_pixels_from_runs<RT, decltype(T)::value, decltype(Q)::value, decltype(I)::value,
+                                                 decltype(D)::value>),
                              dim3(gw), dim3(kBlock), 0, st, v, W.n_obs, W.order, W.seg, W.rperm, W.rec, rcond_cut,
                              W.pb, W.pn, static_cast<RT*>(W.pc), static_cast<RT*>(W.ps), W.pstart, hits, Minv4,
                              valid, m4_zero, sd4, md4, counts);
@@ -743,9 +855,10 @@ hipError_t launch_rhs_runs(const View& vc, const Runs& W, const void* tod, const
   const unsigned g = (unsigned)(8 * ((vc.n_b + 7) / 8));
   by_float(W.f32, [&](auto rt) {
     using RT = typename decltype(rt)::type;
-    by_streams(vc, [&](auto T, auto Q) {
+    by_streams(vc, [&](auto T, auto Q, auto I) {
       by_bool(tod != nullptr, [&](auto D) {
-        hipLaunchKernelGGL((k_rhs_runs<RT, decltype(T)::value, decltype(Q)::value, decltype(D)::value>), dim3(g),
+        hipLaunchKernelGGL((k_rhs_runs<RT, decltype(T)::value, decltype(Q)::value, decltype(I)::value,
+                                        decltype(D)::value>), dim3(g),
                            dim3(kBlock), 0, st, vc, W.bstart, W.tpix, W.tn, static_cast<const RT*>(W.tc),
                            static_cast<const RT*>(W.ts), W.raw, md4, valid, nvalid, J, b);
       });
@@ -761,18 +874,18 @@ hipError_t launch_bin_runs(const View& vc, const Runs& W, const double* pw4, con
   const unsigned g = (unsigned)std::max<int64_t>(1, std::min<int64_t>((W.n_obs + ppb - 1) / ppb, 16384));
   by_float(W.f32, [&](auto rt) {
     using RT = typename decltype(rt)::type;
-    by_streams(vc, [&](auto T, auto Q) {
-      constexpr bool HT = decltype(T)::value, HQ = decltype(Q)::value;
+    by_streams(vc, [&](auto T, auto Q, auto I) {
+      constexpr bool HT = decltype(T)::value, HQ = decltype(Q)::value, HI = decltype(I)::value;
       auto launch = [&](auto kern) {
         hipLaunchKernelGGL(kern, dim3(g), dim3(kBlock), 0, st, W.n_obs, W.pstart, W.pb, W.pn,
                            static_cast<const RT*>(W.pc), static_cast<const RT*>(W.ps), pw4, Minv4, valid, m4, gate);
       };
       if (lpp == 16)
-        launch(k_bin_runs<RT, HT, HQ, 16>);
+        launch(k_bin_runs<RT, HT, HQ, HI, 16>);
       else if (lpp == 32)
-        launch(k_bin_runs<RT, HT, HQ, 32>);
+        launch(k_bin_runs<RT, HT, HQ, HI, 32>);
       else
-        launch(k_bin_runs<RT, HT, HQ, 64>);
+        launch(k_bin_runs<RT, HT, HQ, HI, 64>);
     });
   });
   return hipGetLastError();
@@ -787,24 +900,25 @@ hipError_t launch_unbin_runs(const View& vc, const Runs& W, const double* m4, co
   const unsigned g = (unsigned)(8 * ((n_g + 7) / 8));
   by_float(W.f32, [&](auto rt) {
     using RT = typename decltype(rt)::type;
-    by_streams(vc, [&](auto T, auto Q) {
+    by_streams(vc, [&](auto T, auto Q, auto I) {
       by_bool(ctl != nullptr, [&](auto CG) {
-        constexpr bool HT = decltype(T)::value, HQ = decltype(Q)::value, C = decltype(CG)::value;
+        constexpr bool HT = decltype(T)::value, HQ = decltype(Q)::value, HI = decltype(I)::value;
+        constexpr bool C = decltype(CG)::value;
         auto launch = [&](auto kern) {
           hipLaunchKernelGGL(kern, dim3(g), dim3(nt), 0, st, vc, W.bstart, W.tpix, W.tn,
                              static_cast<const RT*>(W.tc), static_cast<const RT*>(W.ts), m4, nvalid, p, q, ctl,
                              partials);
         };
         if (wpb == 16)
-          launch(k_unbin_runs<RT, HT, HQ, C, 16>);
+          launch(k_unbin_runs<RT, HT, HQ, HI, C, 16>);
         else if (wpb == 8)
-          launch(k_unbin_runs<RT, HT, HQ, C, 8>);
+          launch(k_unbin_runs<RT, HT, HQ, HI, C, 8>);
         else if (wpb == 4)
-          launch(k_unbin_runs<RT, HT, HQ, C, 4>);
+          launch(k_unbin_runs<RT, HT, HQ, HI, C, 4>);
         else if (wpb == 2)
-          launch(k_unbin_runs<RT, HT, HQ, C, 2>);
+          launch(k_unbin_runs<RT, HT, HQ, HI, C, 2>);
         else
-          launch(k_unbin_runs<RT, HT, HQ, C, 1>);
+          launch(k_unbin_runs<RT, HT, HQ, HI, C, 1>);
       });
     });
   });

@@ -23,8 +23,8 @@ DST_OK, DST_ENOCONV = 0, 1
 STATUS = {0: "DST_OK", 1: "DST_ENOCONV", -1: "DST_EINVAL", -2: "DST_ENOMEM", -3: "DST_EHIP", -4: "DST_ENAN",
           -5: "DST_EDEGENERATE", -6: "DST_EBOUNDS", -7: "DST_EBREAKDOWN"}
 DST_F32, DST_F64 = 1, 2
-STREAMS = {"T": 1, "QU": 6, "TQU": 7}
-N_STREAMS = {"T": 1, "QU": 2, "TQU": 3}
+STREAMS = {"T": 1, "QU": 6, "TQU": 7, "IQU": 8}
+N_STREAMS = {"T": 1, "QU": 2, "TQU": 3, "IQU": 1}
 DST_BIN_USE_TOD, DST_BIN_MAP = 1, 2
 DST_SOLVE_NO_CANON, DST_SOLVE_PROFILE, DST_SOLVE_NO_GRAPH, DST_SOLVE_PER_SAMPLE = 1, 2, 4, 8
 DST_SOLVE_AUTOTUNE = 16
