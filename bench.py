@@ -75,7 +75,14 @@ def workload_name(w: int, fk: float) -> str:
             f"3000-sample baselines (43,200 per stream), T/q/u, f_k {fk * 1e3:g} mHz, alpha 1.7, {prec}")
 
 
-def algorithmic_bytes(n_t: int, n_obs: int, n_b: int, s_psi: int, n_runs: int = 0) -> dict:
+def key_bits(n: int) -> int:
+    bits = 1
+    while bits < 32 and (1 << bits) < n:
+        bits += 1
+    return bits
+
+
+def algorithmic_bytes(n_t: int, n_obs: int, n_b: int, s_psi: int, n_runs: int = 0, L: int = 3000) -> dict:
     """Bytes each kernel of one CG iteration must move (per launch).
 
     Per-sample form (the method as written, samples streamed every iteration):
@@ -84,17 +91,22 @@ def algorithmic_bytes(n_t: int, n_obs: int, n_b: int, s_psi: int, n_runs: int = 
               pixel out (24 B);
       unbin:  pointing per sample, the 3 map values of each observed pixel
               in, p in and q out (2 x 3 x 8 B per baseline).
-    Run form (default): one 24 B record per run (baseline or pixel index,
-    length, sums of cos 2psi and sin 2psi) replaces the per-sample pointing;
-    per-pixel and per-baseline terms as above.
+    Run form (default): one record per run replaces the per-sample pointing:
+    a 32-bit key (index and length packed when both fit 32 bits, as the
+    library does; else 8 B) and the sums of cos 2psi and sin 2psi (2 x 8 B,
+    2 x 4 B with FP32 angles); per-pixel and per-baseline terms as above.
     """
     out = {
         "bin_samples": n_t * (4 + s_psi) + n_obs * 24 + 3 * n_b * 8,
         "unbin_samples": n_t * (4 + s_psi) + n_obs * 24 + 2 * 3 * n_b * 8,
     }
     if n_runs:
-        out["bin_runs"] = n_runs * 24 + n_obs * 24 + 3 * n_b * 8
-        out["unbin_runs"] = n_runs * 24 + n_obs * 24 + 2 * 3 * n_b * 8
+        nb = key_bits(L)
+        packed = key_bits(max(n_obs, 1)) + nb <= 32 and key_bits(n_b) + nb <= 32
+        rec = (4 if packed else 8) + 2 * s_psi
+        out["run_record_bytes"] = rec
+        out["bin_runs"] = n_runs * rec + n_obs * 24 + 3 * n_b * 8
+        out["unbin_runs"] = n_runs * rec + n_obs * 24 + 2 * 3 * n_b * 8
     return out
 
 
@@ -331,7 +343,7 @@ def main() -> int:
     n_obs = int(r0["n_valid_pix"][0])
     n_runs = int(r0["n_runs"])
     s_psi = 4 if args.workload == 2 else 8
-    algo = algorithmic_bytes(p.n_samples, n_obs, p.n_baselines, s_psi, n_runs)
+    algo = algorithmic_bytes(p.n_samples, n_obs, p.n_baselines, s_psi, n_runs, p.baseline_length)
     k_ms = {k: float(np.mean([r[f"t_{k}_ms"] for r in runs])) for k in ("bin", "apply", "unbin", "update")}
     dom = max(("bin", "unbin"), key=lambda k: k_ms[k])
     dom_bytes = algo[f"{dom}_runs"]

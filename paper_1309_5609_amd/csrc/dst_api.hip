@@ -296,6 +296,7 @@ int build_runs_plan(dst_ctx* ctx, const dst_problem* prob, Plan& P, const void* 
   DST_TRY(ws(ctx, "r_pv0", v.n_pix, &W.pv[0]));
   DST_TRY(ws(ctx, "r_pv1", v.n_pix, &W.pv[1]));
   DST_TRY(ws(ctx, "r_nobs", 1, &W.n_obs_dev));
+  DST_TRY(ws(ctx, "r_nout", 1, &W.n_out));
   DST_TRY(ws(ctx, "r_cid", v.n_pix, &W.cid));
   DST_TRY(ws(ctx, "r_ccount", v.n_pix + 1, &W.ccount));
   DST_TRY(ws(ctx, "r_pstart", v.n_pix + 1, &W.pstart));
@@ -304,6 +305,7 @@ int build_runs_plan(dst_ctx* ctx, const dst_problem* prob, Plan& P, const void* 
   HIP_TRY(dst::launch_fill_u32(reinterpret_cast<uint32_t*>(W.seg), 4 * v.n_pix, 0u, st));
   HIP_TRY(dst::launch_fill_u32(reinterpret_cast<uint32_t*>(W.cid), v.n_pix, 0xffffffffu, st));
   HIP_TRY(dst::launch_fill_u32(reinterpret_cast<uint32_t*>(W.n_obs_dev), 2, 0u, st));
+  HIP_TRY(dst::launch_fill_u32(reinterpret_cast<uint32_t*>(W.n_out), 2, 0u, st));
   HIP_TRY(dst::launch_fill_u32(reinterpret_cast<uint32_t*>(S.counts), 8, 0u, st));
   HIP_TRY(dst::launch_fill_u32(reinterpret_cast<uint32_t*>(S.err), 4, 0u, st));
   HIP_TRY(dst::runs_count(v, W, S.err, st));
@@ -323,6 +325,8 @@ int build_runs_plan(dst_ctx* ctx, const dst_problem* prob, Plan& P, const void* 
   DST_TRY(ws(ctx, "r_vals0", R, &W.vals[0]));
   DST_TRY(ws(ctx, "r_vals1", R, &W.vals[1]));
   DST_TRY(ws(ctx, "r_pb", R, &W.pb));
+  DST_TRY(ws(ctx, "r_tkey", R, &W.tkey));
+  DST_TRY(ws(ctx, "r_pkey", R, &W.pkey));
   DST_TRY(ws(ctx, "r_pn", R, &W.pn));
   DST_TRY(ws_get(ctx, "r_pc", R * rsz, &W.pc));
   DST_TRY(ws_get(ctx, "r_ps", R * rsz, &W.ps));

@@ -689,39 +689,34 @@ __global__ void __launch_bounds__(kBlock) k_resid_norm(View v, const double* __r
                                                        const double* __restrict__ ka, const double* __restrict__ J,
                                                        CgCtl* __restrict__ ctl, double* __restrict__ partials,
                                                        double* __restrict__ out_norm) {
-  // two-stage: mean of (K a)_T, then the norm; both by the last block
-  __shared__ double lds[2 * 16];
+  // one pass over x = b - K a: sum of x^2, sum of x and count over T-valid
+  // rows; then ||x - mean_T(x) e||^2 = sum x^2 - (sum_T x)^2 / n_e by the last block
+  __shared__ double lds[3 * 16];
   __shared__ bool last;
-  double acc[2] = {0.0, 0.0};
+  double acc[3] = {0.0, 0.0, 0.0};
   const int64_t N = (int64_t)v.n_streams * v.n_b;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (int64_t)gridDim.x * blockDim.x) {
+    const double x = b[i] - ka[i];
+    acc[0] += x * x;
     if (t_valid_row(v, i, J)) {
-      acc[0] += ka[i];
-      acc[1] += 1.0;
+      acc[1] += x;
+      acc[2] += 1.0;
     }
   }
-  block_sum<2>(acc, lds);
+  block_sum<3>(acc, lds);
   if (threadIdx.x == 0) {
     partials[blockIdx.x] = acc[0];
     partials[gridDim.x + blockIdx.x] = acc[1];
+    partials[2 * gridDim.x + blockIdx.x] = acc[2];
   }
   if (!arrive_last(&ctl->counter[3], &last)) return;
-  double tot[2];
-  sum_partials<2>(partials, gridDim.x, tot, lds);
-  __shared__ double mu_s;
+  double tot[3];
+  sum_partials<3>(partials, gridDim.x, tot, lds);
   if (threadIdx.x == 0) {
-    mu_s = tot[1] > 0.0 ? tot[0] / tot[1] : 0.0;
+    const double s2 = tot[0] - (tot[2] > 0.0 ? tot[1] * tot[1] / tot[2] : 0.0);
+    *out_norm = sqrt(s2 > 0.0 ? s2 : 0.0);
     ctl->counter[3] = 0;
   }
-  __syncthreads();
-  const double mu = mu_s;
-  double sq[1] = {0.0};
-  for (int64_t i = threadIdx.x; i < N; i += blockDim.x) {
-    const double d = b[i] - (ka[i] - (t_valid_row(v, i, J) ? mu : 0.0));
-    sq[0] += d * d;
-  }
-  block_sum<1>(sq, lds);
-  if (threadIdx.x == 0) *out_norm = sqrt(sq[0]);
 }
 
 __global__ void k_fill(double* x, int64_t n, double value) {

@@ -41,6 +41,7 @@ struct Runs {
   size_t tmp_bytes = 0;
   int64_t R = 0;
   uint32_t* t0 = nullptr;
+  unsigned long long* n_out = nullptr;  // samples in no run (masked or out of range); zero-filled before runs_count
   uint32_t* bstart = nullptr;
   bool f32 = false;  // run sums of cos 2psi, sin 2psi stored in FP32 (else FP64)
   int32_t* tpix = nullptr;
@@ -65,6 +66,11 @@ struct Runs {
   void* pc = nullptr;
   void* ps = nullptr;
   int64_t* pstart = nullptr;
+  // Iteration keys [R] (time and pixel order): index << nb | (length - 1),
+  // used when nb > 0 (index and length fit 32 bits together).
+  uint32_t* tkey = nullptr;
+  uint32_t* pkey = nullptr;
+  int nb = 0;
 };
 
 hipError_t runs_tmp_bytes(int64_t n_t, int64_t n_pix, size_t* bytes);

@@ -118,11 +118,15 @@ unsigned grid_for(int64_t n, int64_t per_block, unsigned cap) {
 // head[t] = 1 where a run starts: an unmasked sample whose predecessor is on
 // another pixel, is masked, or lies in the previous baseline.
 __global__ void __launch_bounds__(kBlock) k_run_heads(const int32_t* __restrict__ pix, int64_t n_t, int64_t n_pix,
-                                                      int64_t L, uint32_t* __restrict__ head, int* __restrict__ err) {
+                                                      int64_t L, uint32_t* __restrict__ head, int* __restrict__ err,
+                                                      unsigned long long* __restrict__ n_out) {
+  __shared__ unsigned long long lds[16];
+  unsigned long long out[1] = {0};
   for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n_t; t += (int64_t)gridDim.x * blockDim.x) {
     const int p = pix[t];
     uint32_t h = 0;
     if (p >= n_pix) atomicOr(err, 1);
+    out[0] += (p < 0 || p >= n_pix) ? 1 : 0;
     if (p >= 0 && p < n_pix) {
       if (t == 0 || (t % L) == 0)
         h = 1;
@@ -131,6 +135,8 @@ __global__ void __launch_bounds__(kBlock) k_run_heads(const int32_t* __restrict_
     }
     head[t] = h;
   }
+  block_sum<1>(out, lds);
+  if (threadIdx.x == 0 && out[0]) atomicAdd(n_out, out[0]);
 }
 
 // First sample of each run, and the first run of each baseline.
@@ -152,50 +158,71 @@ __global__ void __launch_bounds__(kBlock) k_run_starts(const uint32_t* __restric
 // access.  Samples are summed in time order.
 template <typename PT, typename TT, typename RT, bool HAS_T, bool HAS_QU, bool IQU, bool TOD>
 __global__ void __launch_bounds__(kBlock) k_run_build(View v, const TT* __restrict__ tod,
-                                                      const uint32_t* __restrict__ t0, int64_t R,
+                                                      const uint32_t* __restrict__ t0,
+                                                      const unsigned long long* __restrict__ n_out, int64_t R,
                                                       int32_t* __restrict__ rpix, int32_t* __restrict__ rn,
                                                       RT* __restrict__ rc, RT* __restrict__ rs,
                                                       double* __restrict__ raw, RunRecord* __restrict__ rec) {
   const PT* psi = static_cast<const PT*>(v.psi);
-  const int64_t n_t = v.n_t, L = v.L;
+  const int64_t n_t = v.n_t;
+  constexpr int U = 4;  // samples whose loads are issued together
+  const bool gaps = *n_out != 0;
   for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < R; r += (int64_t)gridDim.x * blockDim.x) {
     const int64_t ts = t0[r];
-    const int p = v.pix[ts];
-    const int64_t tend = min(n_t, (ts / L + 1) * L);
+    // a run ends at the next run's start, the end of its baseline, or (with
+    // masked samples in the timeline) the first sample off its pixel
+    int64_t te = r + 1 < R ? (int64_t)t0[r + 1] : n_t;
+    te = min(te, (ts / v.L + 1) * v.L);
+    if (gaps) {
+      const int p = v.pix[ts];
+      int64_t t = ts + 1;
+      while (t < te && v.pix[t] == p) ++t;
+      te = t;
+    }
+    const int32_t n = (int32_t)(te - ts);
     double C = 0.0, S = 0.0, cc = 0.0, cs = 0.0;
     double dT = 0.0, dq = 0.0, du = 0.0, dQ = 0.0, dU = 0.0;
-    int64_t t = ts;
-    for (; t < tend && v.pix[t] == p; ++t) {
-      double c = 1.0, s = 0.0;
-      if (HAS_QU || IQU) {
-        rot2((double)psi[t], c, s);
-        C += c;
-        S += s;
-        cc += c * c;
-        cs += c * s;
+    for (int k0 = 0; k0 < n; k0 += U) {
+      double ps_[U], xT[U], xq[U], xu[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int64_t t = ts + k0 + u;
+        const bool in = k0 + u < n;
+        ps_[u] = ((HAS_QU || IQU) && in) ? (double)psi[t] : 0.0;
+        xT[u] = (TOD && HAS_T && in) ? (double)tod[v.rowT * n_t + t] : 0.0;
+        xq[u] = (TOD && HAS_QU && in) ? (double)tod[v.rowQ * n_t + t] : 0.0;
+        xu[u] = (TOD && HAS_QU && in) ? (double)tod[v.rowU * n_t + t] : 0.0;
       }
-      if (TOD && IQU) {
-        // radiometer row (1, c, s): sums of d and of the weighted c d, s d
-        const double x = (double)tod[v.rowT * n_t + t];
-        const double wx = v.w[0] * x;
-        dT += x;
-        dQ += c * wx;
-        dU += s * wx;
-      } else if (TOD) {
-        if (HAS_T) dT += (double)tod[v.rowT * n_t + t];
-        if (HAS_QU) {
-          const double xq = (double)tod[v.rowQ * n_t + t];
-          const double xu = (double)tod[v.rowU * n_t + t];
-          dq += xq;
-          du += xu;
-          const double wq = v.w[1] * xq, wu = v.w[2] * xu;
-          dQ += c * wq - s * wu;
-          dU += s * wq + c * wu;
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        if (k0 + u >= n) break;
+        double c = 1.0, s = 0.0;
+        if (HAS_QU || IQU) {
+          rot2(ps_[u], c, s);
+          C += c;
+          S += s;
+          cc += c * c;
+          cs += c * s;
+        }
+        if (TOD && IQU) {
+          // radiometer row (1, c, s): sums of d and of the weighted c d, s d
+          const double wx = v.w[0] * xT[u];
+          dT += xT[u];
+          dQ += c * wx;
+          dU += s * wx;
+        } else if (TOD) {
+          if (HAS_T) dT += xT[u];
+          if (HAS_QU) {
+            dq += xq[u];
+            du += xu[u];
+            const double wq = v.w[1] * xq[u], wu = v.w[2] * xu[u];
+            dQ += c * wq - s * wu;
+            dU += s * wq + c * wu;
+          }
         }
       }
     }
-    const int32_t n = (int32_t)(t - ts);
-    rpix[r] = p;
+    rpix[r] = v.pix[ts];
     rn[r] = n;
     if (HAS_QU || IQU) {
       rc[r] = (RT)C;
@@ -208,7 +235,7 @@ __global__ void __launch_bounds__(kBlock) k_run_build(View v, const TT* __restri
     }
     RunRecord x;
     x.n = n;
-    x.b = (int32_t)(ts / L);
+    x.b = (int32_t)(ts / v.L);
     x.C = C;
     x.S = S;
     x.cc = cc;
@@ -217,6 +244,17 @@ __global__ void __launch_bounds__(kBlock) k_run_build(View v, const TT* __restri
     x.dQ = dQ;
     x.dU = dU;
     rec[r] = x;
+  }
+}
+
+// Packed iteration keys: index << nb | (length - 1), time and pixel order.
+__global__ void __launch_bounds__(kBlock) k_pack_runs(int64_t R, int nb, const int32_t* __restrict__ tpix,
+                                                      const int32_t* __restrict__ tn, const int32_t* __restrict__ pb,
+                                                      const int32_t* __restrict__ pn, uint32_t* __restrict__ tkey,
+                                                      uint32_t* __restrict__ pkey) {
+  for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < R; r += (int64_t)gridDim.x * blockDim.x) {
+    tkey[r] = ((uint32_t)tpix[r] << nb) | (uint32_t)(tn[r] - 1);
+    pkey[r] = ((uint32_t)pb[r] << nb) | (uint32_t)(pn[r] - 1);
   }
 }
 
@@ -495,7 +533,8 @@ __global__ void __launch_bounds__(kBlock) k_rhs_runs(View v, const uint32_t* __r
 // dependent loads in flight); pw4[b] = (w_T p_T, w_q p_q, w_u p_u, 0).
 template <typename RT, bool HAS_T, bool HAS_QU, bool IQU, int LPP>
 __global__ void __launch_bounds__(kBlock) k_bin_runs(int64_t n_obs, const int64_t* __restrict__ pstart,
-                                                     const int32_t* __restrict__ pb, const int32_t* __restrict__ pn,
+                                                     const uint32_t* __restrict__ pb, const int32_t* __restrict__ pn,
+                                                     int nb,
                                                      const RT* __restrict__ pc, const RT* __restrict__ ps,
                                                      const double* __restrict__ pw4,
                                                      const double* __restrict__ Minv4,
@@ -523,8 +562,10 @@ __global__ void __launch_bounds__(kBlock) k_bin_runs(int64_t n_obs, const int64_
       for (int u = 0; u < U; ++u) {
         const int64_t j = jb + LPP * u;
         const bool in = j < j1;
-        bb[u] = in ? pb[j] : -1;
-        nn[u] = (HAS_T && in) ? pn[j] : 0;
+        // packed keys (nb > 0): baseline << nb | (length - 1); else baseline, lengths in pn
+        const uint32_t key = in ? pb[j] : 0u;
+        bb[u] = in ? (int32_t)(nb ? key >> nb : key) : -1;
+        nn[u] = (HAS_T && in) ? (nb ? (int32_t)(key & ((1u << nb) - 1u)) + 1 : pn[j]) : 0;
         cc[u] = ((HAS_QU || IQU) && in) ? (double)pc[j] : 0.0;
         ss[u] = ((HAS_QU || IQU) && in) ? (double)ps[j] : 0.0;
       }
@@ -578,8 +619,8 @@ __global__ void __launch_bounds__(kBlock) k_bin_runs(int64_t n_obs, const int64_
 // partials of p.q and of the T-projection sums.
 template <typename RT, bool HAS_T, bool HAS_QU, bool IQU, bool CG, int WPB>
 __global__ void __launch_bounds__(WPB > 4 ? 64 * WPB : kBlock) k_unbin_runs(View v, const uint32_t* __restrict__ bstart,
-                                                       const int32_t* __restrict__ rpix,
-                                                       const int32_t* __restrict__ rn, const RT* __restrict__ rc,
+                                                       const uint32_t* __restrict__ rpix,
+                                                       const int32_t* __restrict__ rn, int nb, const RT* __restrict__ rc,
                                                        const RT* __restrict__ rs, const double* __restrict__ m4,
                                                        const int32_t* __restrict__ nvalid,
                                                        const double* __restrict__ p, double* __restrict__ q,
@@ -609,8 +650,10 @@ __global__ void __launch_bounds__(WPB > 4 ? 64 * WPB : kBlock) k_unbin_runs(View
       for (int u = 0; u < U; ++u) {
         const int64_t r = rb + 64 * WPB * u;
         const bool in = r < r1;
-        cc_[u] = in ? rpix[r] : -1;
-        nn[u] = (HAS_T && in) ? rn[r] : 0;
+        // packed keys (nb > 0): compact pixel << nb | (length - 1); else pixel, lengths in rn
+        const uint32_t key = in ? rpix[r] : 0u;
+        cc_[u] = in ? (int32_t)(nb ? key >> nb : key) : -1;
+        nn[u] = (HAS_T && in) ? (nb ? (int32_t)(key & ((1u << nb) - 1u)) + 1 : rn[r]) : 0;
         C[u] = ((HAS_QU || IQU) && in) ? (double)rc[r] : 0.0;
         S[u] = ((HAS_QU || IQU) && in) ? (double)rs[r] : 0.0;
       }
@@ -717,7 +760,7 @@ hipError_t runs_tmp_bytes(int64_t n_t, int64_t n_pix, size_t* bytes) {
 hipError_t runs_count(const View& v, Runs& W, int* err, hipStream_t st) {
   const int64_t n_t = v.n_t;
   const unsigned g = grid_for(n_t, kBlock, 8192);
-  hipLaunchKernelGGL(k_run_heads, dim3(g), dim3(kBlock), 0, st, v.pix, n_t, v.n_pix, v.L, W.head, err);
+  hipLaunchKernelGGL(k_run_heads, dim3(g), dim3(kBlock), 0, st, v.pix, n_t, v.n_pix, v.L, W.head, err, W.n_out);
   DST_CHECK(hipGetLastError());
   size_t tmp = W.tmp_bytes;
   DST_CHECK(rocprim::exclusive_scan(W.tmp, tmp, W.head, W.hidx, 0u, (size_t)n_t, rocprim::plus<uint32_t>(), st));
@@ -782,7 +825,8 @@ hipError_t runs_build(const View& v, int psi_f32, const void* tod, int tod_f32, 
           by_bool(tod != nullptr, [&](auto D) {
             hipLaunchKernelGGL((k_run_build<PT, TT, RT, decltype(T)::value, decltype(Q)::value, decltype(I)::value,
                                             decltype(D)::value>),
-                               dim3(grb), dim3(kBlock), 0, st, v, static_cast<const TT*>(tod), W.t0, W.R, W.tpix, W.tn,
+                               dim3(grb), dim3(kBlock), 0, st, v, static_cast<const TT*>(tod), W.t0, W.n_out, W.R,
+                               W.tpix, W.tn,
                                static_cast<RT*>(W.tc), static_cast<RT*>(W.ts), W.raw, W.rec);
           });
         });
@@ -847,6 +891,15 @@ hipError_t runs_build(const View& v, int psi_f32, const void* tod, int tod_f32, 
   }
   // 6. time-order runs carry compact ids from here on
   hipLaunchKernelGGL(k_runs_to_compact, dim3(gr), dim3(kBlock), 0, st, R, W.cid, W.tpix);
+  DST_CHECK(hipGetLastError());
+  // 7. one 32-bit key per run for the iterations (index and length) when both fit
+  const unsigned nb = key_bits(v.L);
+  W.nb = 0;
+  if (W.tkey && W.pkey && key_bits(std::max<int64_t>(W.n_obs, 1)) + nb <= 32 && key_bits(v.n_b) + nb <= 32) {
+    W.nb = (int)nb;
+    hipLaunchKernelGGL(k_pack_runs, dim3(gr), dim3(kBlock), 0, st, R, W.nb, W.tpix, W.tn, W.pb, W.pn, W.tkey,
+                       W.pkey);
+  }
   return hipGetLastError();
 }
 
@@ -877,7 +930,8 @@ hipError_t launch_bin_runs(const View& vc, const Runs& W, const double* pw4, con
     by_streams(vc, [&](auto T, auto Q, auto I) {
       constexpr bool HT = decltype(T)::value, HQ = decltype(Q)::value, HI = decltype(I)::value;
       auto launch = [&](auto kern) {
-        hipLaunchKernelGGL(kern, dim3(g), dim3(kBlock), 0, st, W.n_obs, W.pstart, W.pb, W.pn,
+        hipLaunchKernelGGL(kern, dim3(g), dim3(kBlock), 0, st, W.n_obs, W.pstart,
+                           W.nb ? W.pkey : reinterpret_cast<const uint32_t*>(W.pb), W.pn, W.nb,
                            static_cast<const RT*>(W.pc), static_cast<const RT*>(W.ps), pw4, Minv4, valid, m4, gate);
       };
       if (lpp == 16)
@@ -905,7 +959,8 @@ hipError_t launch_unbin_runs(const View& vc, const Runs& W, const double* m4, co
         constexpr bool HT = decltype(T)::value, HQ = decltype(Q)::value, HI = decltype(I)::value;
         constexpr bool C = decltype(CG)::value;
         auto launch = [&](auto kern) {
-          hipLaunchKernelGGL(kern, dim3(g), dim3(nt), 0, st, vc, W.bstart, W.tpix, W.tn,
+          hipLaunchKernelGGL(kern, dim3(g), dim3(nt), 0, st, vc, W.bstart,
+                             W.nb ? W.tkey : reinterpret_cast<const uint32_t*>(W.tpix), W.tn, W.nb,
                              static_cast<const RT*>(W.tc), static_cast<const RT*>(W.ts), m4, nvalid, p, q, ctl,
                              partials);
         };
