@@ -572,7 +572,8 @@ int solve_group(dst_ctx* ctx, const dst_problem* problems, const std::vector<int
   double *prs, *braw, *b, *a, *r, *z, *p, *q, *ka, *md, *m, *part, *part2;
   dst::MultiCtl* ctl;
   DST_TRY(ws(ctx, "mb_ipos", (size_t)std::max<int64_t>(W.R, 1), &ipos));
-  DST_TRY(ws(ctx, "mb_prs", 4 * (size_t)std::max<int64_t>(W.R, 1), &prs));
+  const int64_t prs_stride = 4 * std::max<int64_t>(W.R, 1);
+  DST_TRY(ws(ctx, "mb_prs", (size_t)dst::kTodBatch * prs_stride, &prs));
   DST_TRY(ws(ctx, "mb_braw", NV, &braw));
   DST_TRY(ws(ctx, "mb_b", NV, &b));
   DST_TRY(ws(ctx, "mb_a", NV, &a));
@@ -593,11 +594,19 @@ int solve_group(dst_ctx* ctx, const dst_problem* problems, const std::vector<int
 
   // per problem: run sums of the data, binned map; then every b at once
   HIP_TRY(dst::launch_run_positions(W, ipos, st));
-  for (int k = 0; k < mu.R; ++k) {
-    const dst_problem& pk = problems[idx[k]];
-    HIP_TRY(dst::launch_multi_tod(vc, S.psi_f32, pk.tod, pk.tod_dtype == DST_F32, W, ipos, S.valid, mu.Rp, k, prs,
+  // realizations in passes of up to kTodBatch with one timeline dtype
+  for (int k = 0; k < mu.R;) {
+    const int32_t dt = problems[idx[k]].tod_dtype;
+    dst::TodSet tods{};
+    int nr = 0;
+    while (k + nr < mu.R && nr < dst::kTodBatch && problems[idx[k + nr]].tod_dtype == dt) {
+      tods.p[nr] = problems[idx[k + nr]].tod;
+      ++nr;
+    }
+    HIP_TRY(dst::launch_multi_tod(vc, S.psi_f32, tods, nr, dt == DST_F32, W, ipos, S.valid, mu.Rp, k, prs, prs_stride,
                                   braw, st));
-    HIP_TRY(dst::launch_multi_pixsum(n_obs, vc, W, prs, S.Minv4, mu.Rp, k, md, st));
+    HIP_TRY(dst::launch_multi_pixsum(n_obs, vc, W, prs, prs_stride, nr, S.Minv4, mu.Rp, k, md, st));
+    k += nr;
   }
   HIP_TRY(dst::launch_multi_unbin(vc, W, mu, dst::UNBIN_RHS, md, S.nvalid, nullptr, braw, b, nullptr, nullptr, st));
   HIP_TRY(dst::launch_multi_start(v, mu, b, a, r, z, p, S.J, ctl, part2, opts.tol, opts.max_iter, st));

@@ -56,15 +56,22 @@ int multi_padded(int R);
 // ipos[run] = position of time-order run `run` in the pixel-order arrays.
 hipError_t launch_run_positions(const Runs& W, uint32_t* ipos, hipStream_t st);
 
-// Realization `ri`: per-run sums of the weighted data (pixel order, [R][4]:
-// w_T d_T, rotated Q, rotated U) and per-baseline sums w_k d_k over valid
-// samples into braw ([n_b][n_streams][Rp], column ri).
-hipError_t launch_multi_tod(const View& vc, int psi_f32, const void* tod, int tod_f32, const Runs& W,
-                            const uint32_t* ipos, const uint8_t* valid, int Rp, int ri, double* prs, double* braw,
-                            hipStream_t st);
-// Realization `ri`: binned map md = M^-1 (sum of the pixel's run sums).
-hipError_t launch_multi_pixsum(int64_t n_obs, const View& vc, const Runs& W, const double* prs, const double* Minv4,
-                               int Rp, int ri, double* md, hipStream_t st);
+// Timelines of up to kTodBatch realizations handled by one setup pass.
+constexpr int kTodBatch = 4;
+struct TodSet {
+  const void* p[kTodBatch];
+};
+
+// Realizations ri0 .. ri0 + nr - 1 (nr <= kTodBatch, same tod dtype): per-run
+// sums of the weighted data at each run's pixel-order position (realization i
+// in prs + i * prs_stride, [R][4]: w_T d_T, rotated Q, rotated U) and
+// per-baseline sums w_k d_k over valid samples into braw ([n_b][n_streams][Rp]).
+hipError_t launch_multi_tod(const View& vc, int psi_f32, const TodSet& tods, int nr, int tod_f32, const Runs& W,
+                            const uint32_t* ipos, const uint8_t* valid, int Rp, int ri0, double* prs,
+                            int64_t prs_stride, double* braw, hipStream_t st);
+// Realizations ri0 .. ri0 + nr - 1: binned maps md = M^-1 (sum of the pixel's run sums).
+hipError_t launch_multi_pixsum(int64_t n_obs, const View& vc, const Runs& W, const double* prs, int64_t prs_stride,
+                               int nr, const double* Minv4, int Rp, int ri0, double* md, hipStream_t st);
 
 // m = M^-1 A^T W F p for every active right-hand side (ctl NULL: all R).
 hipError_t launch_multi_bin(const View& vc, const Runs& W, const Multi& mu, const double* p, const double* Minv4,

@@ -43,91 +43,126 @@ __global__ void __launch_bounds__(kBlock) k_run_positions(int64_t n_obs, const u
   }
 }
 
-// One wavefront per baseline; one lane per run.  Per run: w_T sum d_T and the
-// rotated, weighted q/u sums, stored at the run's pixel-order position; per
-// baseline: w_k sum d_k over valid samples (the data part of b = F^T Z d).
-template <typename PT, typename TT, bool HAS_T, bool HAS_QU>
-__global__ void __launch_bounds__(kBlock) k_multi_tod(View v, const TT* __restrict__ tod,
-                                                      const uint32_t* __restrict__ bstart,
+// One wavefront per baseline; one lane per run; NR realizations per pass
+// (their timelines share the angle loads and the trigonometry).  Per run and
+// realization: w_T sum d_T and the rotated, weighted q/u sums, stored at the
+// run's pixel-order position in that realization's array; per baseline: w_k
+// sum d_k over valid samples (the data part of b = F^T Z d).
+template <typename PT, typename TT, bool HAS_T, bool HAS_QU, int NR>
+__global__ void __launch_bounds__(kBlock) k_multi_tod(View v, TodSet tods, const uint32_t* __restrict__ bstart,
                                                       const uint32_t* __restrict__ t0,
                                                       const int32_t* __restrict__ tpix, const int32_t* __restrict__ tn,
                                                       const uint32_t* __restrict__ ipos,
-                                                      const uint8_t* __restrict__ valid, int Rp, int ri,
-                                                      double* __restrict__ prs, double* __restrict__ braw) {
+                                                      const uint8_t* __restrict__ valid, int Rp, int ri0,
+                                                      double* __restrict__ prs, int64_t prs_stride,
+                                                      double* __restrict__ braw) {
   const PT* psi = static_cast<const PT*>(v.psi);
   const int lane = lane_id();
   const int64_t b = (int64_t)blockIdx.x * kWaves + (threadIdx.x >> 6);
   if (b >= v.n_b) return;
   const int64_t n_t = v.n_t;
   const int64_t r0 = bstart[b], r1 = bstart[b + 1];
-  double acc[3] = {0.0, 0.0, 0.0};
+  double acc[3 * NR];
+#pragma unroll
+  for (int i = 0; i < 3 * NR; ++i) acc[i] = 0.0;
+  constexpr int U = NR >= 3 ? 1 : (NR == 2 ? 2 : 4);  // samples whose loads are issued together
   for (int64_t j = r0 + lane; j < r1; j += 64) {
     const int64_t ts = t0[j];
     const int n = tn[j];
     const uint8_t f = valid[tpix[j]];
-    double dT = 0.0, dq = 0.0, du = 0.0, dQ = 0.0, dU = 0.0;
-    for (int k = 0; k < n; ++k) {
-      const int64_t t = ts + k;
-      if (HAS_T) dT += (double)tod[v.rowT * n_t + t];
-      if (HAS_QU) {
-        double c, s;
-        rot2((double)psi[t], c, s);
-        const double xq = (double)tod[v.rowQ * n_t + t];
-        const double xu = (double)tod[v.rowU * n_t + t];
-        dq += xq;
-        du += xu;
-        const double wq = v.w[1] * xq, wu = v.w[2] * xu;
-        dQ += c * wq - s * wu;
-        dU += s * wq + c * wu;
+    double dT[NR], dq[NR], du[NR], dQ[NR], dU[NR];
+#pragma unroll
+    for (int i = 0; i < NR; ++i) dT[i] = dq[i] = du[i] = dQ[i] = dU[i] = 0.0;
+    for (int k0 = 0; k0 < n; k0 += U) {
+      double ang[U], xT[U][NR], xq[U][NR], xu[U][NR];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int64_t t = ts + k0 + u;
+        const bool in = k0 + u < n;
+        ang[u] = (HAS_QU && in) ? (double)psi[t] : 0.0;
+#pragma unroll
+        for (int i = 0; i < NR; ++i) {
+          const TT* tod = static_cast<const TT*>(tods.p[i]);
+          xT[u][i] = (HAS_T && in) ? (double)tod[v.rowT * n_t + t] : 0.0;
+          xq[u][i] = (HAS_QU && in) ? (double)tod[v.rowQ * n_t + t] : 0.0;
+          xu[u][i] = (HAS_QU && in) ? (double)tod[v.rowU * n_t + t] : 0.0;
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        if (k0 + u >= n) break;
+        double c = 1.0, s = 0.0;
+        if (HAS_QU) rot2(ang[u], c, s);
+#pragma unroll
+        for (int i = 0; i < NR; ++i) {
+          if (HAS_T) dT[i] += xT[u][i];
+          if (HAS_QU) {
+            dq[i] += xq[u][i];
+            du[i] += xu[u][i];
+            const double wq = v.w[1] * xq[u][i], wu = v.w[2] * xu[u][i];
+            dQ[i] += c * wq - s * wu;
+            dU[i] += s * wq + c * wu;
+          }
+        }
       }
     }
     const bool vT = HAS_T && (f & 1), vQ = HAS_QU && (f & 2);
-    double2* o = reinterpret_cast<double2*>(prs + 4 * (int64_t)ipos[j]);
-    o[0] = make_double2(vT ? v.w[0] * dT : 0.0, vQ ? dQ : 0.0);
-    o[1] = make_double2(vQ ? dU : 0.0, 0.0);
-    if (vT) acc[0] += dT;
-    if (vQ) {
-      acc[1] += dq;
-      acc[2] += du;
+    const int64_t pos = ipos[j];
+#pragma unroll
+    for (int i = 0; i < NR; ++i) {
+      double2* o = reinterpret_cast<double2*>(prs + i * prs_stride + 4 * pos);
+      o[0] = make_double2(vT ? v.w[0] * dT[i] : 0.0, vQ ? dQ[i] : 0.0);
+      o[1] = make_double2(vQ ? dU[i] : 0.0, 0.0);
+      if (vT) acc[3 * i] += dT[i];
+      if (vQ) {
+        acc[3 * i + 1] += dq[i];
+        acc[3 * i + 2] += du[i];
+      }
     }
   }
-  dev::wave_sum<3>(acc);
+  dev::wave_sum<3 * NR>(acc);
   if (lane == 0) {
-    const int64_t o = b * v.n_streams * Rp + ri;
-    if (HAS_T) braw[o + v.rowT * Rp] = v.w[0] * acc[0];
-    if (HAS_QU) {
-      braw[o + v.rowQ * Rp] = v.w[1] * acc[1];
-      braw[o + v.rowU * Rp] = v.w[2] * acc[2];
+    const int64_t o = b * v.n_streams * Rp + ri0;
+#pragma unroll
+    for (int i = 0; i < NR; ++i) {
+      if (HAS_T) braw[o + v.rowT * Rp + i] = v.w[0] * acc[3 * i];
+      if (HAS_QU) {
+        braw[o + v.rowQ * Rp + i] = v.w[1] * acc[3 * i + 1];
+        braw[o + v.rowU * Rp + i] = v.w[2] * acc[3 * i + 2];
+      }
     }
   }
 }
 
-// One wavefront per compact pixel: md = M^-1 (sum of its run sums), column ri.
+// One wavefront per compact pixel: md = M^-1 (sum of its run sums), columns
+// ri0 .. ri0 + nr - 1.
 __global__ void __launch_bounds__(kBlock) k_multi_pixsum(int64_t n_obs, View vc, const int64_t* __restrict__ pstart,
-                                                         const double* __restrict__ prs,
-                                                         const double* __restrict__ Minv4, int Rp, int ri,
+                                                         const double* __restrict__ prs, int64_t prs_stride, int nr,
+                                                         const double* __restrict__ Minv4, int Rp, int ri0,
                                                          double* __restrict__ md) {
   const int lane = lane_id();
   const int64_t nw = (int64_t)gridDim.x * kWaves;
   for (int64_t c = (int64_t)blockIdx.x * kWaves + (threadIdx.x >> 6); c < n_obs; c += nw) {
     const int64_t j0 = pstart[c], j1 = pstart[c + 1];
-    double acc[3] = {0.0, 0.0, 0.0};
-    for (int64_t j = j0 + lane; j < j1; j += 64) {
-      const double2* x = reinterpret_cast<const double2*>(prs + 4 * j);
-      const double2 x0 = x[0], x1 = x[1];
-      acc[0] += x0.x;
-      acc[1] += x0.y;
-      acc[2] += x1.x;
-    }
-    dev::wave_sum<3>(acc);
-    if (lane == 0) {
-      const double2* ip = reinterpret_cast<const double2*>(Minv4 + 4 * c);
-      const double2 i01 = ip[0], i23 = ip[1];
-      const int64_t o = c * vc.n_streams * Rp + ri;
-      if (vc.rowT >= 0) md[o + vc.rowT * Rp] = i01.x * acc[0];
-      if (vc.rowQ >= 0) {
-        md[o + vc.rowQ * Rp] = i01.y * acc[1] + i23.x * acc[2];
-        md[o + vc.rowU * Rp] = i23.x * acc[1] + i23.y * acc[2];
+    const double2* ip = reinterpret_cast<const double2*>(Minv4 + 4 * c);
+    const double2 i01 = ip[0], i23 = ip[1];
+    for (int i = 0; i < nr; ++i) {
+      double acc[3] = {0.0, 0.0, 0.0};
+      for (int64_t j = j0 + lane; j < j1; j += 64) {
+        const double2* x = reinterpret_cast<const double2*>(prs + i * prs_stride + 4 * j);
+        const double2 x0 = x[0], x1 = x[1];
+        acc[0] += x0.x;
+        acc[1] += x0.y;
+        acc[2] += x1.x;
+      }
+      dev::wave_sum<3>(acc);
+      if (lane == 0) {
+        const int64_t o = c * vc.n_streams * Rp + ri0 + i;
+        if (vc.rowT >= 0) md[o + vc.rowT * Rp] = i01.x * acc[0];
+        if (vc.rowQ >= 0) {
+          md[o + vc.rowQ * Rp] = i01.y * acc[1] + i23.x * acc[2];
+          md[o + vc.rowU * Rp] = i23.x * acc[1] + i23.y * acc[2];
+        }
       }
     }
   }
@@ -691,28 +726,38 @@ hipError_t launch_run_positions(const Runs& W, uint32_t* ipos, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_multi_tod(const View& vc, int psi_f32, const void* tod, int tod_f32, const Runs& W,
-                            const uint32_t* ipos, const uint8_t* valid, int Rp, int ri, double* prs, double* braw,
-                            hipStream_t st) {
+hipError_t launch_multi_tod(const View& vc, int psi_f32, const TodSet& tods, int nr, int tod_f32, const Runs& W,
+                            const uint32_t* ipos, const uint8_t* valid, int Rp, int ri0, double* prs,
+                            int64_t prs_stride, double* braw, hipStream_t st) {
   const unsigned g = grid_for(vc.n_b, kWaves, INT32_MAX);
   by_float(psi_f32, [&](auto pt) {
     using PT = typename decltype(pt)::type;
     by_float(tod_f32, [&](auto tt) {
       using TT = typename decltype(tt)::type;
       by_streams(vc, [&](auto T, auto Q) {
-        hipLaunchKernelGGL((k_multi_tod<PT, TT, decltype(T)::value, decltype(Q)::value>), dim3(g), dim3(kBlock), 0,
-                           st, vc, static_cast<const TT*>(tod), W.bstart, W.t0, W.tpix, W.tn, ipos, valid, Rp, ri,
-                           prs, braw);
+        constexpr bool HT = decltype(T)::value, HQ = decltype(Q)::value;
+        auto launch = [&](auto kern) {
+          hipLaunchKernelGGL(kern, dim3(g), dim3(kBlock), 0, st, vc, tods, W.bstart, W.t0, W.tpix, W.tn, ipos, valid,
+                             Rp, ri0, prs, prs_stride, braw);
+        };
+        if (nr >= 4)
+          launch(k_multi_tod<PT, TT, HT, HQ, 4>);
+        else if (nr == 3)
+          launch(k_multi_tod<PT, TT, HT, HQ, 3>);
+        else if (nr == 2)
+          launch(k_multi_tod<PT, TT, HT, HQ, 2>);
+        else
+          launch(k_multi_tod<PT, TT, HT, HQ, 1>);
       });
     });
   });
   return hipGetLastError();
 }
 
-hipError_t launch_multi_pixsum(int64_t n_obs, const View& vc, const Runs& W, const double* prs, const double* Minv4,
-                               int Rp, int ri, double* md, hipStream_t st) {
+hipError_t launch_multi_pixsum(int64_t n_obs, const View& vc, const Runs& W, const double* prs, int64_t prs_stride,
+                               int nr, const double* Minv4, int Rp, int ri0, double* md, hipStream_t st) {
   hipLaunchKernelGGL(k_multi_pixsum, dim3(grid_for(n_obs, kWaves, 16384)), dim3(kBlock), 0, st, n_obs, vc, W.pstart,
-                     prs, Minv4, Rp, ri, md);
+                     prs, prs_stride, nr, Minv4, Rp, ri0, md);
   return hipGetLastError();
 }
 
