@@ -46,6 +46,8 @@ VARIANTS = {
     "T": dict(streams="T"),
     "L1": dict(n_samples=700, L=1),
     "L37": dict(n_samples=3001, L=37),
+    # 12 pixels: every pixel holds thousands of runs, spanning many chunks of the flat binning
+    "fewpix": dict(nside=1, n_samples=200000, L=50),
 }
 
 
@@ -246,3 +248,23 @@ def test_autotuned_solve_matches(ctx):
         out = dst.dst_solve(ctx, d, tol=1e-12, flags=dst.DST_SOLVE_AUTOTUNE)
         assert abs(out["iterations"] - ref["iterations"]) <= 1
         assert rel(out["baselines"].cpu().numpy(), ref["baselines"].cpu().numpy()) < 1e-9
+
+
+@pytest.mark.parametrize("name", ["plain", "masked", "fewpix", "QU", "T"])
+def test_bin_launch_shapes_agree(name):
+    """Every launch shape of the binning gives the same solve (summation order aside)."""
+    import os
+    from paper_1309_5609_amd import dst
+    p = make(name)
+    out = {}
+    for lpp in ("32", "64", "16"):
+        os.environ["DST_BIN_LPP"] = lpp
+        try:
+            c = dst.Context(0)
+        finally:
+            del os.environ["DST_BIN_LPP"]
+        out[lpp] = dst.dst_solve(c, dev(p), tol=1e-13, max_iter=3000)
+        c.close()
+    for lpp in ("64", "16"):
+        assert abs(out[lpp]["iterations"] - out["32"]["iterations"]) <= 1
+        assert rel(out[lpp]["baselines"].cpu().numpy(), out["32"]["baselines"].cpu().numpy()) < 1e-10
