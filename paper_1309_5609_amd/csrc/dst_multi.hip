@@ -196,7 +196,7 @@ __global__ void __launch_bounds__(kBlock) k_multi_bin(View vc, int R, int Rp, co
   for (int64_t c = (int64_t)blockIdx.x * kWaves + (threadIdx.x >> 6); c < n_obs; c += nw) {
     const int64_t j0 = pstart[c], j1 = pstart[c + 1];
     double acc[3] = {0.0, 0.0, 0.0};
-    constexpr int U = 2;
+    constexpr int U = 1;  // one run per slot in flight: fewer registers, higher occupancy
     for (int64_t jb = j0 + slot; jb < j1; jb += (int64_t)slots * U) {
       int32_t bb[U], nn[U];
       double C[U], S[U];
@@ -270,7 +270,7 @@ __global__ void __launch_bounds__(kBlock) k_multi_unbin(View vc, int R, int Rp, 
   for (int64_t b = lo + k * kWaves + wave; b < hi; b += nk * kWaves) {
     const int64_t r0 = bstart[b], r1 = bstart[b + 1];
     double acc[3] = {0.0, 0.0, 0.0};
-    constexpr int U = 2;
+    constexpr int U = 1;
     for (int64_t jb = r0 + slot; jb < r1; jb += (int64_t)slots * U) {
       int32_t cc[U], nn[U];
       double C[U], S[U];
