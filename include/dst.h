@@ -108,8 +108,8 @@ int dst_version(void);
 /* Create a context on HIP device `device`.  *ctx receives the handle.
  * Launch shapes of the run-form iteration kernels may be overridden by the
  * environment at creation: DST_BIN_LPP (lanes per pixel in the binning: 64,
- * 32 = default, 16) and DST_UNBIN_WPB (wavefronts per baseline in the rescan:
- * 1 = default, 2, 4, 8, 16).  They change speed only, not results beyond
+ * 32 = default, 16) and DST_UNBIN_BPW (baselines per wavefront in the
+ * rescan: 1, 2, 4 = default, 8).  They change speed only, not results beyond
  * summation order. */
 int dst_create(dst_ctx** ctx, int device);
 

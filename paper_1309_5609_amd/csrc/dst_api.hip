@@ -38,7 +38,7 @@ struct dst_ctx {
   int* err_host = nullptr;    // pinned mirror of the device error flag
   dst::MultiCtl* mctl_host = nullptr;  // pinned mirror of the batched CG state
   hipStream_t cap = nullptr;  // private stream on which iteration graphs are captured
-  int unbin_wpb = 1;          // launch shape of the run rescan (wavefronts per baseline)
+  int unbin_bpw = 4;          // launch shape of the run rescan (baselines per wavefront)
   int bin_lpp = 32;           // launch shape of the run binning (lanes per pixel)
   // launch shapes chosen by the autotuner, per problem shape
   std::map<std::tuple<int64_t, int64_t, int, int>, std::pair<int, int>> tuned;
@@ -268,7 +268,7 @@ struct Plan {
   double* m4 = nullptr;   // per-iteration map (zero on invalid pixels)
   double* pw4 = nullptr;  // weighted interleaved baseline vector
   int lpp = 32;           // launch shapes of the run binning and rescan
-  int wpb = 1;
+  int bpw = 4;
   const int32_t* cid() const { return runs ? W.cid : T.cid; }
 };
 
@@ -286,10 +286,14 @@ int build_runs_plan(dst_ctx* ctx, const dst_problem* prob, Plan& P, const void* 
   DST_TRY(ws(ctx, "r_head", v.n_t, &W.head));
   DST_TRY(ws(ctx, "r_hidx", v.n_t, &W.hidx));
   size_t tmp_bytes = 0;
-  HIP_TRY(dst::runs_tmp_bytes(v.n_t, v.n_pix, &tmp_bytes));
+  HIP_TRY(dst::runs_tmp_bytes(v.n_t, v.n_pix, v.n_b, &tmp_bytes));
   DST_TRY(ws_get(ctx, "r_tmp", tmp_bytes, &W.tmp));
   W.tmp_bytes = tmp_bytes;
   DST_TRY(ws(ctx, "r_bstart", v.n_b + 1, &W.bstart));
+  DST_TRY(ws(ctx, "r_bkey0", v.n_b, &W.bkey[0]));
+  DST_TRY(ws(ctx, "r_bkey1", v.n_b, &W.bkey[1]));
+  DST_TRY(ws(ctx, "r_bord0", v.n_b, &W.bord[0]));
+  DST_TRY(ws(ctx, "r_bord1", v.n_b, &W.bord[1]));
   DST_TRY(ws(ctx, "r_seg", 2 * (size_t)v.n_pix, &W.seg));
   DST_TRY(ws(ctx, "r_pk0", v.n_pix, &W.pk[0]));
   DST_TRY(ws(ctx, "r_pk1", v.n_pix, &W.pk[1]));
@@ -422,7 +426,7 @@ int build_sample_plan(dst_ctx* ctx, const dst_problem* prob, Plan& P, const void
 int build_plan(dst_ctx* ctx, const dst_problem* prob, Plan& P, const void* tod, double** sd4, double** md4,
                double* b, hipStream_t st) {
   P.lpp = ctx->bin_lpp;
-  P.wpb = ctx->unbin_wpb;
+  P.bpw = ctx->unbin_bpw;
   return P.runs ? build_runs_plan(ctx, prob, P, tod, sd4, md4, b, st)
                 : build_sample_plan(ctx, prob, P, tod, sd4, md4, b, st);
 }
@@ -441,7 +445,7 @@ int plan_bin(dst_ctx* ctx, Plan& P, const CgCtl* gate, hipStream_t st) {
 int plan_unbin(dst_ctx* ctx, Plan& P, const double* p, double* q, CgCtl* ctl, double* partials, hipStream_t st) {
   Setup& S = P.S;
   if (P.runs)
-    HIP_TRY(dst::launch_unbin_runs(S.v, P.W, P.m4, S.nvalid, p, q, ctl, partials, P.wpb, st));
+    HIP_TRY(dst::launch_unbin_runs(S.v, P.W, P.m4, S.nvalid, p, q, ctl, partials, P.bpw, st));
   else
     HIP_TRY(dst::launch_unbin_cg(S.v, S.psi_f32, P.m4, S.nvalid, p, q, ctl, partials, st));
   return DST_OK;
@@ -863,7 +867,7 @@ int autotune(dst_ctx* ctx, Plan& P, const double* p, double* scratch, hipStream_
       }
       return best;
     };
-    int best_lpp = P.lpp, best_wpb = P.wpb;
+    int best_lpp = P.lpp, best_bpw = P.bpw;
     float tb = 1e30f, tu = 1e30f;
     for (int lpp : {64, 32, 16}) {
       const float t = time_of([&] {
@@ -875,20 +879,20 @@ int autotune(dst_ctx* ctx, Plan& P, const double* p, double* scratch, hipStream_
         best_lpp = lpp;
       }
     }
-    for (int wpb : {1, 2, 4, 8}) {
+    for (int bpw : {1, 2, 4, 8}) {
       const float t = time_of([&] {
-        return dst::launch_unbin_runs(S.v, P.W, P.m4, S.nvalid, p, scratch, nullptr, nullptr, wpb, st);
+        return dst::launch_unbin_runs(S.v, P.W, P.m4, S.nvalid, p, scratch, nullptr, nullptr, bpw, st);
       });
       if (t < 0.f) return fail(ctx, DST_EHIP, "autotuner: a rescan launch failed");
       if (t < tu) {
         tu = t;
-        best_wpb = wpb;
+        best_bpw = bpw;
       }
     }
-    it = ctx->tuned.emplace(key, std::make_pair(best_lpp, best_wpb)).first;
+    it = ctx->tuned.emplace(key, std::make_pair(best_lpp, best_bpw)).first;
   }
   P.lpp = it->second.first;
-  P.wpb = it->second.second;
+  P.bpw = it->second.second;
   return DST_OK;
 }
 
@@ -906,7 +910,7 @@ int dst_create(dst_ctx** out, int device) {
   dst_ctx* ctx = new (std::nothrow) dst_ctx();
   if (!ctx) return DST_ENOMEM;
   ctx->device = device;
-  if (const char* e = std::getenv("DST_UNBIN_WPB")) ctx->unbin_wpb = std::atoi(e);
+  if (const char* e = std::getenv("DST_UNBIN_BPW")) ctx->unbin_bpw = std::atoi(e);
   if (const char* e = std::getenv("DST_BIN_LPP")) ctx->bin_lpp = std::atoi(e);
   DeviceGuard g(device);
   if (hipHostMalloc(reinterpret_cast<void**>(&ctx->ctl_host), sizeof(CgCtl), hipHostMallocDefault) != hipSuccess ||

@@ -33,7 +33,7 @@ static_assert(sizeof(RunRecord) == 64, "run record must be one 64-byte line");
 // f32, else FP64);
 // raw [3 R]; rec [R]; keys, vals 2 x [R]; seg [2 n_pix] (zero-filled before
 // runs_build); pk, pv 2 x [n_pix]; cid [n_pix] (filled with -1 before
-// runs_build); ccount, pstart [n_pix + 1].
+// runs_build); ccount, pstart [n_pix + 1]; bkey, bord 2 x [n_b].
 struct Runs {
   uint32_t* head = nullptr;
   uint32_t* hidx = nullptr;
@@ -71,9 +71,14 @@ struct Runs {
   uint32_t* tkey = nullptr;
   uint32_t* pkey = nullptr;
   int nb = 0;
+  // Rescan order of the baselines (set by runs_build): sorted by the smallest
+  // compact id each visits, so baselines over the same sky sit together.
+  uint32_t* bkey[2] = {nullptr, nullptr};
+  uint32_t* bord[2] = {nullptr, nullptr};
+  const uint32_t* border = nullptr;
 };
 
-hipError_t runs_tmp_bytes(int64_t n_t, int64_t n_pix, size_t* bytes);
+hipError_t runs_tmp_bytes(int64_t n_t, int64_t n_pix, int64_t n_b, size_t* bytes);
 // Marks run heads and counts the runs (W.R); synchronises `st`.
 hipError_t runs_count(const View& v, Runs& W, int* err, hipStream_t st);
 // Builds the time- and pixel-order runs, compact ids (synchronises `st` once
@@ -91,8 +96,9 @@ hipError_t launch_rhs_runs(const View& vc, const Runs& W, const void* tod, const
 hipError_t launch_bin_runs(const View& vc, const Runs& W, const double* pw4, const double* Minv4,
                            const uint8_t* valid, double* m4, const CgCtl* gate, int lpp, hipStream_t st);
 // q = K p; with ctl the per-baseline CG partials (finished by launch_cg_alpha).
-// wpb: wavefronts per baseline (1, 2 or 4).
+// bpw: baselines per wavefront (1, 2, 4 or 8; else 4), taken in the order
+// W.border.
 hipError_t launch_unbin_runs(const View& vc, const Runs& W, const double* m4, const int32_t* nvalid, const double* p,
-                             double* q, CgCtl* ctl, double* partials, int wpb, hipStream_t st);
+                             double* q, CgCtl* ctl, double* partials, int bpw, hipStream_t st);
 
 }  // namespace dst

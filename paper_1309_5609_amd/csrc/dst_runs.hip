@@ -465,6 +465,25 @@ __global__ void __launch_bounds__(kBlock) k_runs_to_compact(int64_t R, const int
     rpix[r] = cid[rpix[r]];
 }
 
+// Per baseline: the smallest compact id its runs visit (n_obs when it has
+// none), the key that orders baselines for the rescan; val = baseline index.
+__global__ void __launch_bounds__(kBlock) k_baseline_keys(int64_t n_b, int64_t n_obs,
+                                                          const uint32_t* __restrict__ bstart,
+                                                          const int32_t* __restrict__ rpix,
+                                                          uint32_t* __restrict__ key, uint32_t* __restrict__ val) {
+  const int lane = lane_id();
+  const int64_t nw = (int64_t)gridDim.x * kWaves;
+  for (int64_t b = (int64_t)blockIdx.x * kWaves + (threadIdx.x >> 6); b < n_b; b += nw) {
+    uint32_t m = (uint32_t)n_obs;
+    for (int64_t r = bstart[b] + lane; r < bstart[b + 1]; r += 64) m = min(m, (uint32_t)rpix[r]);
+    for (int off = 32; off > 0; off >>= 1) m = min(m, (uint32_t)__shfl_xor((int)m, off, 64));
+    if (lane == 0) {
+      key[b] = m;
+      val[b] = (uint32_t)b;
+    }
+  }
+}
+
 // Per baseline (time-order runs): n_valid, the Jacobi diagonal and with TOD
 //   b_k = w_k sum_{runs, valid_k} (sum of d_k over the run - A-weighted m_d).
 template <typename RT, bool HAS_T, bool HAS_QU, bool IQU, bool TOD>
@@ -611,86 +630,101 @@ __global__ void __launch_bounds__(kBlock) k_bin_runs(int64_t n_obs, const int64_
   }
 }
 
-// q = K p = F^T W (F p - A m) per baseline from its time-order runs.  WPB
-// wavefronts share one baseline (4 / WPB baselines per workgroup); consecutive
-// workgroups run on one XCD and take consecutive baselines, so fewer
-// baselines in flight per XCD (larger WPB) keep the map values they gather
-// in that XCD's L2.  m is zero on invalid blocks.  With CG: per-baseline
-// partials of p.q and of the T-projection sums.
-template <typename RT, bool HAS_T, bool HAS_QU, bool IQU, bool CG, int WPB>
-__global__ void __launch_bounds__(WPB > 4 ? 64 * WPB : kBlock) k_unbin_runs(View v, const uint32_t* __restrict__ bstart,
+// q = K p = F^T W (F p - A m) per baseline from its time-order runs.  BPW
+// baselines share a wavefront (64 / BPW lanes each), taken in the order
+// `border` (baselines sorted by the smallest compact pixel they visit), so
+// the baselines of one wavefront cross nearly the same pixels — for a scan
+// that repeats every sidereal day, the same stretch of sky on different
+// days — and one gather instruction touches fewer distinct map lines.
+// Consecutive workgroups run on one XCD and take consecutive wavefront tasks.
+// m is zero on invalid blocks.  With CG: per-baseline partials of p.q and of
+// the T-projection sums.
+template <typename RT, bool HAS_T, bool HAS_QU, bool IQU, bool CG, int BPW>
+__global__ void __launch_bounds__(kBlock) k_unbin_runs(View v, const uint32_t* __restrict__ bstart,
+                                                       const uint32_t* __restrict__ border,
                                                        const uint32_t* __restrict__ rpix,
                                                        const int32_t* __restrict__ rn, int nb, const RT* __restrict__ rc,
                                                        const RT* __restrict__ rs, const double* __restrict__ m4,
                                                        const int32_t* __restrict__ nvalid,
                                                        const double* __restrict__ p, double* __restrict__ q,
                                                        CgCtl* __restrict__ ctl, double* __restrict__ partials) {
-  constexpr int NW = WPB > 4 ? WPB : kWaves;  // wavefronts per workgroup
-  constexpr int BPB = NW / WPB;              // baselines per workgroup
-  __shared__ double lds[NW][3];
+  constexpr int SEG = 64 / BPW;  // lanes per baseline
   if (CG && ctl->done) return;
   const int lane = lane_id();
-  const int wave = threadIdx.x >> 6;
   const int64_t n_b = v.n_b;
-  const int64_t n_g = (n_b + BPB - 1) / BPB;
+  const int64_t n_g = ((n_b + BPW - 1) / BPW + kWaves - 1) / kWaves;
   const int64_t per = (n_g + 7) / 8;
   const int64_t i = blockIdx.x;
   const int64_t g = (i & 7) * per + (i >> 3);
   if (g >= n_g) return;  // whole workgroup
-  const int64_t b = g * BPB + wave / WPB;
-  const int sub = wave % WPB;
+  const int sl = lane % SEG;
+  const int64_t k = (g * kWaves + (threadIdx.x >> 6)) * BPW + lane / SEG;
+  const int64_t b = k < n_b ? (int64_t)border[k] : n_b;
   double acc[3] = {0.0, 0.0, 0.0};
   if (b < n_b) {
     const int64_t r0 = bstart[b], r1 = bstart[b + 1];
     constexpr int U = 4;
-    for (int64_t rb = r0 + sub * 64 + lane; rb < r1; rb += 64 * WPB * U) {
-      int32_t cc_[U], nn[U];
-      double C[U], S[U];
+    // Software pipeline: the run stream of the next step is loaded while the
+    // map values of this step are gathered.
+    uint32_t key[U];
+    int32_t len[U];
+    RT C[U], S[U];
+    auto fetch = [&](int64_t rb) {
 #pragma unroll
       for (int u = 0; u < U; ++u) {
-        const int64_t r = rb + 64 * WPB * u;
+        const int64_t r = rb + SEG * u;
         const bool in = r < r1;
-        // packed keys (nb > 0): compact pixel << nb | (length - 1); else pixel, lengths in rn
-        const uint32_t key = in ? rpix[r] : 0u;
-        cc_[u] = in ? (int32_t)(nb ? key >> nb : key) : -1;
-        nn[u] = (HAS_T && in) ? (nb ? (int32_t)(key & ((1u << nb) - 1u)) + 1 : rn[r]) : 0;
-        C[u] = ((HAS_QU || IQU) && in) ? (double)rc[r] : 0.0;
-        S[u] = ((HAS_QU || IQU) && in) ? (double)rs[r] : 0.0;
+        key[u] = in ? rpix[r] : 0u;
+        len[u] = (HAS_T && !nb && in) ? rn[r] : 0;
+        C[u] = ((HAS_QU || IQU) && in) ? rc[r] : (RT)0;
+        S[u] = ((HAS_QU || IQU) && in) ? rs[r] : (RT)0;
       }
+    };
+    fetch(r0 + sl);
+    for (int64_t rb = r0 + sl; rb < r1; rb += SEG * U) {
+      int32_t cc_[U], nn[U];
+      double Cd[U], Sd[U];
 #pragma unroll
       for (int u = 0; u < U; ++u) {
+        // packed keys (nb > 0): compact pixel << nb | (length - 1); else pixel, lengths in rn
+        const bool in = rb + SEG * u < r1;
+        cc_[u] = in ? (int32_t)(nb ? key[u] >> nb : key[u]) : -1;
+        nn[u] = (HAS_T && in) ? (nb ? (int32_t)(key[u] & ((1u << nb) - 1u)) + 1 : len[u]) : 0;
+        Cd[u] = (double)C[u];
+        Sd[u] = (double)S[u];
+      }
+      double2 m01[U];
+      double mU[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        m01[u] = make_double2(0.0, 0.0);
+        mU[u] = 0.0;
         if (cc_[u] < 0) continue;
         const double2* mp = reinterpret_cast<const double2*>(m4 + 4 * (int64_t)cc_[u]);
-        const double2 m01 = mp[0];
+        m01[u] = mp[0];
+        if (HAS_QU || IQU) mU[u] = mp[1].x;
+      }
+      fetch(rb + SEG * U);
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
         if (IQU) {
-          acc[0] += (double)nn[u] * m01.x + C[u] * m01.y + S[u] * mp[1].x;
+          acc[0] += (double)nn[u] * m01[u].x + Cd[u] * m01[u].y + Sd[u] * mU[u];
           continue;
         }
-        if (HAS_T) acc[0] += (double)nn[u] * m01.x;
+        if (HAS_T) acc[0] += (double)nn[u] * m01[u].x;
         if (HAS_QU) {
-          const double mU = mp[1].x;
-          acc[1] += C[u] * m01.y + S[u] * mU;
-          acc[2] += C[u] * mU - S[u] * m01.y;
+          acc[1] += Cd[u] * m01[u].y + Sd[u] * mU[u];
+          acc[2] += Cd[u] * mU[u] - Sd[u] * m01[u].y;
         }
       }
     }
   }
-  wave_sum<3>(acc);
-  if (WPB > 1) {
-    if (lane == 0) {
-      lds[wave][0] = acc[0];
-      lds[wave][1] = acc[1];
-      lds[wave][2] = acc[2];
-    }
-    __syncthreads();
-    if (sub != 0) return;
-    for (int w = 1; w < WPB; ++w) {
-      acc[0] += lds[wave + w][0];
-      acc[1] += lds[wave + w][1];
-      acc[2] += lds[wave + w][2];
-    }
+#pragma unroll
+  for (int off = SEG / 2; off > 0; off >>= 1) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) acc[c] += __shfl_xor(acc[c], off, 64);
   }
-  if (lane == 0 && b < n_b) {
+  if (sl == 0 && b < n_b) {
     const int nT = nvalid[b], nQ = nvalid[n_b + b];
     double pq = 0.0, eq = 0.0, ep = 0.0;
     if (HAS_T) {
@@ -736,7 +770,7 @@ unsigned key_bits(int64_t n) {
 
 // ---------------------------------------------------------------- host side
 
-hipError_t runs_tmp_bytes(int64_t n_t, int64_t n_pix, size_t* bytes) {
+hipError_t runs_tmp_bytes(int64_t n_t, int64_t n_pix, int64_t n_b, size_t* bytes) {
   size_t a = 0, b = 0, c = 0;
   DST_CHECK(rocprim::exclusive_scan(nullptr, a, static_cast<const uint32_t*>(nullptr),
                                     static_cast<uint32_t*>(nullptr), 0u, (size_t)n_t, rocprim::plus<uint32_t>()));
@@ -753,7 +787,13 @@ hipError_t runs_tmp_bytes(int64_t n_t, int64_t n_pix, size_t* bytes) {
   }
   DST_CHECK(rocprim::exclusive_scan(nullptr, c, static_cast<const int64_t*>(nullptr), static_cast<int64_t*>(nullptr),
                                     (int64_t)0, (size_t)n_pix + 1, rocprim::plus<int64_t>()));
-  *bytes = std::max(std::max(a, b), std::max(c, d));
+  size_t e = 0;
+  {
+    rocprim::double_buffer<uint32_t> keys(nullptr, nullptr);
+    rocprim::double_buffer<uint32_t> vals(nullptr, nullptr);
+    DST_CHECK(rocprim::radix_sort_pairs(nullptr, e, keys, vals, (size_t)n_b, 0u, 32u));
+  }
+  *bytes = std::max(std::max(std::max(a, b), std::max(c, d)), e);
   return hipSuccess;
 }
 
@@ -900,6 +940,17 @@ hipError_t runs_build(const View& v, int psi_f32, const void* tod, int tod_f32, 
     hipLaunchKernelGGL(k_pack_runs, dim3(gr), dim3(kBlock), 0, st, R, W.nb, W.tpix, W.tn, W.pb, W.pn, W.tkey,
                        W.pkey);
   }
+  // 8. rescan order of the baselines: by the smallest compact id each visits (stable)
+  if (v.n_b > 0) {
+    hipLaunchKernelGGL(k_baseline_keys, dim3(grid_for(v.n_b, kWaves, 4096)), dim3(kBlock), 0, st, v.n_b, W.n_obs,
+                       W.bstart, W.tpix, W.bkey[0], W.bord[0]);
+    DST_CHECK(hipGetLastError());
+    rocprim::double_buffer<uint32_t> keys(W.bkey[0], W.bkey[1]);
+    rocprim::double_buffer<uint32_t> vals(W.bord[0], W.bord[1]);
+    size_t tmp = W.tmp_bytes;
+    DST_CHECK(rocprim::radix_sort_pairs(W.tmp, tmp, keys, vals, (size_t)v.n_b, 0u, key_bits(W.n_obs + 1), st));
+    W.border = vals.current();
+  }
   return hipGetLastError();
 }
 
@@ -946,11 +997,9 @@ hipError_t launch_bin_runs(const View& vc, const Runs& W, const double* pw4, con
 }
 
 hipError_t launch_unbin_runs(const View& vc, const Runs& W, const double* m4, const int32_t* nvalid, const double* p,
-                             double* q, CgCtl* ctl, double* partials, int wpb, hipStream_t st) {
-  if (wpb != 1 && wpb != 2 && wpb != 4 && wpb != 8 && wpb != 16) wpb = 1;
-  const int64_t bpb = wpb > 4 ? 1 : kWaves / wpb;
-  const unsigned nt = wpb > 4 ? 64 * wpb : kBlock;
-  const int64_t n_g = (vc.n_b + bpb - 1) / bpb;
+                             double* q, CgCtl* ctl, double* partials, int bpw, hipStream_t st) {
+  if (bpw != 1 && bpw != 2 && bpw != 4 && bpw != 8) bpw = 4;
+  const int64_t n_g = ((vc.n_b + bpw - 1) / bpw + kWaves - 1) / kWaves;
   const unsigned g = (unsigned)(8 * ((n_g + 7) / 8));
   by_float(W.f32, [&](auto rt) {
     using RT = typename decltype(rt)::type;
@@ -959,18 +1008,16 @@ hipError_t launch_unbin_runs(const View& vc, const Runs& W, const double* m4, co
         constexpr bool HT = decltype(T)::value, HQ = decltype(Q)::value, HI = decltype(I)::value;
         constexpr bool C = decltype(CG)::value;
         auto launch = [&](auto kern) {
-          hipLaunchKernelGGL(kern, dim3(g), dim3(nt), 0, st, vc, W.bstart,
+          hipLaunchKernelGGL(kern, dim3(g), dim3(kBlock), 0, st, vc, W.bstart, W.border,
                              W.nb ? W.tkey : reinterpret_cast<const uint32_t*>(W.tpix), W.tn, W.nb,
                              static_cast<const RT*>(W.tc), static_cast<const RT*>(W.ts), m4, nvalid, p, q, ctl,
                              partials);
         };
-        if (wpb == 16)
-          launch(k_unbin_runs<RT, HT, HQ, HI, C, 16>);
-        else if (wpb == 8)
+        if (bpw == 8)
           launch(k_unbin_runs<RT, HT, HQ, HI, C, 8>);
-        else if (wpb == 4)
+        else if (bpw == 4)
           launch(k_unbin_runs<RT, HT, HQ, HI, C, 4>);
-        else if (wpb == 2)
+        else if (bpw == 2)
           launch(k_unbin_runs<RT, HT, HQ, HI, C, 2>);
         else
           launch(k_unbin_runs<RT, HT, HQ, HI, C, 1>);

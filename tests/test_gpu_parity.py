@@ -268,3 +268,23 @@ def test_bin_launch_shapes_agree(name):
     for lpp in ("64", "16"):
         assert abs(out[lpp]["iterations"] - out["32"]["iterations"]) <= 1
         assert rel(out[lpp]["baselines"].cpu().numpy(), out["32"]["baselines"].cpu().numpy()) < 1e-10
+
+
+@pytest.mark.parametrize("name", ["plain", "masked", "fewpix", "QU", "T", "ragged"])
+def test_rescan_launch_shapes_agree(name):
+    """Every launch shape of the rescan (baselines per wavefront) gives the same solve."""
+    import os
+    from paper_1309_5609_amd import dst
+    p = make(name)
+    out = {}
+    for bpw in ("4", "1", "2", "8"):
+        os.environ["DST_UNBIN_BPW"] = bpw
+        try:
+            c = dst.Context(0)
+        finally:
+            del os.environ["DST_UNBIN_BPW"]
+        out[bpw] = dst.dst_solve(c, dev(p), tol=1e-13, max_iter=3000)
+        c.close()
+    for bpw in ("1", "2", "8"):
+        assert abs(out[bpw]["iterations"] - out["4"]["iterations"]) <= 1
+        assert rel(out[bpw]["baselines"].cpu().numpy(), out["4"]["baselines"].cpu().numpy()) < 1e-10
