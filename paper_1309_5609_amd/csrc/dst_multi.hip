@@ -237,13 +237,16 @@ __global__ void __launch_bounds__(kBlock) k_multi_bin(View vc, int R, int Rp, co
 }
 
 // Rescan and baseline sums, one wavefront per baseline, each XCD (workgroup
-// i runs on XCD i mod 8) sweeping a contiguous eighth of the baselines.
+// i runs on XCD i mod 8) sweeping a contiguous eighth of the baselines in the
+// rescan order (baselines sorted by the smallest compact id they visit, so
+// those over the same sky are processed together and share map lines in L2).
 //   OPERATOR / CG:  q = w (n_valid p - sum_runs A . m)  (= K p)
 //   RHS:            q = braw - w sum_runs A . m         (= F^T Z d with m = m_d)
 // CG also writes per-workgroup partials [block][3][Rp] of p.q and of the
 // T-projection sums (q_T and p_T over T-valid baselines).
 template <typename RT, bool HAS_T, bool HAS_QU, int MODE>
 __global__ void __launch_bounds__(kBlock) k_multi_unbin(View vc, int R, int Rp, const uint32_t* __restrict__ bstart,
+                                                        const uint32_t* __restrict__ border,
                                                         const int32_t* __restrict__ tpix,
                                                         const int32_t* __restrict__ tn, const RT* __restrict__ tc,
                                                         const RT* __restrict__ ts, const double* __restrict__ m,
@@ -267,7 +270,8 @@ __global__ void __launch_bounds__(kBlock) k_multi_unbin(View vc, int R, int Rp, 
   const int64_t x = blockIdx.x & 7, k = blockIdx.x >> 3, nk = gridDim.x >> 3;
   const int64_t lo = x * per, hi = std::min(n_b, lo + per);
   double dots[3] = {0.0, 0.0, 0.0};
-  for (int64_t b = lo + k * kWaves + wave; b < hi; b += nk * kWaves) {
+  for (int64_t bk = lo + k * kWaves + wave; bk < hi; bk += nk * kWaves) {
+    const int64_t b = border[bk];
     const int64_t r0 = bstart[b], r1 = bstart[b + 1];
     double acc[3] = {0.0, 0.0, 0.0};
     constexpr int U = 1;
@@ -790,7 +794,7 @@ hipError_t launch_multi_unbin(const View& vc, const Runs& W, const Multi& mu, in
     by_streams(vc, [&](auto T, auto Q) {
       constexpr bool HT = decltype(T)::value, HQ = decltype(Q)::value;
       auto launch = [&](auto kern) {
-        hipLaunchKernelGGL(kern, dim3(g), dim3(kBlock), 0, st, vc, mu.R, mu.Rp, W.bstart, W.tpix, W.tn,
+        hipLaunchKernelGGL(kern, dim3(g), dim3(kBlock), 0, st, vc, mu.R, mu.Rp, W.bstart, W.border, W.tpix, W.tn,
                            static_cast<const RT*>(W.tc), static_cast<const RT*>(W.ts), m, nvalid, p, braw, q, ctl,
                            partials);
       };
