@@ -576,8 +576,7 @@ int solve_group(dst_ctx* ctx, const dst_problem* problems, const std::vector<int
   double *prs, *braw, *b, *a, *r, *z, *p, *q, *ka, *md, *m, *part, *part2;
   dst::MultiCtl* ctl;
   DST_TRY(ws(ctx, "mb_ipos", (size_t)std::max<int64_t>(W.R, 1), &ipos));
-  const int64_t prs_stride = 4 * std::max<int64_t>(W.R, 1);
-  DST_TRY(ws(ctx, "mb_prs", (size_t)dst::kTodBatch * prs_stride, &prs));
+  DST_TRY(ws(ctx, "mb_prs", (size_t)4 * dst::kTodBatch * std::max<int64_t>(W.R, 1), &prs));
   DST_TRY(ws(ctx, "mb_braw", NV, &braw));
   DST_TRY(ws(ctx, "mb_b", NV, &b));
   DST_TRY(ws(ctx, "mb_a", NV, &a));
@@ -607,9 +606,8 @@ int solve_group(dst_ctx* ctx, const dst_problem* problems, const std::vector<int
       tods.p[nr] = problems[idx[k + nr]].tod;
       ++nr;
     }
-    HIP_TRY(dst::launch_multi_tod(vc, S.psi_f32, tods, nr, dt == DST_F32, W, ipos, S.valid, mu.Rp, k, prs, prs_stride,
-                                  braw, st));
-    HIP_TRY(dst::launch_multi_pixsum(n_obs, vc, W, prs, prs_stride, nr, S.Minv4, mu.Rp, k, md, st));
+    HIP_TRY(dst::launch_multi_tod(vc, S.psi_f32, tods, nr, dt == DST_F32, W, ipos, S.valid, mu.Rp, k, prs, braw, st));
+    HIP_TRY(dst::launch_multi_pixsum(n_obs, vc, W, prs, nr, S.Minv4, mu.Rp, k, md, st));
     k += nr;
   }
   HIP_TRY(dst::launch_multi_unbin(vc, W, mu, dst::UNBIN_RHS, md, S.nvalid, nullptr, braw, b, nullptr, nullptr, st));

@@ -63,15 +63,17 @@ struct TodSet {
 };
 
 // Realizations ri0 .. ri0 + nr - 1 (nr <= kTodBatch, same tod dtype): per-run
-// sums of the weighted data at each run's pixel-order position (realization i
-// in prs + i * prs_stride, [R][4]: w_T d_T, rotated Q, rotated U) and
-// per-baseline sums w_k d_k over valid samples into braw ([n_b][n_streams][Rp]).
+// sums of the weighted data at each run's pixel-order position, one record of
+// kTodBatch x 4 doubles per run (one 128-byte line: realization i at
+// [4 i .. 4 i + 2] = w_T d_T, rotated Q, rotated U), and per-baseline sums
+// w_k d_k over valid samples into braw ([n_b][n_streams][Rp]).  prs holds
+// 4 kTodBatch R doubles.
 hipError_t launch_multi_tod(const View& vc, int psi_f32, const TodSet& tods, int nr, int tod_f32, const Runs& W,
-                            const uint32_t* ipos, const uint8_t* valid, int Rp, int ri0, double* prs,
-                            int64_t prs_stride, double* braw, hipStream_t st);
+                            const uint32_t* ipos, const uint8_t* valid, int Rp, int ri0, double* prs, double* braw,
+                            hipStream_t st);
 // Realizations ri0 .. ri0 + nr - 1: binned maps md = M^-1 (sum of the pixel's run sums).
-hipError_t launch_multi_pixsum(int64_t n_obs, const View& vc, const Runs& W, const double* prs, int64_t prs_stride,
-                               int nr, const double* Minv4, int Rp, int ri0, double* md, hipStream_t st);
+hipError_t launch_multi_pixsum(int64_t n_obs, const View& vc, const Runs& W, const double* prs, int nr,
+                               const double* Minv4, int Rp, int ri0, double* md, hipStream_t st);
 
 // m = M^-1 A^T W F p for every active right-hand side (ctl NULL: all R).
 hipError_t launch_multi_bin(const View& vc, const Runs& W, const Multi& mu, const double* p, const double* Minv4,

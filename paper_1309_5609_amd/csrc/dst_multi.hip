@@ -45,17 +45,17 @@ __global__ void __launch_bounds__(kBlock) k_run_positions(int64_t n_obs, const u
 
 // One wavefront per baseline; one lane per run; NR realizations per pass
 // (their timelines share the angle loads and the trigonometry).  Per run and
-// realization: w_T sum d_T and the rotated, weighted q/u sums, stored at the
-// run's pixel-order position in that realization's array; per baseline: w_k
-// sum d_k over valid samples (the data part of b = F^T Z d).
+// realization: w_T sum d_T and the rotated, weighted q/u sums, stored in the
+// run's record (one 128-byte line holding every realization of the pass) at
+// its pixel-order position, so each scattered store writes a whole line; per
+// baseline: w_k sum d_k over valid samples (the data part of b = F^T Z d).
 template <typename PT, typename TT, bool HAS_T, bool HAS_QU, int NR>
 __global__ void __launch_bounds__(kBlock) k_multi_tod(View v, TodSet tods, const uint32_t* __restrict__ bstart,
                                                       const uint32_t* __restrict__ t0,
                                                       const int32_t* __restrict__ tpix, const int32_t* __restrict__ tn,
                                                       const uint32_t* __restrict__ ipos,
                                                       const uint8_t* __restrict__ valid, int Rp, int ri0,
-                                                      double* __restrict__ prs, int64_t prs_stride,
-                                                      double* __restrict__ braw) {
+                                                      double* __restrict__ prs, double* __restrict__ braw) {
   const PT* psi = static_cast<const PT*>(v.psi);
   const int lane = lane_id();
   const int64_t b = (int64_t)blockIdx.x * kWaves + (threadIdx.x >> 6);
@@ -110,7 +110,7 @@ __global__ void __launch_bounds__(kBlock) k_multi_tod(View v, TodSet tods, const
     const int64_t pos = ipos[j];
 #pragma unroll
     for (int i = 0; i < NR; ++i) {
-      double2* o = reinterpret_cast<double2*>(prs + i * prs_stride + 4 * pos);
+      double2* o = reinterpret_cast<double2*>(prs + 4 * (kTodBatch * pos + i));
       o[0] = make_double2(vT ? v.w[0] * dT[i] : 0.0, vQ ? dQ[i] : 0.0);
       o[1] = make_double2(vQ ? dU[i] : 0.0, 0.0);
       if (vT) acc[3 * i] += dT[i];
@@ -135,9 +135,10 @@ __global__ void __launch_bounds__(kBlock) k_multi_tod(View v, TodSet tods, const
 }
 
 // One wavefront per compact pixel: md = M^-1 (sum of its run sums), columns
-// ri0 .. ri0 + nr - 1.
+// ri0 .. ri0 + nr - 1 (the pixel's run records are contiguous).
+template <int NR>
 __global__ void __launch_bounds__(kBlock) k_multi_pixsum(int64_t n_obs, View vc, const int64_t* __restrict__ pstart,
-                                                         const double* __restrict__ prs, int64_t prs_stride, int nr,
+                                                         const double* __restrict__ prs,
                                                          const double* __restrict__ Minv4, int Rp, int ri0,
                                                          double* __restrict__ md) {
   const int lane = lane_id();
@@ -146,27 +147,34 @@ __global__ void __launch_bounds__(kBlock) k_multi_pixsum(int64_t n_obs, View vc,
     const int64_t j0 = pstart[c], j1 = pstart[c + 1];
     const double2* ip = reinterpret_cast<const double2*>(Minv4 + 4 * c);
     const double2 i01 = ip[0], i23 = ip[1];
-    for (int i = 0; i < nr; ++i) {
-      double acc[3] = {0.0, 0.0, 0.0};
-      for (int64_t j = j0 + lane; j < j1; j += 64) {
-        const double2* x = reinterpret_cast<const double2*>(prs + i * prs_stride + 4 * j);
+    double acc[3 * NR];
+#pragma unroll
+    for (int i = 0; i < 3 * NR; ++i) acc[i] = 0.0;
+    for (int64_t j = j0 + lane; j < j1; j += 64) {
+#pragma unroll
+      for (int i = 0; i < NR; ++i) {
+        const double2* x = reinterpret_cast<const double2*>(prs + 4 * (kTodBatch * j + i));
         const double2 x0 = x[0], x1 = x[1];
-        acc[0] += x0.x;
-        acc[1] += x0.y;
-        acc[2] += x1.x;
+        acc[3 * i] += x0.x;
+        acc[3 * i + 1] += x0.y;
+        acc[3 * i + 2] += x1.x;
       }
-      dev::wave_sum<3>(acc);
-      if (lane == 0) {
+    }
+    dev::wave_sum<3 * NR>(acc);
+    if (lane == 0) {
+#pragma unroll
+      for (int i = 0; i < NR; ++i) {
         const int64_t o = c * vc.n_streams * Rp + ri0 + i;
-        if (vc.rowT >= 0) md[o + vc.rowT * Rp] = i01.x * acc[0];
+        if (vc.rowT >= 0) md[o + vc.rowT * Rp] = i01.x * acc[3 * i];
         if (vc.rowQ >= 0) {
-          md[o + vc.rowQ * Rp] = i01.y * acc[1] + i23.x * acc[2];
-          md[o + vc.rowU * Rp] = i23.x * acc[1] + i23.y * acc[2];
+          md[o + vc.rowQ * Rp] = i01.y * acc[3 * i + 1] + i23.x * acc[3 * i + 2];
+          md[o + vc.rowU * Rp] = i23.x * acc[3 * i + 1] + i23.y * acc[3 * i + 2];
         }
       }
     }
   }
 }
+
 
 // ---------------------------------------------------------------- operator
 
@@ -731,8 +739,8 @@ hipError_t launch_run_positions(const Runs& W, uint32_t* ipos, hipStream_t st) {
 }
 
 hipError_t launch_multi_tod(const View& vc, int psi_f32, const TodSet& tods, int nr, int tod_f32, const Runs& W,
-                            const uint32_t* ipos, const uint8_t* valid, int Rp, int ri0, double* prs,
-                            int64_t prs_stride, double* braw, hipStream_t st) {
+                            const uint32_t* ipos, const uint8_t* valid, int Rp, int ri0, double* prs, double* braw,
+                            hipStream_t st) {
   const unsigned g = grid_for(vc.n_b, kWaves, INT32_MAX);
   by_float(psi_f32, [&](auto pt) {
     using PT = typename decltype(pt)::type;
@@ -742,7 +750,7 @@ hipError_t launch_multi_tod(const View& vc, int psi_f32, const TodSet& tods, int
         constexpr bool HT = decltype(T)::value, HQ = decltype(Q)::value;
         auto launch = [&](auto kern) {
           hipLaunchKernelGGL(kern, dim3(g), dim3(kBlock), 0, st, vc, tods, W.bstart, W.t0, W.tpix, W.tn, ipos, valid,
-                             Rp, ri0, prs, prs_stride, braw);
+                             Rp, ri0, prs, braw);
         };
         if (nr >= 4)
           launch(k_multi_tod<PT, TT, HT, HQ, 4>);
@@ -758,10 +766,17 @@ hipError_t launch_multi_tod(const View& vc, int psi_f32, const TodSet& tods, int
   return hipGetLastError();
 }
 
-hipError_t launch_multi_pixsum(int64_t n_obs, const View& vc, const Runs& W, const double* prs, int64_t prs_stride,
-                               int nr, const double* Minv4, int Rp, int ri0, double* md, hipStream_t st) {
-  hipLaunchKernelGGL(k_multi_pixsum, dim3(grid_for(n_obs, kWaves, 16384)), dim3(kBlock), 0, st, n_obs, vc, W.pstart,
-                     prs, prs_stride, nr, Minv4, Rp, ri0, md);
+hipError_t launch_multi_pixsum(int64_t n_obs, const View& vc, const Runs& W, const double* prs, int nr,
+                               const double* Minv4, int Rp, int ri0, double* md, hipStream_t st) {
+  const dim3 g(grid_for(n_obs, kWaves, 16384));
+  if (nr >= 4)
+    hipLaunchKernelGGL(k_multi_pixsum<4>, g, dim3(kBlock), 0, st, n_obs, vc, W.pstart, prs, Minv4, Rp, ri0, md);
+  else if (nr == 3)
+    hipLaunchKernelGGL(k_multi_pixsum<3>, g, dim3(kBlock), 0, st, n_obs, vc, W.pstart, prs, Minv4, Rp, ri0, md);
+  else if (nr == 2)
+    hipLaunchKernelGGL(k_multi_pixsum<2>, g, dim3(kBlock), 0, st, n_obs, vc, W.pstart, prs, Minv4, Rp, ri0, md);
+  else
+    hipLaunchKernelGGL(k_multi_pixsum<1>, g, dim3(kBlock), 0, st, n_obs, vc, W.pstart, prs, Minv4, Rp, ri0, md);
   return hipGetLastError();
 }
 
