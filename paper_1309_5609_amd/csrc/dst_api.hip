@@ -283,8 +283,8 @@ int build_runs_plan(dst_ctx* ctx, const dst_problem* prob, Plan& P, const void* 
   S.psi_f32 = prob->psi_dtype == DST_F32;
   S.tod_f32 = prob->tod_dtype == DST_F32;
   dst::Runs& W = P.W;
-  DST_TRY(ws(ctx, "r_head", v.n_t, &W.head));
-  DST_TRY(ws(ctx, "r_hidx", v.n_t, &W.hidx));
+  DST_TRY(ws(ctx, "r_tcount", dst::run_tiles(v.n_t), &W.tcount));
+  DST_TRY(ws(ctx, "r_toff", dst::run_tiles(v.n_t), &W.toff));
   size_t tmp_bytes = 0;
   HIP_TRY(dst::runs_tmp_bytes(v.n_t, v.n_pix, v.n_b, &tmp_bytes));
   DST_TRY(ws_get(ctx, "r_tmp", tmp_bytes, &W.tmp));

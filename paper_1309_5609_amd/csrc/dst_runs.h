@@ -28,15 +28,16 @@ static_assert(sizeof(RunRecord) == 64, "run record must be one 64-byte line");
 // first visit, so pixels that a stretch of the scan crosses sit close
 // together in per-pixel arrays.
 //
-// Buffers belong to the caller's workspace.  Sizes: head, hidx [n_t];
+// Buffers belong to the caller's workspace.  Sizes: tcount, toff
+// [run_tiles(n_t)];
 // bstart [n_b + 1]; t0, tpix, tn, pb, pn [R] and tc, ts, pc, ps [R] (FP32 when
 // f32, else FP64);
 // raw [3 R]; rec [R]; keys, vals 2 x [R]; seg [2 n_pix] (zero-filled before
 // runs_build); pk, pv 2 x [n_pix]; cid [n_pix] (filled with -1 before
 // runs_build); ccount, pstart [n_pix + 1]; bkey, bord 2 x [n_b].
 struct Runs {
-  uint32_t* head = nullptr;
-  uint32_t* hidx = nullptr;
+  uint32_t* tcount = nullptr;  // run starts per tile of the run detection
+  uint32_t* toff = nullptr;    // their exclusive scan
   void* tmp = nullptr;
   size_t tmp_bytes = 0;
   int64_t R = 0;
@@ -78,6 +79,8 @@ struct Runs {
   const uint32_t* border = nullptr;
 };
 
+// Number of tiles the run detection splits n_t samples into.
+int64_t run_tiles(int64_t n_t);
 hipError_t runs_tmp_bytes(int64_t n_t, int64_t n_pix, int64_t n_b, size_t* bytes);
 // Marks run heads and counts the runs (W.R); synchronises `st`.
 hipError_t runs_count(const View& v, Runs& W, int* err, hipStream_t st);

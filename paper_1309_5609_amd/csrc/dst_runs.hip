@@ -115,39 +115,69 @@ unsigned grid_for(int64_t n, int64_t per_block, unsigned cap) {
 
 // ---------------------------------------------------------------- run building
 
-// head[t] = 1 where a run starts: an unmasked sample whose predecessor is on
-// another pixel, is masked, or lies in the previous baseline.
-__global__ void __launch_bounds__(kBlock) k_run_heads(const int32_t* __restrict__ pix, int64_t n_t, int64_t n_pix,
-                                                      int64_t L, uint32_t* __restrict__ head, int* __restrict__ err,
-                                                      unsigned long long* __restrict__ n_out) {
-  __shared__ unsigned long long lds[16];
-  unsigned long long out[1] = {0};
-  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n_t; t += (int64_t)gridDim.x * blockDim.x) {
-    const int p = pix[t];
-    uint32_t h = 0;
-    if (p >= n_pix) atomicOr(err, 1);
-    out[0] += (p < 0 || p >= n_pix) ? 1 : 0;
-    if (p >= 0 && p < n_pix) {
-      if (t == 0 || (t % L) == 0)
-        h = 1;
-      else
-        h = pix[t - 1] != p;
-    }
-    head[t] = h;
-  }
-  block_sum<1>(out, lds);
-  if (threadIdx.x == 0 && out[0]) atomicAdd(n_out, out[0]);
+// Run detection in tiles of kTile samples, one wavefront per tile, 64
+// samples at a time.  Sample t starts a run when its pixel is valid and it is
+// the first sample of its baseline or follows a sample on another pixel (or
+// a masked one); a run ends before the next start, at the end of its
+// baseline or at the first sample off its pixel.
+constexpr int64_t kTile = 4096;
+
+__device__ __forceinline__ bool run_head(const int32_t* __restrict__ pix, int64_t t, int p, int64_t L,
+                                         int64_t n_pix) {
+  return p >= 0 && p < n_pix && ((t % L) == 0 || pix[t - 1] != p);
 }
 
-// First sample of each run, and the first run of each baseline.
-__global__ void __launch_bounds__(kBlock) k_run_starts(const uint32_t* __restrict__ head,
-                                                       const uint32_t* __restrict__ hidx, int64_t n_t, int64_t L,
-                                                       int64_t n_b, uint32_t* __restrict__ t0,
-                                                       uint32_t* __restrict__ bstart) {
-  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n_t; t += (int64_t)gridDim.x * blockDim.x) {
-    if (head[t]) t0[hidx[t]] = (uint32_t)t;
-    if ((t % L) == 0) bstart[t / L] = hidx[t];
-    if (t == n_t - 1) bstart[n_b] = hidx[t] + head[t];
+// Per tile: number of run starts; samples off the map (masked or out of
+// range) are counted into n_out, indices >= n_pix raise err.
+__global__ void __launch_bounds__(kBlock) k_tile_heads(const int32_t* __restrict__ pix, int64_t n_t, int64_t n_pix,
+                                                       int64_t L, int64_t n_tiles, uint32_t* __restrict__ tcount,
+                                                       int* __restrict__ err, unsigned long long* __restrict__ n_out) {
+  const int lane = lane_id();
+  const int64_t nw = (int64_t)gridDim.x * kWaves;
+  for (int64_t tile = (int64_t)blockIdx.x * kWaves + (threadIdx.x >> 6); tile < n_tiles; tile += nw) {
+    const int64_t a = tile * kTile, z = min(n_t, a + kTile);
+    uint32_t cnt = 0, out = 0;
+    bool bad = false;
+    for (int64_t c0 = a; c0 < z; c0 += 64) {
+      const int64_t t = c0 + lane;
+      const bool in = t < z;
+      const int p = in ? pix[t] : 0;
+      bad |= in && p >= n_pix;
+      cnt += (uint32_t)__popcll(__ballot(in && run_head(pix, t, p, L, n_pix)));
+      out += (uint32_t)__popcll(__ballot(in && (p < 0 || p >= n_pix)));
+    }
+    if (__ballot(bad) != 0ull && lane == 0) atomicOr(err, 1);
+    if (lane == 0) {
+      tcount[tile] = cnt;
+      if (out) atomicAdd(n_out, (unsigned long long)out);
+    }
+  }
+}
+
+// First sample of each run (t0, time order) and the first run of each
+// baseline (bstart); toff = exclusive scan of the tile counts, R runs in all.
+__global__ void __launch_bounds__(kBlock) k_tile_starts(const int32_t* __restrict__ pix, int64_t n_t, int64_t n_pix,
+                                                        int64_t L, int64_t n_b, int64_t n_tiles,
+                                                        const uint32_t* __restrict__ toff, uint32_t R,
+                                                        uint32_t* __restrict__ t0, uint32_t* __restrict__ bstart) {
+  const int lane = lane_id();
+  const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));  // lanes below this one
+  const int64_t nw = (int64_t)gridDim.x * kWaves;
+  for (int64_t tile = (int64_t)blockIdx.x * kWaves + (threadIdx.x >> 6); tile < n_tiles; tile += nw) {
+    const int64_t a = tile * kTile, z = min(n_t, a + kTile);
+    uint32_t run = toff[tile];
+    for (int64_t c0 = a; c0 < z; c0 += 64) {
+      const int64_t t = c0 + lane;
+      const bool in = t < z;
+      const int p = in ? pix[t] : -1;
+      const bool h = in && run_head(pix, t, p, L, n_pix);
+      const uint64_t m = __ballot(h);
+      const uint32_t idx = run + (uint32_t)__popcll(m & lt);
+      if (h) t0[idx] = (uint32_t)t;
+      if (in && (t % L) == 0) bstart[t / L] = idx;
+      run += (uint32_t)__popcll(m);
+    }
+    if (tile == n_tiles - 1 && lane == 0) bstart[n_b] = R;
   }
 }
 
@@ -773,7 +803,8 @@ unsigned key_bits(int64_t n) {
 hipError_t runs_tmp_bytes(int64_t n_t, int64_t n_pix, int64_t n_b, size_t* bytes) {
   size_t a = 0, b = 0, c = 0;
   DST_CHECK(rocprim::exclusive_scan(nullptr, a, static_cast<const uint32_t*>(nullptr),
-                                    static_cast<uint32_t*>(nullptr), 0u, (size_t)n_t, rocprim::plus<uint32_t>()));
+                                    static_cast<uint32_t*>(nullptr), 0u, (size_t)run_tiles(n_t),
+                                    rocprim::plus<uint32_t>()));
   {
     rocprim::double_buffer<uint32_t> keys(nullptr, nullptr);
     rocprim::double_buffer<uint32_t> vals(nullptr, nullptr);
@@ -797,16 +828,20 @@ hipError_t runs_tmp_bytes(int64_t n_t, int64_t n_pix, int64_t n_b, size_t* bytes
   return hipSuccess;
 }
 
+int64_t run_tiles(int64_t n_t) { return (n_t + kTile - 1) / kTile; }
+
 hipError_t runs_count(const View& v, Runs& W, int* err, hipStream_t st) {
-  const int64_t n_t = v.n_t;
-  const unsigned g = grid_for(n_t, kBlock, 8192);
-  hipLaunchKernelGGL(k_run_heads, dim3(g), dim3(kBlock), 0, st, v.pix, n_t, v.n_pix, v.L, W.head, err, W.n_out);
+  const int64_t n_t = v.n_t, n_tiles = run_tiles(n_t);
+  const unsigned g = grid_for(n_tiles, kWaves, 8192);
+  hipLaunchKernelGGL(k_tile_heads, dim3(g), dim3(kBlock), 0, st, v.pix, n_t, v.n_pix, v.L, n_tiles, W.tcount, err,
+                     W.n_out);
   DST_CHECK(hipGetLastError());
   size_t tmp = W.tmp_bytes;
-  DST_CHECK(rocprim::exclusive_scan(W.tmp, tmp, W.head, W.hidx, 0u, (size_t)n_t, rocprim::plus<uint32_t>(), st));
+  DST_CHECK(rocprim::exclusive_scan(W.tmp, tmp, W.tcount, W.toff, 0u, (size_t)n_tiles, rocprim::plus<uint32_t>(),
+                                    st));
   uint32_t last[2] = {0, 0};
-  DST_CHECK(hipMemcpyAsync(&last[0], W.hidx + n_t - 1, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
-  DST_CHECK(hipMemcpyAsync(&last[1], W.head + n_t - 1, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+  DST_CHECK(hipMemcpyAsync(&last[0], W.toff + n_tiles - 1, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+  DST_CHECK(hipMemcpyAsync(&last[1], W.tcount + n_tiles - 1, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
   DST_CHECK(hipStreamSynchronize(st));
   W.R = (int64_t)last[0] + last[1];
   return hipSuccess;
@@ -850,7 +885,8 @@ hipError_t runs_build(const View& v, int psi_f32, const void* tod, int tod_f32, 
   const int64_t n_t = v.n_t, n_pix = v.n_pix, R = W.R;
   const unsigned g = grid_for(n_t, kBlock, 8192);
   // 1. run starts and per-baseline run ranges
-  hipLaunchKernelGGL(k_run_starts, dim3(g), dim3(kBlock), 0, st, W.head, W.hidx, n_t, v.L, v.n_b, W.t0, W.bstart);
+  hipLaunchKernelGGL(k_tile_starts, dim3(grid_for(run_tiles(n_t), kWaves, 8192)), dim3(kBlock), 0, st, v.pix, n_t,
+                     v.n_pix, v.L, v.n_b, run_tiles(n_t), W.toff, (uint32_t)R, W.t0, W.bstart);
   DST_CHECK(hipGetLastError());
   // 2. run records and setup moments (time order)
   const bool pf = psi_f32 && (v.rowQ >= 0 || v.iqu);
