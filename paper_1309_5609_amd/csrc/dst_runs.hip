@@ -358,26 +358,39 @@ __global__ void __launch_bounds__(kBlock) k_pixels_from_runs(
     double acc[NA];  // h, cc, cs, dT, dQ, dU (and C, S for the radiometer block)
 #pragma unroll
     for (int i = 0; i < NA; ++i) acc[i] = 0.0;
-    for (int64_t j = j0 + lane; j < j1; j += 64) {
-      const RunRecord x = rec[rperm[j]];
-      const int64_t d = d0 + (j - j0);
-      pb[d] = x.b;
-      pn[d] = x.n;
-      acc[0] += (double)x.n;
-      if (HAS_QU || IQU) {
-        pc[d] = (RT)x.C;
-        ps[d] = (RT)x.S;
-        acc[1] += x.cc;
-        acc[2] += x.cs;
-      }
-      if (IQU) {
-        acc[NA - 2] += x.C;
-        acc[NA - 1] += x.S;
-      }
-      if (TOD) {
-        acc[3] += x.dT;
-        acc[4] += x.dQ;
-        acc[5] += x.dU;
+    constexpr int U = 2;  // runs whose (dependent) index and record loads are issued together
+    for (int64_t jb = j0 + lane; jb < j1; jb += 64 * U) {
+      uint32_t q[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) q[u] = jb + 64 * u < j1 ? rperm[jb + 64 * u] : 0u;
+      RunRecord xs[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        if (jb + 64 * u < j1) xs[u] = rec[q[u]];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int64_t j = jb + 64 * u;
+        if (j >= j1) break;
+        const RunRecord& x = xs[u];
+        const int64_t d = d0 + (j - j0);
+        pb[d] = x.b;
+        pn[d] = x.n;
+        acc[0] += (double)x.n;
+        if (HAS_QU || IQU) {
+          pc[d] = (RT)x.C;
+          ps[d] = (RT)x.S;
+          acc[1] += x.cc;
+          acc[2] += x.cs;
+        }
+        if (IQU) {
+          acc[NA - 2] += x.C;
+          acc[NA - 1] += x.S;
+        }
+        if (TOD) {
+          acc[3] += x.dT;
+          acc[4] += x.dQ;
+          acc[5] += x.dU;
+        }
       }
     }
     wave_sum<NA>(acc);
@@ -529,29 +542,49 @@ __global__ void __launch_bounds__(kBlock) k_rhs_runs(View v, const uint32_t* __r
   if (b < 0) return;
   const int64_t r0 = bstart[b], r1 = bstart[b + 1];
   double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};  // T, q, u residual sums; n_T, n_QU
-  for (int64_t r = r0 + threadIdx.x; r < r1; r += kBlock) {
-    const int c = rpix[r];
-    const uint8_t f = valid[c];
-    const double n = (double)rn[r];
-    const double* m = raw + 3 * r;
-    const double2* mp = reinterpret_cast<const double2*>(md4 + 4 * (int64_t)c);
-    if (IQU && (f & 1)) {
-      acc[3] += n;
+  constexpr int U = 2;  // runs whose loads (and dependent gathers) are issued together
+  for (int64_t rb = r0 + threadIdx.x; rb < r1; rb += kBlock * U) {
+    int c[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) c[u] = rb + kBlock * u < r1 ? rpix[rb + kBlock * u] : -1;
+    uint8_t f[U];
+    double2 m01[U], m2[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      f[u] = 0;
+      m01[u] = m2[u] = make_double2(0.0, 0.0);
+      if (c[u] < 0) continue;
+      f[u] = valid[c[u]];
       if (TOD) {
-        const double C = (double)rc[r], S = (double)rs[r];
-        acc[0] += m[0] - (n * mp[0].x + C * mp[0].y + S * mp[1].x);
+        const double2* mp = reinterpret_cast<const double2*>(md4 + 4 * (int64_t)c[u]);
+        m01[u] = mp[0];
+        m2[u] = mp[1];
       }
-    } else if (HAS_T && (f & 1)) {
-      acc[3] += n;
-      if (TOD) acc[0] += m[0] - n * mp[0].x;
     }
-    if (HAS_QU && (f & 2)) {
-      acc[4] += n;
-      if (TOD) {
-        const double C = (double)rc[r], S = (double)rs[r];
-        const double mQ = mp[0].y, mU = mp[1].x;
-        acc[1] += m[1] - (C * mQ + S * mU);
-        acc[2] += m[2] - (C * mU - S * mQ);
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (c[u] < 0) continue;
+      const int64_t r = rb + kBlock * u;
+      const double n = (double)rn[r];
+      const double* m = raw + 3 * r;
+      if (IQU && (f[u] & 1)) {
+        acc[3] += n;
+        if (TOD) {
+          const double C = (double)rc[r], S = (double)rs[r];
+          acc[0] += m[0] - (n * m01[u].x + C * m01[u].y + S * m2[u].x);
+        }
+      } else if (HAS_T && (f[u] & 1)) {
+        acc[3] += n;
+        if (TOD) acc[0] += m[0] - n * m01[u].x;
+      }
+      if (HAS_QU && (f[u] & 2)) {
+        acc[4] += n;
+        if (TOD) {
+          const double C = (double)rc[r], S = (double)rs[r];
+          const double mQ = m01[u].y, mU = m2[u].x;
+          acc[1] += m[1] - (C * mQ + S * mU);
+          acc[2] += m[2] - (C * mU - S * mQ);
+        }
       }
     }
   }

@@ -48,6 +48,8 @@ VARIANTS = {
     "L37": dict(n_samples=3001, L=37),
     # 12 pixels: every pixel holds thousands of runs, spanning many chunks of the flat binning
     "fewpix": dict(nside=1, n_samples=200000, L=50),
+    # baselines longer than a 4096-sample tile of the run detection, with masked samples
+    "longbase": dict(n_samples=23011, L=5003, mask_fraction=0.05),
 }
 
 
