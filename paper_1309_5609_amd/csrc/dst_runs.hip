@@ -121,10 +121,35 @@ unsigned grid_for(int64_t n, int64_t per_block, unsigned cap) {
 // a masked one); a run ends before the next start, at the end of its
 // baseline or at the first sample off its pixel.
 constexpr int64_t kTile = 4096;
+constexpr int kChunks = 4;  // 64-sample chunks whose loads are issued together
 
-__device__ __forceinline__ bool run_head(const int32_t* __restrict__ pix, int64_t t, int p, int64_t L,
-                                         int64_t n_pix) {
-  return p >= 0 && p < n_pix && ((t % L) == 0 || pix[t - 1] != p);
+// Pixels of kChunks consecutive 64-sample chunks from c0 (lane = sample),
+// each sample's predecessor, and the run-start flags; samples at or past z
+// read as masked.  Sample indices are below 2^32.
+struct ChunkHeads {
+  int p[kChunks];
+  uint64_t head[kChunks];
+};
+__device__ __forceinline__ void chunk_heads(const int32_t* __restrict__ pix, int64_t c0, int64_t z, int64_t n_pix,
+                                            uint32_t L, ChunkHeads& o) {
+  const int lane = lane_id();
+#pragma unroll
+  for (int k = 0; k < kChunks; ++k) {
+    const int64_t t = c0 + 64 * k + lane;
+    o.p[k] = t < z ? pix[t] : -1;
+  }
+  const int before = (lane == 0 && c0 > 0) ? pix[c0 - 1] : -1;  // the sample before the first chunk
+#pragma unroll
+  for (int k = 0; k < kChunks; ++k) {
+    const int64_t t = c0 + 64 * k + lane;
+    // both shuffles run on every lane (a lane reading an inactive lane gets no data)
+    const int up = __shfl_up(o.p[k], 1, 64);
+    const int last = k == 0 ? before : __shfl(o.p[k > 0 ? k - 1 : 0], 63, 64);
+    const int prev = lane == 0 ? last : up;
+    const int p = o.p[k];
+    const bool on = t < z && p >= 0 && p < n_pix;
+    o.head[k] = __ballot(on && (((uint32_t)t % L) == 0u || prev != p));
+  }
 }
 
 // Per tile: number of run starts; samples off the map (masked or out of
@@ -138,13 +163,16 @@ __global__ void __launch_bounds__(kBlock) k_tile_heads(const int32_t* __restrict
     const int64_t a = tile * kTile, z = min(n_t, a + kTile);
     uint32_t cnt = 0, out = 0;
     bool bad = false;
-    for (int64_t c0 = a; c0 < z; c0 += 64) {
-      const int64_t t = c0 + lane;
-      const bool in = t < z;
-      const int p = in ? pix[t] : 0;
-      bad |= in && p >= n_pix;
-      cnt += (uint32_t)__popcll(__ballot(in && run_head(pix, t, p, L, n_pix)));
-      out += (uint32_t)__popcll(__ballot(in && (p < 0 || p >= n_pix)));
+    for (int64_t c0 = a; c0 < z; c0 += 64 * kChunks) {
+      ChunkHeads h;
+      chunk_heads(pix, c0, z, n_pix, (uint32_t)L, h);
+#pragma unroll
+      for (int k = 0; k < kChunks; ++k) {
+        const bool in = c0 + 64 * k + lane < z;
+        bad |= in && h.p[k] >= n_pix;
+        cnt += (uint32_t)__popcll(h.head[k]);
+        out += (uint32_t)__popcll(__ballot(in && (h.p[k] < 0 || h.p[k] >= n_pix)));
+      }
     }
     if (__ballot(bad) != 0ull && lane == 0) atomicOr(err, 1);
     if (lane == 0) {
@@ -166,16 +194,17 @@ __global__ void __launch_bounds__(kBlock) k_tile_starts(const int32_t* __restric
   for (int64_t tile = (int64_t)blockIdx.x * kWaves + (threadIdx.x >> 6); tile < n_tiles; tile += nw) {
     const int64_t a = tile * kTile, z = min(n_t, a + kTile);
     uint32_t run = toff[tile];
-    for (int64_t c0 = a; c0 < z; c0 += 64) {
-      const int64_t t = c0 + lane;
-      const bool in = t < z;
-      const int p = in ? pix[t] : -1;
-      const bool h = in && run_head(pix, t, p, L, n_pix);
-      const uint64_t m = __ballot(h);
-      const uint32_t idx = run + (uint32_t)__popcll(m & lt);
-      if (h) t0[idx] = (uint32_t)t;
-      if (in && (t % L) == 0) bstart[t / L] = idx;
-      run += (uint32_t)__popcll(m);
+    for (int64_t c0 = a; c0 < z; c0 += 64 * kChunks) {
+      ChunkHeads h;
+      chunk_heads(pix, c0, z, n_pix, (uint32_t)L, h);
+#pragma unroll
+      for (int k = 0; k < kChunks; ++k) {
+        const int64_t t = c0 + 64 * k + lane;
+        const uint32_t idx = run + (uint32_t)__popcll(h.head[k] & lt);
+        if ((h.head[k] >> lane) & 1ull) t0[idx] = (uint32_t)t;
+        if (t < z && ((uint32_t)t % (uint32_t)L) == 0u) bstart[(uint32_t)t / (uint32_t)L] = idx;
+        run += (uint32_t)__popcll(h.head[k]);
+      }
     }
     if (tile == n_tiles - 1 && lane == 0) bstart[n_b] = R;
   }
