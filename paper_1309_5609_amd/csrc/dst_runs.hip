@@ -214,7 +214,12 @@ __global__ void __launch_bounds__(kBlock) k_tile_starts(const int32_t* __restric
 // sums.  Time-order outputs feed the rescan and the right-hand side (pixel,
 // length, C, S, and the sums of d_T, d_q, d_u); a 64-byte record per run
 // feeds the per-pixel setup, which reads it in pixel order with one aligned
-// access.  Samples are summed in time order.
+// access.  Samples are summed in time order.  A wavefront takes 64
+// consecutive runs; when the samples they span fit kStage, the wavefront
+// first copies them (angles and timelines) into LDS with coalesced loads and
+// each lane then reads its run from there.
+constexpr int kStage = 256;
+
 template <typename PT, typename TT, typename RT, bool HAS_T, bool HAS_QU, bool IQU, bool TOD>
 __global__ void __launch_bounds__(kBlock) k_run_build(View v, const TT* __restrict__ tod,
                                                       const uint32_t* __restrict__ t0,
@@ -222,23 +227,55 @@ __global__ void __launch_bounds__(kBlock) k_run_build(View v, const TT* __restri
                                                       int32_t* __restrict__ rpix, int32_t* __restrict__ rn,
                                                       RT* __restrict__ rc, RT* __restrict__ rs,
                                                       double* __restrict__ raw, RunRecord* __restrict__ rec) {
+  constexpr bool SA = HAS_QU || IQU;                 // angles used
+  constexpr bool ST = TOD && (HAS_T || IQU);         // T (or radiometer) timeline used
+  constexpr bool SQ = TOD && HAS_QU && !IQU;         // q/u timelines used
+  constexpr int NROW = (ST ? 1 : 0) + (SQ ? 2 : 0);
+  __shared__ PT s_psi[SA ? kWaves : 1][SA ? kStage : 1];
+  __shared__ TT s_tod[NROW > 0 ? kWaves : 1][NROW > 0 ? NROW : 1][NROW > 0 ? kStage : 1];
   const PT* psi = static_cast<const PT*>(v.psi);
   const int64_t n_t = v.n_t;
-  constexpr int U = 4;  // samples whose loads are issued together
+  const int lane = lane_id();
+  const int wave = threadIdx.x >> 6;
+  constexpr int iT = 0, iQ = ST ? 1 : 0, iU = iQ + 1;
+  constexpr int U = 4;  // samples whose loads are issued together (direct path)
   const bool gaps = *n_out != 0;
-  for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < R; r += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t ts = t0[r];
-    // a run ends at the next run's start, the end of its baseline, or (with
-    // masked samples in the timeline) the first sample off its pixel
-    int64_t te = r + 1 < R ? (int64_t)t0[r + 1] : n_t;
-    te = min(te, (ts / v.L + 1) * v.L);
-    if (gaps) {
-      const int p = v.pix[ts];
-      int64_t t = ts + 1;
-      while (t < te && v.pix[t] == p) ++t;
-      te = t;
+  for (int64_t rb = ((int64_t)blockIdx.x * kWaves + wave) * 64; rb < R; rb += (int64_t)gridDim.x * kWaves * 64) {
+    const int64_t r = rb + lane;
+    const bool has = r < R;
+    int64_t ts = 0, te = 0;
+    if (has) {
+      ts = t0[r];
+      // a run ends at the next run's start, the end of its baseline, or (with
+      // masked samples in the timeline) the first sample off its pixel
+      te = r + 1 < R ? (int64_t)t0[r + 1] : n_t;
+      te = min(te, (ts / v.L + 1) * v.L);
+      if (gaps) {
+        const int p = v.pix[ts];
+        int64_t t = ts + 1;
+        while (t < te && v.pix[t] == p) ++t;
+        te = t;
+      }
     }
     const int32_t n = (int32_t)(te - ts);
+    // samples spanned by the wavefront's runs (lane 0 always holds one)
+    const int last = R - 1 - rb < 63 ? (int)(R - 1 - rb) : 63;
+    const int64_t lo = __shfl(ts, 0, 64), hi = __shfl(te, last, 64);
+    const bool staged = hi - lo <= kStage;
+    if (staged) {
+      for (int i = lane; i < hi - lo; i += 64) {
+        const int64_t t = lo + i;
+        if (SA) s_psi[SA ? wave : 0][i] = psi[t];
+        if (ST) s_tod[wave][iT][i] = tod[v.rowT * n_t + t];
+        if (SQ) {
+          s_tod[wave][iQ][i] = tod[v.rowQ * n_t + t];
+          s_tod[wave][SQ ? iU : 0][i] = tod[v.rowU * n_t + t];
+        }
+      }
+      // LDS operations of one wavefront execute in issue order; the barrier
+      // keeps the compiler from moving the reads above the writes.
+      __builtin_amdgcn_wave_barrier();
+    }
     double C = 0.0, S = 0.0, cc = 0.0, cs = 0.0;
     double dT = 0.0, dq = 0.0, du = 0.0, dQ = 0.0, dU = 0.0;
     for (int k0 = 0; k0 < n; k0 += U) {
@@ -247,16 +284,24 @@ __global__ void __launch_bounds__(kBlock) k_run_build(View v, const TT* __restri
       for (int u = 0; u < U; ++u) {
         const int64_t t = ts + k0 + u;
         const bool in = k0 + u < n;
-        ps_[u] = ((HAS_QU || IQU) && in) ? (double)psi[t] : 0.0;
-        xT[u] = (TOD && HAS_T && in) ? (double)tod[v.rowT * n_t + t] : 0.0;
-        xq[u] = (TOD && HAS_QU && in) ? (double)tod[v.rowQ * n_t + t] : 0.0;
-        xu[u] = (TOD && HAS_QU && in) ? (double)tod[v.rowU * n_t + t] : 0.0;
+        const int64_t i = t - lo;
+        if (staged) {
+          ps_[u] = (SA && in) ? (double)s_psi[SA ? wave : 0][SA ? i : 0] : 0.0;
+          xT[u] = (ST && in) ? (double)s_tod[NROW > 0 ? wave : 0][0][NROW > 0 ? i : 0] : 0.0;
+          xq[u] = (SQ && in) ? (double)s_tod[wave][iQ][i] : 0.0;
+          xu[u] = (SQ && in) ? (double)s_tod[wave][SQ ? iU : 0][i] : 0.0;
+        } else {
+          ps_[u] = (SA && in) ? (double)psi[t] : 0.0;
+          xT[u] = (ST && in) ? (double)tod[v.rowT * n_t + t] : 0.0;
+          xq[u] = (SQ && in) ? (double)tod[v.rowQ * n_t + t] : 0.0;
+          xu[u] = (SQ && in) ? (double)tod[v.rowU * n_t + t] : 0.0;
+        }
       }
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         if (k0 + u >= n) break;
         double c = 1.0, s = 0.0;
-        if (HAS_QU || IQU) {
+        if (SA) {
           rot2(ps_[u], c, s);
           C += c;
           S += s;
@@ -281,9 +326,11 @@ __global__ void __launch_bounds__(kBlock) k_run_build(View v, const TT* __restri
         }
       }
     }
+    if (staged) __builtin_amdgcn_wave_barrier();  // reads done before the next stage overwrites
+    if (!has) continue;
     rpix[r] = v.pix[ts];
     rn[r] = n;
-    if (HAS_QU || IQU) {
+    if (SA) {
       rc[r] = (RT)C;
       rs[r] = (RT)S;
     }
@@ -952,7 +999,7 @@ hipError_t runs_build(const View& v, int psi_f32, const void* tod, int tod_f32, 
   DST_CHECK(hipGetLastError());
   // 2. run records and setup moments (time order)
   const bool pf = psi_f32 && (v.rowQ >= 0 || v.iqu);
-  const unsigned grb = grid_for(R, kBlock, 16384);
+  const unsigned grb = grid_for(R, kBlock, 16384);  // 64 runs per wavefront, 256 per workgroup
   by_float(pf, [&](auto pt) {
     using PT = typename decltype(pt)::type;
     by_float(tod_f32, [&](auto tt) {
