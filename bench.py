@@ -325,20 +325,28 @@ def main() -> int:
         del src, dstb
 
     for i in range(args.warmup):
-        out = dst.dst_solve(ctx, dp, tol=args.tol, max_iter=2000, flags=dst.DST_SOLVE_PROFILE)
+        out = dst.dst_solve(ctx, dp, tol=args.tol, max_iter=2000)
         log(f"warmup {i}: {out['iterations']} iterations, {out['t_total_ms']:.1f} ms")
 
+    # timed: K solves as a caller runs them (CG iterations replayed from a captured graph)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    runs = []
+    plain = []
     for i in range(args.steps):
-        runs.append(dst.dst_solve(ctx, dp, tol=args.tol, max_iter=2000, flags=dst.DST_SOLVE_PROFILE))
+        plain.append(dst.dst_solve(ctx, dp, tol=args.tol, max_iter=2000))
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    iters = sum(r["iterations"] for r in runs)
+    iters = sum(r["iterations"] for r in plain)
     value = p.n_samples * iters / wall
-    r0 = runs[-1]
     log(f"timed {args.steps} solves: {wall * 1e3:.1f} ms, {iters} iterations, {value:.3e} samples*iters/s")
+    # the same K solves again with HIP events around every kernel of every iteration on the solve's stream
+    # (DST_SOLVE_PROFILE: kernels launched one by one, so this pass is slower): kernel durations for the roofline
+    torch.cuda.synchronize()
+    tp = time.perf_counter()
+    runs = [dst.dst_solve(ctx, dp, tol=args.tol, max_iter=2000, flags=dst.DST_SOLVE_PROFILE) for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    prof_wall = time.perf_counter() - tp
+    r0 = runs[-1]
 
     n_obs = int(r0["n_valid_pix"][0])
     n_runs = int(r0["n_runs"])
@@ -353,7 +361,7 @@ def main() -> int:
                   "unbin": f"k_unbin_runs<{rt}, true, true, false, true, 4>"}[dom]
     traffic = measured_traffic(dom_kernel)
     achieved = dom_bytes / (k_ms[dom] * 1e-3) / 1e9
-    iter_ms = float(np.mean([r["t_iter_ms"] for r in runs]))
+    iter_ms = float(np.mean([r["t_iter_ms"] for r in plain]))
     b_iter = algo["bin_samples"] + algo["unbin_samples"]
 
     # mixed precision on the same data: FP32 timelines and angles (FP64 accumulation, inverse and CG)
@@ -364,16 +372,16 @@ def main() -> int:
         dst.dst_solve(ctx, dp32, tol=args.tol, max_iter=2000)
         torch.cuda.synchronize()
         tm = time.perf_counter()
-        mruns = [dst.dst_solve(ctx, dp32, tol=args.tol, max_iter=2000, flags=dst.DST_SOLVE_PROFILE)
-                 for _ in range(args.steps)]
+        mruns = [dst.dst_solve(ctx, dp32, tol=args.tol, max_iter=2000) for _ in range(args.steps)]
         torch.cuda.synchronize()
         mwall = time.perf_counter() - tm
         mit = sum(r["iterations"] for r in mruns)
+        mprof = dst.dst_solve(ctx, dp32, tol=args.tol, max_iter=2000, flags=dst.DST_SOLVE_PROFILE)
         mixed = {"value": p.n_samples * mit / mwall, "ms_per_step": mwall * 1e3 / args.steps,
                  "iter_ms": float(np.mean([r["t_iter_ms"] for r in mruns])),
                  "setup_ms": float(np.mean([r["t_setup_ms"] for r in mruns])),
                  "iterations_per_solve": mruns[-1]["iterations"],
-                 "kernel_ms": {k: float(np.mean([r[f"t_{k}_ms"] for r in mruns])) for k in ("bin", "unbin")},
+                 "kernel_ms": {k: mprof[f"t_{k}_ms"] for k in ("bin", "unbin")},
                  "dtype": "f32 timelines and angles, f32 run records, f64 accumulation / inverse / CG"}
         del dp32
         log(f"mixed form: {mixed['value']:.3e} samples*iters/s")
@@ -432,7 +440,10 @@ def main() -> int:
                    "streams": p.streams, "tol": args.tol, "parallelism": "1 GPU"},
         "roofline": {"bound": "hbm", "kernel": dom_kernel, "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "algorithmic_bytes_per_launch": dom_bytes, "avg_launch_ms": k_ms[dom]},
+                     "algorithmic_bytes_per_launch": dom_bytes, "avg_launch_ms": k_ms[dom],
+                     "timing": ("HIP events around each kernel launch on the solve's stream, over a second "
+                                f"timed pass of the same {args.steps} solves ({prof_wall * 1e3 / args.steps:.2f} ms "
+                                "per solve with the events)")},
         "per_sample_model": {"bytes_per_iteration": b_iter,
                              "equivalent_GBs": b_iter / (iter_ms * 1e-3) / 1e9,
                              "note": "per-sample algorithmic bytes of one CG iteration / measured iteration time"},
@@ -447,7 +458,7 @@ def main() -> int:
         "iter_ms": iter_ms,
         "iteration_throughput": p.n_samples / (iter_ms * 1e-3),
         "iteration_hbm_frac": b_iter / (iter_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
-        "setup_ms": float(np.mean([r["t_setup_ms"] for r in runs])),
+        "setup_ms": float(np.mean([r["t_setup_ms"] for r in plain])),
         "kernel_ms": k_ms,
         "rel_residual": r0["rel_residual"],
         "true_rel_residual": r0["true_rel_residual"],
