@@ -40,6 +40,7 @@ struct dst_ctx {
   hipStream_t cap = nullptr;  // private stream on which iteration graphs are captured
   int unbin_bpw = 4;          // launch shape of the run rescan (baselines per wavefront)
   int bin_lpp = 32;           // launch shape of the run binning (lanes per pixel)
+  int run_split_bits = 0;     // > 0: longest run 2^bits samples (runs split beyond; results unchanged)
   // launch shapes chosen by the autotuner, per problem shape
   std::map<std::tuple<int64_t, int64_t, int, int>, std::pair<int, int>> tuned;
 };
@@ -312,6 +313,7 @@ int build_runs_plan(dst_ctx* ctx, const dst_problem* prob, Plan& P, const void* 
   HIP_TRY(dst::launch_fill_u32(reinterpret_cast<uint32_t*>(W.n_out), 2, 0u, st));
   HIP_TRY(dst::launch_fill_u32(reinterpret_cast<uint32_t*>(S.counts), 8, 0u, st));
   HIP_TRY(dst::launch_fill_u32(reinterpret_cast<uint32_t*>(S.err), 4, 0u, st));
+  W.split_bits = ctx->run_split_bits;
   HIP_TRY(dst::runs_count(v, W, S.err, st));
   const int64_t R = W.R;
   DST_TRY(ws(ctx, "r_t0", R, &W.t0));
@@ -322,8 +324,11 @@ int build_runs_plan(dst_ctx* ctx, const dst_problem* prob, Plan& P, const void* 
   const size_t rsz = W.f32 ? sizeof(float) : sizeof(double);
   DST_TRY(ws_get(ctx, "r_tc", R * rsz, &W.tc));
   DST_TRY(ws_get(ctx, "r_ts", R * rsz, &W.ts));
-  DST_TRY(ws(ctx, "r_raw", 3 * (size_t)R, &W.raw));
-  DST_TRY(ws(ctx, "r_rec", R, &W.rec));
+  // intensity-only problems: one raw sum and a 16-byte record per run
+  const bool t_only = v.rowT >= 0 && v.rowQ < 0 && !v.iqu;
+  DST_TRY(ws(ctx, "r_raw", (t_only ? 1 : 3) * (size_t)R, &W.raw));
+  DST_TRY(ws_get(ctx, "r_rec", (size_t)R * (t_only ? sizeof(dst::RunRecordT) : sizeof(dst::RunRecord)),
+                 reinterpret_cast<void**>(&W.rec)));
   DST_TRY(ws(ctx, "r_keys0", R, &W.keys[0]));
   DST_TRY(ws(ctx, "r_keys1", R, &W.keys[1]));
   DST_TRY(ws(ctx, "r_vals0", R, &W.vals[0]));
@@ -910,6 +915,7 @@ int dst_create(dst_ctx** out, int device) {
   ctx->device = device;
   if (const char* e = std::getenv("DST_UNBIN_BPW")) ctx->unbin_bpw = std::atoi(e);
   if (const char* e = std::getenv("DST_BIN_LPP")) ctx->bin_lpp = std::atoi(e);
+  if (const char* e = std::getenv("DST_RUN_SPLIT_BITS")) ctx->run_split_bits = std::atoi(e);
   DeviceGuard g(device);
   if (hipHostMalloc(reinterpret_cast<void**>(&ctx->ctl_host), sizeof(CgCtl), hipHostMallocDefault) != hipSuccess ||
       hipHostMalloc(reinterpret_cast<void**>(&ctx->err_host), sizeof(int), hipHostMallocDefault) != hipSuccess ||

@@ -20,6 +20,15 @@ struct alignas(64) RunRecord {
 };
 static_assert(sizeof(RunRecord) == 64, "run record must be one 64-byte line");
 
+// Intensity-only problems keep a 16-byte record per run (length, baseline,
+// sum of d_T) and one raw sum per run: the angle moments are not needed.
+struct alignas(16) RunRecordT {
+  int32_t n;
+  int32_t b;
+  double dT;
+};
+static_assert(sizeof(RunRecordT) == 16, "intensity run record must be 16 bytes");
+
 // A run is a maximal stretch of consecutive unmasked samples on one pixel
 // inside one baseline.  Runs are kept twice: in time order (t*: rescan and
 // baseline sums; bstart[b] .. bstart[b+1] are the runs of baseline b) and in
@@ -49,8 +58,8 @@ struct Runs {
   int32_t* tn = nullptr;
   void* tc = nullptr;
   void* ts = nullptr;
-  double* raw = nullptr;       // [3 R] sums of d_T, d_q, d_u per run (time order)
-  RunRecord* rec = nullptr;    // [R] per-run records (time order)
+  double* raw = nullptr;       // [3 R] sums of d_T, d_q, d_u per run (time order); [R] (d_T) for T only
+  RunRecord* rec = nullptr;    // [R] per-run records (time order); RunRecordT for T only
   uint32_t* keys[2] = {nullptr, nullptr};
   uint32_t* vals[2] = {nullptr, nullptr};
   const uint32_t* rperm = nullptr;
@@ -72,6 +81,11 @@ struct Runs {
   uint32_t* tkey = nullptr;
   uint32_t* pkey = nullptr;
   int nb = 0;
+  // Set by runs_count: bits of the run length in a packed key, and the mask
+  // of the forced run splits (t & smask == 0 starts a run; all ones: none).
+  int len_bits = 0;
+  uint32_t smask = 0xffffffffu;
+  int split_bits = 0;  // > 0: split runs at 2^split_bits samples at most (set by the caller)
   // Rescan order of the baselines (set by runs_build): sorted by the smallest
   // compact id each visits, so baselines over the same sky sit together.
   uint32_t* bkey[2] = {nullptr, nullptr};

@@ -118,8 +118,11 @@ unsigned grid_for(int64_t n, int64_t per_block, unsigned cap) {
 // Run detection in tiles of kTile samples, one wavefront per tile, 64
 // samples at a time.  Sample t starts a run when its pixel is valid and it is
 // the first sample of its baseline or follows a sample on another pixel (or
-// a masked one); a run ends before the next start, at the end of its
-// baseline or at the first sample off its pixel.
+// a masked one), or when t is a multiple of the split length (a power of two
+// chosen so that a compact pixel id or a baseline index and the run length
+// fit one 32-bit key; no split when whole baselines fit).  A run ends before
+// the next start, at the end of its baseline or at the first sample off its
+// pixel.  Splitting a run changes no sum, only how it is grouped.
 constexpr int64_t kTile = 4096;
 constexpr int kChunks = 4;  // 64-sample chunks whose loads are issued together
 
@@ -131,7 +134,7 @@ struct ChunkHeads {
   uint64_t head[kChunks];
 };
 __device__ __forceinline__ void chunk_heads(const int32_t* __restrict__ pix, int64_t c0, int64_t z, int64_t n_pix,
-                                            uint32_t L, ChunkHeads& o) {
+                                            uint32_t L, uint32_t smask, ChunkHeads& o) {
   const int lane = lane_id();
 #pragma unroll
   for (int k = 0; k < kChunks; ++k) {
@@ -148,14 +151,15 @@ __device__ __forceinline__ void chunk_heads(const int32_t* __restrict__ pix, int
     const int prev = lane == 0 ? last : up;
     const int p = o.p[k];
     const bool on = t < z && p >= 0 && p < n_pix;
-    o.head[k] = __ballot(on && (((uint32_t)t % L) == 0u || prev != p));
+    o.head[k] = __ballot(on && (((uint32_t)t % L) == 0u || ((uint32_t)t & smask) == 0u || prev != p));
   }
 }
 
 // Per tile: number of run starts; samples off the map (masked or out of
 // range) are counted into n_out, indices >= n_pix raise err.
 __global__ void __launch_bounds__(kBlock) k_tile_heads(const int32_t* __restrict__ pix, int64_t n_t, int64_t n_pix,
-                                                       int64_t L, int64_t n_tiles, uint32_t* __restrict__ tcount,
+                                                       int64_t L, uint32_t smask, int64_t n_tiles,
+                                                       uint32_t* __restrict__ tcount,
                                                        int* __restrict__ err, unsigned long long* __restrict__ n_out) {
   const int lane = lane_id();
   const int64_t nw = (int64_t)gridDim.x * kWaves;
@@ -165,7 +169,7 @@ __global__ void __launch_bounds__(kBlock) k_tile_heads(const int32_t* __restrict
     bool bad = false;
     for (int64_t c0 = a; c0 < z; c0 += 64 * kChunks) {
       ChunkHeads h;
-      chunk_heads(pix, c0, z, n_pix, (uint32_t)L, h);
+      chunk_heads(pix, c0, z, n_pix, (uint32_t)L, smask, h);
 #pragma unroll
       for (int k = 0; k < kChunks; ++k) {
         const bool in = c0 + 64 * k + lane < z;
@@ -185,7 +189,7 @@ __global__ void __launch_bounds__(kBlock) k_tile_heads(const int32_t* __restrict
 // First sample of each run (t0, time order) and the first run of each
 // baseline (bstart); toff = exclusive scan of the tile counts, R runs in all.
 __global__ void __launch_bounds__(kBlock) k_tile_starts(const int32_t* __restrict__ pix, int64_t n_t, int64_t n_pix,
-                                                        int64_t L, int64_t n_b, int64_t n_tiles,
+                                                        int64_t L, uint32_t smask, int64_t n_b, int64_t n_tiles,
                                                         const uint32_t* __restrict__ toff, uint32_t R,
                                                         uint32_t* __restrict__ t0, uint32_t* __restrict__ bstart) {
   const int lane = lane_id();
@@ -196,7 +200,7 @@ __global__ void __launch_bounds__(kBlock) k_tile_starts(const int32_t* __restric
     uint32_t run = toff[tile];
     for (int64_t c0 = a; c0 < z; c0 += 64 * kChunks) {
       ChunkHeads h;
-      chunk_heads(pix, c0, z, n_pix, (uint32_t)L, h);
+      chunk_heads(pix, c0, z, n_pix, (uint32_t)L, smask, h);
 #pragma unroll
       for (int k = 0; k < kChunks; ++k) {
         const int64_t t = c0 + 64 * k + lane;
@@ -228,6 +232,7 @@ __global__ void __launch_bounds__(kBlock) k_run_build(View v, const TT* __restri
                                                       RT* __restrict__ rc, RT* __restrict__ rs,
                                                       double* __restrict__ raw, RunRecord* __restrict__ rec) {
   constexpr bool SA = HAS_QU || IQU;                 // angles used
+  constexpr bool TONLY = HAS_T && !HAS_QU && !IQU;   // intensity only: 16-byte records
   constexpr bool ST = TOD && (HAS_T || IQU);         // T (or radiometer) timeline used
   constexpr bool SQ = TOD && HAS_QU && !IQU;         // q/u timelines used
   constexpr int NROW = (ST ? 1 : 0) + (SQ ? 2 : 0);
@@ -334,6 +339,15 @@ __global__ void __launch_bounds__(kBlock) k_run_build(View v, const TT* __restri
       rc[r] = (RT)C;
       rs[r] = (RT)S;
     }
+    if (TONLY) {
+      if (TOD) raw[r] = dT;
+      RunRecordT x;
+      x.n = n;
+      x.b = (int32_t)(ts / v.L);
+      x.dT = dT;
+      reinterpret_cast<RunRecordT*>(rec)[r] = x;
+      continue;
+    }
     if (TOD) {
       raw[3 * r + 0] = dT;
       raw[3 * r + 1] = dq;
@@ -422,6 +436,7 @@ __global__ void __launch_bounds__(kBlock) k_pixels_from_runs(
     const int64_t* __restrict__ pstart, int32_t* __restrict__ hits, double* __restrict__ Minv4,
     uint8_t* __restrict__ valid, double* __restrict__ m4_zero, double* __restrict__ sd4, double* __restrict__ md4,
     unsigned long long* __restrict__ counts) {
+  constexpr bool TONLY = HAS_T && !HAS_QU && !IQU;  // 16-byte records
   __shared__ unsigned long long lds[4 * 16];
   unsigned long long cnt[4] = {0, 0, 0, 0};
   const int lane = lane_id();
@@ -441,8 +456,17 @@ __global__ void __launch_bounds__(kBlock) k_pixels_from_runs(
       for (int u = 0; u < U; ++u) q[u] = jb + 64 * u < j1 ? rperm[jb + 64 * u] : 0u;
       RunRecord xs[U];
 #pragma unroll
-      for (int u = 0; u < U; ++u)
-        if (jb + 64 * u < j1) xs[u] = rec[q[u]];
+      for (int u = 0; u < U; ++u) {
+        if (jb + 64 * u >= j1) continue;
+        if (TONLY) {
+          const RunRecordT y = reinterpret_cast<const RunRecordT*>(rec)[q[u]];
+          xs[u].n = y.n;
+          xs[u].b = y.b;
+          xs[u].dT = y.dT;
+        } else {
+          xs[u] = rec[q[u]];
+        }
+      }
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         const int64_t j = jb + 64 * u;
@@ -642,7 +666,7 @@ __global__ void __launch_bounds__(kBlock) k_rhs_runs(View v, const uint32_t* __r
       if (c[u] < 0) continue;
       const int64_t r = rb + kBlock * u;
       const double n = (double)rn[r];
-      const double* m = raw + 3 * r;
+      const double* m = raw + (HAS_T && !HAS_QU && !IQU ? 1 : 3) * r;
       if (IQU && (f[u] & 1)) {
         acc[3] += n;
         if (TOD) {
@@ -941,8 +965,19 @@ int64_t run_tiles(int64_t n_t) { return (n_t + kTile - 1) / kTile; }
 
 hipError_t runs_count(const View& v, Runs& W, int* err, hipStream_t st) {
   const int64_t n_t = v.n_t, n_tiles = run_tiles(n_t);
+  // run-length bits of the packed keys: all of L when it fits beside the
+  // pixel (bounded by n_pix) and baseline indices, else runs are split
+  int room = 32 - (int)std::max(key_bits(std::max<int64_t>(v.n_pix, 1)), key_bits(std::max<int64_t>(v.n_b, 1)));
+  if (W.split_bits > 0) room = std::min(room, W.split_bits);
+  if ((int)key_bits(v.L) <= room || room < 1) {
+    W.len_bits = (int)key_bits(v.L);
+    W.smask = 0xffffffffu;
+  } else {
+    W.len_bits = room;
+    W.smask = (1u << room) - 1u;
+  }
   const unsigned g = grid_for(n_tiles, kWaves, 8192);
-  hipLaunchKernelGGL(k_tile_heads, dim3(g), dim3(kBlock), 0, st, v.pix, n_t, v.n_pix, v.L, n_tiles, W.tcount, err,
+  hipLaunchKernelGGL(k_tile_heads, dim3(g), dim3(kBlock), 0, st, v.pix, n_t, v.n_pix, v.L, W.smask, n_tiles, W.tcount, err,
                      W.n_out);
   DST_CHECK(hipGetLastError());
   size_t tmp = W.tmp_bytes;
@@ -995,7 +1030,7 @@ hipError_t runs_build(const View& v, int psi_f32, const void* tod, int tod_f32, 
   const unsigned g = grid_for(n_t, kBlock, 8192);
   // 1. run starts and per-baseline run ranges
   hipLaunchKernelGGL(k_tile_starts, dim3(grid_for(run_tiles(n_t), kWaves, 8192)), dim3(kBlock), 0, st, v.pix, n_t,
-                     v.n_pix, v.L, v.n_b, run_tiles(n_t), W.toff, (uint32_t)R, W.t0, W.bstart);
+                     v.n_pix, v.L, W.smask, v.n_b, run_tiles(n_t), W.toff, (uint32_t)R, W.t0, W.bstart);
   DST_CHECK(hipGetLastError());
   // 2. run records and setup moments (time order)
   const bool pf = psi_f32 && (v.rowQ >= 0 || v.iqu);
@@ -1078,7 +1113,7 @@ hipError_t runs_build(const View& v, int psi_f32, const void* tod, int tod_f32, 
   hipLaunchKernelGGL(k_runs_to_compact, dim3(gr), dim3(kBlock), 0, st, R, W.cid, W.tpix);
   DST_CHECK(hipGetLastError());
   // 7. one 32-bit key per run for the iterations (index and length) when both fit
-  const unsigned nb = key_bits(v.L);
+  const unsigned nb = (unsigned)W.len_bits;
   W.nb = 0;
   if (W.tkey && W.pkey && key_bits(std::max<int64_t>(W.n_obs, 1)) + nb <= 32 && key_bits(v.n_b) + nb <= 32) {
     W.nb = (int)nb;

@@ -290,3 +290,24 @@ def test_rescan_launch_shapes_agree(name):
     for bpw in ("1", "2", "8"):
         assert abs(out[bpw]["iterations"] - out["4"]["iterations"]) <= 1
         assert rel(out[bpw]["baselines"].cpu().numpy(), out["4"]["baselines"].cpu().numpy()) < 1e-10
+
+
+@pytest.mark.parametrize("name", ["plain", "masked", "fewpix", "longbase", "T"])
+def test_run_splits_agree(name):
+    """Runs split at 4 samples (DST_RUN_SPLIT_BITS=2) give the solve of whole runs: same hits, same baselines."""
+    import os
+    from paper_1309_5609_amd import dst
+    p = make(name)
+    out = {}
+    for bits in ("0", "2"):
+        os.environ["DST_RUN_SPLIT_BITS"] = bits
+        try:
+            c = dst.Context(0)
+        finally:
+            del os.environ["DST_RUN_SPLIT_BITS"]
+        out[bits] = dst.dst_solve(c, dev(p), tol=1e-13, max_iter=3000)
+        c.close()
+    assert out["2"]["n_runs"] > out["0"]["n_runs"]
+    assert np.array_equal(out["2"]["hits"].cpu().numpy(), out["0"]["hits"].cpu().numpy())
+    assert abs(out["2"]["iterations"] - out["0"]["iterations"]) <= 1
+    assert rel(out["2"]["baselines"].cpu().numpy(), out["0"]["baselines"].cpu().numpy()) < 1e-10
