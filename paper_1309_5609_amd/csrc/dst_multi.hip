@@ -49,6 +49,11 @@ __global__ void __launch_bounds__(kBlock) k_run_positions(int64_t n_obs, const u
 // run's record (one 128-byte line holding every realization of the pass) at
 // its pixel-order position, so each scattered store writes a whole line; per
 // baseline: w_k sum d_k over valid samples (the data part of b = F^T Z d).
+// When the samples of 64 consecutive runs fit kStageM, the wavefront first
+// copies them (angles and timelines) into LDS with coalesced loads and the
+// lanes read their runs from there.
+constexpr int kStageM = 256;
+
 template <typename PT, typename TT, bool HAS_T, bool HAS_QU, int NR>
 __global__ void __launch_bounds__(kBlock) k_multi_tod(View v, TodSet tods, const uint32_t* __restrict__ bstart,
                                                       const uint32_t* __restrict__ t0,
@@ -56,20 +61,49 @@ __global__ void __launch_bounds__(kBlock) k_multi_tod(View v, TodSet tods, const
                                                       const uint32_t* __restrict__ ipos,
                                                       const uint8_t* __restrict__ valid, int Rp, int ri0,
                                                       double* __restrict__ prs, double* __restrict__ braw) {
+  constexpr int NROW = (HAS_T ? 1 : 0) + (HAS_QU ? 2 : 0);  // timeline rows per realization
+  constexpr int iT = 0, iQ = HAS_T ? 1 : 0, iU = iQ + 1;
+  __shared__ PT s_psi[HAS_QU ? kWaves : 1][HAS_QU ? kStageM : 1];
+  __shared__ TT s_tod[kWaves][NR * NROW][kStageM];
   const PT* psi = static_cast<const PT*>(v.psi);
   const int lane = lane_id();
-  const int64_t b = (int64_t)blockIdx.x * kWaves + (threadIdx.x >> 6);
-  if (b >= v.n_b) return;
+  const int wave = threadIdx.x >> 6;
+  const int64_t b = (int64_t)blockIdx.x * kWaves + wave;
+  if (b >= v.n_b) return;  // the block's waves never synchronise with each other
   const int64_t n_t = v.n_t;
   const int64_t r0 = bstart[b], r1 = bstart[b + 1];
   double acc[3 * NR];
 #pragma unroll
   for (int i = 0; i < 3 * NR; ++i) acc[i] = 0.0;
   constexpr int U = NR >= 3 ? 1 : (NR == 2 ? 2 : 4);  // samples whose loads are issued together
-  for (int64_t j = r0 + lane; j < r1; j += 64) {
-    const int64_t ts = t0[j];
-    const int n = tn[j];
-    const uint8_t f = valid[tpix[j]];
+  for (int64_t jb = r0; jb < r1; jb += 64) {
+    const int64_t j = jb + lane;
+    const bool has = j < r1;
+    const int64_t ts = has ? (int64_t)t0[j] : 0;
+    const int n = has ? tn[j] : 0;
+    const uint8_t f = has ? valid[tpix[j]] : 0;
+    // samples spanned by these runs (lane 0 always holds one)
+    const int last = r1 - 1 - jb < 63 ? (int)(r1 - 1 - jb) : 63;
+    const int64_t lo = __shfl(ts, 0, 64), hi = __shfl(ts + n, last, 64);
+    const bool staged = hi - lo <= kStageM;
+    if (staged) {
+      for (int e = lane; e < hi - lo; e += 64) {
+        const int64_t t = lo + e;
+        if (HAS_QU) s_psi[HAS_QU ? wave : 0][e] = psi[t];
+#pragma unroll
+        for (int i = 0; i < NR; ++i) {
+          const TT* tod = static_cast<const TT*>(tods.p[i]);
+          if (HAS_T) s_tod[wave][NROW * i + iT][e] = tod[v.rowT * n_t + t];
+          if (HAS_QU) {
+            s_tod[wave][NROW * i + iQ][e] = tod[v.rowQ * n_t + t];
+            s_tod[wave][NROW * i + iU][e] = tod[v.rowU * n_t + t];
+          }
+        }
+      }
+      // LDS operations of one wavefront execute in issue order; the barrier
+      // keeps the compiler from moving the reads above the writes.
+      __builtin_amdgcn_wave_barrier();
+    }
     double dT[NR], dq[NR], du[NR], dQ[NR], dU[NR];
 #pragma unroll
     for (int i = 0; i < NR; ++i) dT[i] = dq[i] = du[i] = dQ[i] = dU[i] = 0.0;
@@ -79,13 +113,24 @@ __global__ void __launch_bounds__(kBlock) k_multi_tod(View v, TodSet tods, const
       for (int u = 0; u < U; ++u) {
         const int64_t t = ts + k0 + u;
         const bool in = k0 + u < n;
-        ang[u] = (HAS_QU && in) ? (double)psi[t] : 0.0;
+        const int64_t e = t - lo;
+        if (staged) {
+          ang[u] = (HAS_QU && in) ? (double)s_psi[HAS_QU ? wave : 0][HAS_QU ? e : 0] : 0.0;
 #pragma unroll
-        for (int i = 0; i < NR; ++i) {
-          const TT* tod = static_cast<const TT*>(tods.p[i]);
-          xT[u][i] = (HAS_T && in) ? (double)tod[v.rowT * n_t + t] : 0.0;
-          xq[u][i] = (HAS_QU && in) ? (double)tod[v.rowQ * n_t + t] : 0.0;
-          xu[u][i] = (HAS_QU && in) ? (double)tod[v.rowU * n_t + t] : 0.0;
+          for (int i = 0; i < NR; ++i) {
+            xT[u][i] = (HAS_T && in) ? (double)s_tod[wave][NROW * i + iT][e] : 0.0;
+            xq[u][i] = (HAS_QU && in) ? (double)s_tod[wave][NROW * i + iQ][e] : 0.0;
+            xu[u][i] = (HAS_QU && in) ? (double)s_tod[wave][NROW * i + iU][e] : 0.0;
+          }
+        } else {
+          ang[u] = (HAS_QU && in) ? (double)psi[t] : 0.0;
+#pragma unroll
+          for (int i = 0; i < NR; ++i) {
+            const TT* tod = static_cast<const TT*>(tods.p[i]);
+            xT[u][i] = (HAS_T && in) ? (double)tod[v.rowT * n_t + t] : 0.0;
+            xq[u][i] = (HAS_QU && in) ? (double)tod[v.rowQ * n_t + t] : 0.0;
+            xu[u][i] = (HAS_QU && in) ? (double)tod[v.rowU * n_t + t] : 0.0;
+          }
         }
       }
 #pragma unroll
@@ -106,6 +151,8 @@ __global__ void __launch_bounds__(kBlock) k_multi_tod(View v, TodSet tods, const
         }
       }
     }
+    if (staged) __builtin_amdgcn_wave_barrier();  // reads done before the next stage overwrites
+    if (!has) continue;
     const bool vT = HAS_T && (f & 1), vQ = HAS_QU && (f & 2);
     const int64_t pos = ipos[j];
 #pragma unroll
@@ -387,6 +434,8 @@ __device__ __forceinline__ void sum_partials_by_rhs(const double* __restrict__ p
   double s[N];
 #pragma unroll
   for (int i = 0; i < N; ++i) s[i] = 0.0;
+  // the loads of eight blocks are issued together; the sums keep their order
+#pragma unroll 8
   for (int blk = ch; blk < n_part; blk += nch) {
 #pragma unroll
     for (int i = 0; i < N; ++i) s[i] += part[((int64_t)blk * N + i) * Rp + r];
