@@ -197,14 +197,30 @@ __global__ void __launch_bounds__(kBlock) k_multi_pixsum(int64_t n_obs, View vc,
     double acc[3 * NR];
 #pragma unroll
     for (int i = 0; i < 3 * NR; ++i) acc[i] = 0.0;
-    for (int64_t j = j0 + lane; j < j1; j += 64) {
+    // two records per lane in flight
+    for (int64_t jb = j0 + lane; jb < j1; jb += 128) {
+      double2 x0[2][NR], x1[2][NR];
 #pragma unroll
-      for (int i = 0; i < NR; ++i) {
-        const double2* x = reinterpret_cast<const double2*>(prs + 4 * (kTodBatch * j + i));
-        const double2 x0 = x[0], x1 = x[1];
-        acc[3 * i] += x0.x;
-        acc[3 * i + 1] += x0.y;
-        acc[3 * i + 2] += x1.x;
+      for (int u = 0; u < 2; ++u) {
+        const int64_t j = jb + 64 * u;
+#pragma unroll
+        for (int i = 0; i < NR; ++i) {
+          x0[u][i] = x1[u][i] = make_double2(0.0, 0.0);
+          if (j < j1) {
+            const double2* x = reinterpret_cast<const double2*>(prs + 4 * (kTodBatch * j + i));
+            x0[u][i] = x[0];
+            x1[u][i] = x[1];
+          }
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+#pragma unroll
+        for (int i = 0; i < NR; ++i) {
+          acc[3 * i] += x0[u][i].x;
+          acc[3 * i + 1] += x0[u][i].y;
+          acc[3 * i + 2] += x1[u][i].x;
+        }
       }
     }
     dev::wave_sum<3 * NR>(acc);
