@@ -267,29 +267,31 @@ __global__ void __launch_bounds__(kBlock) k_multi_bin(View vc, int R, int Rp, co
   for (int64_t c = (int64_t)blockIdx.x * kWaves + (threadIdx.x >> 6); c < n_obs; c += nw) {
     const int64_t j0 = pstart[c], j1 = pstart[c + 1];
     double acc[3] = {0.0, 0.0, 0.0};
-    constexpr int U = 1;  // one run per slot in flight: fewer registers, higher occupancy
-    for (int64_t jb = j0 + slot; jb < j1; jb += (int64_t)slots * U) {
-      int32_t bb[U], nn[U];
-      double C[U], S[U];
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const int64_t j = jb + (int64_t)slots * u;
-        const bool in = j < j1;
-        bb[u] = in ? pb[j] : -1;
-        nn[u] = (HAS_T && in) ? pn[j] : 0;
-        C[u] = (HAS_QU && in) ? (double)pc[j] : 0.0;
-        S[u] = (HAS_QU && in) ? (double)ps[j] : 0.0;
-      }
-      if (!act) continue;
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-        if (bb[u] < 0) continue;
-        const double* pr = p + (int64_t)bb[u] * nS * Rp + r;
-        if (HAS_T) acc[0] += (double)nn[u] * (w0 * pr[oT]);
+    // The run data of 64 runs at a time are loaded once, one run per lane
+    // (coalesced), and handed to the slots by shuffles, so the only loads
+    // left in the run loop are the gathers of p.
+    for (int64_t wb = j0; wb < j1; wb += 64) {
+      const int64_t jl = wb + lane;
+      const bool inw = jl < j1;
+      const int w_b = inw ? pb[jl] : -1;
+      const int w_n = (HAS_T && inw) ? pn[jl] : 0;
+      const RT w_c = (HAS_QU && inw) ? pc[jl] : (RT)0;
+      const RT w_s = (HAS_QU && inw) ? ps[jl] : (RT)0;
+      const int nwin = j1 - wb < 64 ? (int)(j1 - wb) : 64;
+#pragma unroll 2
+      for (int k0 = 0; k0 < nwin; k0 += slots) {  // uniform: every lane takes part in the shuffles
+        const int kk = k0 + slot;
+        const int src = kk < nwin ? kk : 0;
+        const int bb = __shfl(w_b, src, 64);
+        const int nn = __shfl(w_n, src, 64);
+        const double C = (double)__shfl(w_c, src, 64), S = (double)__shfl(w_s, src, 64);
+        if (!act || kk >= nwin || bb < 0) continue;
+        const double* pr = p + (int64_t)bb * nS * Rp + r;
+        if (HAS_T) acc[0] += (double)nn * (w0 * pr[oT]);
         if (HAS_QU) {
           const double xq = w1 * pr[oQ], xu = w2 * pr[oU];
-          acc[1] += C[u] * xq - S[u] * xu;
-          acc[2] += S[u] * xq + C[u] * xu;
+          acc[1] += C * xq - S * xu;
+          acc[2] += S * xq + C * xu;
         }
       }
     }
@@ -345,29 +347,30 @@ __global__ void __launch_bounds__(kBlock) k_multi_unbin(View vc, int R, int Rp, 
     const int64_t b = border[bk];
     const int64_t r0 = bstart[b], r1 = bstart[b + 1];
     double acc[3] = {0.0, 0.0, 0.0};
-    constexpr int U = 1;
-    for (int64_t jb = r0 + slot; jb < r1; jb += (int64_t)slots * U) {
-      int32_t cc[U], nn[U];
-      double C[U], S[U];
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const int64_t j = jb + (int64_t)slots * u;
-        const bool in = j < r1;
-        cc[u] = in ? tpix[j] : -1;
-        nn[u] = (HAS_T && in) ? tn[j] : 0;
-        C[u] = (HAS_QU && in) ? (double)tc[j] : 0.0;
-        S[u] = (HAS_QU && in) ? (double)ts[j] : 0.0;
-      }
-      if (!act) continue;
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-        if (cc[u] < 0) continue;
-        const double* mr = m + (int64_t)cc[u] * nS * Rp + r;
-        if (HAS_T) acc[0] += (double)nn[u] * mr[oT];
+    // run data of 64 runs at a time: one coalesced load per lane, handed to
+    // the slots by shuffles; the run loop only gathers m
+    for (int64_t wb = r0; wb < r1; wb += 64) {
+      const int64_t jl = wb + lane;
+      const bool inw = jl < r1;
+      const int w_c = inw ? tpix[jl] : -1;
+      const int w_n = (HAS_T && inw) ? tn[jl] : 0;
+      const RT w_C = (HAS_QU && inw) ? tc[jl] : (RT)0;
+      const RT w_S = (HAS_QU && inw) ? ts[jl] : (RT)0;
+      const int nwin = r1 - wb < 64 ? (int)(r1 - wb) : 64;
+#pragma unroll 2
+      for (int k0 = 0; k0 < nwin; k0 += slots) {  // uniform: every lane takes part in the shuffles
+        const int kk = k0 + slot;
+        const int src = kk < nwin ? kk : 0;
+        const int cc = __shfl(w_c, src, 64);
+        const int nn = __shfl(w_n, src, 64);
+        const double C = (double)__shfl(w_C, src, 64), S = (double)__shfl(w_S, src, 64);
+        if (!act || kk >= nwin || cc < 0) continue;
+        const double* mr = m + (int64_t)cc * nS * Rp + r;
+        if (HAS_T) acc[0] += (double)nn * mr[oT];
         if (HAS_QU) {
           const double mQ = mr[oQ], mU = mr[oU];
-          acc[1] += C[u] * mQ + S[u] * mU;
-          acc[2] += C[u] * mU - S[u] * mQ;
+          acc[1] += C * mQ + S * mU;
+          acc[2] += C * mU - S * mQ;
         }
       }
     }
