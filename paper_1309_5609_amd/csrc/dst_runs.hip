@@ -793,6 +793,152 @@ __global__ void __launch_bounds__(kBlock) k_bin_runs(int64_t n_obs, const int64_
   }
 }
 
+// The same binning with a three-stage software pipeline over the
+// wavefront's pixels (launch shape -LPP): while the baseline values of one
+// pixel's first LPP * U runs are gathered, the run stream of its next pixel
+// and the run range of the one after are loaded.  Faster with FP32 run sums
+// (more registers, so fewer wavefronts, which the FP64 form does not recoup).
+template <typename RT, bool HAS_T, bool HAS_QU, bool IQU, int LPP>
+__global__ void __launch_bounds__(kBlock) k_bin_runs_pipe(int64_t n_obs, const int64_t* __restrict__ pstart,
+                                                          const uint32_t* __restrict__ pb,
+                                                          const int32_t* __restrict__ pn, int nb,
+                                                          const RT* __restrict__ pc, const RT* __restrict__ ps,
+                                                          const double* __restrict__ pw4,
+                                                          const double* __restrict__ Minv4,
+                                                          const uint8_t* __restrict__ valid, double* __restrict__ m4,
+                                                          const CgCtl* __restrict__ gate) {
+  if (gate && gate->done) return;
+  constexpr int PPW = 64 / LPP;
+  constexpr int U = LPP >= 64 ? 2 : (LPP == 32 ? 4 : 8);
+  const int lane = lane_id();
+  const int grp = lane / LPP, sub = lane % LPP;
+  const int64_t step = (int64_t)gridDim.x * kWaves * PPW;
+  // run range of compact pixel cx; empty when invalid or past the end
+  auto head = [&](int64_t cx, int64_t& j0x, int64_t& j1x) {
+    const bool inr = cx < n_obs;
+    const bool h = inr && valid[cx] != 0;  // m stays 0 on invalid pixels
+    j0x = inr ? pstart[cx] : 0;
+    const int64_t e = inr ? pstart[cx + 1] : 0;
+    j1x = h ? e : j0x;
+  };
+  uint32_t nkey[U];
+  int32_t nlen[U];
+  RT nC[U], nS[U];
+  auto fetch = [&](int64_t j0x, int64_t j1x) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t j = j0x + sub + LPP * u;
+      const bool in = j < j1x;
+      nkey[u] = in ? pb[j] : 0u;
+      nlen[u] = (HAS_T && !nb && in) ? pn[j] : 0;
+      nC[u] = ((HAS_QU || IQU) && in) ? pc[j] : (RT)0;
+      nS[u] = ((HAS_QU || IQU) && in) ? ps[j] : (RT)0;
+    }
+  };
+  int64_t cb = ((int64_t)blockIdx.x * kWaves + (threadIdx.x >> 6)) * PPW;
+  int64_t a0, a1, b0, b1;
+  head(cb + grp, a0, a1);
+  fetch(a0, a1);
+  head(cb + step + grp, b0, b1);
+  for (; cb < n_obs; cb += step) {
+    const int64_t c = cb + grp;
+    const int64_t j0 = a0, j1 = a1;
+    const bool have = j1 > j0;  // valid observed pixels have runs; the range is empty otherwise
+    int32_t bb[U], nn[U];
+    double cc[U], ss[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const bool in = j0 + sub + LPP * u < j1;
+      // packed keys (nb > 0): baseline << nb | (length - 1); else baseline, lengths in pn
+      bb[u] = in ? (int32_t)(nb ? nkey[u] >> nb : nkey[u]) : -1;
+      nn[u] = (HAS_T && in) ? (nb ? (int32_t)(nkey[u] & ((1u << nb) - 1u)) + 1 : nlen[u]) : 0;
+      cc[u] = (double)nC[u];
+      ss[u] = (double)nS[u];
+    }
+    double2 x0[U];
+    double u0[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      x0[u] = make_double2(0.0, 0.0);
+      u0[u] = 0.0;
+      if (bb[u] < 0) continue;
+      const double2* q0 = reinterpret_cast<const double2*>(pw4 + 4 * (int64_t)bb[u]);
+      x0[u] = q0[0];
+      if (HAS_QU) u0[u] = q0[1].x;
+    }
+    fetch(b0, b1);
+    a0 = b0;
+    a1 = b1;
+    head(cb + 2 * step + grp, b0, b1);
+    double acc[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (IQU) {
+        acc[0] += (double)nn[u] * x0[u].x;
+        acc[1] += cc[u] * x0[u].x;
+        acc[2] += ss[u] * x0[u].x;
+        continue;
+      }
+      if (HAS_T) acc[0] += (double)nn[u] * x0[u].x;
+      if (HAS_QU) {
+        acc[1] += cc[u] * x0[u].y - ss[u] * u0[u];
+        acc[2] += ss[u] * x0[u].y + cc[u] * u0[u];
+      }
+    }
+    // runs past the first LPP * U of a long pixel
+    for (int64_t jb = j0 + sub + LPP * U; jb < j1; jb += LPP * U) {
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int64_t j = jb + LPP * u;
+        const bool in = j < j1;
+        const uint32_t key = in ? pb[j] : 0u;
+        bb[u] = in ? (int32_t)(nb ? key >> nb : key) : -1;
+        nn[u] = (HAS_T && in) ? (nb ? (int32_t)(key & ((1u << nb) - 1u)) + 1 : pn[j]) : 0;
+        cc[u] = ((HAS_QU || IQU) && in) ? (double)pc[j] : 0.0;
+        ss[u] = ((HAS_QU || IQU) && in) ? (double)ps[j] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        if (bb[u] < 0) continue;
+        const double2* q0 = reinterpret_cast<const double2*>(pw4 + 4 * (int64_t)bb[u]);
+        const double2 x = q0[0];
+        if (IQU) {
+          acc[0] += (double)nn[u] * x.x;
+          acc[1] += cc[u] * x.x;
+          acc[2] += ss[u] * x.x;
+          continue;
+        }
+        if (HAS_T) acc[0] += (double)nn[u] * x.x;
+        if (HAS_QU) {
+          const double uu = q0[1].x;
+          acc[1] += cc[u] * x.y - ss[u] * uu;
+          acc[2] += ss[u] * x.y + cc[u] * uu;
+        }
+      }
+    }
+#pragma unroll
+    for (int off = LPP / 2; off > 0; off >>= 1) {
+#pragma unroll
+      for (int i = 0; i < 3; ++i) acc[i] += __shfl_xor(acc[i], off, 64);
+    }
+    if (IQU && have && sub == 0) {
+      const double2* ip = reinterpret_cast<const double2*>(Minv4 + 8 * c);
+      const double2 i01 = ip[0], i23 = ip[1], i45 = ip[2];  // (00, 01), (02, 11), (12, 22)
+      double2* mp = reinterpret_cast<double2*>(m4 + 4 * c);
+      mp[0] = make_double2(i01.x * acc[0] + i01.y * acc[1] + i23.x * acc[2],
+                           i01.y * acc[0] + i23.y * acc[1] + i45.x * acc[2]);
+      mp[1] = make_double2(i23.x * acc[0] + i45.x * acc[1] + i45.y * acc[2], 0.0);
+    }
+    if (!IQU && have && sub == 0) {
+      const double2* ip = reinterpret_cast<const double2*>(Minv4 + 4 * c);
+      const double2 i01 = ip[0], i23 = ip[1];
+      double2* mp = reinterpret_cast<double2*>(m4 + 4 * c);
+      mp[0] = make_double2(i01.x * acc[0], i01.y * acc[1] + i23.x * acc[2]);
+      mp[1] = make_double2(i23.x * acc[1] + i23.y * acc[2], 0.0);
+    }
+  }
+}
+
 // q = K p = F^T W (F p - A m) per baseline from its time-order runs.  BPW
 // baselines share a wavefront (64 / BPW lanes each), taken in the order
 // `border` (baselines sorted by the smallest compact pixel they visit), so
@@ -1153,7 +1299,11 @@ hipError_t launch_rhs_runs(const View& vc, const Runs& W, const void* tod, const
 
 hipError_t launch_bin_runs(const View& vc, const Runs& W, const double* pw4, const double* Minv4,
                            const uint8_t* valid, double* m4, const CgCtl* gate, int lpp, hipStream_t st) {
-  if (lpp != 64 && lpp != 32 && lpp != 16) lpp = 64;
+  // 0: the default (32 with FP64 run sums, the pipelined 64 with FP32)
+  if (lpp == 0) lpp = W.f32 ? -64 : 32;
+  if (lpp != 64 && lpp != 32 && lpp != 16 && lpp != -64) lpp = 32;
+  const bool pipe = lpp < 0;
+  if (pipe) lpp = -lpp;
   const int64_t ppb = kWaves * (64 / lpp);
   const unsigned g = (unsigned)std::max<int64_t>(1, std::min<int64_t>((W.n_obs + ppb - 1) / ppb, 16384));
   by_float(W.f32, [&](auto rt) {
@@ -1165,7 +1315,9 @@ hipError_t launch_bin_runs(const View& vc, const Runs& W, const double* pw4, con
                            W.nb ? W.pkey : reinterpret_cast<const uint32_t*>(W.pb), W.pn, W.nb,
                            static_cast<const RT*>(W.pc), static_cast<const RT*>(W.ps), pw4, Minv4, valid, m4, gate);
       };
-      if (lpp == 16)
+      if (pipe)
+        launch(k_bin_runs_pipe<RT, HT, HQ, HI, 64>);
+      else if (lpp == 16)
         launch(k_bin_runs<RT, HT, HQ, HI, 16>);
       else if (lpp == 32)
         launch(k_bin_runs<RT, HT, HQ, HI, 32>);
