@@ -885,34 +885,57 @@ __global__ void __launch_bounds__(kBlock) k_bin_runs_pipe(int64_t n_obs, const i
         acc[2] += ss[u] * x0[u].y + cc[u] * u0[u];
       }
     }
-    // runs past the first LPP * U of a long pixel
-    for (int64_t jb = j0 + sub + LPP * U; jb < j1; jb += LPP * U) {
+    // runs past the first LPP * U of a long pixel, with the next step's run
+    // stream loaded while this step's baseline values are gathered
+    int64_t jb = j0 + sub + LPP * U;
+    if (jb < j1) {
+      uint32_t rkey[U];
+      int32_t rlen[U];
+      RT rC[U], rS[U];
+      auto rfetch = [&](int64_t jx) {
 #pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const int64_t j = jb + LPP * u;
-        const bool in = j < j1;
-        const uint32_t key = in ? pb[j] : 0u;
-        bb[u] = in ? (int32_t)(nb ? key >> nb : key) : -1;
-        nn[u] = (HAS_T && in) ? (nb ? (int32_t)(key & ((1u << nb) - 1u)) + 1 : pn[j]) : 0;
-        cc[u] = ((HAS_QU || IQU) && in) ? (double)pc[j] : 0.0;
-        ss[u] = ((HAS_QU || IQU) && in) ? (double)ps[j] : 0.0;
-      }
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-        if (bb[u] < 0) continue;
-        const double2* q0 = reinterpret_cast<const double2*>(pw4 + 4 * (int64_t)bb[u]);
-        const double2 x = q0[0];
-        if (IQU) {
-          acc[0] += (double)nn[u] * x.x;
-          acc[1] += cc[u] * x.x;
-          acc[2] += ss[u] * x.x;
-          continue;
+        for (int u = 0; u < U; ++u) {
+          const int64_t j = jx + LPP * u;
+          const bool in = j < j1;
+          rkey[u] = in ? pb[j] : 0u;
+          rlen[u] = (HAS_T && !nb && in) ? pn[j] : 0;
+          rC[u] = ((HAS_QU || IQU) && in) ? pc[j] : (RT)0;
+          rS[u] = ((HAS_QU || IQU) && in) ? ps[j] : (RT)0;
         }
-        if (HAS_T) acc[0] += (double)nn[u] * x.x;
-        if (HAS_QU) {
-          const double uu = q0[1].x;
-          acc[1] += cc[u] * x.y - ss[u] * uu;
-          acc[2] += ss[u] * x.y + cc[u] * uu;
+      };
+      rfetch(jb);
+      for (; jb < j1; jb += LPP * U) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const bool in = jb + LPP * u < j1;
+          bb[u] = in ? (int32_t)(nb ? rkey[u] >> nb : rkey[u]) : -1;
+          nn[u] = (HAS_T && in) ? (nb ? (int32_t)(rkey[u] & ((1u << nb) - 1u)) + 1 : rlen[u]) : 0;
+          cc[u] = (double)rC[u];
+          ss[u] = (double)rS[u];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          x0[u] = make_double2(0.0, 0.0);
+          u0[u] = 0.0;
+          if (bb[u] < 0) continue;
+          const double2* q0 = reinterpret_cast<const double2*>(pw4 + 4 * (int64_t)bb[u]);
+          x0[u] = q0[0];
+          if (HAS_QU) u0[u] = q0[1].x;
+        }
+        rfetch(jb + LPP * U);
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          if (IQU) {
+            acc[0] += (double)nn[u] * x0[u].x;
+            acc[1] += cc[u] * x0[u].x;
+            acc[2] += ss[u] * x0[u].x;
+            continue;
+          }
+          if (HAS_T) acc[0] += (double)nn[u] * x0[u].x;
+          if (HAS_QU) {
+            acc[1] += cc[u] * x0[u].y - ss[u] * u0[u];
+            acc[2] += ss[u] * x0[u].y + cc[u] * u0[u];
+          }
         }
       }
     }
