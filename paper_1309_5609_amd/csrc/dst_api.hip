@@ -581,7 +581,7 @@ int solve_group(dst_ctx* ctx, const dst_problem* problems, const std::vector<int
   double *prs, *braw, *b, *a, *r, *z, *p, *q, *ka, *md, *m, *part, *part2;
   dst::MultiCtl* ctl;
   DST_TRY(ws(ctx, "mb_ipos", (size_t)std::max<int64_t>(W.R, 1), &ipos));
-  DST_TRY(ws(ctx, "mb_prs", (size_t)4 * dst::kTodBatch * std::max<int64_t>(W.R, 1), &prs));
+  DST_TRY(ws(ctx, "mb_prs", (size_t)dst::kRunRec * std::max<int64_t>(W.R, 1), &prs));
   DST_TRY(ws(ctx, "mb_braw", NV, &braw));
   DST_TRY(ws(ctx, "mb_b", NV, &b));
   DST_TRY(ws(ctx, "mb_a", NV, &a));

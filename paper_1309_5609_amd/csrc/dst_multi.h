@@ -56,18 +56,20 @@ int multi_padded(int R);
 // ipos[run] = position of time-order run `run` in the pixel-order arrays.
 hipError_t launch_run_positions(const Runs& W, uint32_t* ipos, hipStream_t st);
 
-// Timelines of up to kTodBatch realizations handled by one setup pass.
-constexpr int kTodBatch = 4;
+// Timelines of up to kTodBatch realizations handled by one setup pass; their
+// per-run data sums share one record of kRunRec doubles (one 128-byte line).
+constexpr int kTodBatch = 5;
+constexpr int kRunRec = 16;
+static_assert(3 * kTodBatch <= kRunRec, "a pass's run sums must fit one record");
 struct TodSet {
   const void* p[kTodBatch];
 };
 
 // Realizations ri0 .. ri0 + nr - 1 (nr <= kTodBatch, same tod dtype): per-run
 // sums of the weighted data at each run's pixel-order position, one record of
-// kTodBatch x 4 doubles per run (one 128-byte line: realization i at
-// [4 i .. 4 i + 2] = w_T d_T, rotated Q, rotated U), and per-baseline sums
-// w_k d_k over valid samples into braw ([n_b][n_streams][Rp]).  prs holds
-// 4 kTodBatch R doubles.
+// kRunRec doubles per run (one 128-byte line: realization i at [3 i .. 3 i + 2]
+// = w_T d_T, rotated Q, rotated U), and per-baseline sums w_k d_k over valid
+// samples into braw ([n_b][n_streams][Rp]).  prs holds kRunRec R doubles.
 hipError_t launch_multi_tod(const View& vc, int psi_f32, const TodSet& tods, int nr, int tod_f32, const Runs& W,
                             const uint32_t* ipos, const uint8_t* valid, int Rp, int ri0, double* prs, double* braw,
                             hipStream_t st);

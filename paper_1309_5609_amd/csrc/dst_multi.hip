@@ -49,7 +49,8 @@ __global__ void __launch_bounds__(kBlock) k_run_positions(int64_t n_obs, const u
 // run's record (one 128-byte line holding every realization of the pass) at
 // its pixel-order position, so each scattered store writes a whole line; per
 // baseline: w_k sum d_k over valid samples (the data part of b = F^T Z d).
-// When the samples of 64 consecutive runs fit kStageM, the wavefront first
+// When the samples of 64 consecutive runs fit kStageM (half that with FP64
+// timelines), the wavefront first
 // copies them (angles and timelines) into LDS with coalesced loads and the
 // lanes read their runs from there.
 constexpr int kStageM = 256;
@@ -63,8 +64,9 @@ __global__ void __launch_bounds__(kBlock) k_multi_tod(View v, TodSet tods, const
                                                       double* __restrict__ prs, double* __restrict__ braw) {
   constexpr int NROW = (HAS_T ? 1 : 0) + (HAS_QU ? 2 : 0);  // timeline rows per realization
   constexpr int iT = 0, iQ = HAS_T ? 1 : 0, iU = iQ + 1;
-  __shared__ PT s_psi[HAS_QU ? kWaves : 1][HAS_QU ? kStageM : 1];
-  __shared__ TT s_tod[kWaves][NR * NROW][kStageM];
+  constexpr int SM = sizeof(TT) == 4 ? kStageM : kStageM / 2;  // staged samples (LDS per workgroup ~64 KB)
+  __shared__ PT s_psi[HAS_QU ? kWaves : 1][HAS_QU ? SM : 1];
+  __shared__ TT s_tod[kWaves][NR * NROW][SM];
   const PT* psi = static_cast<const PT*>(v.psi);
   const int lane = lane_id();
   const int wave = threadIdx.x >> 6;
@@ -85,7 +87,7 @@ __global__ void __launch_bounds__(kBlock) k_multi_tod(View v, TodSet tods, const
     // samples spanned by these runs (lane 0 always holds one)
     const int last = r1 - 1 - jb < 63 ? (int)(r1 - 1 - jb) : 63;
     const int64_t lo = __shfl(ts, 0, 64), hi = __shfl(ts + n, last, 64);
-    const bool staged = hi - lo <= kStageM;
+    const bool staged = hi - lo <= SM;
     if (staged) {
       for (int e = lane; e < hi - lo; e += 64) {
         const int64_t t = lo + e;
@@ -155,11 +157,20 @@ __global__ void __launch_bounds__(kBlock) k_multi_tod(View v, TodSet tods, const
     if (!has) continue;
     const bool vT = HAS_T && (f & 1), vQ = HAS_QU && (f & 2);
     const int64_t pos = ipos[j];
+    double rec[kRunRec];
+#pragma unroll
+    for (int e = 0; e < kRunRec; ++e) rec[e] = 0.0;
 #pragma unroll
     for (int i = 0; i < NR; ++i) {
-      double2* o = reinterpret_cast<double2*>(prs + 4 * (kTodBatch * pos + i));
-      o[0] = make_double2(vT ? v.w[0] * dT[i] : 0.0, vQ ? dQ[i] : 0.0);
-      o[1] = make_double2(vQ ? dU[i] : 0.0, 0.0);
+      rec[3 * i] = vT ? v.w[0] * dT[i] : 0.0;
+      rec[3 * i + 1] = vQ ? dQ[i] : 0.0;
+      rec[3 * i + 2] = vQ ? dU[i] : 0.0;
+    }
+    double2* o = reinterpret_cast<double2*>(prs + (int64_t)kRunRec * pos);
+#pragma unroll
+    for (int e = 0; e < kRunRec / 2; ++e) o[e] = make_double2(rec[2 * e], rec[2 * e + 1]);
+#pragma unroll
+    for (int i = 0; i < NR; ++i) {
       if (vT) acc[3 * i] += dT[i];
       if (vQ) {
         acc[3 * i + 1] += dq[i];
@@ -197,30 +208,21 @@ __global__ void __launch_bounds__(kBlock) k_multi_pixsum(int64_t n_obs, View vc,
     double acc[3 * NR];
 #pragma unroll
     for (int i = 0; i < 3 * NR; ++i) acc[i] = 0.0;
-    // two records per lane in flight
+    // two records per lane in flight; the first 3 NR doubles of each
+    constexpr int ND = (3 * NR + 1) / 2;
     for (int64_t jb = j0 + lane; jb < j1; jb += 128) {
-      double2 x0[2][NR], x1[2][NR];
+      double2 x[2][ND];
 #pragma unroll
       for (int u = 0; u < 2; ++u) {
         const int64_t j = jb + 64 * u;
+        const double2* xr = reinterpret_cast<const double2*>(prs + (int64_t)kRunRec * j);
 #pragma unroll
-        for (int i = 0; i < NR; ++i) {
-          x0[u][i] = x1[u][i] = make_double2(0.0, 0.0);
-          if (j < j1) {
-            const double2* x = reinterpret_cast<const double2*>(prs + 4 * (kTodBatch * j + i));
-            x0[u][i] = x[0];
-            x1[u][i] = x[1];
-          }
-        }
+        for (int e = 0; e < ND; ++e) x[u][e] = j < j1 ? xr[e] : make_double2(0.0, 0.0);
       }
 #pragma unroll
       for (int u = 0; u < 2; ++u) {
 #pragma unroll
-        for (int i = 0; i < NR; ++i) {
-          acc[3 * i] += x0[u][i].x;
-          acc[3 * i + 1] += x0[u][i].y;
-          acc[3 * i + 2] += x1[u][i].x;
-        }
+        for (int e = 0; e < 3 * NR; ++e) acc[e] += (e & 1) ? x[u][e >> 1].y : x[u][e >> 1].x;
       }
     }
     dev::wave_sum<3 * NR>(acc);
@@ -820,7 +822,9 @@ hipError_t launch_multi_tod(const View& vc, int psi_f32, const TodSet& tods, int
           hipLaunchKernelGGL(kern, dim3(g), dim3(kBlock), 0, st, vc, tods, W.bstart, W.t0, W.tpix, W.tn, ipos, valid,
                              Rp, ri0, prs, braw);
         };
-        if (nr >= 4)
+        if (nr >= 5)
+          launch(k_multi_tod<PT, TT, HT, HQ, 5>);
+        else if (nr == 4)
           launch(k_multi_tod<PT, TT, HT, HQ, 4>);
         else if (nr == 3)
           launch(k_multi_tod<PT, TT, HT, HQ, 3>);
@@ -837,7 +841,9 @@ hipError_t launch_multi_tod(const View& vc, int psi_f32, const TodSet& tods, int
 hipError_t launch_multi_pixsum(int64_t n_obs, const View& vc, const Runs& W, const double* prs, int nr,
                                const double* Minv4, int Rp, int ri0, double* md, hipStream_t st) {
   const dim3 g(grid_for(n_obs, kWaves, 16384));
-  if (nr >= 4)
+  if (nr >= 5)
+    hipLaunchKernelGGL(k_multi_pixsum<5>, g, dim3(kBlock), 0, st, n_obs, vc, W.pstart, prs, Minv4, Rp, ri0, md);
+  else if (nr == 4)
     hipLaunchKernelGGL(k_multi_pixsum<4>, g, dim3(kBlock), 0, st, n_obs, vc, W.pstart, prs, Minv4, Rp, ri0, md);
   else if (nr == 3)
     hipLaunchKernelGGL(k_multi_pixsum<3>, g, dim3(kBlock), 0, st, n_obs, vc, W.pstart, prs, Minv4, Rp, ri0, md);
