@@ -108,13 +108,12 @@ int dst_version(void);
 /* Create a context on HIP device `device`.  *ctx receives the handle.
  * Launch shapes of the run-form iteration kernels may be overridden by the
  * environment at creation: DST_BIN_LPP (lanes per pixel in the binning: 64,
- * 32, 16, or -64 for 64 with a software pipeline over pixels; default 32
- * with FP64 angles, -64 with FP32) and DST_UNBIN_BPW (baselines per
- * wavefront in the rescan: 1, 2, 4 = default, 8).  DST_RUN_SPLIT_BITS = k
- * splits runs of consecutive samples on one pixel at 2^k samples at most
- * (runs are split anyway where a pixel id and a run length would not fit
- * one 32-bit key).
- * They change speed only, not results beyond summation order. */
+ * 32 = default, 16, or -64 for 64 with a software pipeline over pixels) and
+ * DST_UNBIN_BPW (baselines per wavefront in the rescan: 1, 2, 4 = default,
+ * 8).  DST_RUN_SPLIT_BITS = k splits runs of consecutive samples on one
+ * pixel at 2^k samples at most (runs are split anyway where a pixel id and a
+ * run length would not fit one 32-bit key).  They change speed only, not
+ * results beyond summation order. */
 int dst_create(dst_ctx** ctx, int device);
 
 /* Destroy a context and free its workspace (NULL is accepted). */

@@ -39,7 +39,7 @@ struct dst_ctx {
   dst::MultiCtl* mctl_host = nullptr;  // pinned mirror of the batched CG state
   hipStream_t cap = nullptr;  // private stream on which iteration graphs are captured
   int unbin_bpw = 4;          // launch shape of the run rescan (baselines per wavefront)
-  int bin_lpp = 0;            // launch shape of the run binning (lanes per pixel; 0: by precision)
+  int bin_lpp = 0;            // launch shape of the run binning (lanes per pixel; 0: default 32)
   int run_split_bits = 0;     // > 0: longest run 2^bits samples (runs split beyond; results unchanged)
   // launch shapes chosen by the autotuner, per problem shape
   std::map<std::tuple<int64_t, int64_t, int, int>, std::pair<int, int>> tuned;
@@ -268,7 +268,7 @@ struct Plan {
   dst::Runs W;            // run form
   double* m4 = nullptr;   // per-iteration map (zero on invalid pixels)
   double* pw4 = nullptr;  // weighted interleaved baseline vector
-  int lpp = 0;            // launch shapes of the run binning (0: by precision) and rescan
+  int lpp = 0;            // launch shapes of the run binning (0: default) and rescan
   int bpw = 4;
   const int32_t* cid() const { return runs ? W.cid : T.cid; }
 };

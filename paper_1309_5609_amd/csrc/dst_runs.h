@@ -109,8 +109,7 @@ hipError_t runs_build(const View& v, int psi_f32, const void* tod, int tod_f32, 
 hipError_t launch_rhs_runs(const View& vc, const Runs& W, const void* tod, const double* md4, const uint8_t* valid,
                            int32_t* nvalid, double* J, double* b, hipStream_t st);
 // m = M^-1 A^T W F p (pw4 = interleaved w .* p).
-// lpp: lanes per pixel (64, 32 or 16; -64: 64 with the pixel pipeline; 0: 32
-// with FP64 run sums, -64 with FP32).
+// lpp: lanes per pixel (64, 32 or 16; -64: 64 with the pixel pipeline; 0: 32).
 hipError_t launch_bin_runs(const View& vc, const Runs& W, const double* pw4, const double* Minv4,
                            const uint8_t* valid, double* m4, const CgCtl* gate, int lpp, hipStream_t st);
 // q = K p; with ctl the per-baseline CG partials (finished by launch_cg_alpha).

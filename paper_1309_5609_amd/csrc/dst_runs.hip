@@ -710,10 +710,40 @@ __global__ void __launch_bounds__(kBlock) k_rhs_runs(View v, const uint32_t* __r
 
 // ---------------------------------------------------------------- iteration kernels
 
+// Run stream of U runs j, j + stride, ... (key, length, sum of cos 2psi, sum
+// of sin 2psi).  Every load is issued, with index 0 for runs at or past j1, so
+// the loads of all U runs are in flight together with no branches between
+// them; the caller zeroes those runs' terms.  PK: packed keys (index << nb |
+// length - 1), else index keys with the lengths in len_arr.
+template <typename RT, bool LEN, bool ANG, bool PK, int U>
+__device__ __forceinline__ void load_runs(const uint32_t* __restrict__ key_arr, const int32_t* __restrict__ len_arr,
+                                          const RT* __restrict__ c_arr, const RT* __restrict__ s_arr, int64_t j,
+                                          int64_t stride, int64_t j1, uint32_t (&key)[U], int32_t (&len)[U],
+                                          RT (&C)[U], RT (&S)[U]) {
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int64_t jj = j + stride * u < j1 ? j + stride * u : 0;
+    key[u] = key_arr[jj];
+    len[u] = (LEN && !PK) ? len_arr[jj] : 0;
+    C[u] = ANG ? c_arr[jj] : (RT)0;
+    S[u] = ANG ? s_arr[jj] : (RT)0;
+  }
+}
+
+// Index, length and angle sums of a loaded run; zero terms past j1.
+template <typename RT, bool PK>
+__device__ __forceinline__ void decode_run(uint32_t key, int32_t len, RT c, RT s, bool in, int nb, int32_t& idx,
+                                           double& n, double& C, double& S) {
+  idx = (int32_t)(PK ? key >> nb : key);
+  n = in ? (double)(PK ? (int32_t)(key & ((1u << nb) - 1u)) + 1 : len) : 0.0;
+  C = in ? (double)c : 0.0;
+  S = in ? (double)s : 0.0;
+}
+
 // m = M^-1 A^T W F p per compact pixel from its pixel-order runs.  LPP lanes
 // work on one pixel (64 / LPP pixels per wavefront, each with its own chain of
 // dependent loads in flight); pw4[b] = (w_T p_T, w_q p_q, w_u p_u, 0).
-template <typename RT, bool HAS_T, bool HAS_QU, bool IQU, int LPP>
+template <typename RT, bool HAS_T, bool HAS_QU, bool IQU, int LPP, bool PK>
 __global__ void __launch_bounds__(kBlock) k_bin_runs(int64_t n_obs, const int64_t* __restrict__ pstart,
                                                      const uint32_t* __restrict__ pb, const int32_t* __restrict__ pn,
                                                      int nb,
@@ -738,35 +768,34 @@ __global__ void __launch_bounds__(kBlock) k_bin_runs(int64_t n_obs, const int64_
     }
     double acc[3] = {0.0, 0.0, 0.0};
     for (int64_t jb = j0 + sub; jb < j1; jb += LPP * U) {
-      int32_t bb[U], nn[U];
-      double cc[U], ss[U];
+      uint32_t key[U];
+      int32_t len[U];
+      RT cr[U], sr[U];
+      // packed keys (PK): baseline << nb | (length - 1); else baseline, lengths in pn
+      load_runs<RT, HAS_T, HAS_QU || IQU, PK, U>(pb, pn, pc, ps, jb, LPP, j1, key, len, cr, sr);
+      double2 x0[U];
+      double u0[U], nn[U], cc[U], ss[U];
 #pragma unroll
       for (int u = 0; u < U; ++u) {
-        const int64_t j = jb + LPP * u;
-        const bool in = j < j1;
-        // packed keys (nb > 0): baseline << nb | (length - 1); else baseline, lengths in pn
-        const uint32_t key = in ? pb[j] : 0u;
-        bb[u] = in ? (int32_t)(nb ? key >> nb : key) : -1;
-        nn[u] = (HAS_T && in) ? (nb ? (int32_t)(key & ((1u << nb) - 1u)) + 1 : pn[j]) : 0;
-        cc[u] = ((HAS_QU || IQU) && in) ? (double)pc[j] : 0.0;
-        ss[u] = ((HAS_QU || IQU) && in) ? (double)ps[j] : 0.0;
+        int32_t bb;
+        decode_run<RT, PK>(key[u], len[u], cr[u], sr[u], jb + LPP * u < j1, nb, bb, nn[u], cc[u], ss[u]);
+        // runs past j1 read baseline pw4 of run 0 (a valid index) and add nothing
+        const double2* q0 = reinterpret_cast<const double2*>(pw4 + 4 * (int64_t)bb);
+        x0[u] = q0[0];
+        u0[u] = HAS_QU ? q0[1].x : 0.0;
       }
 #pragma unroll
       for (int u = 0; u < U; ++u) {
-        if (bb[u] < 0) continue;
-        const double2* q0 = reinterpret_cast<const double2*>(pw4 + 4 * (int64_t)bb[u]);
-        const double2 x0 = q0[0];
         if (IQU) {
-          acc[0] += (double)nn[u] * x0.x;
-          acc[1] += cc[u] * x0.x;
-          acc[2] += ss[u] * x0.x;
+          acc[0] += nn[u] * x0[u].x;
+          acc[1] += cc[u] * x0[u].x;
+          acc[2] += ss[u] * x0[u].x;
           continue;
         }
-        if (HAS_T) acc[0] += (double)nn[u] * x0.x;
+        if (HAS_T) acc[0] += nn[u] * x0[u].x;
         if (HAS_QU) {
-          const double u0 = q0[1].x;
-          acc[1] += cc[u] * x0.y - ss[u] * u0;
-          acc[2] += ss[u] * x0.y + cc[u] * u0;
+          acc[1] += cc[u] * x0[u].y - ss[u] * u0[u];
+          acc[2] += ss[u] * x0[u].y + cc[u] * u0[u];
         }
       }
     }
@@ -796,8 +825,9 @@ __global__ void __launch_bounds__(kBlock) k_bin_runs(int64_t n_obs, const int64_
 // The same binning with a three-stage software pipeline over the
 // wavefront's pixels (launch shape -LPP): while the baseline values of one
 // pixel's first LPP * U runs are gathered, the run stream of its next pixel
-// and the run range of the one after are loaded.  Faster with FP32 run sums
-// (more registers, so fewer wavefronts, which the FP64 form does not recoup).
+// and the run range of the one after are loaded.  More registers, so fewer
+// wavefronts: measured slower than the plain kernel at 32 lanes per pixel in
+// both precisions, kept as a launch shape for the autotuner.
 template <typename RT, bool HAS_T, bool HAS_QU, bool IQU, int LPP>
 __global__ void __launch_bounds__(kBlock) k_bin_runs_pipe(int64_t n_obs, const int64_t* __restrict__ pstart,
                                                           const uint32_t* __restrict__ pb,
@@ -1322,8 +1352,7 @@ hipError_t launch_rhs_runs(const View& vc, const Runs& W, const void* tod, const
 
 hipError_t launch_bin_runs(const View& vc, const Runs& W, const double* pw4, const double* Minv4,
                            const uint8_t* valid, double* m4, const CgCtl* gate, int lpp, hipStream_t st) {
-  // 0: the default (32 with FP64 run sums, the pipelined 64 with FP32)
-  if (lpp == 0) lpp = W.f32 ? -64 : 32;
+  if (lpp == 0) lpp = 32;  // the default
   if (lpp != 64 && lpp != 32 && lpp != 16 && lpp != -64) lpp = 32;
   const bool pipe = lpp < 0;
   if (pipe) lpp = -lpp;
@@ -1338,14 +1367,19 @@ hipError_t launch_bin_runs(const View& vc, const Runs& W, const double* pw4, con
                            W.nb ? W.pkey : reinterpret_cast<const uint32_t*>(W.pb), W.pn, W.nb,
                            static_cast<const RT*>(W.pc), static_cast<const RT*>(W.ps), pw4, Minv4, valid, m4, gate);
       };
-      if (pipe)
+      if (pipe) {
         launch(k_bin_runs_pipe<RT, HT, HQ, HI, 64>);
-      else if (lpp == 16)
-        launch(k_bin_runs<RT, HT, HQ, HI, 16>);
-      else if (lpp == 32)
-        launch(k_bin_runs<RT, HT, HQ, HI, 32>);
-      else
-        launch(k_bin_runs<RT, HT, HQ, HI, 64>);
+        return;
+      }
+      by_bool(W.nb != 0, [&](auto K) {
+        constexpr bool PK = decltype(K)::value;
+        if (lpp == 16)
+          launch(k_bin_runs<RT, HT, HQ, HI, 16, PK>);
+        else if (lpp == 32)
+          launch(k_bin_runs<RT, HT, HQ, HI, 32, PK>);
+        else
+          launch(k_bin_runs<RT, HT, HQ, HI, 64, PK>);
+      });
     });
   });
   return hipGetLastError();
