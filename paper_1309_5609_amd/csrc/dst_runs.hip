@@ -1001,7 +1001,7 @@ __global__ void __launch_bounds__(kBlock) k_bin_runs_pipe(int64_t n_obs, const i
 // Consecutive workgroups run on one XCD and take consecutive wavefront tasks.
 // m is zero on invalid blocks.  With CG: per-baseline partials of p.q and of
 // the T-projection sums.
-template <typename RT, bool HAS_T, bool HAS_QU, bool IQU, bool CG, int BPW>
+template <typename RT, bool HAS_T, bool HAS_QU, bool IQU, bool CG, int BPW, bool PK>
 __global__ void __launch_bounds__(kBlock) k_unbin_runs(View v, const uint32_t* __restrict__ bstart,
                                                        const uint32_t* __restrict__ border,
                                                        const uint32_t* __restrict__ rpix,
@@ -1037,7 +1037,7 @@ __global__ void __launch_bounds__(kBlock) k_unbin_runs(View v, const uint32_t* _
         const int64_t r = rb + SEG * u;
         const bool in = r < r1;
         key[u] = in ? rpix[r] : 0u;
-        len[u] = (HAS_T && !nb && in) ? rn[r] : 0;
+        len[u] = (HAS_T && !PK && in) ? rn[r] : 0;
         C[u] = ((HAS_QU || IQU) && in) ? rc[r] : (RT)0;
         S[u] = ((HAS_QU || IQU) && in) ? rs[r] : (RT)0;
       }
@@ -1048,10 +1048,10 @@ __global__ void __launch_bounds__(kBlock) k_unbin_runs(View v, const uint32_t* _
       double Cd[U], Sd[U];
 #pragma unroll
       for (int u = 0; u < U; ++u) {
-        // packed keys (nb > 0): compact pixel << nb | (length - 1); else pixel, lengths in rn
+        // packed keys (PK): compact pixel << nb | (length - 1); else pixel, lengths in rn
         const bool in = rb + SEG * u < r1;
-        cc_[u] = in ? (int32_t)(nb ? key[u] >> nb : key[u]) : -1;
-        nn[u] = (HAS_T && in) ? (nb ? (int32_t)(key[u] & ((1u << nb) - 1u)) + 1 : len[u]) : 0;
+        cc_[u] = in ? (int32_t)(PK ? key[u] >> nb : key[u]) : -1;
+        nn[u] = (HAS_T && in) ? (PK ? (int32_t)(key[u] & ((1u << nb) - 1u)) + 1 : len[u]) : 0;
         Cd[u] = (double)C[u];
         Sd[u] = (double)S[u];
       }
@@ -1402,14 +1402,17 @@ hipError_t launch_unbin_runs(const View& vc, const Runs& W, const double* m4, co
                              static_cast<const RT*>(W.tc), static_cast<const RT*>(W.ts), m4, nvalid, p, q, ctl,
                              partials);
         };
-        if (bpw == 8)
-          launch(k_unbin_runs<RT, HT, HQ, HI, C, 8>);
-        else if (bpw == 4)
-          launch(k_unbin_runs<RT, HT, HQ, HI, C, 4>);
-        else if (bpw == 2)
-          launch(k_unbin_runs<RT, HT, HQ, HI, C, 2>);
-        else
-          launch(k_unbin_runs<RT, HT, HQ, HI, C, 1>);
+        by_bool(W.nb != 0, [&](auto K) {
+          constexpr bool PK = decltype(K)::value;
+          if (bpw == 8)
+            launch(k_unbin_runs<RT, HT, HQ, HI, C, 8, PK>);
+          else if (bpw == 4)
+            launch(k_unbin_runs<RT, HT, HQ, HI, C, 4, PK>);
+          else if (bpw == 2)
+            launch(k_unbin_runs<RT, HT, HQ, HI, C, 2, PK>);
+          else
+            launch(k_unbin_runs<RT, HT, HQ, HI, C, 1, PK>);
+        });
       });
     });
   });
