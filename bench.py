@@ -356,9 +356,10 @@ def main() -> int:
     dom = max(("bin", "unbin"), key=lambda k: k_ms[k])
     dom_bytes = algo[f"{dom}_runs"]
     rt = "float" if args.workload == 2 else "double"
-    # the default launch shapes: 32 lanes per pixel in the binning, 4 baselines per wavefront in the rescan
-    dom_kernel = {"bin": f"k_bin_runs<{rt}, true, true, false, 32>",
-                  "unbin": f"k_unbin_runs<{rt}, true, true, false, true, 4>"}[dom]
+    # the default launch shapes: 32 lanes per pixel in the binning, 4 baselines per wavefront in the rescan,
+    # packed 32-bit run keys
+    dom_kernel = {"bin": f"k_bin_runs<{rt}, true, true, false, 32, true>",
+                  "unbin": f"k_unbin_runs<{rt}, true, true, false, true, 4, true>"}[dom]
     traffic = measured_traffic(dom_kernel)
     achieved = dom_bytes / (k_ms[dom] * 1e-3) / 1e9
     iter_ms = float(np.mean([r["t_iter_ms"] for r in plain]))
