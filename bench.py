@@ -207,7 +207,7 @@ def batched_form(ctx, p, dp, n_real: int, tol: float, steps: int, warmup: int, p
     return out
 
 
-# Uneven survey batch (config 4): 8 polarimeter channels of 3 .. 30 days plus a
+# Uneven batch of channels: 8 polarimeter channels of 3 .. 30 days plus a
 # 12-month intensity-only stream at N_side 512, FP32 timelines and angles.
 # Per channel: days, baseline length, f_k (Hz), alpha, spin-axis phase.
 UNEVEN_CHANNELS = [(3, 1500, 0.010, 1.0), (5, 2000, 0.015, 1.15), (7, 2500, 0.022, 1.3), (10, 3000, 0.033, 1.45),
@@ -216,7 +216,7 @@ UNEVEN_T_STREAM = (365, 6000, 0.010, 1.0)
 
 
 def uneven_form(ctx, tol: float, steps: int, warmup: int) -> dict:
-    """Config 4, generated on the GPU by the library (pointing expansion, sky scan, noise) and solved by
+    """The uneven channel batch, generated on the GPU by the library (pointing expansion, sky scan, noise) and solved by
     dst_solve_batched (channels share no pointing, so they are solved one after another, autotuned)."""
     import numpy as np
     import torch
@@ -288,7 +288,7 @@ def main() -> int:
     ap.add_argument("--tol", type=float, default=1e-10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--realizations", type=int, default=32, help="batch size of the Monte Carlo form (0: skip)")
-    ap.add_argument("--no-uneven", action="store_true", help="skip the uneven survey batch (N_side 512)")
+    ap.add_argument("--no-uneven", action="store_true", help="skip the uneven channel batch (N_side 512)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a 1 GiB device copy (reference kernel for HBM counters)")
     args = ap.parse_args()
