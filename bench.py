@@ -66,6 +66,12 @@ def log(msg: str) -> None:
     print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
 
 
+def scalars(out: dict) -> dict:
+    """A solve's info without its output tensors, so that K solves in a row do not hold K sets of maps
+    (a caller that kept them all would make every solve allocate new device memory)."""
+    return {k: v for k, v in out.items() if not hasattr(v, "data_ptr")}
+
+
 def workload_name(w: int, fk: float) -> str:
     if w == 0:
         return (f"6-hour single-channel destripe: 1,080,000 samples at 50 Hz, HEALPix N_side 64, "
@@ -333,7 +339,7 @@ def main() -> int:
     t0 = time.perf_counter()
     plain = []
     for i in range(args.steps):
-        plain.append(dst.dst_solve(ctx, dp, tol=args.tol, max_iter=2000))
+        plain.append(scalars(dst.dst_solve(ctx, dp, tol=args.tol, max_iter=2000)))
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     iters = sum(r["iterations"] for r in plain)
@@ -343,7 +349,9 @@ def main() -> int:
     # (DST_SOLVE_PROFILE: kernels launched one by one, so this pass is slower): kernel durations for the roofline
     torch.cuda.synchronize()
     tp = time.perf_counter()
-    runs = [dst.dst_solve(ctx, dp, tol=args.tol, max_iter=2000, flags=dst.DST_SOLVE_PROFILE) for _ in range(args.steps)]
+    runs = [scalars(dst.dst_solve(ctx, dp, tol=args.tol, max_iter=2000, flags=dst.DST_SOLVE_PROFILE))
+            for _ in range(args.steps - 1)]
+    runs.append(dst.dst_solve(ctx, dp, tol=args.tol, max_iter=2000, flags=dst.DST_SOLVE_PROFILE))
     torch.cuda.synchronize()
     prof_wall = time.perf_counter() - tp
     r0 = runs[-1]
@@ -373,7 +381,7 @@ def main() -> int:
         dst.dst_solve(ctx, dp32, tol=args.tol, max_iter=2000)
         torch.cuda.synchronize()
         tm = time.perf_counter()
-        mruns = [dst.dst_solve(ctx, dp32, tol=args.tol, max_iter=2000) for _ in range(args.steps)]
+        mruns = [scalars(dst.dst_solve(ctx, dp32, tol=args.tol, max_iter=2000)) for _ in range(args.steps)]
         torch.cuda.synchronize()
         mwall = time.perf_counter() - tm
         mit = sum(r["iterations"] for r in mruns)

@@ -645,20 +645,21 @@ int solve_group(dst_ctx* ctx, const dst_problem* problems, const std::vector<int
     if (timed) HIP_TRY(hipEventRecord(e[3], s));
     return DST_OK;
   };
+  // one iteration captured once, replayed check_every times per check
   GraphGuard gg;
   if (use_graph && h.running > 0)
-    DST_TRY(capture_graph(ctx, check_every, [&](hipStream_t s) { return iteration(s, false); }, &gg.exec));
+    DST_TRY(capture_graph(ctx, 1, [&](hipStream_t s) { return iteration(s, false); }, &gg.exec));
   HIP_TRY(hipEventRecord(ev[2], st));
   int launched = 0;
   while (h.running > 0 && launched < opts.max_iter) {
-    if (gg.exec) {
-      HIP_TRY(hipGraphLaunch(gg.exec, st));
-      launched += check_every;
-    } else {
-      const int k = std::min(check_every, opts.max_iter - launched);
-      for (int i = 0; i < k; ++i) DST_TRY(iteration(st, profile));
-      launched += k;
+    const int k = std::min(check_every, opts.max_iter - launched);
+    for (int i = 0; i < k; ++i) {
+      if (gg.exec)
+        HIP_TRY(hipGraphLaunch(gg.exec, st));
+      else
+        DST_TRY(iteration(st, profile));
     }
+    launched += k;
     HIP_TRY(hipMemcpyAsync(&h, ctl, sizeof(dst::MultiCtl), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
   }
@@ -1174,23 +1175,23 @@ int dst_solve(dst_ctx* ctx, const dst_problem* prob, const dst_solve_opts* opts_
     DST_TRY(gmres_loop(ctx, P, v, b, a, r, q, opts, &fin, st));
     HIP_TRY(hipEventRecord(ev[3], st));
   } else {
-  // batches of check_every iterations, replayed from one captured graph
-  // unless profiling or asked not to
+  // batches of check_every iterations between convergence checks; one
+  // iteration is captured once and replayed, unless profiling or asked not to
   CgCtl& h = *ctx->ctl_host;
   GraphGuard gg;
   if (!(opts.flags & (DST_SOLVE_NO_GRAPH | DST_SOLVE_PROFILE)) && h.done == dst::DONE_RUNNING)
-    DST_TRY(capture_graph(ctx, check_every, [&](hipStream_t s) { return one_iteration(s, false); }, &gg.exec));
+    DST_TRY(capture_graph(ctx, 1, [&](hipStream_t s) { return one_iteration(s, false); }, &gg.exec));
   HIP_TRY(hipEventRecord(ev[2], st));
   int launched = 0;
   while (h.done == dst::DONE_RUNNING && launched < opts.max_iter) {
-    if (gg.exec) {
-      HIP_TRY(hipGraphLaunch(gg.exec, st));
-      launched += check_every;
-    } else {
-      const int k = std::min(check_every, opts.max_iter - launched);
-      for (int i = 0; i < k; ++i) DST_TRY(one_iteration(st, profile));
-      launched += k;
+    const int k = std::min(check_every, opts.max_iter - launched);
+    for (int i = 0; i < k; ++i) {
+      if (gg.exec)
+        HIP_TRY(hipGraphLaunch(gg.exec, st));
+      else
+        DST_TRY(one_iteration(st, profile));
     }
+    launched += k;
     HIP_TRY(hipMemcpyAsync(ctx->ctl_host, ctl, sizeof(CgCtl), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
   }
