@@ -322,8 +322,7 @@ int build_runs_plan(dst_ctx* ctx, const dst_problem* prob, Plan& P, const void* 
   // FP32 angles (mixed precision): run sums of cos 2psi, sin 2psi kept in FP32
   W.f32 = S.psi_f32 && (v.rowQ >= 0 || v.iqu);
   const size_t rsz = W.f32 ? sizeof(float) : sizeof(double);
-  DST_TRY(ws_get(ctx, "r_tc", R * rsz, &W.tc));
-  DST_TRY(ws_get(ctx, "r_ts", R * rsz, &W.ts));
+  DST_TRY(ws_get(ctx, "r_tcs", 2 * R * rsz, &W.tcs));
   // intensity-only problems: one raw sum and a 16-byte record per run
   const bool t_only = v.rowT >= 0 && v.rowQ < 0 && !v.iqu;
   DST_TRY(ws(ctx, "r_raw", (t_only ? 1 : 3) * (size_t)R, &W.raw));
@@ -337,8 +336,7 @@ int build_runs_plan(dst_ctx* ctx, const dst_problem* prob, Plan& P, const void* 
   DST_TRY(ws(ctx, "r_tkey", R, &W.tkey));
   DST_TRY(ws(ctx, "r_pkey", R, &W.pkey));
   DST_TRY(ws(ctx, "r_pn", R, &W.pn));
-  DST_TRY(ws_get(ctx, "r_pc", R * rsz, &W.pc));
-  DST_TRY(ws_get(ctx, "r_ps", R * rsz, &W.ps));
+  DST_TRY(ws_get(ctx, "r_pcs", 2 * R * rsz, &W.pcs));
   // per-pixel arrays sized for every pixel (the observed count is known later)
   DST_TRY(ws(ctx, "hits", v.n_pix, &S.hits));
   DST_TRY(ws(ctx, "Minv4", (v.iqu ? 8 : 4) * (size_t)v.n_pix, &S.Minv4));  // IQU: 6 entries of a 3x3 inverse

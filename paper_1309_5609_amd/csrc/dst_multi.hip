@@ -252,8 +252,8 @@ __device__ __forceinline__ bool lane_active(int r, int R, const MultiCtl* ctl) {
 template <typename RT, bool HAS_T, bool HAS_QU>
 __global__ void __launch_bounds__(kBlock) k_multi_bin(View vc, int R, int Rp, const int64_t* __restrict__ pstart,
                                                       const int32_t* __restrict__ pb, const int32_t* __restrict__ pn,
-                                                      const RT* __restrict__ pc, const RT* __restrict__ ps,
-                                                      const double* __restrict__ p, const double* __restrict__ Minv4,
+                                                      const RT* __restrict__ pcs, const double* __restrict__ p,
+                                                      const double* __restrict__ Minv4,
                                                       double* __restrict__ m, const MultiCtl* __restrict__ ctl) {
   if (ctl && ctl->running == 0) return;
   const int lane = lane_id();
@@ -277,8 +277,8 @@ __global__ void __launch_bounds__(kBlock) k_multi_bin(View vc, int R, int Rp, co
       const bool inw = jl < j1;
       const int w_b = inw ? pb[jl] : -1;
       const int w_n = (HAS_T && inw) ? pn[jl] : 0;
-      const RT w_c = (HAS_QU && inw) ? pc[jl] : (RT)0;
-      const RT w_s = (HAS_QU && inw) ? ps[jl] : (RT)0;
+      const CS2<RT> w_cs = (HAS_QU && inw) ? reinterpret_cast<const CS2<RT>*>(pcs)[jl] : make_cs<RT>(0.0, 0.0);
+      const RT w_c = w_cs.x, w_s = w_cs.y;
       const int nwin = j1 - wb < 64 ? (int)(j1 - wb) : 64;
 #pragma unroll 2
       for (int k0 = 0; k0 < nwin; k0 += slots) {  // uniform: every lane takes part in the shuffles
@@ -323,8 +323,8 @@ template <typename RT, bool HAS_T, bool HAS_QU, int MODE>
 __global__ void __launch_bounds__(kBlock) k_multi_unbin(View vc, int R, int Rp, const uint32_t* __restrict__ bstart,
                                                         const uint32_t* __restrict__ border,
                                                         const int32_t* __restrict__ tpix,
-                                                        const int32_t* __restrict__ tn, const RT* __restrict__ tc,
-                                                        const RT* __restrict__ ts, const double* __restrict__ m,
+                                                        const int32_t* __restrict__ tn, const RT* __restrict__ tcs,
+                                                        const double* __restrict__ m,
                                                         const int32_t* __restrict__ nvalid,
                                                         const double* __restrict__ p, const double* __restrict__ braw,
                                                         double* __restrict__ q, MultiCtl* __restrict__ ctl,
@@ -356,8 +356,8 @@ __global__ void __launch_bounds__(kBlock) k_multi_unbin(View vc, int R, int Rp, 
       const bool inw = jl < r1;
       const int w_c = inw ? tpix[jl] : -1;
       const int w_n = (HAS_T && inw) ? tn[jl] : 0;
-      const RT w_C = (HAS_QU && inw) ? tc[jl] : (RT)0;
-      const RT w_S = (HAS_QU && inw) ? ts[jl] : (RT)0;
+      const CS2<RT> w_cs = (HAS_QU && inw) ? reinterpret_cast<const CS2<RT>*>(tcs)[jl] : make_cs<RT>(0.0, 0.0);
+      const RT w_C = w_cs.x, w_S = w_cs.y;
       const int nwin = r1 - wb < 64 ? (int)(r1 - wb) : 64;
 #pragma unroll 2
       for (int k0 = 0; k0 < nwin; k0 += slots) {  // uniform: every lane takes part in the shuffles
@@ -861,8 +861,8 @@ hipError_t launch_multi_bin(const View& vc, const Runs& W, const Multi& mu, cons
     using RT = typename decltype(rt)::type;
     by_streams(vc, [&](auto T, auto Q) {
       hipLaunchKernelGGL((k_multi_bin<RT, decltype(T)::value, decltype(Q)::value>), dim3(g), dim3(kBlock), 0, st,
-                         vc, mu.R, mu.Rp, W.pstart, W.pb, W.pn, static_cast<const RT*>(W.pc),
-                         static_cast<const RT*>(W.ps), p, Minv4, m, ctl);
+                         vc, mu.R, mu.Rp, W.pstart, W.pb, W.pn, static_cast<const RT*>(W.pcs), p,
+                         Minv4, m, ctl);
     });
   });
   return hipGetLastError();
@@ -884,8 +884,7 @@ hipError_t launch_multi_unbin(const View& vc, const Runs& W, const Multi& mu, in
       constexpr bool HT = decltype(T)::value, HQ = decltype(Q)::value;
       auto launch = [&](auto kern) {
         hipLaunchKernelGGL(kern, dim3(g), dim3(kBlock), 0, st, vc, mu.R, mu.Rp, W.bstart, W.border, W.tpix, W.tn,
-                           static_cast<const RT*>(W.tc), static_cast<const RT*>(W.ts), m, nvalid, p, braw, q, ctl,
-                           partials);
+                           static_cast<const RT*>(W.tcs), m, nvalid, p, braw, q, ctl, partials);
       };
       if (mode == UNBIN_CG)
         launch(k_multi_unbin<RT, HT, HQ, UNBIN_CG>);

@@ -4,10 +4,24 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <type_traits>
 
 #include "dst_internal.h"
 
 namespace dst {
+
+// Per-run pair (sum of cos 2psi, sum of sin 2psi) in the run sums' precision:
+// one 16-byte (FP64) or 8-byte (FP32) load per run in the iterations.
+template <typename RT>
+using CS2 = typename std::conditional<std::is_same<RT, double>::value, double2, float2>::type;
+
+template <typename RT>
+__host__ __device__ inline CS2<RT> make_cs(double c, double s) {
+  CS2<RT> v;
+  v.x = (RT)c;
+  v.y = (RT)s;
+  return v;
+}
 
 // Per-run record read by the per-pixel setup (one aligned 64-byte access):
 // length, baseline, sums over the run of cos 2psi, sin 2psi, cos^2 2psi,
@@ -39,8 +53,8 @@ static_assert(sizeof(RunRecordT) == 16, "intensity run record must be 16 bytes")
 //
 // Buffers belong to the caller's workspace.  Sizes: tcount, toff
 // [run_tiles(n_t)];
-// bstart [n_b + 1]; t0, tpix, tn, pb, pn [R] and tc, ts, pc, ps [R] (FP32 when
-// f32, else FP64);
+// bstart [n_b + 1]; t0, tpix, tn, pb, pn [R] and the pairs tcs, pcs [2 R] (FP32
+// when f32, else FP64);
 // raw [3 R]; rec [R]; keys, vals 2 x [R]; seg [2 n_pix] (zero-filled before
 // runs_build); pk, pv 2 x [n_pix]; cid [n_pix] (filled with -1 before
 // runs_build); ccount, pstart [n_pix + 1]; bkey, bord 2 x [n_b].
@@ -53,11 +67,10 @@ struct Runs {
   uint32_t* t0 = nullptr;
   unsigned long long* n_out = nullptr;  // samples in no run (masked or out of range); zero-filled before runs_count
   uint32_t* bstart = nullptr;
-  bool f32 = false;  // run sums of cos 2psi, sin 2psi stored in FP32 (else FP64)
+  bool f32 = false;  // run sums of cos 2psi, sin 2psi (tcs, pcs) stored in FP32 (else FP64)
   int32_t* tpix = nullptr;
   int32_t* tn = nullptr;
-  void* tc = nullptr;
-  void* ts = nullptr;
+  void* tcs = nullptr;  // [2 R] CS2 pairs per run, time order
   double* raw = nullptr;       // [3 R] sums of d_T, d_q, d_u per run (time order); [R] (d_T) for T only
   RunRecord* rec = nullptr;    // [R] per-run records (time order); RunRecordT for T only
   uint32_t* keys[2] = {nullptr, nullptr};
@@ -73,8 +86,7 @@ struct Runs {
   int64_t n_obs = 0;
   int32_t* pb = nullptr;
   int32_t* pn = nullptr;
-  void* pc = nullptr;
-  void* ps = nullptr;
+  void* pcs = nullptr;  // [2 R] CS2 pairs per run, pixel order
   int64_t* pstart = nullptr;
   // Iteration keys [R] (time and pixel order): index << nb | (length - 1),
   // used when nb > 0 (index and length fit 32 bits together).

@@ -229,8 +229,8 @@ __global__ void __launch_bounds__(kBlock) k_run_build(View v, const TT* __restri
                                                       const uint32_t* __restrict__ t0,
                                                       const unsigned long long* __restrict__ n_out, int64_t R,
                                                       int32_t* __restrict__ rpix, int32_t* __restrict__ rn,
-                                                      RT* __restrict__ rc, RT* __restrict__ rs,
-                                                      double* __restrict__ raw, RunRecord* __restrict__ rec) {
+                                                      RT* __restrict__ rcs, double* __restrict__ raw,
+                                                      RunRecord* __restrict__ rec) {
   constexpr bool SA = HAS_QU || IQU;                 // angles used
   constexpr bool TONLY = HAS_T && !HAS_QU && !IQU;   // intensity only: 16-byte records
   constexpr bool ST = TOD && (HAS_T || IQU);         // T (or radiometer) timeline used
@@ -335,10 +335,7 @@ __global__ void __launch_bounds__(kBlock) k_run_build(View v, const TT* __restri
     if (!has) continue;
     rpix[r] = v.pix[ts];
     rn[r] = n;
-    if (SA) {
-      rc[r] = (RT)C;
-      rs[r] = (RT)S;
-    }
+    if (SA) reinterpret_cast<CS2<RT>*>(rcs)[r] = make_cs<RT>(C, S);
     if (TONLY) {
       if (TOD) raw[r] = dT;
       RunRecordT x;
@@ -432,7 +429,7 @@ template <typename RT, bool HAS_T, bool HAS_QU, bool IQU, bool TOD>
 __global__ void __launch_bounds__(kBlock) k_pixels_from_runs(
     View v, int64_t n_obs, const uint32_t* __restrict__ order, const int64_t* __restrict__ seg,
     const uint32_t* __restrict__ rperm, const RunRecord* __restrict__ rec, double rcond_cut,
-    int32_t* __restrict__ pb, int32_t* __restrict__ pn, RT* __restrict__ pc, RT* __restrict__ ps,
+    int32_t* __restrict__ pb, int32_t* __restrict__ pn, RT* __restrict__ pcs,
     const int64_t* __restrict__ pstart, int32_t* __restrict__ hits, double* __restrict__ Minv4,
     uint8_t* __restrict__ valid, double* __restrict__ m4_zero, double* __restrict__ sd4, double* __restrict__ md4,
     unsigned long long* __restrict__ counts) {
@@ -477,8 +474,7 @@ __global__ void __launch_bounds__(kBlock) k_pixels_from_runs(
         pn[d] = x.n;
         acc[0] += (double)x.n;
         if (HAS_QU || IQU) {
-          pc[d] = (RT)x.C;
-          ps[d] = (RT)x.S;
+          reinterpret_cast<CS2<RT>*>(pcs)[d] = make_cs<RT>(x.C, x.S);
           acc[1] += x.cc;
           acc[2] += x.cs;
         }
@@ -632,7 +628,7 @@ __global__ void __launch_bounds__(kBlock) k_baseline_keys(int64_t n_b, int64_t n
 template <typename RT, bool HAS_T, bool HAS_QU, bool IQU, bool TOD>
 __global__ void __launch_bounds__(kBlock) k_rhs_runs(View v, const uint32_t* __restrict__ bstart,
                                                      const int32_t* __restrict__ rpix, const int32_t* __restrict__ rn,
-                                                     const RT* __restrict__ rc, const RT* __restrict__ rs,
+                                                     const RT* __restrict__ rcs,
                                                      const double* __restrict__ raw, const double* __restrict__ md4,
                                                      const uint8_t* __restrict__ valid, int32_t* __restrict__ nvalid,
                                                      double* __restrict__ J, double* __restrict__ b_out) {
@@ -670,7 +666,8 @@ __global__ void __launch_bounds__(kBlock) k_rhs_runs(View v, const uint32_t* __r
       if (IQU && (f[u] & 1)) {
         acc[3] += n;
         if (TOD) {
-          const double C = (double)rc[r], S = (double)rs[r];
+          const CS2<RT> cs = reinterpret_cast<const CS2<RT>*>(rcs)[r];
+          const double C = (double)cs.x, S = (double)cs.y;
           acc[0] += m[0] - (n * m01[u].x + C * m01[u].y + S * m2[u].x);
         }
       } else if (HAS_T && (f[u] & 1)) {
@@ -680,7 +677,8 @@ __global__ void __launch_bounds__(kBlock) k_rhs_runs(View v, const uint32_t* __r
       if (HAS_QU && (f[u] & 2)) {
         acc[4] += n;
         if (TOD) {
-          const double C = (double)rc[r], S = (double)rs[r];
+          const CS2<RT> cs = reinterpret_cast<const CS2<RT>*>(rcs)[r];
+          const double C = (double)cs.x, S = (double)cs.y;
           const double mQ = m01[u].y, mU = m2[u].x;
           acc[1] += m[1] - (C * mQ + S * mU);
           acc[2] += m[2] - (C * mU - S * mQ);
@@ -717,7 +715,7 @@ __global__ void __launch_bounds__(kBlock) k_rhs_runs(View v, const uint32_t* __r
 // length - 1), else index keys with the lengths in len_arr.
 template <typename RT, bool LEN, bool ANG, bool PK, int U>
 __device__ __forceinline__ void load_runs(const uint32_t* __restrict__ key_arr, const int32_t* __restrict__ len_arr,
-                                          const RT* __restrict__ c_arr, const RT* __restrict__ s_arr, int64_t j,
+                                          const RT* __restrict__ cs_arr, int64_t j,
                                           int64_t stride, int64_t j1, uint32_t (&key)[U], int32_t (&len)[U],
                                           RT (&C)[U], RT (&S)[U]) {
 #pragma unroll
@@ -725,8 +723,9 @@ __device__ __forceinline__ void load_runs(const uint32_t* __restrict__ key_arr, 
     const int64_t jj = j + stride * u < j1 ? j + stride * u : 0;
     key[u] = key_arr[jj];
     len[u] = (LEN && !PK) ? len_arr[jj] : 0;
-    C[u] = ANG ? c_arr[jj] : (RT)0;
-    S[u] = ANG ? s_arr[jj] : (RT)0;
+    const CS2<RT> cs = ANG ? reinterpret_cast<const CS2<RT>*>(cs_arr)[jj] : make_cs<RT>(0.0, 0.0);
+    C[u] = cs.x;
+    S[u] = cs.y;
   }
 }
 
@@ -747,7 +746,7 @@ template <typename RT, bool HAS_T, bool HAS_QU, bool IQU, int LPP, bool PK>
 __global__ void __launch_bounds__(kBlock) k_bin_runs(int64_t n_obs, const int64_t* __restrict__ pstart,
                                                      const uint32_t* __restrict__ pb, const int32_t* __restrict__ pn,
                                                      int nb,
-                                                     const RT* __restrict__ pc, const RT* __restrict__ ps,
+                                                     const RT* __restrict__ pcs,
                                                      const double* __restrict__ pw4,
                                                      const double* __restrict__ Minv4,
                                                      const uint8_t* __restrict__ valid, double* __restrict__ m4,
@@ -772,7 +771,7 @@ __global__ void __launch_bounds__(kBlock) k_bin_runs(int64_t n_obs, const int64_
       int32_t len[U];
       RT cr[U], sr[U];
       // packed keys (PK): baseline << nb | (length - 1); else baseline, lengths in pn
-      load_runs<RT, HAS_T, HAS_QU || IQU, PK, U>(pb, pn, pc, ps, jb, LPP, j1, key, len, cr, sr);
+      load_runs<RT, HAS_T, HAS_QU || IQU, PK, U>(pb, pn, pcs, jb, LPP, j1, key, len, cr, sr);
       double2 x0[U];
       double u0[U], nn[U], cc[U], ss[U];
 #pragma unroll
@@ -832,7 +831,7 @@ template <typename RT, bool HAS_T, bool HAS_QU, bool IQU, int LPP>
 __global__ void __launch_bounds__(kBlock) k_bin_runs_pipe(int64_t n_obs, const int64_t* __restrict__ pstart,
                                                           const uint32_t* __restrict__ pb,
                                                           const int32_t* __restrict__ pn, int nb,
-                                                          const RT* __restrict__ pc, const RT* __restrict__ ps,
+                                                          const RT* __restrict__ pcs,
                                                           const double* __restrict__ pw4,
                                                           const double* __restrict__ Minv4,
                                                           const uint8_t* __restrict__ valid, double* __restrict__ m4,
@@ -861,8 +860,9 @@ __global__ void __launch_bounds__(kBlock) k_bin_runs_pipe(int64_t n_obs, const i
       const bool in = j < j1x;
       nkey[u] = in ? pb[j] : 0u;
       nlen[u] = (HAS_T && !nb && in) ? pn[j] : 0;
-      nC[u] = ((HAS_QU || IQU) && in) ? pc[j] : (RT)0;
-      nS[u] = ((HAS_QU || IQU) && in) ? ps[j] : (RT)0;
+      const CS2<RT> cs = ((HAS_QU || IQU) && in) ? reinterpret_cast<const CS2<RT>*>(pcs)[j] : make_cs<RT>(0.0, 0.0);
+      nC[u] = cs.x;
+      nS[u] = cs.y;
     }
   };
   int64_t cb = ((int64_t)blockIdx.x * kWaves + (threadIdx.x >> 6)) * PPW;
@@ -929,8 +929,10 @@ __global__ void __launch_bounds__(kBlock) k_bin_runs_pipe(int64_t n_obs, const i
           const bool in = j < j1;
           rkey[u] = in ? pb[j] : 0u;
           rlen[u] = (HAS_T && !nb && in) ? pn[j] : 0;
-          rC[u] = ((HAS_QU || IQU) && in) ? pc[j] : (RT)0;
-          rS[u] = ((HAS_QU || IQU) && in) ? ps[j] : (RT)0;
+          const CS2<RT> cs =
+              ((HAS_QU || IQU) && in) ? reinterpret_cast<const CS2<RT>*>(pcs)[j] : make_cs<RT>(0.0, 0.0);
+          rC[u] = cs.x;
+          rS[u] = cs.y;
         }
       };
       rfetch(jb);
@@ -1005,8 +1007,8 @@ template <typename RT, bool HAS_T, bool HAS_QU, bool IQU, bool CG, int BPW, bool
 __global__ void __launch_bounds__(kBlock) k_unbin_runs(View v, const uint32_t* __restrict__ bstart,
                                                        const uint32_t* __restrict__ border,
                                                        const uint32_t* __restrict__ rpix,
-                                                       const int32_t* __restrict__ rn, int nb, const RT* __restrict__ rc,
-                                                       const RT* __restrict__ rs, const double* __restrict__ m4,
+                                                       const int32_t* __restrict__ rn, int nb, const RT* __restrict__ rcs,
+                                                       const double* __restrict__ m4,
                                                        const int32_t* __restrict__ nvalid,
                                                        const double* __restrict__ p, double* __restrict__ q,
                                                        CgCtl* __restrict__ ctl, double* __restrict__ partials) {
@@ -1038,8 +1040,10 @@ __global__ void __launch_bounds__(kBlock) k_unbin_runs(View v, const uint32_t* _
         const bool in = r < r1;
         key[u] = in ? rpix[r] : 0u;
         len[u] = (HAS_T && !PK && in) ? rn[r] : 0;
-        C[u] = ((HAS_QU || IQU) && in) ? rc[r] : (RT)0;
-        S[u] = ((HAS_QU || IQU) && in) ? rs[r] : (RT)0;
+        const CS2<RT> cs =
+            ((HAS_QU || IQU) && in) ? reinterpret_cast<const CS2<RT>*>(rcs)[r] : make_cs<RT>(0.0, 0.0);
+        C[u] = cs.x;
+        S[u] = cs.y;
       }
     };
     fetch(r0 + sl);
@@ -1246,7 +1250,7 @@ hipError_t runs_build(const View& v, int psi_f32, const void* tod, int tod_f32, 
                                             decltype(D)::value>),
                                dim3(grb), dim3(kBlock), 0, st, v, static_cast<const TT*>(tod), W.t0, W.n_out, W.R,
                                W.tpix, W.tn,
-                               static_cast<RT*>(W.tc), static_cast<RT*>(W.ts), W.raw, W.rec);
+                               static_cast<RT*>(W.tcs), W.raw, W.rec);
           });
         });
       });
@@ -1301,7 +1305,7 @@ hipError_t runs_build(const View& v, int psi_f32, const void* tod, int tod_f32, 
           hipLaunchKernelGGL((k_pixels_from_runs<RT, decltype(T)::value, decltype(Q)::value, decltype(I)::value,
                                                  decltype(D)::value>),
                              dim3(gw), dim3(kBlock), 0, st, v, W.n_obs, W.order, W.seg, W.rperm, W.rec, rcond_cut,
-                             W.pb, W.pn, static_cast<RT*>(W.pc), static_cast<RT*>(W.ps), W.pstart, hits, Minv4,
+                             W.pb, W.pn, static_cast<RT*>(W.pcs), W.pstart, hits, Minv4,
                              valid, m4_zero, sd4, md4, counts);
         });
       });
@@ -1342,8 +1346,8 @@ hipError_t launch_rhs_runs(const View& vc, const Runs& W, const void* tod, const
       by_bool(tod != nullptr, [&](auto D) {
         hipLaunchKernelGGL((k_rhs_runs<RT, decltype(T)::value, decltype(Q)::value, decltype(I)::value,
                                         decltype(D)::value>), dim3(g),
-                           dim3(kBlock), 0, st, vc, W.bstart, W.tpix, W.tn, static_cast<const RT*>(W.tc),
-                           static_cast<const RT*>(W.ts), W.raw, md4, valid, nvalid, J, b);
+                           dim3(kBlock), 0, st, vc, W.bstart, W.tpix, W.tn, static_cast<const RT*>(W.tcs),
+                           W.raw, md4, valid, nvalid, J, b);
       });
     });
   });
@@ -1365,7 +1369,7 @@ hipError_t launch_bin_runs(const View& vc, const Runs& W, const double* pw4, con
       auto launch = [&](auto kern) {
         hipLaunchKernelGGL(kern, dim3(g), dim3(kBlock), 0, st, W.n_obs, W.pstart,
                            W.nb ? W.pkey : reinterpret_cast<const uint32_t*>(W.pb), W.pn, W.nb,
-                           static_cast<const RT*>(W.pc), static_cast<const RT*>(W.ps), pw4, Minv4, valid, m4, gate);
+                           static_cast<const RT*>(W.pcs), pw4, Minv4, valid, m4, gate);
       };
       if (pipe) {
         launch(k_bin_runs_pipe<RT, HT, HQ, HI, 64>);
@@ -1399,7 +1403,7 @@ hipError_t launch_unbin_runs(const View& vc, const Runs& W, const double* m4, co
         auto launch = [&](auto kern) {
           hipLaunchKernelGGL(kern, dim3(g), dim3(kBlock), 0, st, vc, W.bstart, W.border,
                              W.nb ? W.tkey : reinterpret_cast<const uint32_t*>(W.tpix), W.tn, W.nb,
-                             static_cast<const RT*>(W.tc), static_cast<const RT*>(W.ts), m4, nvalid, p, q, ctl,
+                             static_cast<const RT*>(W.tcs), m4, nvalid, p, q, ctl,
                              partials);
         };
         by_bool(W.nb != 0, [&](auto K) {
