@@ -364,14 +364,20 @@ __global__ void __launch_bounds__(kBlock) k_run_build(View v, const TT* __restri
   }
 }
 
-// Packed iteration keys: index << nb | (length - 1), time and pixel order.
-__global__ void __launch_bounds__(kBlock) k_pack_runs(int64_t R, int nb, const int32_t* __restrict__ tpix,
-                                                      const int32_t* __restrict__ tn, const int32_t* __restrict__ pb,
-                                                      const int32_t* __restrict__ pn, uint32_t* __restrict__ tkey,
-                                                      uint32_t* __restrict__ pkey) {
+// Time-order runs: pixel -> compact id; with nb > 0, in the same pass, the
+// packed iteration keys index << nb | (length - 1) in time and pixel order.
+__global__ void __launch_bounds__(kBlock) k_compact_runs(int64_t R, int nb, const int32_t* __restrict__ cid,
+                                                         int32_t* __restrict__ tpix, const int32_t* __restrict__ tn,
+                                                         const int32_t* __restrict__ pb,
+                                                         const int32_t* __restrict__ pn, uint32_t* __restrict__ tkey,
+                                                         uint32_t* __restrict__ pkey) {
   for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < R; r += (int64_t)gridDim.x * blockDim.x) {
-    tkey[r] = ((uint32_t)tpix[r] << nb) | (uint32_t)(tn[r] - 1);
-    pkey[r] = ((uint32_t)pb[r] << nb) | (uint32_t)(pn[r] - 1);
+    const int32_t c = cid[tpix[r]];
+    tpix[r] = c;
+    if (nb > 0) {
+      tkey[r] = ((uint32_t)c << nb) | (uint32_t)(tn[r] - 1);
+      pkey[r] = ((uint32_t)pb[r] << nb) | (uint32_t)(pn[r] - 1);
+    }
   }
 }
 
@@ -595,13 +601,6 @@ __global__ void __launch_bounds__(kBlock) k_pixels_from_runs(
 #pragma unroll
     for (int i = 0; i < 4; ++i) atomicAdd(&counts[i], cnt[i]);
   }
-}
-
-// Time-order runs: pixel -> compact id.
-__global__ void __launch_bounds__(kBlock) k_runs_to_compact(int64_t R, const int32_t* __restrict__ cid,
-                                                            int32_t* __restrict__ rpix) {
-  for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < R; r += (int64_t)gridDim.x * blockDim.x)
-    rpix[r] = cid[rpix[r]];
 }
 
 // Per baseline: the smallest compact id its runs visit (n_obs when it has
@@ -1312,17 +1311,15 @@ hipError_t runs_build(const View& v, int psi_f32, const void* tod, int tod_f32, 
     });
     DST_CHECK(hipGetLastError());
   }
-  // 6. time-order runs carry compact ids from here on
-  hipLaunchKernelGGL(k_runs_to_compact, dim3(gr), dim3(kBlock), 0, st, R, W.cid, W.tpix);
-  DST_CHECK(hipGetLastError());
-  // 7. one 32-bit key per run for the iterations (index and length) when both fit
+  // 6-7. time-order runs carry compact ids from here on, and each run gets
+  // one 32-bit key for the iterations (index and length) when both fit
   const unsigned nb = (unsigned)W.len_bits;
   W.nb = 0;
-  if (W.tkey && W.pkey && key_bits(std::max<int64_t>(W.n_obs, 1)) + nb <= 32 && key_bits(v.n_b) + nb <= 32) {
+  if (W.tkey && W.pkey && key_bits(std::max<int64_t>(W.n_obs, 1)) + nb <= 32 && key_bits(v.n_b) + nb <= 32)
     W.nb = (int)nb;
-    hipLaunchKernelGGL(k_pack_runs, dim3(gr), dim3(kBlock), 0, st, R, W.nb, W.tpix, W.tn, W.pb, W.pn, W.tkey,
-                       W.pkey);
-  }
+  hipLaunchKernelGGL(k_compact_runs, dim3(gr), dim3(kBlock), 0, st, R, W.nb, W.cid, W.tpix, W.tn, W.pb, W.pn,
+                     W.tkey, W.pkey);
+  DST_CHECK(hipGetLastError());
   // 8. rescan order of the baselines: by the smallest compact id each visits (stable)
   if (v.n_b > 0) {
     hipLaunchKernelGGL(k_baseline_keys, dim3(grid_for(v.n_b, kWaves, 4096)), dim3(kBlock), 0, st, v.n_b, W.n_obs,
