@@ -1157,7 +1157,7 @@ int dst_solve(dst_ctx* ctx, const dst_problem* prob, const dst_solve_opts* opts_
     if (timed) HIP_TRY(hipEventRecord(e[1], s));
     if (timed) HIP_TRY(hipEventRecord(e[2], s));
     DST_TRY(plan_unbin(ctx, P, p, q, ctl, partials, s));
-    HIP_TRY(dst::launch_cg_alpha(vc, ctl, partials, s));
+    HIP_TRY(dst::launch_cg_alpha(P.runs ? dst::unbin_runs_parts(vc, P.bpw) : vc.n_b, ctl, partials, s));
     if (timed) HIP_TRY(hipEventRecord(e[3], s));
     HIP_TRY(dst::launch_cg_update(v, a, r, z, p, q, S.J, ctl, partials, s));
     HIP_TRY(dst::launch_cg_beta(dst::cg_update_blocks(v), ctl, partials, s));

@@ -62,7 +62,8 @@ hipError_t launch_bin_pixel(const View& vc, int psi_f32, const Transpose& T, con
 hipError_t launch_unbin_cg(const View& vc, int psi_f32, const double* m4, const int32_t* nvalid, const double* p,
                            double* q, CgCtl* ctl, double* partials, hipStream_t st);
 // Single-workgroup finishes of the CG step (alpha) and of the residual update (beta).
-hipError_t launch_cg_alpha(const View& v, CgCtl* ctl, const double* partials, hipStream_t st);
+// alpha reads n_part partials of each kind (n_b from k_unbin_cg).
+hipError_t launch_cg_alpha(int64_t n_part, CgCtl* ctl, const double* partials, hipStream_t st);
 hipError_t launch_cg_beta(int n_part, CgCtl* ctl, const double* partials, hipStream_t st);
 // p = z + beta p (z == NULL: p unchanged) and pw4 = interleaved w .* p
 hipError_t launch_p_update4(const View& v, double* p, const double* z, double* pw4, const CgCtl* ctl, int use_beta,

@@ -490,17 +490,18 @@ __global__ void __launch_bounds__(kBlock) k_unbin_cg(View v, const double* __res
 }
 
 // Finishes the step length: mu (mean of the T part of K p over T-valid
-// baselines, the null-space projection) and alpha = r.z / p.(P K p), from the
-// per-baseline partials of k_unbin_cg.  One workgroup; fixed summation order.
-__global__ void __launch_bounds__(1024) k_cg_alpha(int64_t n_b, CgCtl* __restrict__ ctl,
+// baselines, the null-space projection) and alpha = r.z / p.(P K p), from
+// n_part partials of each kind (per baseline from k_unbin_cg, per workgroup
+// from the run rescan).  One workgroup; fixed summation order.
+__global__ void __launch_bounds__(1024) k_cg_alpha(int64_t n_part, CgCtl* __restrict__ ctl,
                                                    const double* __restrict__ partials) {
   if (ctl->done) return;
   __shared__ double lds[3 * 16];
   double tot[3] = {0.0, 0.0, 0.0};
-  for (int64_t j = threadIdx.x; j < n_b; j += blockDim.x) {
+  for (int64_t j = threadIdx.x; j < n_part; j += blockDim.x) {
     tot[0] += partials[j];
-    tot[1] += partials[n_b + j];
-    tot[2] += partials[2 * n_b + j];
+    tot[1] += partials[n_part + j];
+    tot[2] += partials[2 * n_part + j];
   }
   block_sum<3>(tot, lds);
   if (threadIdx.x == 0) {
@@ -804,8 +805,8 @@ hipError_t launch_unbin_cg(const View& v, int psi_f32, const double* m4, const i
   return hipGetLastError();
 }
 
-hipError_t launch_cg_alpha(const View& v, CgCtl* ctl, const double* partials, hipStream_t st) {
-  hipLaunchKernelGGL(k_cg_alpha, dim3(1), dim3(1024), 0, st, v.n_b, ctl, partials);
+hipError_t launch_cg_alpha(int64_t n_part, CgCtl* ctl, const double* partials, hipStream_t st) {
+  hipLaunchKernelGGL(k_cg_alpha, dim3(1), dim3(1024), 0, st, n_part, ctl, partials);
   return hipGetLastError();
 }
 

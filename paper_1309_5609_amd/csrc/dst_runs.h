@@ -124,9 +124,11 @@ hipError_t launch_rhs_runs(const View& vc, const Runs& W, const void* tod, const
 // lpp: lanes per pixel (64, 32 or 16; -64: 64 with the pixel pipeline; 0: 32).
 hipError_t launch_bin_runs(const View& vc, const Runs& W, const double* pw4, const double* Minv4,
                            const uint8_t* valid, double* m4, const CgCtl* gate, int lpp, hipStream_t st);
-// q = K p; with ctl the per-baseline CG partials (finished by launch_cg_alpha).
+// q = K p; with ctl the per-workgroup CG partials, unbin_runs_parts(vc, bpw)
+// of each kind (finished by launch_cg_alpha).
 // bpw: baselines per wavefront (1, 2, 4 or 8; else 4), taken in the order
 // W.border.
+int64_t unbin_runs_parts(const View& vc, int bpw);
 hipError_t launch_unbin_runs(const View& vc, const Runs& W, const double* m4, const int32_t* nvalid, const double* p,
                              double* q, CgCtl* ctl, double* partials, int bpw, hipStream_t st);
 

@@ -1000,8 +1000,10 @@ __global__ void __launch_bounds__(kBlock) k_bin_runs_pipe(int64_t n_obs, const i
 // that repeats every sidereal day, the same stretch of sky on different
 // days — and one gather instruction touches fewer distinct map lines.
 // Consecutive workgroups run on one XCD and take consecutive wavefront tasks.
-// m is zero on invalid blocks.  With CG: per-baseline partials of p.q and of
-// the T-projection sums.
+// m is zero on invalid blocks.  With CG: per-workgroup partials of p.q and of
+// the T-projection sums, partials[j * gridDim.x + blockIdx.x] for j = 0, 1, 2
+// (summed in a fixed order: a wavefront butterfly, then the wavefronts in
+// turn), so the step length is finished from a few thousand numbers.
 template <typename RT, bool HAS_T, bool HAS_QU, bool IQU, bool CG, int BPW, bool PK>
 __global__ void __launch_bounds__(kBlock) k_unbin_runs(View v, const uint32_t* __restrict__ bstart,
                                                        const uint32_t* __restrict__ border,
@@ -1019,7 +1021,13 @@ __global__ void __launch_bounds__(kBlock) k_unbin_runs(View v, const uint32_t* _
   const int64_t per = (n_g + 7) / 8;
   const int64_t i = blockIdx.x;
   const int64_t g = (i & 7) * per + (i >> 3);
-  if (g >= n_g) return;  // whole workgroup
+  if (g >= n_g) {  // whole workgroup
+    if (CG && threadIdx.x == 0) {
+#pragma unroll
+      for (int j = 0; j < 3; ++j) partials[j * (int64_t)gridDim.x + i] = 0.0;
+    }
+    return;
+  }
   const int sl = lane % SEG;
   const int64_t k = (g * kWaves + (threadIdx.x >> 6)) * BPW + lane / SEG;
   const int64_t b = k < n_b ? (int64_t)border[k] : n_b;
@@ -1089,9 +1097,9 @@ __global__ void __launch_bounds__(kBlock) k_unbin_runs(View v, const uint32_t* _
 #pragma unroll
     for (int c = 0; c < 3; ++c) acc[c] += __shfl_xor(acc[c], off, 64);
   }
+  double pq = 0.0, eq = 0.0, ep = 0.0;
   if (sl == 0 && b < n_b) {
     const int nT = nvalid[b], nQ = nvalid[n_b + b];
-    double pq = 0.0, eq = 0.0, ep = 0.0;
     if (HAS_T) {
       const double pbv = p[v.rowT * n_b + b];
       const double o = v.w[0] * (pbv * (double)nT - acc[0]);
@@ -1110,10 +1118,27 @@ __global__ void __launch_bounds__(kBlock) k_unbin_runs(View v, const uint32_t* _
       q[v.rowU * n_b + b] = ou;
       pq += pbq * oq + pbu * ou;
     }
-    if (CG) {
-      partials[b] = pq;
-      partials[n_b + b] = eq;
-      partials[2 * n_b + b] = ep;
+  }
+  if (CG) {
+    __shared__ double red[kWaves][3];
+    double t[3] = {pq, eq, ep};
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+#pragma unroll
+      for (int j = 0; j < 3; ++j) t[j] += __shfl_xor(t[j], off, 64);
+    }
+    if (lane == 0) {
+#pragma unroll
+      for (int j = 0; j < 3; ++j) red[threadIdx.x >> 6][j] = t[j];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+#pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        double x = 0.0;
+        for (int w = 0; w < kWaves; ++w) x += red[w][j];
+        partials[j * (int64_t)gridDim.x + i] = x;
+      }
     }
   }
 }
@@ -1386,11 +1411,16 @@ hipError_t launch_bin_runs(const View& vc, const Runs& W, const double* pw4, con
   return hipGetLastError();
 }
 
+int64_t unbin_runs_parts(const View& vc, int bpw) {
+  if (bpw != 1 && bpw != 2 && bpw != 4 && bpw != 8) bpw = 4;
+  const int64_t n_g = ((vc.n_b + bpw - 1) / bpw + kWaves - 1) / kWaves;
+  return 8 * ((n_g + 7) / 8);
+}
+
 hipError_t launch_unbin_runs(const View& vc, const Runs& W, const double* m4, const int32_t* nvalid, const double* p,
                              double* q, CgCtl* ctl, double* partials, int bpw, hipStream_t st) {
   if (bpw != 1 && bpw != 2 && bpw != 4 && bpw != 8) bpw = 4;
-  const int64_t n_g = ((vc.n_b + bpw - 1) / bpw + kWaves - 1) / kWaves;
-  const unsigned g = (unsigned)(8 * ((n_g + 7) / 8));
+  const unsigned g = (unsigned)unbin_runs_parts(vc, bpw);
   by_float(W.f32, [&](auto rt) {
     using RT = typename decltype(rt)::type;
     by_streams(vc, [&](auto T, auto Q, auto I) {
