@@ -465,8 +465,8 @@ int plan_operator(dst_ctx* ctx, Plan& P, const double* vin, double* out, hipStre
 
 // Captures `reps` calls of body(stream) on the context's private stream and
 // instantiates the graph.  The iteration kernels read their scalars from
-// device memory and return at once after the stop, so one graph serves every
-// batch of iterations.
+// device memory and return at once after the stop, so one graph of one
+// iteration serves every iteration of the solve.
 template <typename F>
 int capture_graph(dst_ctx* ctx, int reps, F&& body, hipGraphExec_t* exec) {
   *exec = nullptr;
