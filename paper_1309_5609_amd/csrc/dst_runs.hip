@@ -364,20 +364,15 @@ __global__ void __launch_bounds__(kBlock) k_run_build(View v, const TT* __restri
   }
 }
 
-// Time-order runs: pixel -> compact id; with nb > 0, in the same pass, the
-// packed iteration keys index << nb | (length - 1) in time and pixel order.
+// Time-order runs: pixel -> compact id and, with nb > 0, the packed
+// iteration key index << nb | (length - 1).
 __global__ void __launch_bounds__(kBlock) k_compact_runs(int64_t R, int nb, const int32_t* __restrict__ cid,
                                                          int32_t* __restrict__ tpix, const int32_t* __restrict__ tn,
-                                                         const int32_t* __restrict__ pb,
-                                                         const int32_t* __restrict__ pn, uint32_t* __restrict__ tkey,
-                                                         uint32_t* __restrict__ pkey) {
+                                                         uint32_t* __restrict__ tkey) {
   for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < R; r += (int64_t)gridDim.x * blockDim.x) {
     const int32_t c = cid[tpix[r]];
     tpix[r] = c;
-    if (nb > 0) {
-      tkey[r] = ((uint32_t)c << nb) | (uint32_t)(tn[r] - 1);
-      pkey[r] = ((uint32_t)pb[r] << nb) | (uint32_t)(pn[r] - 1);
-    }
+    if (nb > 0) tkey[r] = ((uint32_t)c << nb) | (uint32_t)(tn[r] - 1);
   }
 }
 
@@ -392,18 +387,20 @@ __global__ void __launch_bounds__(kBlock) k_key_segments(const uint32_t* __restr
 }
 
 // First visit of each pixel (start of its earliest run; the run sort is
-// stable, so that run heads the pixel's segment); UINT32_MAX if unobserved.
+// stable, so that run heads the pixel's segment); `none` (n_t, after every
+// sample) if unobserved.
 __global__ void __launch_bounds__(kBlock) k_first_visit(const int64_t* __restrict__ seg,
                                                         const uint32_t* __restrict__ rperm,
                                                         const uint32_t* __restrict__ t0, int64_t n_pix,
-                                                        uint32_t* __restrict__ first, uint32_t* __restrict__ pidx,
+                                                        uint32_t none, uint32_t* __restrict__ first,
+                                                        uint32_t* __restrict__ pidx,
                                                         unsigned long long* __restrict__ n_obs) {
   __shared__ unsigned long long lds[16];
   unsigned long long cnt[1] = {0};
   for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n_pix; p += (int64_t)gridDim.x * blockDim.x) {
     const int64_t j0 = seg[2 * p], j1 = seg[2 * p + 1];
     const bool hit = j1 > j0;
-    first[p] = hit ? t0[rperm[j0]] : 0xffffffffu;
+    first[p] = hit ? t0[rperm[j0]] : none;
     pidx[p] = (uint32_t)p;
     cnt[0] += hit;
   }
@@ -435,7 +432,7 @@ template <typename RT, bool HAS_T, bool HAS_QU, bool IQU, bool TOD>
 __global__ void __launch_bounds__(kBlock) k_pixels_from_runs(
     View v, int64_t n_obs, const uint32_t* __restrict__ order, const int64_t* __restrict__ seg,
     const uint32_t* __restrict__ rperm, const RunRecord* __restrict__ rec, double rcond_cut,
-    int32_t* __restrict__ pb, int32_t* __restrict__ pn, RT* __restrict__ pcs,
+    int32_t* __restrict__ pb, int32_t* __restrict__ pn, int nb, uint32_t* __restrict__ pkey, RT* __restrict__ pcs,
     const int64_t* __restrict__ pstart, int32_t* __restrict__ hits, double* __restrict__ Minv4,
     uint8_t* __restrict__ valid, double* __restrict__ m4_zero, double* __restrict__ sd4, double* __restrict__ md4,
     unsigned long long* __restrict__ counts) {
@@ -478,6 +475,7 @@ __global__ void __launch_bounds__(kBlock) k_pixels_from_runs(
         const int64_t d = d0 + (j - j0);
         pb[d] = x.b;
         pn[d] = x.n;
+        if (nb > 0) pkey[d] = ((uint32_t)x.b << nb) | (uint32_t)(x.n - 1);
         acc[0] += (double)x.n;
         if (HAS_QU || IQU) {
           reinterpret_cast<CS2<RT>*>(pcs)[d] = make_cs<RT>(x.C, x.S);
@@ -1152,6 +1150,14 @@ using RunSortConfig = rocprim::radix_sort_config<
     rocprim::default_config, rocprim::default_config,
     rocprim::radix_sort_onesweep_config<rocprim::kernel_config<1024, 16>, rocprim::kernel_config<1024, 16>,
                                         kRunSortBits, rocprim::block_radix_rank_algorithm::match>>;
+// Pixels by first visit (keys 0..n_t): the same passes, also below the
+// library's merge-sort limit (its merge sort took about 130 us for the
+// 786,432 pixels of N_side 256).
+using PixSortConfig = rocprim::radix_sort_config<
+    rocprim::default_config, rocprim::default_config,
+    rocprim::radix_sort_onesweep_config<rocprim::kernel_config<1024, 16>, rocprim::kernel_config<1024, 16>,
+                                        kRunSortBits, rocprim::block_radix_rank_algorithm::match>,
+    0>;
 
 // Key bits to sort: keys run over 0..n_pix - 1.
 unsigned key_bits(int64_t n) {
@@ -1184,7 +1190,7 @@ hipError_t runs_tmp_bytes(int64_t n_t, int64_t n_pix, int64_t n_b, size_t* bytes
   {
     rocprim::double_buffer<uint32_t> keys(nullptr, nullptr);
     rocprim::double_buffer<uint32_t> vals(nullptr, nullptr);
-    DST_CHECK(rocprim::radix_sort_pairs(nullptr, d, keys, vals, (size_t)n_pix, 0u, 32u));
+    DST_CHECK(rocprim::radix_sort_pairs<PixSortConfig>(nullptr, d, keys, vals, (size_t)n_pix, 0u, 32u));
   }
   DST_CHECK(rocprim::exclusive_scan(nullptr, c, static_cast<const int64_t*>(nullptr), static_cast<int64_t*>(nullptr),
                                     (int64_t)0, (size_t)n_pix + 1, rocprim::plus<int64_t>()));
@@ -1307,14 +1313,16 @@ hipError_t runs_build(const View& v, int psi_f32, const void* tod, int tod_f32, 
   }
   // 4. observed pixels -> compact ids in order of first visit; run offsets
   const unsigned gp = grid_for(n_pix, kBlock, 4096);
-  hipLaunchKernelGGL(k_first_visit, dim3(gp), dim3(kBlock), 0, st, W.seg, W.rperm, W.t0, n_pix, W.pk[0], W.pv[0],
+  hipLaunchKernelGGL(k_first_visit, dim3(gp), dim3(kBlock), 0, st, W.seg, W.rperm, W.t0, n_pix, (uint32_t)n_t,
+                     W.pk[0], W.pv[0],
                      W.n_obs_dev);
   DST_CHECK(hipGetLastError());
   {
     rocprim::double_buffer<uint32_t> keys(W.pk[0], W.pk[1]);
     rocprim::double_buffer<uint32_t> vals(W.pv[0], W.pv[1]);
     size_t tmp = W.tmp_bytes;
-    DST_CHECK(rocprim::radix_sort_pairs(W.tmp, tmp, keys, vals, (size_t)n_pix, 0u, 32u, st));
+    DST_CHECK(rocprim::radix_sort_pairs<PixSortConfig>(W.tmp, tmp, keys, vals, (size_t)n_pix, 0u,
+                                                       key_bits(n_t + 1), st));
     W.order = vals.current();
   }
   unsigned long long nobs = 0;
@@ -1329,7 +1337,12 @@ hipError_t runs_build(const View& v, int psi_f32, const void* tod, int tod_f32, 
     DST_CHECK(rocprim::exclusive_scan(W.tmp, tmp, W.ccount, W.pstart, (int64_t)0, (size_t)W.n_obs + 1,
                                       rocprim::plus<int64_t>(), st));
   }
-  // 5. per-pixel setup from the runs; pixel-order run arrays
+  // one 32-bit key per run for the iterations (index and length) when both fit
+  const unsigned nb = (unsigned)W.len_bits;
+  W.nb = 0;
+  if (W.tkey && W.pkey && key_bits(std::max<int64_t>(W.n_obs, 1)) + nb <= 32 && key_bits(v.n_b) + nb <= 32)
+    W.nb = (int)nb;
+  // 5. per-pixel setup from the runs; pixel-order run arrays and keys
   if (W.n_obs > 0) {
     const unsigned gw = grid_for(W.n_obs, kWaves, 4096);
     by_float(W.f32, [&](auto rt) {
@@ -1339,21 +1352,15 @@ hipError_t runs_build(const View& v, int psi_f32, const void* tod, int tod_f32, 
           hipLaunchKernelGGL((k_pixels_from_runs<RT, decltype(T)::value, decltype(Q)::value, decltype(I)::value,
                                                  decltype(D)::value>),
                              dim3(gw), dim3(kBlock), 0, st, v, W.n_obs, W.order, W.seg, W.rperm, W.rec, rcond_cut,
-                             W.pb, W.pn, static_cast<RT*>(W.pcs), W.pstart, hits, Minv4,
+                             W.pb, W.pn, W.nb, W.pkey, static_cast<RT*>(W.pcs), W.pstart, hits, Minv4,
                              valid, m4_zero, sd4, md4, counts);
         });
       });
     });
     DST_CHECK(hipGetLastError());
   }
-  // 6-7. time-order runs carry compact ids from here on, and each run gets
-  // one 32-bit key for the iterations (index and length) when both fit
-  const unsigned nb = (unsigned)W.len_bits;
-  W.nb = 0;
-  if (W.tkey && W.pkey && key_bits(std::max<int64_t>(W.n_obs, 1)) + nb <= 32 && key_bits(v.n_b) + nb <= 32)
-    W.nb = (int)nb;
-  hipLaunchKernelGGL(k_compact_runs, dim3(gr), dim3(kBlock), 0, st, R, W.nb, W.cid, W.tpix, W.tn, W.pb, W.pn,
-                     W.tkey, W.pkey);
+  // 6-7. time-order runs carry compact ids from here on, and their keys
+  hipLaunchKernelGGL(k_compact_runs, dim3(gr), dim3(kBlock), 0, st, R, W.nb, W.cid, W.tpix, W.tn, W.tkey);
   DST_CHECK(hipGetLastError());
   // 8. rescan order of the baselines: by the smallest compact id each visits (stable)
   if (v.n_b > 0) {
