@@ -1120,27 +1120,6 @@ int dst_solve(dst_ctx* ctx, const dst_problem* prob, const dst_solve_opts* opts_
   HIP_TRY(dst::launch_cg_start(v, b, ka_ptr, opts.a0, a, r, z, p, S.J, ctl, partials, opts.tol, opts.max_iter, st));
   HIP_TRY(dst::launch_p_update4(v, p, nullptr, P.pw4, nullptr, 0, st));
   if (opts.flags & DST_SOLVE_AUTOTUNE) DST_TRY(autotune(ctx, P, p, ka, st));
-  HIP_TRY(hipEventRecord(ev[1], st));
-  HIP_TRY(hipMemcpyAsync(ctx->ctl_host, ctl, sizeof(CgCtl), hipMemcpyDeviceToHost, st));
-  DST_TRY(finish(ctx, &S, st));
-  {
-    unsigned long long c[4];
-    HIP_TRY(hipMemcpy(c, S.counts, sizeof c, hipMemcpyDeviceToHost));
-    if (info) {
-      info->n_valid_pix[0] = (int64_t)c[0];
-      info->n_valid_pix[1] = (int64_t)c[1];
-      info->n_valid_samples[0] = (int64_t)c[2];
-      info->n_valid_samples[1] = (int64_t)c[3];
-    }
-    if (c[2] + c[3] == 0) {
-      HIP_TRY(hipMemsetAsync(baselines_out, 0, N * sizeof(double), st));
-      if (map_out) HIP_TRY(hipMemsetAsync(map_out, 0, 3 * v.n_pix * sizeof(double), st));
-      if (binned_out) HIP_TRY(hipMemsetAsync(binned_out, 0, 3 * v.n_pix * sizeof(double), st));
-      if (hits_out) HIP_TRY(dst::launch_scatter(v.n_pix, P.cid(), S.hits, hits_out, md4, nullptr, nullptr, st));
-      HIP_TRY(hipStreamSynchronize(st));
-      return fail(ctx, DST_EDEGENERATE, "no valid sample in the problem");
-    }
-  }
 
   // PCG iterations: pixel-major bin + inverse (m = M^-1 A^T W F p) -> rescan and
   // baseline sums (q = K p, alpha) -> a, r, z update (beta) -> p and its copy
@@ -1166,6 +1145,33 @@ int dst_solve(dst_ctx* ctx, const dst_problem* prob, const dst_solve_opts* opts_
     return DST_OK;
   };
 
+  // One iteration is captured once and replayed, unless profiling or asked
+  // not to; captured here, while the setup still runs on the GPU.
+  GraphGuard gg;
+  if (!use_gmres && !(opts.flags & (DST_SOLVE_NO_GRAPH | DST_SOLVE_PROFILE)))
+    DST_TRY(capture_graph(ctx, 1, [&](hipStream_t s) { return one_iteration(s, false); }, &gg.exec));
+  HIP_TRY(hipEventRecord(ev[1], st));
+  HIP_TRY(hipMemcpyAsync(ctx->ctl_host, ctl, sizeof(CgCtl), hipMemcpyDeviceToHost, st));
+  DST_TRY(finish(ctx, &S, st));
+  {
+    unsigned long long c[4];
+    HIP_TRY(hipMemcpy(c, S.counts, sizeof c, hipMemcpyDeviceToHost));
+    if (info) {
+      info->n_valid_pix[0] = (int64_t)c[0];
+      info->n_valid_pix[1] = (int64_t)c[1];
+      info->n_valid_samples[0] = (int64_t)c[2];
+      info->n_valid_samples[1] = (int64_t)c[3];
+    }
+    if (c[2] + c[3] == 0) {
+      HIP_TRY(hipMemsetAsync(baselines_out, 0, N * sizeof(double), st));
+      if (map_out) HIP_TRY(hipMemsetAsync(map_out, 0, 3 * v.n_pix * sizeof(double), st));
+      if (binned_out) HIP_TRY(hipMemsetAsync(binned_out, 0, 3 * v.n_pix * sizeof(double), st));
+      if (hits_out) HIP_TRY(dst::launch_scatter(v.n_pix, P.cid(), S.hits, hits_out, md4, nullptr, nullptr, st));
+      HIP_TRY(hipStreamSynchronize(st));
+      return fail(ctx, DST_EDEGENERATE, "no valid sample in the problem");
+    }
+  }
+
   CgCtl fin{};
   if (use_gmres) {
     // restarted GMRES from the projected residual of the start-up
@@ -1173,12 +1179,8 @@ int dst_solve(dst_ctx* ctx, const dst_problem* prob, const dst_solve_opts* opts_
     DST_TRY(gmres_loop(ctx, P, v, b, a, r, q, opts, &fin, st));
     HIP_TRY(hipEventRecord(ev[3], st));
   } else {
-  // batches of check_every iterations between convergence checks; one
-  // iteration is captured once and replayed, unless profiling or asked not to
+  // batches of check_every iterations between convergence checks
   CgCtl& h = *ctx->ctl_host;
-  GraphGuard gg;
-  if (!(opts.flags & (DST_SOLVE_NO_GRAPH | DST_SOLVE_PROFILE)) && h.done == dst::DONE_RUNNING)
-    DST_TRY(capture_graph(ctx, 1, [&](hipStream_t s) { return one_iteration(s, false); }, &gg.exec));
   HIP_TRY(hipEventRecord(ev[2], st));
   int launched = 0;
   while (h.done == dst::DONE_RUNNING && launched < opts.max_iter) {
