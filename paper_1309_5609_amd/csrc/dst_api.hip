@@ -36,6 +36,12 @@ struct dst_ctx {
   std::unordered_map<std::string, Buf> ws;
   CgCtl* ctl_host = nullptr;  // pinned mirror of the device CG scalars
   int* err_host = nullptr;    // pinned mirror of the device error flag
+  // pinned mirrors of the setup's four counts and of the true residual norm
+  struct Readback {
+    unsigned long long counts[4];
+    double rnorm;
+  };
+  Readback* rb_host = nullptr;
   dst::MultiCtl* mctl_host = nullptr;  // pinned mirror of the batched CG state
   hipStream_t cap = nullptr;  // private stream on which iteration graphs are captured
   int unbin_bpw = 4;          // launch shape of the run rescan (baselines per wavefront)
@@ -226,11 +232,11 @@ int run_setup(dst_ctx* ctx, const dst_problem* prob, Setup& S, bool baselines, d
 
 // Wait for the stream and report a pixel index out of range.
 int finish(dst_ctx* ctx, const Setup* S, hipStream_t st) {
+  // the error flag rides on the same synchronisation (pinned mirror)
+  if (S && S->err) HIP_TRY(hipMemcpyAsync(ctx->err_host, S->err, sizeof(int), hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
-  if (S && S->err) {
-    HIP_TRY(hipMemcpy(ctx->err_host, S->err, sizeof(int), hipMemcpyDeviceToHost));
-    if (*ctx->err_host) return fail(ctx, DST_EBOUNDS, "a pixel index >= n_pix (%lld) was found", (long long)S->v.n_pix);
-  }
+  if (S && S->err && *ctx->err_host)
+    return fail(ctx, DST_EBOUNDS, "a pixel index >= n_pix (%lld) was found", (long long)S->v.n_pix);
   return DST_OK;
 }
 
@@ -918,6 +924,8 @@ int dst_create(dst_ctx** out, int device) {
   DeviceGuard g(device);
   if (hipHostMalloc(reinterpret_cast<void**>(&ctx->ctl_host), sizeof(CgCtl), hipHostMallocDefault) != hipSuccess ||
       hipHostMalloc(reinterpret_cast<void**>(&ctx->err_host), sizeof(int), hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc(reinterpret_cast<void**>(&ctx->rb_host), sizeof(dst_ctx::Readback), hipHostMallocDefault) !=
+          hipSuccess ||
       hipHostMalloc(reinterpret_cast<void**>(&ctx->mctl_host), sizeof(dst::MultiCtl), hipHostMallocDefault) !=
           hipSuccess) {
     (void)hipGetLastError();
@@ -936,6 +944,7 @@ int dst_destroy(dst_ctx* ctx) {
     if (kv.second.ptr) (void)hipFree(kv.second.ptr);
   if (ctx->ctl_host) (void)hipHostFree(ctx->ctl_host);
   if (ctx->err_host) (void)hipHostFree(ctx->err_host);
+  if (ctx->rb_host) (void)hipHostFree(ctx->rb_host);
   if (ctx->mctl_host) (void)hipHostFree(ctx->mctl_host);
   if (ctx->cap) (void)hipStreamDestroy(ctx->cap);
   delete ctx;
@@ -1152,10 +1161,11 @@ int dst_solve(dst_ctx* ctx, const dst_problem* prob, const dst_solve_opts* opts_
     DST_TRY(capture_graph(ctx, 1, [&](hipStream_t s) { return one_iteration(s, false); }, &gg.exec));
   HIP_TRY(hipEventRecord(ev[1], st));
   HIP_TRY(hipMemcpyAsync(ctx->ctl_host, ctl, sizeof(CgCtl), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipMemcpyAsync(ctx->rb_host->counts, S.counts, 4 * sizeof(unsigned long long), hipMemcpyDeviceToHost,
+                         st));
   DST_TRY(finish(ctx, &S, st));
   {
-    unsigned long long c[4];
-    HIP_TRY(hipMemcpy(c, S.counts, sizeof c, hipMemcpyDeviceToHost));
+    const unsigned long long* c = ctx->rb_host->counts;
     if (info) {
       info->n_valid_pix[0] = (int64_t)c[0];
       info->n_valid_pix[1] = (int64_t)c[1];
@@ -1207,9 +1217,9 @@ int dst_solve(dst_ctx* ctx, const dst_problem* prob, const dst_solve_opts* opts_
   if (map_out) HIP_TRY(dst::launch_scatter(v.n_pix, P.cid(), nullptr, nullptr, md4, P.m4, map_out, st));
   if (binned_out) HIP_TRY(dst::launch_scatter(v.n_pix, P.cid(), nullptr, nullptr, md4, nullptr, binned_out, st));
   if (hits_out) HIP_TRY(dst::launch_scatter(v.n_pix, P.cid(), S.hits, hits_out, md4, nullptr, nullptr, st));
-  double true_norm = 0.0;
+  HIP_TRY(hipMemcpyAsync(&ctx->rb_host->rnorm, rnorm, sizeof(double), hipMemcpyDeviceToHost, st));
   DST_TRY(finish(ctx, &S, st));
-  HIP_TRY(hipMemcpy(&true_norm, rnorm, sizeof(double), hipMemcpyDeviceToHost));
+  const double true_norm = ctx->rb_host->rnorm;
 
   if (info) {
     info->iterations = fin.iter;
