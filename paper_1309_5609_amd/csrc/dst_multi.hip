@@ -247,9 +247,24 @@ __device__ __forceinline__ bool lane_active(int r, int R, const MultiCtl* ctl) {
   return r < R && (ctl == nullptr || ctl->done[r] == DONE_RUNNING);
 }
 
+// V consecutive realizations' values of one row (V = 1 or 2; 16-byte aligned
+// when V = 2 because Rp is even then).
+template <int V>
+__device__ __forceinline__ void load_v(const double* q, double (&x)[V]) {
+  if constexpr (V == 2) {
+    const double2 t = *reinterpret_cast<const double2*>(q);
+    x[0] = t.x;
+    x[1] = t.y;
+  } else {
+    x[0] = q[0];
+  }
+}
+
 // m = M^-1 A^T W F p per compact pixel (one wavefront per pixel), for every
-// active realization.  p is unweighted; the weights are applied here.
-template <typename RT, bool HAS_T, bool HAS_QU>
+// active realization.  p is unweighted; the weights are applied here.  Each
+// lane carries V consecutive realizations, so one gather instruction serves
+// 64 V / Rp runs.
+template <typename RT, bool HAS_T, bool HAS_QU, int V>
 __global__ void __launch_bounds__(kBlock) k_multi_bin(View vc, int R, int Rp, const int64_t* __restrict__ pstart,
                                                       const int32_t* __restrict__ pb, const int32_t* __restrict__ pn,
                                                       const RT* __restrict__ pcs, const double* __restrict__ p,
@@ -257,10 +272,17 @@ __global__ void __launch_bounds__(kBlock) k_multi_bin(View vc, int R, int Rp, co
                                                       double* __restrict__ m, const MultiCtl* __restrict__ ctl) {
   if (ctl && ctl->running == 0) return;
   const int lane = lane_id();
-  const int r = lane & (Rp - 1);
-  const int slot = lane / Rp;
-  const int slots = 64 / Rp;
-  const bool act = lane_active(r, R, ctl);
+  const int Rl = Rp / V;  // lanes per slot
+  const int r0 = (lane & (Rl - 1)) * V;
+  const int slot = lane / Rl;
+  const int slots = 64 / Rl;
+  bool actv[V];
+  bool any = false;
+#pragma unroll
+  for (int v = 0; v < V; ++v) {
+    actv[v] = lane_active(r0 + v, R, ctl);
+    any = any || actv[v];
+  }
   const int nS = vc.n_streams;
   const int oT = vc.rowT * Rp, oQ = vc.rowQ * Rp, oU = vc.rowU * Rp;
   const double w0 = vc.w[0], w1 = vc.w[1], w2 = vc.w[2];
@@ -268,7 +290,9 @@ __global__ void __launch_bounds__(kBlock) k_multi_bin(View vc, int R, int Rp, co
   const int64_t nw = (int64_t)gridDim.x * kWaves;
   for (int64_t c = (int64_t)blockIdx.x * kWaves + (threadIdx.x >> 6); c < n_obs; c += nw) {
     const int64_t j0 = pstart[c], j1 = pstart[c + 1];
-    double acc[3] = {0.0, 0.0, 0.0};
+    double acc[3 * V];  // [row][v]
+#pragma unroll
+    for (int i = 0; i < 3 * V; ++i) acc[i] = 0.0;
     // The run data of 64 runs at a time are loaded once, one run per lane
     // (coalesced), and handed to the slots by shuffles, so the only loads
     // left in the run loop are the gathers of p.
@@ -287,25 +311,40 @@ __global__ void __launch_bounds__(kBlock) k_multi_bin(View vc, int R, int Rp, co
         const int bb = __shfl(w_b, src, 64);
         const int nn = __shfl(w_n, src, 64);
         const double C = (double)__shfl(w_c, src, 64), S = (double)__shfl(w_s, src, 64);
-        if (!act || kk >= nwin || bb < 0) continue;
-        const double* pr = p + (int64_t)bb * nS * Rp + r;
-        if (HAS_T) acc[0] += (double)nn * (w0 * pr[oT]);
+        if (!any || kk >= nwin || bb < 0) continue;
+        const double* pr = p + (int64_t)bb * nS * Rp + r0;
+        if (HAS_T) {
+          double t[V];
+          load_v<V>(pr + oT, t);
+#pragma unroll
+          for (int v = 0; v < V; ++v) acc[v] += (double)nn * (w0 * t[v]);
+        }
         if (HAS_QU) {
-          const double xq = w1 * pr[oQ], xu = w2 * pr[oU];
-          acc[1] += C * xq - S * xu;
-          acc[2] += S * xq + C * xu;
+          double tq[V], tu[V];
+          load_v<V>(pr + oQ, tq);
+          load_v<V>(pr + oU, tu);
+#pragma unroll
+          for (int v = 0; v < V; ++v) {
+            const double xq = w1 * tq[v], xu = w2 * tu[v];
+            acc[V + v] += C * xq - S * xu;
+            acc[2 * V + v] += S * xq + C * xu;
+          }
         }
       }
     }
-    dev::lane_group_sum<3>(acc, Rp);
-    if (slot == 0 && act) {
+    dev::lane_group_sum<3 * V>(acc, Rl);
+    if (slot == 0 && any) {
       const double2* ip = reinterpret_cast<const double2*>(Minv4 + 4 * c);
       const double2 i01 = ip[0], i23 = ip[1];
-      double* mo = m + c * nS * Rp + r;
-      if (HAS_T) mo[oT] = i01.x * acc[0];
-      if (HAS_QU) {
-        mo[oQ] = i01.y * acc[1] + i23.x * acc[2];
-        mo[oU] = i23.x * acc[1] + i23.y * acc[2];
+      double* mo = m + c * nS * Rp + r0;
+#pragma unroll
+      for (int v = 0; v < V; ++v) {
+        if (!actv[v]) continue;
+        if (HAS_T) mo[oT + v] = i01.x * acc[v];
+        if (HAS_QU) {
+          mo[oQ + v] = i01.y * acc[V + v] + i23.x * acc[2 * V + v];
+          mo[oU + v] = i23.x * acc[V + v] + i23.y * acc[2 * V + v];
+        }
       }
     }
   }
@@ -860,9 +899,14 @@ hipError_t launch_multi_bin(const View& vc, const Runs& W, const Multi& mu, cons
   by_float(W.f32, [&](auto rt) {
     using RT = typename decltype(rt)::type;
     by_streams(vc, [&](auto T, auto Q) {
-      hipLaunchKernelGGL((k_multi_bin<RT, decltype(T)::value, decltype(Q)::value>), dim3(g), dim3(kBlock), 0, st,
-                         vc, mu.R, mu.Rp, W.pstart, W.pb, W.pn, static_cast<const RT*>(W.pcs), p,
-                         Minv4, m, ctl);
+      auto launch = [&](auto kern) {
+        hipLaunchKernelGGL(kern, dim3(g), dim3(kBlock), 0, st, vc, mu.R, mu.Rp, W.pstart, W.pb, W.pn,
+                           static_cast<const RT*>(W.pcs), p, Minv4, m, ctl);
+      };
+      if (mu.Rp >= 2)
+        launch(k_multi_bin<RT, decltype(T)::value, decltype(Q)::value, 2>);
+      else
+        launch(k_multi_bin<RT, decltype(T)::value, decltype(Q)::value, 1>);
     });
   });
   return hipGetLastError();
