@@ -358,7 +358,7 @@ __global__ void __launch_bounds__(kBlock) k_multi_bin(View vc, int R, int Rp, co
 //   RHS:            q = braw - w sum_runs A . m         (= F^T Z d with m = m_d)
 // CG also writes per-workgroup partials [block][3][Rp] of p.q and of the
 // T-projection sums (q_T and p_T over T-valid baselines).
-template <typename RT, bool HAS_T, bool HAS_QU, int MODE>
+template <typename RT, bool HAS_T, bool HAS_QU, int MODE, int V>
 __global__ void __launch_bounds__(kBlock) k_multi_unbin(View vc, int R, int Rp, const uint32_t* __restrict__ bstart,
                                                         const uint32_t* __restrict__ border,
                                                         const int32_t* __restrict__ tpix,
@@ -372,10 +372,17 @@ __global__ void __launch_bounds__(kBlock) k_multi_unbin(View vc, int R, int Rp, 
   if (MODE == UNBIN_CG && ctl->running == 0) return;
   const int lane = lane_id();
   const int wave = threadIdx.x >> 6;
-  const int r = lane & (Rp - 1);
-  const int slot = lane / Rp;
-  const int slots = 64 / Rp;
-  const bool act = lane_active(r, R, MODE == UNBIN_CG ? ctl : nullptr);
+  const int Rl = Rp / V;  // lanes per slot; each lane carries V consecutive realizations
+  const int r0 = (lane & (Rl - 1)) * V;
+  const int slot = lane / Rl;
+  const int slots = 64 / Rl;
+  bool actv[V];
+  bool any = false;
+#pragma unroll
+  for (int v = 0; v < V; ++v) {
+    actv[v] = lane_active(r0 + v, R, MODE == UNBIN_CG ? ctl : nullptr);
+    any = any || actv[v];
+  }
   const int nS = vc.n_streams;
   const int oT = vc.rowT * Rp, oQ = vc.rowQ * Rp, oU = vc.rowU * Rp;
   const double w0 = vc.w[0], w1 = vc.w[1], w2 = vc.w[2];
@@ -383,21 +390,25 @@ __global__ void __launch_bounds__(kBlock) k_multi_unbin(View vc, int R, int Rp, 
   const int64_t per = (n_b + 7) / 8;
   const int64_t x = blockIdx.x & 7, k = blockIdx.x >> 3, nk = gridDim.x >> 3;
   const int64_t lo = x * per, hi = std::min(n_b, lo + per);
-  double dots[3] = {0.0, 0.0, 0.0};
+  double dots[3 * V];  // [kind][v]
+#pragma unroll
+  for (int i = 0; i < 3 * V; ++i) dots[i] = 0.0;
   for (int64_t bk = lo + k * kWaves + wave; bk < hi; bk += nk * kWaves) {
     const int64_t b = border[bk];
-    const int64_t r0 = bstart[b], r1 = bstart[b + 1];
-    double acc[3] = {0.0, 0.0, 0.0};
+    const int64_t rs0 = bstart[b], rs1 = bstart[b + 1];
+    double acc[3 * V];  // [row][v]
+#pragma unroll
+    for (int i = 0; i < 3 * V; ++i) acc[i] = 0.0;
     // run data of 64 runs at a time: one coalesced load per lane, handed to
     // the slots by shuffles; the run loop only gathers m
-    for (int64_t wb = r0; wb < r1; wb += 64) {
+    for (int64_t wb = rs0; wb < rs1; wb += 64) {
       const int64_t jl = wb + lane;
-      const bool inw = jl < r1;
+      const bool inw = jl < rs1;
       const int w_c = inw ? tpix[jl] : -1;
       const int w_n = (HAS_T && inw) ? tn[jl] : 0;
       const CS2<RT> w_cs = (HAS_QU && inw) ? reinterpret_cast<const CS2<RT>*>(tcs)[jl] : make_cs<RT>(0.0, 0.0);
       const RT w_C = w_cs.x, w_S = w_cs.y;
-      const int nwin = r1 - wb < 64 ? (int)(r1 - wb) : 64;
+      const int nwin = rs1 - wb < 64 ? (int)(rs1 - wb) : 64;
 #pragma unroll 2
       for (int k0 = 0; k0 < nwin; k0 += slots) {  // uniform: every lane takes part in the shuffles
         const int kk = k0 + slot;
@@ -405,44 +416,58 @@ __global__ void __launch_bounds__(kBlock) k_multi_unbin(View vc, int R, int Rp, 
         const int cc = __shfl(w_c, src, 64);
         const int nn = __shfl(w_n, src, 64);
         const double C = (double)__shfl(w_C, src, 64), S = (double)__shfl(w_S, src, 64);
-        if (!act || kk >= nwin || cc < 0) continue;
-        const double* mr = m + (int64_t)cc * nS * Rp + r;
-        if (HAS_T) acc[0] += (double)nn * mr[oT];
+        if (!any || kk >= nwin || cc < 0) continue;
+        const double* mr = m + (int64_t)cc * nS * Rp + r0;
+        if (HAS_T) {
+          double t[V];
+          load_v<V>(mr + oT, t);
+#pragma unroll
+          for (int v = 0; v < V; ++v) acc[v] += (double)nn * t[v];
+        }
         if (HAS_QU) {
-          const double mQ = mr[oQ], mU = mr[oU];
-          acc[1] += C * mQ + S * mU;
-          acc[2] += C * mU - S * mQ;
+          double mQ[V], mU[V];
+          load_v<V>(mr + oQ, mQ);
+          load_v<V>(mr + oU, mU);
+#pragma unroll
+          for (int v = 0; v < V; ++v) {
+            acc[V + v] += C * mQ[v] + S * mU[v];
+            acc[2 * V + v] += C * mU[v] - S * mQ[v];
+          }
         }
       }
     }
-    dev::lane_group_sum<3>(acc, Rp);
-    if (slot == 0 && act) {
-      const int64_t o = b * nS * Rp + r;
-      if (MODE == UNBIN_RHS) {
-        if (HAS_T) q[o + oT] = braw[o + oT] - w0 * acc[0];
-        if (HAS_QU) {
-          q[o + oQ] = braw[o + oQ] - w1 * acc[1];
-          q[o + oU] = braw[o + oU] - w2 * acc[2];
-        }
-      } else {
-        const double nT = (double)nvalid[b], nQ = (double)nvalid[n_b + b];
-        if (HAS_T) {
-          const double pv = p[o + oT];
-          const double out = w0 * (pv * nT - acc[0]);
-          q[o + oT] = out;
-          dots[0] += pv * out;
-          if (nT > 0.0) {
-            dots[1] += out;
-            dots[2] += pv;
+    dev::lane_group_sum<3 * V>(acc, Rl);
+    if (slot == 0 && any) {
+#pragma unroll
+      for (int v = 0; v < V; ++v) {
+        if (!actv[v]) continue;
+        const int64_t o = b * nS * Rp + r0 + v;
+        if (MODE == UNBIN_RHS) {
+          if (HAS_T) q[o + oT] = braw[o + oT] - w0 * acc[v];
+          if (HAS_QU) {
+            q[o + oQ] = braw[o + oQ] - w1 * acc[V + v];
+            q[o + oU] = braw[o + oU] - w2 * acc[2 * V + v];
           }
-        }
-        if (HAS_QU) {
-          const double pq = p[o + oQ], pu = p[o + oU];
-          const double oq = w1 * (pq * nQ - acc[1]);
-          const double ou = w2 * (pu * nQ - acc[2]);
-          q[o + oQ] = oq;
-          q[o + oU] = ou;
-          dots[0] += pq * oq + pu * ou;
+        } else {
+          const double nT = (double)nvalid[b], nQ = (double)nvalid[n_b + b];
+          if (HAS_T) {
+            const double pv = p[o + oT];
+            const double out = w0 * (pv * nT - acc[v]);
+            q[o + oT] = out;
+            dots[v] += pv * out;
+            if (nT > 0.0) {
+              dots[V + v] += out;
+              dots[2 * V + v] += pv;
+            }
+          }
+          if (HAS_QU) {
+            const double pq = p[o + oQ], pu = p[o + oU];
+            const double oq = w1 * (pq * nQ - acc[V + v]);
+            const double ou = w2 * (pu * nQ - acc[2 * V + v]);
+            q[o + oQ] = oq;
+            q[o + oU] = ou;
+            dots[v] += pq * oq + pu * ou;
+          }
         }
       }
     }
@@ -450,7 +475,10 @@ __global__ void __launch_bounds__(kBlock) k_multi_unbin(View vc, int R, int Rp, 
   if (MODE == UNBIN_CG) {
     if (slot == 0) {
 #pragma unroll
-      for (int i = 0; i < 3; ++i) lds[wave][i][r] = dots[i];
+      for (int i = 0; i < 3; ++i) {
+#pragma unroll
+        for (int v = 0; v < V; ++v) lds[wave][i][r0 + v] = dots[i * V + v];
+      }
     }
     __syncthreads();
     if ((int)threadIdx.x < Rp) {
@@ -930,12 +958,19 @@ hipError_t launch_multi_unbin(const View& vc, const Runs& W, const Multi& mu, in
         hipLaunchKernelGGL(kern, dim3(g), dim3(kBlock), 0, st, vc, mu.R, mu.Rp, W.bstart, W.border, W.tpix, W.tn,
                            static_cast<const RT*>(W.tcs), m, nvalid, p, braw, q, ctl, partials);
       };
-      if (mode == UNBIN_CG)
-        launch(k_multi_unbin<RT, HT, HQ, UNBIN_CG>);
-      else if (mode == UNBIN_RHS)
-        launch(k_multi_unbin<RT, HT, HQ, UNBIN_RHS>);
+      auto by_mode = [&](auto VV) {
+        constexpr int V = decltype(VV)::value;
+        if (mode == UNBIN_CG)
+          launch(k_multi_unbin<RT, HT, HQ, UNBIN_CG, V>);
+        else if (mode == UNBIN_RHS)
+          launch(k_multi_unbin<RT, HT, HQ, UNBIN_RHS, V>);
+        else
+          launch(k_multi_unbin<RT, HT, HQ, UNBIN_OPERATOR, V>);
+      };
+      if (mu.Rp >= 2)
+        by_mode(std::integral_constant<int, 2>{});
       else
-        launch(k_multi_unbin<RT, HT, HQ, UNBIN_OPERATOR>);
+        by_mode(std::integral_constant<int, 1>{});
     });
   });
   return hipGetLastError();
