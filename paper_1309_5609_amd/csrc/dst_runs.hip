@@ -705,8 +705,8 @@ __global__ void __launch_bounds__(kBlock) k_rhs_runs(View v, const uint32_t* __r
 
 // ---------------------------------------------------------------- iteration kernels
 
-// Run stream of U runs j, j + stride, ... (key, length, sum of cos 2psi, sum
-// of sin 2psi).  Every load is issued, with index 0 for runs at or past j1, so
+// Run stream of U runs j, j + stride, ... (key, length, and the interleaved
+// pair of sums of cos 2psi and sin 2psi, one load).  Every load is issued, with index 0 for runs at or past j1, so
 // the loads of all U runs are in flight together with no branches between
 // them; the caller zeroes those runs' terms.  PK: packed keys (index << nb |
 // length - 1), else index keys with the lengths in len_arr.
