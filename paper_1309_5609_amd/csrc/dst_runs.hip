@@ -92,15 +92,6 @@ __device__ __forceinline__ void sym3_eig_range(double a00, double a01, double a0
   lmin = q + 2.0 * pp * cos(phi + 2.0943951023931957);  // + 2 pi / 3
 }
 
-// Workgroup i runs on XCD i mod 8; give each XCD a contiguous range of
-// baselines.  Returns -1 for padding groups.
-__device__ __forceinline__ int64_t xcd_baseline(int64_t n_b) {
-  const int64_t per = (n_b + 7) / 8;
-  const int64_t i = blockIdx.x;
-  const int64_t b = (i & 7) * per + (i >> 3);
-  return b < n_b ? b : -1;
-}
-
 __global__ void __launch_bounds__(kBlock) k_iota(uint32_t* __restrict__ x, int64_t n) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
     x[i] = (uint32_t)i;
@@ -622,69 +613,95 @@ __global__ void __launch_bounds__(kBlock) k_baseline_keys(int64_t n_b, int64_t n
 
 // Per baseline (time-order runs): n_valid, the Jacobi diagonal and with TOD
 //   b_k = w_k sum_{runs, valid_k} (sum of d_k over the run - A-weighted m_d).
-template <typename RT, bool HAS_T, bool HAS_QU, bool IQU, bool TOD>
+// The rescan's layout: 16 lanes per baseline, four baselines per wavefront in
+// the rescan order, the loads of four runs per lane issued together.
+template <typename RT, bool HAS_T, bool HAS_QU, bool IQU, bool TOD, bool PK>
 __global__ void __launch_bounds__(kBlock) k_rhs_runs(View v, const uint32_t* __restrict__ bstart,
-                                                     const int32_t* __restrict__ rpix, const int32_t* __restrict__ rn,
+                                                     const uint32_t* __restrict__ border,
+                                                     const uint32_t* __restrict__ rkey,
+                                                     const int32_t* __restrict__ rn, int nb,
                                                      const RT* __restrict__ rcs,
                                                      const double* __restrict__ raw, const double* __restrict__ md4,
                                                      const uint8_t* __restrict__ valid, int32_t* __restrict__ nvalid,
                                                      double* __restrict__ J, double* __restrict__ b_out) {
-  __shared__ double lds[5 * 16];
+  constexpr int BPW = 4, SEG = 64 / BPW;
+  const int lane = lane_id();
   const int64_t n_b = v.n_b;
-  const int64_t b = xcd_baseline(n_b);
-  if (b < 0) return;
-  const int64_t r0 = bstart[b], r1 = bstart[b + 1];
+  const int64_t n_g = ((n_b + BPW - 1) / BPW + kWaves - 1) / kWaves;
+  const int64_t per = (n_g + 7) / 8;
+  const int64_t gi = blockIdx.x;
+  const int64_t g = (gi & 7) * per + (gi >> 3);
+  if (g >= n_g) return;  // whole workgroup
+  const int sl = lane % SEG;
+  const int64_t k = (g * kWaves + (threadIdx.x >> 6)) * BPW + lane / SEG;
+  const int64_t b = k < n_b ? (int64_t)border[k] : n_b;
   double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};  // T, q, u residual sums; n_T, n_QU
-  constexpr int U = 2;  // runs whose loads (and dependent gathers) are issued together
-  for (int64_t rb = r0 + threadIdx.x; rb < r1; rb += kBlock * U) {
-    int c[U];
+  if (b < n_b) {
+    const int64_t r0 = bstart[b], r1 = bstart[b + 1];
+    constexpr int U = 4;
+    for (int64_t rb = r0 + sl; rb < r1; rb += SEG * U) {
+      int c[U], nn[U];
 #pragma unroll
-    for (int u = 0; u < U; ++u) c[u] = rb + kBlock * u < r1 ? rpix[rb + kBlock * u] : -1;
-    uint8_t f[U];
-    double2 m01[U], m2[U];
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      f[u] = 0;
-      m01[u] = m2[u] = make_double2(0.0, 0.0);
-      if (c[u] < 0) continue;
-      f[u] = valid[c[u]];
-      if (TOD) {
-        const double2* mp = reinterpret_cast<const double2*>(md4 + 4 * (int64_t)c[u]);
-        m01[u] = mp[0];
-        m2[u] = mp[1];
+      for (int u = 0; u < U; ++u) {
+        const int64_t r = rb + SEG * u;
+        const bool in = r < r1;
+        const uint32_t key = in ? rkey[r] : 0u;
+        // packed keys (PK): compact pixel << nb | (length - 1); else pixel, lengths in rn
+        c[u] = in ? (int)(PK ? key >> nb : key) : -1;
+        nn[u] = in ? (PK ? (int)(key & ((1u << nb) - 1u)) + 1 : rn[r]) : 0;
       }
-    }
+      uint8_t f[U];
+      double2 m01[U];
+      double m2x[U];
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-      if (c[u] < 0) continue;
-      const int64_t r = rb + kBlock * u;
-      const double n = (double)rn[r];
-      const double* m = raw + (HAS_T && !HAS_QU && !IQU ? 1 : 3) * r;
-      if (IQU && (f[u] & 1)) {
-        acc[3] += n;
+      for (int u = 0; u < U; ++u) {
+        f[u] = 0;
+        m01[u] = make_double2(0.0, 0.0);
+        m2x[u] = 0.0;
+        if (c[u] < 0) continue;
+        f[u] = valid[c[u]];
         if (TOD) {
-          const CS2<RT> cs = reinterpret_cast<const CS2<RT>*>(rcs)[r];
-          const double C = (double)cs.x, S = (double)cs.y;
-          acc[0] += m[0] - (n * m01[u].x + C * m01[u].y + S * m2[u].x);
+          const double2* mp = reinterpret_cast<const double2*>(md4 + 4 * (int64_t)c[u]);
+          m01[u] = mp[0];
+          m2x[u] = mp[1].x;
         }
-      } else if (HAS_T && (f[u] & 1)) {
-        acc[3] += n;
-        if (TOD) acc[0] += m[0] - n * m01[u].x;
       }
-      if (HAS_QU && (f[u] & 2)) {
-        acc[4] += n;
-        if (TOD) {
-          const CS2<RT> cs = reinterpret_cast<const CS2<RT>*>(rcs)[r];
-          const double C = (double)cs.x, S = (double)cs.y;
-          const double mQ = m01[u].y, mU = m2[u].x;
-          acc[1] += m[1] - (C * mQ + S * mU);
-          acc[2] += m[2] - (C * mU - S * mQ);
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        if (c[u] < 0) continue;
+        const int64_t r = rb + SEG * u;
+        const double n = (double)nn[u];
+        const double* m = raw + (HAS_T && !HAS_QU && !IQU ? 1 : 3) * r;
+        if (IQU && (f[u] & 1)) {
+          acc[3] += n;
+          if (TOD) {
+            const CS2<RT> cs = reinterpret_cast<const CS2<RT>*>(rcs)[r];
+            const double C = (double)cs.x, S = (double)cs.y;
+            acc[0] += m[0] - (n * m01[u].x + C * m01[u].y + S * m2x[u]);
+          }
+        } else if (HAS_T && (f[u] & 1)) {
+          acc[3] += n;
+          if (TOD) acc[0] += m[0] - n * m01[u].x;
+        }
+        if (HAS_QU && (f[u] & 2)) {
+          acc[4] += n;
+          if (TOD) {
+            const CS2<RT> cs = reinterpret_cast<const CS2<RT>*>(rcs)[r];
+            const double C = (double)cs.x, S = (double)cs.y;
+            const double mQ = m01[u].y, mU = m2x[u];
+            acc[1] += m[1] - (C * mQ + S * mU);
+            acc[2] += m[2] - (C * mU - S * mQ);
+          }
         }
       }
     }
   }
-  block_sum<5>(acc, lds);
-  if (threadIdx.x == 0) {
+#pragma unroll
+  for (int off = SEG / 2; off > 0; off >>= 1) {
+#pragma unroll
+    for (int i = 0; i < 5; ++i) acc[i] += __shfl_xor(acc[i], off, 64);
+  }
+  if (sl == 0 && b < n_b) {
     const int nT = (int)acc[3], nQ = (int)acc[4];
     nvalid[b] = nT;
     nvalid[n_b + b] = nQ;
@@ -1378,15 +1395,19 @@ hipError_t runs_build(const View& v, int psi_f32, const void* tod, int tod_f32, 
 
 hipError_t launch_rhs_runs(const View& vc, const Runs& W, const void* tod, const double* md4, const uint8_t* valid,
                            int32_t* nvalid, double* J, double* b, hipStream_t st) {
-  const unsigned g = (unsigned)(8 * ((vc.n_b + 7) / 8));
+  const int64_t n_g = ((vc.n_b + 3) / 4 + kWaves - 1) / kWaves;  // four baselines per wavefront
+  const unsigned g = (unsigned)(8 * ((n_g + 7) / 8));
   by_float(W.f32, [&](auto rt) {
     using RT = typename decltype(rt)::type;
     by_streams(vc, [&](auto T, auto Q, auto I) {
       by_bool(tod != nullptr, [&](auto D) {
-        hipLaunchKernelGGL((k_rhs_runs<RT, decltype(T)::value, decltype(Q)::value, decltype(I)::value,
-                                        decltype(D)::value>), dim3(g),
-                           dim3(kBlock), 0, st, vc, W.bstart, W.tpix, W.tn, static_cast<const RT*>(W.tcs),
-                           W.raw, md4, valid, nvalid, J, b);
+        by_bool(W.nb != 0, [&](auto K) {
+          hipLaunchKernelGGL((k_rhs_runs<RT, decltype(T)::value, decltype(Q)::value, decltype(I)::value,
+                                          decltype(D)::value, decltype(K)::value>),
+                             dim3(g), dim3(kBlock), 0, st, vc, W.bstart, W.border,
+                             W.nb ? W.tkey : reinterpret_cast<const uint32_t*>(W.tpix), W.tn, W.nb,
+                             static_cast<const RT*>(W.tcs), W.raw, md4, valid, nvalid, J, b);
+        });
       });
     });
   });
