@@ -415,7 +415,7 @@ __global__ void __launch_bounds__(kBlock) k_compact(const uint32_t* __restrict__
   }
 }
 
-// One wavefront per compact pixel: its runs (pixel order, time order within
+// 32 lanes per compact pixel: its runs (pixel order, time order within
 // the pixel) -> the pixel-order run arrays; hits, weight blocks, inverse,
 // validity; with TOD the sum map and binned map.  The sum of sin^2 2psi over
 // a run is its length minus the sum of cos^2 2psi.
@@ -430,25 +430,33 @@ __global__ void __launch_bounds__(kBlock) k_pixels_from_runs(
   constexpr bool TONLY = HAS_T && !HAS_QU && !IQU;  // 16-byte records
   __shared__ unsigned long long lds[4 * 16];
   unsigned long long cnt[4] = {0, 0, 0, 0};
+  // LPP lanes per pixel (two pixels per wavefront), U runs per lane and step
+  constexpr int LPP = 32, PPW = 64 / LPP, U = 4;
   const int lane = lane_id();
-  const int64_t nw = (int64_t)gridDim.x * kWaves;
-  for (int64_t c = (int64_t)blockIdx.x * kWaves + (threadIdx.x >> 6); c < n_obs; c += nw) {
-    const uint32_t p = order[c];
-    const int64_t j0 = seg[2 * (int64_t)p], j1 = seg[2 * (int64_t)p + 1];
-    const int64_t d0 = pstart[c];
+  const int grp = lane / LPP, sub = lane % LPP;
+  const int64_t nw = (int64_t)gridDim.x * kWaves * PPW;
+  for (int64_t cb = ((int64_t)blockIdx.x * kWaves + (threadIdx.x >> 6)) * PPW; cb < n_obs; cb += nw) {
+    const int64_t c = cb + grp;
+    const bool have = c < n_obs;
+    int64_t j0 = 0, j1 = 0, d0 = 0;
+    if (have) {
+      const uint32_t p = order[c];
+      j0 = seg[2 * (int64_t)p];
+      j1 = seg[2 * (int64_t)p + 1];
+      d0 = pstart[c];
+    }
     constexpr int NA = IQU ? 8 : 6;
     double acc[NA];  // h, cc, cs, dT, dQ, dU (and C, S for the radiometer block)
 #pragma unroll
     for (int i = 0; i < NA; ++i) acc[i] = 0.0;
-    constexpr int U = 2;  // runs whose (dependent) index and record loads are issued together
-    for (int64_t jb = j0 + lane; jb < j1; jb += 64 * U) {
+    for (int64_t jb = j0 + sub; jb < j1; jb += LPP * U) {
       uint32_t q[U];
 #pragma unroll
-      for (int u = 0; u < U; ++u) q[u] = jb + 64 * u < j1 ? rperm[jb + 64 * u] : 0u;
+      for (int u = 0; u < U; ++u) q[u] = jb + LPP * u < j1 ? rperm[jb + LPP * u] : 0u;
       RunRecord xs[U];
 #pragma unroll
       for (int u = 0; u < U; ++u) {
-        if (jb + 64 * u >= j1) continue;
+        if (jb + LPP * u >= j1) continue;
         if (TONLY) {
           const RunRecordT y = reinterpret_cast<const RunRecordT*>(rec)[q[u]];
           xs[u].n = y.n;
@@ -460,7 +468,7 @@ __global__ void __launch_bounds__(kBlock) k_pixels_from_runs(
       }
 #pragma unroll
       for (int u = 0; u < U; ++u) {
-        const int64_t j = jb + 64 * u;
+        const int64_t j = jb + LPP * u;
         if (j >= j1) break;
         const RunRecord& x = xs[u];
         const int64_t d = d0 + (j - j0);
@@ -484,8 +492,12 @@ __global__ void __launch_bounds__(kBlock) k_pixels_from_runs(
         }
       }
     }
-    wave_sum<NA>(acc);
-    if (IQU && lane == 0) {
+#pragma unroll
+    for (int off = LPP / 2; off > 0; off >>= 1) {
+#pragma unroll
+      for (int i = 0; i < NA; ++i) acc[i] += __shfl_xor(acc[i], off, 64);
+    }
+    if (IQU && have && sub == 0) {
       // full 3x3 block w [[h, C, S], [C, cc, cs], [S, cs, ss]] of the radiometer row
       const int64_t h = (int64_t)acc[0];
       const double w = v.w[0];
@@ -533,7 +545,7 @@ __global__ void __launch_bounds__(kBlock) k_pixels_from_runs(
       cnt[0] += f ? 1 : 0;
       cnt[2] += f ? (unsigned long long)h : 0ull;
     }
-    if (!IQU && lane == 0) {
+    if (!IQU && have && sub == 0) {
       const int64_t h = (int64_t)acc[0];
       double inv[4] = {0.0, 0.0, 0.0, 0.0};
       uint8_t f = 0;
@@ -1361,7 +1373,7 @@ hipError_t runs_build(const View& v, int psi_f32, const void* tod, int tod_f32, 
     W.nb = (int)nb;
   // 5. per-pixel setup from the runs; pixel-order run arrays and keys
   if (W.n_obs > 0) {
-    const unsigned gw = grid_for(W.n_obs, kWaves, 4096);
+    const unsigned gw = grid_for(W.n_obs, 2 * kWaves, 4096);  // two pixels per wavefront
     by_float(W.f32, [&](auto rt) {
       using RT = typename decltype(rt)::type;
       by_streams(v, [&](auto T, auto Q, auto I) {
