@@ -38,13 +38,21 @@
  * dst_destroy).
  *
  * Streams and synchrony.  Work is issued on the caller's `stream` (NULL = the
- * null stream); each entry point returns after that work has completed, so
- * outputs are ready and device-detected errors are reported by the call that
- * caused them.
+ * null stream).  dst_pixel_setup, dst_bin, dst_unbin, dst_baseline_reduce and
+ * dst_residual are stream-ordered and asynchronous: they return once their
+ * work is queued, and their outputs are ready when the stream reaches that
+ * point.  Calls that need sizes or results on the host (dst_apply_operator,
+ * dst_solve, dst_solve_batched, dst_pointing_expand, dst_noise_generate) wait
+ * for their stream before returning.  The workspace of a context is shared by
+ * its calls, so calls on one context must be ordered (one stream, or streams
+ * synchronised in between); use one context per concurrent stream.
  *
  * Errors.  Functions return a dst_status.  Argument errors are found before
- * any launch and leave outputs untouched.  dst_last_error() gives a message
- * for the context's most recent failure.  No C++ exception crosses the ABI.
+ * any launch and leave outputs untouched.  A pixel index >= n_pix found on
+ * the device sets a flag in the context; the next call that waits for its
+ * stream (or dst_synchronize) returns DST_EBOUNDS and clears it.
+ * dst_last_error() gives a message for the context's most recent failure.  No
+ * C++ exception crosses the ABI.
  *
  * Threads.  A context may be used by one host thread at a time.
  */
@@ -57,7 +65,7 @@
 extern "C" {
 #endif
 
-#define DST_ABI_VERSION 1
+#define DST_ABI_VERSION 2
 
 typedef enum {
   DST_OK = 0,
@@ -121,6 +129,11 @@ int dst_destroy(dst_ctx* ctx);
 
 /* Message describing the context's most recent error ("" if none). */
 const char* dst_last_error(const dst_ctx* ctx);
+
+/* Wait for `stream` and report what the asynchronous calls of this context
+ * found on the device: DST_EBOUNDS (flag then cleared) if a pixel index >=
+ * n_pix was met since the last report, else DST_OK. */
+int dst_synchronize(dst_ctx* ctx, void* stream);
 
 /* Per-pixel setup (Eq. 9 and the per-pixel weight matrices after Eqs. 10-11).
  *   hits_out  [n_pix] int32   number of unmasked samples per pixel (NULL to skip)
@@ -201,12 +214,23 @@ typedef struct {
   /* with DST_SOLVE_PROFILE: mean device time per launch of each kernel class (ms) */
   double t_bin_ms, t_apply_ms, t_unbin_ms, t_update_ms;
   int64_t n_runs;           /* runs of the run-compressed pointing (0 in the per-sample form) */
+  int64_t n_components;     /* connected components of the baseline-pixel graph over samples valid
+                               for the T (or radiometer) stream: one null vector of Eq. 13 each
+                               (0 without such a stream) */
 } dst_solve_info;
 
 /* Destripe one channel (Eq. 13 by PCG, then Eqs. 10-12 for the maps).
- *   baselines_out [n_streams][n_b] f64   solution a (T baselines with zero
- *                 mean over baselines holding valid T samples unless
- *                 DST_SOLVE_NO_CANON)
+ *
+ * Null space.  A constant added to the T baselines (DST_IQU: the radiometer
+ * baselines) of one connected component of the bipartite graph baseline <->
+ * pixel, linked by the valid samples of that stream, equals the same constant
+ * added to the I map of the component's pixels (Eq. 8), so K has one null
+ * vector per component.  The solver removes the component means from b and
+ * from every K p, and reports the baselines with zero mean over each
+ * component's baselines (baselines without valid samples are 0).
+ *
+ *   baselines_out [n_streams][n_b] f64   solution a (canonical as above
+ *                 unless DST_SOLVE_NO_CANON)
  *   map_out       [n_pix][3] f64 or NULL  destriped map m = M^-1 A^T W (d - F a)
  *   binned_out    [n_pix][3] f64 or NULL  binned map   m = M^-1 A^T W d
  *   hits_out      [n_pix] int32 or NULL

@@ -84,6 +84,19 @@ def _entries(pix, psi, n_pix, streams, weights, rcond_cut):
     return dict(t=t, k=k, row=row, p=p, A=A, w=w, ok=ok, present=present, M=M, okT=okT, okQU=okQU)
 
 
+def baseline_weights(pix, psi, n_pix, L, streams, weights, rcond_cut=1e-3):
+    """Diagonal of ``F^T W F`` over valid entries, [n_streams][n_b]: ``w_k`` times the number of valid
+    samples of stream k in each baseline, summed entry by entry from the explicit pointing entries."""
+    e = _entries(pix, psi, n_pix, streams, weights, rcond_cut)
+    n_t = np.asarray(pix).size
+    n_b = -(-n_t // L)
+    ns = len(e["present"])
+    sel = np.nonzero(e["ok"])[0]
+    out = np.zeros(ns * n_b)
+    np.add.at(out, e["row"][sel] * n_b + e["t"][sel] // L, e["w"][sel])
+    return out.reshape(ns, n_b)
+
+
 def joint_lstsq(pix, psi, tod, n_pix, L, streams, weights, rcond_cut=1e-3):
     """Minimum-norm joint weighted LS over (m, a), tiny problems only.
 

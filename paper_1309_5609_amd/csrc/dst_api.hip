@@ -18,6 +18,7 @@
 #include <vector>
 
 #include "dst.h"
+#include "dst_comp.h"
 #include "dst_internal.h"
 #include "dst_multi.h"
 #include "dst_pixel.h"
@@ -36,9 +37,11 @@ struct dst_ctx {
   std::unordered_map<std::string, Buf> ws;
   CgCtl* ctl_host = nullptr;  // pinned mirror of the device CG scalars
   int* err_host = nullptr;    // pinned mirror of the device error flag
+  int* err_dev = nullptr;     // device error flag (sticky: set by kernels, cleared when reported)
   // pinned mirrors of the setup's four counts and of the true residual norm
   struct Readback {
     unsigned long long counts[4];
+    int32_t ncomp[4];
     double rnorm;
   };
   Readback* rb_host = nullptr;
@@ -215,11 +218,10 @@ int run_setup(dst_ctx* ctx, const dst_problem* prob, Setup& S, bool baselines, d
   DST_TRY(ws(ctx, "Minv4", 4 * v.n_pix, &S.Minv4));
   DST_TRY(ws(ctx, "valid", v.n_pix, &S.valid));
   DST_TRY(ws(ctx, "counts", 4, &S.counts));
-  DST_TRY(ws(ctx, "err", 4, &S.err));
+  S.err = ctx->err_dev;
   HIP_TRY(dst::launch_fill_u32(reinterpret_cast<uint32_t*>(S.hits), v.n_pix, 0u, st));
   HIP_TRY(dst::launch_fill(S.M4, 4 * v.n_pix, 0.0, st));
   HIP_TRY(dst::launch_fill_u32(reinterpret_cast<uint32_t*>(S.counts), 8, 0u, st));
-  HIP_TRY(dst::launch_fill_u32(reinterpret_cast<uint32_t*>(S.err), 4, 0u, st));
   HIP_TRY(dst::launch_pointing(v, S.psi_f32, S.hits, S.M4, S.err, st));
   HIP_TRY(dst::launch_invert(v, S.hits, S.M4, prob->rcond_cut, S.Minv4, S.valid, blocks_out, S.counts, st));
   if (baselines) {
@@ -230,13 +232,26 @@ int run_setup(dst_ctx* ctx, const dst_problem* prob, Setup& S, bool baselines, d
   return DST_OK;
 }
 
-// Wait for the stream and report a pixel index out of range.
+// Wait for the stream and report a pixel index out of range found by any
+// kernel of this context since the last report (the flag is sticky until
+// reported, so asynchronous calls report at the next synchronisation).
 int finish(dst_ctx* ctx, const Setup* S, hipStream_t st) {
+  (void)S;
   // the error flag rides on the same synchronisation (pinned mirror)
-  if (S && S->err) HIP_TRY(hipMemcpyAsync(ctx->err_host, S->err, sizeof(int), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipMemcpyAsync(ctx->err_host, ctx->err_dev, sizeof(int), hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
-  if (S && S->err && *ctx->err_host)
-    return fail(ctx, DST_EBOUNDS, "a pixel index >= n_pix (%lld) was found", (long long)S->v.n_pix);
+  if (*ctx->err_host) {
+    HIP_TRY(dst::launch_fill_u32(reinterpret_cast<uint32_t*>(ctx->err_dev), 4, 0u, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    *ctx->err_host = 0;
+    return fail(ctx, DST_EBOUNDS, "a pixel index >= n_pix was found in the pointing");
+  }
+  return DST_OK;
+}
+
+// End of an asynchronous entry point: launch errors only.
+int issued(dst_ctx* ctx) {
+  HIP_TRY(hipGetLastError());
   return DST_OK;
 }
 
@@ -276,8 +291,27 @@ struct Plan {
   double* pw4 = nullptr;  // weighted interleaved baseline vector
   int lpp = 0;            // launch shapes of the run binning (0: default) and rescan
   int bpw = 4;
+  dst::Comp C;            // components of the baseline-pixel graph (streams with a T-like row)
   const int32_t* cid() const { return runs ? W.cid : T.cid; }
+  dst::CompView cv() const { return C.ncomp ? C.view() : dst::CompView{}; }
 };
+
+// Components of the baseline-pixel graph over T-valid samples (after the
+// per-baseline counts); elements elem_start / eb in pixel order.
+int build_components(dst_ctx* ctx, Plan& P, int64_t n_obs, const int64_t* elem_start, const int32_t* eb,
+                     hipStream_t st) {
+  const View& v = P.full;
+  if (v.rowT < 0) return DST_OK;
+  dst::Comp& C = P.C;
+  DST_TRY(ws(ctx, "comp_parent", v.n_b, &C.parent));
+  DST_TRY(ws(ctx, "comp_label", v.n_b, &C.label));
+  DST_TRY(ws(ctx, "comp_start", v.n_b + 1, &C.start));
+  DST_TRY(ws(ctx, "comp_member", v.n_b, &C.member));
+  DST_TRY(ws(ctx, "comp_cursor", v.n_b, &C.cursor));
+  DST_TRY(ws(ctx, "comp_n", 4, &C.ncomp));
+  HIP_TRY(dst::launch_components(v.n_b, n_obs, elem_start, eb, P.S.valid, P.S.nvalid, C, st));
+  return DST_OK;
+}
 
 // Run form of the setup: runs in time and pixel order, compact ids in pixel
 // order, per-pixel blocks and (with tod) binned map, per-baseline counts and b.
@@ -312,13 +346,12 @@ int build_runs_plan(dst_ctx* ctx, const dst_problem* prob, Plan& P, const void* 
   DST_TRY(ws(ctx, "r_ccount", v.n_pix + 1, &W.ccount));
   DST_TRY(ws(ctx, "r_pstart", v.n_pix + 1, &W.pstart));
   DST_TRY(ws(ctx, "counts", 4, &S.counts));
-  DST_TRY(ws(ctx, "err", 4, &S.err));
+  S.err = ctx->err_dev;
   HIP_TRY(dst::launch_fill_u32(reinterpret_cast<uint32_t*>(W.seg), 4 * v.n_pix, 0u, st));
   HIP_TRY(dst::launch_fill_u32(reinterpret_cast<uint32_t*>(W.cid), v.n_pix, 0xffffffffu, st));
   HIP_TRY(dst::launch_fill_u32(reinterpret_cast<uint32_t*>(W.n_obs_dev), 2, 0u, st));
   HIP_TRY(dst::launch_fill_u32(reinterpret_cast<uint32_t*>(W.n_out), 2, 0u, st));
   HIP_TRY(dst::launch_fill_u32(reinterpret_cast<uint32_t*>(S.counts), 8, 0u, st));
-  HIP_TRY(dst::launch_fill_u32(reinterpret_cast<uint32_t*>(S.err), 4, 0u, st));
   W.split_bits = ctx->run_split_bits;
   HIP_TRY(dst::runs_count(v, W, S.err, st));
   const int64_t R = W.R;
@@ -363,7 +396,7 @@ int build_runs_plan(dst_ctx* ctx, const dst_problem* prob, Plan& P, const void* 
   S.v = v;
   S.v.n_pix = W.n_obs;
   HIP_TRY(dst::launch_rhs_runs(S.v, W, tod, m4d, S.valid, S.nvalid, S.J, b, st));
-  return DST_OK;
+  return build_components(ctx, P, W.n_obs, W.pstart, W.pb, st);
 }
 
 // With tod: also the sum map sd4, binned map md4 (compact [n_obs][4]) and the
@@ -400,12 +433,11 @@ int build_sample_plan(dst_ctx* ctx, const dst_problem* prob, Plan& P, const void
   const size_t psz = S.psi_f32 ? sizeof(float) : sizeof(double);
   DST_TRY(ws_get(ctx, "spsi", (v.rowQ >= 0 ? (size_t)v.n_t : 1) * psz, &T.spsi));
   DST_TRY(ws(ctx, "counts", 4, &S.counts));
-  DST_TRY(ws(ctx, "err", 4, &S.err));
+  S.err = ctx->err_dev;
   HIP_TRY(dst::launch_fill_u32(reinterpret_cast<uint32_t*>(T.seg), 4 * (v.n_pix + 1), 0u, st));
   HIP_TRY(dst::launch_fill_u32(reinterpret_cast<uint32_t*>(T.cid), v.n_pix, 0xffffffffu, st));
   HIP_TRY(dst::launch_fill_u32(reinterpret_cast<uint32_t*>(T.n_obs_dev), 2, 0u, st));
   HIP_TRY(dst::launch_fill_u32(reinterpret_cast<uint32_t*>(S.counts), 8, 0u, st));
-  HIP_TRY(dst::launch_fill_u32(reinterpret_cast<uint32_t*>(S.err), 4, 0u, st));
   HIP_TRY(dst::transpose_build(v, T, S.err, st));
   // compact view: pixel ids are the compact ids, n_pix the observed pixels
   S.v = v;
@@ -429,7 +461,7 @@ int build_sample_plan(dst_ctx* ctx, const dst_problem* prob, Plan& P, const void
   HIP_TRY(dst::launch_setup_pixels(v, S.psi_f32, T, tod, S.tod_f32, prob->rcond_cut, S.hits, S.Minv4, S.valid, P.m4,
                                    s4, m4d, S.counts, st));
   HIP_TRY(dst::launch_rhs_unbin(S.v, S.psi_f32, tod, S.tod_f32, m4d, S.valid, S.nvalid, S.J, b, st));
-  return DST_OK;
+  return build_components(ctx, P, T.n_obs, T.cstart, T.sb, st);
 }
 
 int build_plan(dst_ctx* ctx, const dst_problem* prob, Plan& P, const void* tod, double** sd4, double** md4,
@@ -620,6 +652,9 @@ int solve_group(dst_ctx* ctx, const dst_problem* problems, const std::vector<int
     k += nr;
   }
   HIP_TRY(dst::launch_multi_unbin(vc, W, mu, dst::UNBIN_RHS, md, S.nvalid, nullptr, braw, b, nullptr, nullptr, st));
+  const dst::CompView cv = P.cv();
+  const int64_t sbm = (int64_t)v.n_streams * mu.Rp;  // stride of one baseline in the multi layout
+  HIP_TRY(dst::launch_comp_project(cv, b, sbm, mu.Rp, st));
   HIP_TRY(dst::launch_multi_start(v, mu, b, a, r, z, p, S.J, ctl, part2, opts.tol, opts.max_iter, st));
   HIP_TRY(hipEventRecord(ev[1], st));
   dst::MultiCtl& h = *ctx->mctl_host;
@@ -627,6 +662,8 @@ int solve_group(dst_ctx* ctx, const dst_problem* problems, const std::vector<int
   DST_TRY(finish(ctx, &S, st));
   unsigned long long counts[4];
   HIP_TRY(hipMemcpy(counts, S.counts, sizeof counts, hipMemcpyDeviceToHost));
+  int32_t ncomp = 0;
+  if (P.C.ncomp) HIP_TRY(hipMemcpy(&ncomp, P.C.ncomp, sizeof ncomp, hipMemcpyDeviceToHost));
   if (counts[2] + counts[3] == 0) return fail(ctx, DST_EDEGENERATE, "no valid sample in the problem");
 
   // PCG: bin (m = M^-1 A^T W F p) -> rescan + sums (q = K p, alpha) ->
@@ -641,7 +678,8 @@ int solve_group(dst_ctx* ctx, const dst_problem* problems, const std::vector<int
     HIP_TRY(dst::launch_multi_bin(vc, W, mu, p, S.Minv4, m, ctl, s));
     if (timed) HIP_TRY(hipEventRecord(e[1], s));
     HIP_TRY(dst::launch_multi_unbin(vc, W, mu, dst::UNBIN_CG, m, S.nvalid, p, nullptr, q, ctl, part, s));
-    HIP_TRY(dst::launch_multi_alpha(vc, mu, ctl, part, s));
+    if (ncomp > 1) HIP_TRY(dst::launch_multi_comp(v, mu, cv, q, p, ctl, s));
+    HIP_TRY(dst::launch_multi_alpha(vc, mu, ctl, part, cv, s));
     if (timed) HIP_TRY(hipEventRecord(e[2], s));
     HIP_TRY(dst::launch_multi_update(v, mu, a, r, z, q, p, S.J, ctl, part2, s));
     HIP_TRY(dst::launch_multi_beta(v, mu, ctl, part2, s));
@@ -670,9 +708,13 @@ int solve_group(dst_ctx* ctx, const dst_problem* problems, const std::vector<int
   HIP_TRY(hipEventRecord(ev[3], st));
 
   // canonical baselines, true residuals, outputs
-  if (!(opts.flags & DST_SOLVE_NO_CANON)) HIP_TRY(dst::launch_multi_canonicalise(v, mu, a, S.J, ctl, part2, st));
+  if (!(opts.flags & DST_SOLVE_NO_CANON)) {
+    HIP_TRY(dst::launch_comp_project(cv, a, sbm, mu.Rp, st));
+    HIP_TRY(dst::launch_multi_canonicalise(v, mu, a, S.J, ctl, part2, st));
+  }
   HIP_TRY(dst::launch_multi_bin(vc, W, mu, a, S.Minv4, m, nullptr, st));
   HIP_TRY(dst::launch_multi_unbin(vc, W, mu, dst::UNBIN_OPERATOR, m, S.nvalid, a, nullptr, ka, nullptr, nullptr, st));
+  HIP_TRY(dst::launch_comp_project(cv, ka, sbm, mu.Rp, st));
   HIP_TRY(dst::launch_multi_resid(v, mu, b, ka, S.J, ctl, part2, st));
   for (int k = 0; k < mu.R; ++k) {
     const int i = idx[k];
@@ -718,6 +760,7 @@ int solve_group(dst_ctx* ctx, const dst_problem* problems, const std::vector<int
     in.n_valid_pix[1] = (int64_t)counts[1];
     in.n_valid_samples[0] = (int64_t)counts[2];
     in.n_valid_samples[1] = (int64_t)counts[3];
+    in.n_components = ncomp;
     in.t_setup_ms = t_setup;
     in.t_iter_ms = max_it > 0 ? t_iter / max_it : 0.0;
     in.t_total_ms = t_total;
@@ -735,10 +778,12 @@ int solve_group(dst_ctx* ctx, const dst_problem* problems, const std::vector<int
 // Gram-Schmidt with one reorthogonalisation (two batched dot / combine
 // passes); Givens rotations and the triangular solve on the host.  On entry
 // b is projected, a holds a0 (or 0), r = b - P K a0 and ctl_host the start-up
-// scalars (b_norm, r_norm, n_e).  q is scratch.  *fin receives iterations,
+// scalars (b_norm, r_norm, n_e).  q is scratch.  With several components of
+// the baseline-pixel graph (cv set), every K v loses its component means
+// first.  *fin receives iterations,
 // stop code and the residual estimate for the common exit path.
 int gmres_loop(dst_ctx* ctx, Plan& P, const View& v, const double* b, double* a, double* r, double* q,
-               const dst_solve_opts& opts, CgCtl* fin, hipStream_t st) {
+               const dst_solve_opts& opts, const dst::CompView& cv, CgCtl* fin, hipStream_t st) {
   Setup& S = P.S;
   const int64_t N = (int64_t)v.n_streams * v.n_b;
   const int m = opts.restart > 0 ? opts.restart : 50;
@@ -777,6 +822,7 @@ int gmres_loop(dst_ctx* ctx, Plan& P, const View& v, const double* b, double* a,
       // w = P K J v_j
       HIP_TRY(dst::launch_scale(slot(j), 0.0, S.J, z, N, st));
       DST_TRY(plan_operator(ctx, P, z, q, st));
+      HIP_TRY(dst::launch_comp_project(cv, q, 1, 1, st));
       DST_TRY(dot_with(V, j + 2, q));  // e.w, v_0.w .. v_j.w
       dst::GmresCoef c{};
       c.c[0] = n_e > 0.0 ? hd[0] / n_e : 0.0;
@@ -829,6 +875,7 @@ int gmres_loop(dst_ctx* ctx, Plan& P, const View& v, const double* b, double* a,
     if (rel <= opts.tol || it >= opts.max_iter || broke) break;
     // restart from r = b - P K a
     DST_TRY(plan_operator(ctx, P, a, q, st));
+    HIP_TRY(dst::launch_comp_project(cv, q, 1, 1, st));
     DST_TRY(dot_with(e, 1, q));
     const double mu = n_e > 0.0 ? hd[0] / n_e : 0.0;
     HIP_TRY(dst::launch_restart_resid(b, q, mu, e, r, N, st));
@@ -927,7 +974,9 @@ int dst_create(dst_ctx** out, int device) {
       hipHostMalloc(reinterpret_cast<void**>(&ctx->rb_host), sizeof(dst_ctx::Readback), hipHostMallocDefault) !=
           hipSuccess ||
       hipHostMalloc(reinterpret_cast<void**>(&ctx->mctl_host), sizeof(dst::MultiCtl), hipHostMallocDefault) !=
-          hipSuccess) {
+          hipSuccess ||
+      hipMalloc(reinterpret_cast<void**>(&ctx->err_dev), 4 * sizeof(int)) != hipSuccess ||
+      hipMemset(ctx->err_dev, 0, 4 * sizeof(int)) != hipSuccess) {
     (void)hipGetLastError();
     dst_destroy(ctx);
     return DST_ENOMEM;
@@ -944,6 +993,7 @@ int dst_destroy(dst_ctx* ctx) {
     if (kv.second.ptr) (void)hipFree(kv.second.ptr);
   if (ctx->ctl_host) (void)hipHostFree(ctx->ctl_host);
   if (ctx->err_host) (void)hipHostFree(ctx->err_host);
+  if (ctx->err_dev) (void)hipFree(ctx->err_dev);
   if (ctx->rb_host) (void)hipHostFree(ctx->rb_host);
   if (ctx->mctl_host) (void)hipHostFree(ctx->mctl_host);
   if (ctx->cap) (void)hipStreamDestroy(ctx->cap);
@@ -952,6 +1002,12 @@ int dst_destroy(dst_ctx* ctx) {
 }
 
 const char* dst_last_error(const dst_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+int dst_synchronize(dst_ctx* ctx, void* stream) {
+  if (!ctx) return DST_EINVAL;
+  DeviceGuard g(ctx->device);
+  return finish(ctx, nullptr, static_cast<hipStream_t>(stream));
+}
 
 int dst_pixel_setup(dst_ctx* ctx, const dst_problem* prob, int32_t* hits_out, double* blocks_out, uint8_t* valid_out,
                     void* stream) {
@@ -966,7 +1022,7 @@ int dst_pixel_setup(dst_ctx* ctx, const dst_problem* prob, int32_t* hits_out, do
   DST_TRY(run_setup(ctx, prob, S, false, blocks_out, st));
   if (hits_out) HIP_TRY(hipMemcpyAsync(hits_out, S.hits, v.n_pix * sizeof(int32_t), hipMemcpyDeviceToDevice, st));
   if (valid_out) HIP_TRY(hipMemcpyAsync(valid_out, S.valid, v.n_pix, hipMemcpyDeviceToDevice, st));
-  return finish(ctx, &S, st);
+  return issued(ctx);
 }
 
 int dst_bin(dst_ctx* ctx, const dst_problem* prob, const double* baselines, uint32_t flags, double* map_out,
@@ -996,7 +1052,7 @@ int dst_bin(dst_ctx* ctx, const dst_problem* prob, const double* baselines, uint
   }
   (void)m4;
   if (hits_out) HIP_TRY(hipMemcpyAsync(hits_out, S.hits, v.n_pix * sizeof(int32_t), hipMemcpyDeviceToDevice, st));
-  return finish(ctx, &S, st);
+  return issued(ctx);
 }
 
 int dst_unbin(dst_ctx* ctx, const dst_problem* prob, const double* map, double* tod_out, void* stream) {
@@ -1007,12 +1063,8 @@ int dst_unbin(dst_ctx* ctx, const dst_problem* prob, const double* map, double* 
   ctx->err.clear();
   DeviceGuard g(ctx->device);
   hipStream_t st = static_cast<hipStream_t>(stream);
-  Setup S;
-  S.v = v;
-  DST_TRY(ws(ctx, "err", 4, &S.err));
-  HIP_TRY(dst::launch_fill_u32(reinterpret_cast<uint32_t*>(S.err), 4, 0u, st));
-  HIP_TRY(dst::launch_scan(v, prob->psi_dtype == DST_F32, map, tod_out, S.err, st));
-  return finish(ctx, &S, st);
+  HIP_TRY(dst::launch_scan(v, prob->psi_dtype == DST_F32, map, tod_out, ctx->err_dev, st));
+  return issued(ctx);
 }
 
 int dst_baseline_reduce(dst_ctx* ctx, const dst_problem* prob, const void* x, double* out, void* stream) {
@@ -1028,7 +1080,7 @@ int dst_baseline_reduce(dst_ctx* ctx, const dst_problem* prob, const void* x, do
   S.v = v;
   DST_TRY(run_setup(ctx, prob, S, false, nullptr, st));
   HIP_TRY(dst::launch_reduce(v, x, prob->tod_dtype == DST_F32, S.valid, out, st));
-  return finish(ctx, &S, st);
+  return issued(ctx);
 }
 
 int dst_residual(dst_ctx* ctx, const dst_problem* prob, const double* a, double* out, void* stream) {
@@ -1044,7 +1096,7 @@ int dst_residual(dst_ctx* ctx, const dst_problem* prob, const double* a, double*
   S.v = v;
   DST_TRY(run_setup(ctx, prob, S, true, nullptr, st));
   DST_TRY(operator_pass(ctx, S, prob->tod, a, -1.0, out, st));
-  return finish(ctx, &S, st);
+  return issued(ctx);
 }
 
 int dst_apply_operator(dst_ctx* ctx, const dst_problem* prob, const double* vin, double* out, void* stream) {
@@ -1121,9 +1173,14 @@ int dst_solve(dst_ctx* ctx, const dst_problem* prob, const dst_solve_opts* opts_
   DST_TRY(ws(ctx, "cg_ctl", 1, &ctl));
   HIP_TRY(dst::launch_fill_u32(reinterpret_cast<uint32_t*>(ctl), sizeof(CgCtl) / 4, 0u, st));
 
+  // several components: b and K a0 lose their component means here (one
+  // component: the global mean inside the start-up kernels)
+  const dst::CompView cv = P.cv();
+  HIP_TRY(dst::launch_comp_project(cv, b, 1, 1, st));
   const double* ka_ptr = nullptr;
   if (opts.a0) {
     DST_TRY(plan_operator(ctx, P, opts.a0, ka, st));
+    HIP_TRY(dst::launch_comp_project(cv, ka, 1, 1, st));
     ka_ptr = ka;
   }
   HIP_TRY(dst::launch_cg_start(v, b, ka_ptr, opts.a0, a, r, z, p, S.J, ctl, partials, opts.tol, opts.max_iter, st));
@@ -1145,7 +1202,7 @@ int dst_solve(dst_ctx* ctx, const dst_problem* prob, const dst_solve_opts* opts_
     if (timed) HIP_TRY(hipEventRecord(e[1], s));
     if (timed) HIP_TRY(hipEventRecord(e[2], s));
     DST_TRY(plan_unbin(ctx, P, p, q, ctl, partials, s));
-    HIP_TRY(dst::launch_cg_alpha(P.runs ? dst::unbin_runs_parts(vc, P.bpw) : vc.n_b, ctl, partials, s));
+    HIP_TRY(dst::launch_cg_alpha(P.runs ? dst::unbin_runs_parts(vc, P.bpw) : vc.n_b, ctl, partials, cv, q, p, s));
     if (timed) HIP_TRY(hipEventRecord(e[3], s));
     HIP_TRY(dst::launch_cg_update(v, a, r, z, p, q, S.J, ctl, partials, s));
     HIP_TRY(dst::launch_cg_beta(dst::cg_update_blocks(v), ctl, partials, s));
@@ -1163,7 +1220,11 @@ int dst_solve(dst_ctx* ctx, const dst_problem* prob, const dst_solve_opts* opts_
   HIP_TRY(hipMemcpyAsync(ctx->ctl_host, ctl, sizeof(CgCtl), hipMemcpyDeviceToHost, st));
   HIP_TRY(hipMemcpyAsync(ctx->rb_host->counts, S.counts, 4 * sizeof(unsigned long long), hipMemcpyDeviceToHost,
                          st));
+  ctx->rb_host->ncomp[0] = 0;
+  if (P.C.ncomp) HIP_TRY(hipMemcpyAsync(ctx->rb_host->ncomp, P.C.ncomp, sizeof(int32_t), hipMemcpyDeviceToHost, st));
   DST_TRY(finish(ctx, &S, st));
+  const int ncomp = ctx->rb_host->ncomp[0];
+  if (info) info->n_components = ncomp;
   {
     const unsigned long long* c = ctx->rb_host->counts;
     if (info) {
@@ -1186,7 +1247,7 @@ int dst_solve(dst_ctx* ctx, const dst_problem* prob, const dst_solve_opts* opts_
   if (use_gmres) {
     // restarted GMRES from the projected residual of the start-up
     HIP_TRY(hipEventRecord(ev[2], st));
-    DST_TRY(gmres_loop(ctx, P, v, b, a, r, q, opts, &fin, st));
+    DST_TRY(gmres_loop(ctx, P, v, b, a, r, q, opts, ncomp > 1 ? cv : dst::CompView{}, &fin, st));
     HIP_TRY(hipEventRecord(ev[3], st));
   } else {
   // batches of check_every iterations between convergence checks
@@ -1210,8 +1271,12 @@ int dst_solve(dst_ctx* ctx, const dst_problem* prob, const dst_solve_opts* opts_
   }
 
   // canonical baselines, true residual, maps (destriped = m_d - M^-1 A^T W F a)
-  if (!(opts.flags & DST_SOLVE_NO_CANON)) HIP_TRY(dst::launch_canonicalise(v, a, S.J, partials, ctl, st));
+  if (!(opts.flags & DST_SOLVE_NO_CANON)) {
+    HIP_TRY(dst::launch_comp_project(cv, a, 1, 1, st));
+    HIP_TRY(dst::launch_canonicalise(v, a, S.J, partials, ctl, st));
+  }
   DST_TRY(plan_operator(ctx, P, a, ka, st));
+  HIP_TRY(dst::launch_comp_project(cv, ka, 1, 1, st));
   HIP_TRY(dst::launch_residual_norm(v, b, ka, S.J, ctl, partials, rnorm, st));
   HIP_TRY(hipMemcpyAsync(baselines_out, a, N * sizeof(double), hipMemcpyDeviceToDevice, st));
   if (map_out) HIP_TRY(dst::launch_scatter(v.n_pix, P.cid(), nullptr, nullptr, md4, P.m4, map_out, st));

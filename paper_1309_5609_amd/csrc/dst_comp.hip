@@ -1,0 +1,246 @@
+// Connected components of the baseline-pixel graph (the null vectors of the
+// destriping operator, Eq. 13 with the full model of Eq. 8) and the
+// per-component projection.
+//
+// Build: a lock-free union-find over the baselines (hooks by compare-and-swap,
+// always the larger root under the smaller, so parents only decrease and no
+// cycle can form; finds halve their path), fed by one wavefront per valid
+// pixel that links the baselines of the pixel's elements; then each baseline
+// takes its root, roots are numbered in increasing order and, when there is
+// more than one component, the members of each are listed in increasing
+// baseline order (a deterministic order, so sums over a component do not
+// depend on scheduling).
+#include <hip/hip_runtime.h>
+
+#include "dst_comp.h"
+
+namespace dst {
+namespace {
+
+constexpr int kBlk = 256;
+
+__device__ __forceinline__ int32_t uf_load(const int32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ void uf_store(int32_t* p, int32_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Loads and stores of values other threads wrote through atomics or in
+// other wavefronts, at device scope (not served from a stale L1 line).
+__device__ __forceinline__ uint32_t ld_u32(const uint32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ void st_u32(uint32_t* p, uint32_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Root of x with path halving.  Parents only ever point to smaller indices,
+// so the walk ends.
+__device__ int32_t uf_find(int32_t* parent, int32_t x) {
+  int32_t p = uf_load(parent + x);
+  while (p != x) {
+    const int32_t gp = uf_load(parent + p);
+    if (gp != p) uf_store(parent + x, gp);  // gp is an ancestor of x: the invariant holds
+    x = p;
+    p = gp;
+  }
+  return x;
+}
+
+__device__ void uf_union(int32_t* parent, int32_t a, int32_t b) {
+  a = uf_find(parent, a);
+  b = uf_find(parent, b);
+  while (a != b) {
+    if (a < b) {
+      const int32_t t = a;
+      a = b;
+      b = t;
+    }
+    // hook root a (the larger) under b; on failure a was hooked meanwhile
+    const int32_t old = atomicCAS(parent + a, a, b);
+    if (old == a) return;
+    a = uf_find(parent, old);
+    b = uf_find(parent, b);
+  }
+}
+
+__global__ void __launch_bounds__(kBlk) k_uf_init(int64_t n_b, int32_t* __restrict__ parent,
+                                                  int32_t* __restrict__ ncomp) {
+  for (int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; b < n_b; b += (int64_t)gridDim.x * blockDim.x)
+    parent[b] = (int32_t)b;
+  if (blockIdx.x == 0 && threadIdx.x < 4) ncomp[threadIdx.x] = 0;
+}
+
+// One wavefront per compact pixel with a valid T block: every element whose
+// baseline differs from its predecessor's is linked to the pixel's first.
+__global__ void __launch_bounds__(kBlk) k_uf_link(int64_t n_obs, const int64_t* __restrict__ elem_start,
+                                                  const int32_t* __restrict__ eb, const uint8_t* __restrict__ valid,
+                                                  int32_t* __restrict__ parent) {
+  const int lane = threadIdx.x & 63;
+  const int64_t nwave = (int64_t)gridDim.x * (kBlk / 64);
+  for (int64_t c = (int64_t)blockIdx.x * (kBlk / 64) + (threadIdx.x >> 6); c < n_obs; c += nwave) {
+    if (!(valid[c] & 1)) continue;
+    const int64_t e0 = elem_start[c], e1 = elem_start[c + 1];
+    if (e1 - e0 < 2) continue;
+    const int32_t first = eb[e0];
+    for (int64_t e = e0 + 1 + lane; e < e1; e += 64) {
+      const int32_t b = eb[e];
+      if (b != eb[e - 1]) uf_union(parent, first, b);
+    }
+  }
+}
+
+// label[b] = root of b for baselines with valid samples (-1 otherwise); roots
+// are counted.
+__global__ void __launch_bounds__(kBlk) k_uf_label(int64_t n_b, const int32_t* __restrict__ nvalid_T,
+                                                   int32_t* __restrict__ parent, int32_t* __restrict__ label,
+                                                   int32_t* __restrict__ ncomp) {
+  for (int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; b < n_b; b += (int64_t)gridDim.x * blockDim.x) {
+    if (nvalid_T[b] > 0) {
+      const int32_t r = uf_find(parent, (int32_t)b);
+      label[b] = r;
+      if (r == (int32_t)b) atomicAdd(ncomp, 1);
+    } else {
+      label[b] = -1;
+    }
+  }
+}
+
+// Exclusive scan over one workgroup of 1024 threads; returns the exclusive
+// prefix of v and writes the total to *total (all threads).
+__device__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* lds, uint32_t* total) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  uint32_t inc = v;
+  for (int off = 1; off < 64; off <<= 1) {
+    const uint32_t t = __shfl_up(inc, off, 64);
+    if (lane >= off) inc += t;
+  }
+  if (lane == 63) lds[wave] = inc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t run = 0;
+    for (int w = 0; w < nw; ++w) {
+      const uint32_t t = lds[w];
+      lds[w] = run;
+      run += t;
+    }
+    lds[32] = run;
+  }
+  __syncthreads();
+  const uint32_t out = lds[wave] + inc - v;
+  *total = lds[32];
+  __syncthreads();
+  return out;
+}
+
+// Component lists when there is more than one component (one workgroup of
+// 1024 threads; returns at once otherwise).  label[b] becomes the compact
+// component id; cursor holds the id of each root, then the fill cursors.
+__global__ void __launch_bounds__(1024) k_comp_lists(int64_t n_b, int32_t* __restrict__ label,
+                                                     uint32_t* __restrict__ start, uint32_t* __restrict__ member,
+                                                     uint32_t* __restrict__ cursor,
+                                                     const int32_t* __restrict__ ncomp_dev) {
+  const int ncomp = *ncomp_dev;
+  if (ncomp <= 1) return;
+  __shared__ uint32_t lds[64];
+  // compact ids of the roots, in increasing order
+  uint32_t run = 0;
+  for (int64_t b0 = 0; b0 < n_b; b0 += blockDim.x) {
+    const int64_t b = b0 + threadIdx.x;
+    const uint32_t f = (b < n_b && uf_load(label + b) == (int32_t)b) ? 1u : 0u;
+    uint32_t tot;
+    const uint32_t ex = block_exclusive_scan(f, lds, &tot);
+    if (f) st_u32(cursor + b, run + ex);
+    run += tot;
+  }
+  for (int64_t c = threadIdx.x; c <= ncomp; c += blockDim.x) st_u32(start + c, 0u);
+  __syncthreads();
+  // relabel with the compact id (each thread reads and writes only its own
+  // label; the roots' ids stay in cursor) and count the members
+  for (int64_t b = threadIdx.x; b < n_b; b += blockDim.x) {
+    const int32_t r = uf_load(label + b);
+    if (r >= 0) {
+      const uint32_t c = ld_u32(cursor + r);
+      uf_store(label + b, (int32_t)c);
+      atomicAdd(start + c, 1u);
+    }
+  }
+  __syncthreads();
+  // counts -> offsets
+  run = 0;
+  for (int64_t c0 = 0; c0 <= ncomp; c0 += blockDim.x) {
+    const int64_t c = c0 + threadIdx.x;
+    const uint32_t v = c < ncomp ? ld_u32(start + c) : 0u;
+    uint32_t tot;
+    const uint32_t ex = block_exclusive_scan(v, lds, &tot);
+    if (c <= ncomp) st_u32(start + c, run + ex);
+    run += tot;
+  }
+  __syncthreads();
+  for (int64_t c = threadIdx.x; c < ncomp; c += blockDim.x) st_u32(cursor + c, ld_u32(start + c));
+  __syncthreads();
+  // members in increasing baseline order: wavefront 0 takes 64 baselines at a
+  // time; lanes of one component get consecutive slots in lane order
+  if (threadIdx.x >= 64) return;
+  const int lane = threadIdx.x;
+  const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;
+  for (int64_t b0 = 0; b0 < n_b; b0 += 64) {
+    const int64_t b = b0 + lane;
+    const int32_t c = b < n_b ? uf_load(label + b) : -1;
+    bool pending = c >= 0;
+    while (__ballot(pending)) {
+      const uint64_t pm = __ballot(pending);
+      const int leader = __ffsll((unsigned long long)pm) - 1;
+      const int32_t lc = __shfl(c, leader, 64);
+      const bool mine = pending && c == lc;
+      const uint64_t mm = __ballot(mine);
+      // the leader takes the component's next slots (read-modify-write, so
+      // later chunks see every earlier update)
+      uint32_t base = lane == leader ? atomicAdd(cursor + lc, (uint32_t)__popcll(mm)) : 0u;
+      base = __shfl(base, leader, 64);
+      if (mine) {
+        st_u32(member + base + __popcll(mm & below), (uint32_t)b);
+        pending = false;
+      }
+    }
+  }
+}
+
+__global__ void __launch_bounds__(1024) k_comp_project(CompView cv, double* __restrict__ x, int64_t sb, int Rp) {
+  __shared__ double lds[16 * 64];
+  const int ncomp = *cv.ncomp;
+  if (ncomp <= 1) return;
+  (void)comp_project_block(cv, ncomp, x, nullptr, sb, Rp, lds);
+}
+
+unsigned grid_of(int64_t n, int64_t per, unsigned cap) {
+  int64_t g = (n + per - 1) / per;
+  if (g < 1) g = 1;
+  if (g > cap) g = cap;
+  return (unsigned)g;
+}
+
+}  // namespace
+
+hipError_t launch_components(int64_t n_b, int64_t n_obs, const int64_t* elem_start, const int32_t* eb,
+                             const uint8_t* valid, const int32_t* nvalid_T, Comp& C, hipStream_t st) {
+  hipLaunchKernelGGL(k_uf_init, dim3(grid_of(n_b, kBlk, 4096)), dim3(kBlk), 0, st, n_b, C.parent, C.ncomp);
+  if (n_obs > 0)
+    hipLaunchKernelGGL(k_uf_link, dim3(grid_of(n_obs, kBlk / 64, 65536)), dim3(kBlk), 0, st, n_obs, elem_start, eb,
+                       valid, C.parent);
+  hipLaunchKernelGGL(k_uf_label, dim3(grid_of(n_b, kBlk, 4096)), dim3(kBlk), 0, st, n_b, nvalid_T, C.parent, C.label,
+                     C.ncomp);
+  hipLaunchKernelGGL(k_comp_lists, dim3(1), dim3(1024), 0, st, n_b, C.label, C.start, C.member, C.cursor, C.ncomp);
+  return hipGetLastError();
+}
+
+hipError_t launch_comp_project(const CompView& cv, double* x, int64_t sb, int Rp, hipStream_t st) {
+  if (!cv.ncomp) return hipSuccess;
+  hipLaunchKernelGGL(k_comp_project, dim3(1), dim3(1024), 0, st, cv, x, sb, Rp);
+  return hipGetLastError();
+}
+
+}  // namespace dst

@@ -17,6 +17,7 @@
 
 #include <cstdint>
 
+#include "dst_comp.h"
 #include "dst_internal.h"
 #include "dst_runs.h"
 
@@ -34,6 +35,7 @@ struct MultiCtl {
   double r_norm[kMaxRhs];
   double mu_b[kMaxRhs];     // T mean of b removed at start-up
   double true_norm[kMaxRhs];
+  double corr[kMaxRhs];     // p.(K p - P K p) when the graph has several components
   int32_t iter[kMaxRhs];
   int32_t done[kMaxRhs];    // DONE_* codes; DONE_PAD marks padding slots
   double n_e;               // number of T-valid baselines
@@ -93,7 +95,13 @@ hipError_t launch_multi_unbin(const View& vc, const Runs& W, const Multi& mu, in
 hipError_t launch_multi_start(const View& v, const Multi& mu, double* b, double* a, double* r, double* z, double* p,
                               const double* J, MultiCtl* ctl, double* partials, double tol, int max_iter,
                               hipStream_t st);
-hipError_t launch_multi_alpha(const View& vc, const Multi& mu, MultiCtl* ctl, const double* partials, hipStream_t st);
+// With several components of the baseline-pixel graph, q = K p loses each
+// component's mean in place (per right-hand side) and ctl->corr the matching
+// p.q correction; nothing happens with one component.
+hipError_t launch_multi_comp(const View& v, const Multi& mu, const CompView& cv, double* q, const double* p,
+                             MultiCtl* ctl, hipStream_t st);
+hipError_t launch_multi_alpha(const View& vc, const Multi& mu, MultiCtl* ctl, const double* partials,
+                              const CompView& cv, hipStream_t st);
 int multi_update_blocks(const View& v, const Multi& mu);
 hipError_t launch_multi_update(const View& v, const Multi& mu, double* a, double* r, double* z, const double* q,
                                const double* p, const double* J, MultiCtl* ctl, double* partials, hipStream_t st);

@@ -653,16 +653,33 @@ __global__ void __launch_bounds__(kBlock) k_multi_init_fin(int n_part, int R, in
   }
 }
 
-// alpha_r = r.z / (p.K p) with K p projected on the T null space.
+// Several components: q loses each component's mean (per right-hand side)
+// and ctl->corr[r] = sum over components of mean * (sum of p over the component).
+__global__ void __launch_bounds__(1024) k_multi_comp(CompView cv, double* __restrict__ q,
+                                                     const double* __restrict__ p, int64_t sb, int Rp,
+                                                     MultiCtl* __restrict__ ctl) {
+  if (ctl->running == 0) return;
+  const int ncomp = *cv.ncomp;
+  if (ncomp <= 1) return;
+  __shared__ double lds[16 * 64];
+  const double corr = comp_project_block(cv, ncomp, q, p, sb, Rp, lds);
+  if ((int)threadIdx.x < Rp) ctl->corr[threadIdx.x] = corr;
+}
+
+// alpha_r = r.z / (p.K p) with K p projected on the T null space (one
+// component: the mean mu of its T part, applied by the update; several: q
+// was projected in place by k_multi_comp).
 __global__ void __launch_bounds__(kBlock) k_multi_alpha(int n_part, int Rp, MultiCtl* __restrict__ ctl,
-                                                        const double* __restrict__ partials) {
+                                                        const double* __restrict__ partials,
+                                                        const int32_t* __restrict__ ncomp_dev) {
   if (ctl->running == 0) return;
   __shared__ double lds[3][kBlock];
   sum_partials_by_rhs<3>(partials, n_part, Rp, lds);
   const int t = threadIdx.x;
+  const bool split = ncomp_dev && *ncomp_dev > 1;
   if (t < Rp && ctl->done[t] == DONE_RUNNING) {
-    const double mu = ctl->n_e > 0.0 ? lds[1][t] / ctl->n_e : 0.0;
-    const double pkp = lds[0][t] - mu * lds[2][t];
+    const double mu = split ? 0.0 : (ctl->n_e > 0.0 ? lds[1][t] / ctl->n_e : 0.0);
+    const double pkp = split ? lds[0][t] - ctl->corr[t] : lds[0][t] - mu * lds[2][t];
     ctl->mu[t] = mu;
     if (!isfinite(pkp))
       ctl->done[t] = DONE_NAN;
@@ -993,9 +1010,17 @@ hipError_t launch_multi_start(const View& v, const Multi& mu, double* b, double*
   return hipGetLastError();
 }
 
+hipError_t launch_multi_comp(const View& v, const Multi& mu, const CompView& cv, double* q, const double* p,
+                             MultiCtl* ctl, hipStream_t st) {
+  if (!cv.ncomp) return hipSuccess;
+  hipLaunchKernelGGL(k_multi_comp, dim3(1), dim3(1024), 0, st, cv, q, p, (int64_t)v.n_streams * mu.Rp, mu.Rp, ctl);
+  return hipGetLastError();
+}
+
 hipError_t launch_multi_alpha(const View& vc, const Multi& mu, MultiCtl* ctl, const double* partials,
-                              hipStream_t st) {
-  hipLaunchKernelGGL(k_multi_alpha, dim3(1), dim3(kBlock), 0, st, multi_unbin_blocks(vc), mu.Rp, ctl, partials);
+                              const CompView& cv, hipStream_t st) {
+  hipLaunchKernelGGL(k_multi_alpha, dim3(1), dim3(kBlock), 0, st, multi_unbin_blocks(vc), mu.Rp, ctl, partials,
+                     cv.ncomp);
   return hipGetLastError();
 }
 

@@ -6,6 +6,7 @@
 #include <cstdint>
 
 #include "dst_internal.h"
+#include "dst_comp.h"
 
 namespace dst {
 
@@ -62,8 +63,11 @@ hipError_t launch_bin_pixel(const View& vc, int psi_f32, const Transpose& T, con
 hipError_t launch_unbin_cg(const View& vc, int psi_f32, const double* m4, const int32_t* nvalid, const double* p,
                            double* q, CgCtl* ctl, double* partials, hipStream_t st);
 // Single-workgroup finishes of the CG step (alpha) and of the residual update (beta).
-// alpha reads n_part partials of each kind (n_b from k_unbin_cg).
-hipError_t launch_cg_alpha(int64_t n_part, CgCtl* ctl, const double* partials, hipStream_t st);
+// alpha reads n_part partials of each kind (n_b from k_unbin_cg); when the
+// baseline-pixel graph has several components it projects q = K p in place
+// (p: the search direction).
+hipError_t launch_cg_alpha(int64_t n_part, CgCtl* ctl, const double* partials, const CompView& cv, double* q,
+                           const double* p, hipStream_t st);
 hipError_t launch_cg_beta(int n_part, CgCtl* ctl, const double* partials, hipStream_t st);
 // p = z + beta p (z == NULL: p unchanged) and pw4 = interleaved w .* p
 hipError_t launch_p_update4(const View& v, double* p, const double* z, double* pw4, const CgCtl* ctl, int use_beta,

@@ -21,6 +21,7 @@
 #include "dst_internal.h"
 #include "dst_trig.h"
 #include "dst_pixel.h"
+#include "dst_comp.h"
 
 namespace dst {
 namespace {
@@ -489,14 +490,19 @@ __global__ void __launch_bounds__(kBlock) k_unbin_cg(View v, const double* __res
   }
 }
 
-// Finishes the step length: mu (mean of the T part of K p over T-valid
-// baselines, the null-space projection) and alpha = r.z / p.(P K p), from
-// n_part partials of each kind (per baseline from k_unbin_cg, per workgroup
-// from the run rescan).  One workgroup; fixed summation order.
+// Finishes the step length: the null-space projection of K p and
+// alpha = r.z / p.(P K p), from n_part partials of each kind (per baseline
+// from k_unbin_cg, per workgroup from the run rescan).  With one component
+// of the baseline-pixel graph the projection is mu, the mean of the T part
+// of K p over T-valid baselines (applied by the residual update); with more,
+// q = K p loses each component's mean here, in place, and p.(P K p) the
+// matching sum.  One workgroup; fixed summation order.
 __global__ void __launch_bounds__(1024) k_cg_alpha(int64_t n_part, CgCtl* __restrict__ ctl,
-                                                   const double* __restrict__ partials) {
+                                                   const double* __restrict__ partials, CompView cv,
+                                                   double* __restrict__ q, const double* __restrict__ p) {
   if (ctl->done) return;
   __shared__ double lds[3 * 16];
+  __shared__ double clds[16 * 64];
   double tot[3] = {0.0, 0.0, 0.0};
   for (int64_t j = threadIdx.x; j < n_part; j += blockDim.x) {
     tot[0] += partials[j];
@@ -504,9 +510,12 @@ __global__ void __launch_bounds__(1024) k_cg_alpha(int64_t n_part, CgCtl* __rest
     tot[2] += partials[2 * n_part + j];
   }
   block_sum<3>(tot, lds);
+  const int ncomp = cv.ncomp ? *cv.ncomp : 0;
+  double corr = 0.0;
+  if (ncomp > 1) corr = comp_project_block(cv, ncomp, q, p, 1, 1, clds);
   if (threadIdx.x == 0) {
-    const double mu = ctl->n_e > 0.0 ? tot[1] / ctl->n_e : 0.0;
-    const double pkp = tot[0] - mu * tot[2];
+    const double mu = ncomp > 1 ? 0.0 : (ctl->n_e > 0.0 ? tot[1] / ctl->n_e : 0.0);
+    const double pkp = ncomp > 1 ? tot[0] - corr : tot[0] - mu * tot[2];
     ctl->mu = mu;
     if (!isfinite(pkp)) {
       ctl->done = DONE_NAN;
@@ -805,8 +814,9 @@ hipError_t launch_unbin_cg(const View& v, int psi_f32, const double* m4, const i
   return hipGetLastError();
 }
 
-hipError_t launch_cg_alpha(int64_t n_part, CgCtl* ctl, const double* partials, hipStream_t st) {
-  hipLaunchKernelGGL(k_cg_alpha, dim3(1), dim3(1024), 0, st, n_part, ctl, partials);
+hipError_t launch_cg_alpha(int64_t n_part, CgCtl* ctl, const double* partials, const CompView& cv, double* q,
+                           const double* p, hipStream_t st) {
+  hipLaunchKernelGGL(k_cg_alpha, dim3(1), dim3(1024), 0, st, n_part, ctl, partials, cv, q, p);
   return hipGetLastError();
 }
 

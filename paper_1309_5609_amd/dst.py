@@ -31,7 +31,8 @@ DST_SOLVE_AUTOTUNE = 16
 DST_SOLVE_GMRES = 32
 DST_NOISE_ACCUMULATE = 1
 
-EXPORTS = ("dst_version", "dst_create", "dst_destroy", "dst_last_error", "dst_pixel_setup", "dst_bin", "dst_unbin",
+EXPORTS = ("dst_version", "dst_create", "dst_destroy", "dst_last_error", "dst_synchronize", "dst_pixel_setup",
+           "dst_bin", "dst_unbin",
            "dst_baseline_reduce", "dst_residual", "dst_apply_operator", "dst_solve", "dst_solve_batched",
            "dst_pointing_expand", "dst_noise_generate")
 
@@ -54,7 +55,7 @@ class dst_solve_info(ctypes.Structure):
                 ("n_valid_pix", ctypes.c_int64 * 2), ("n_valid_samples", ctypes.c_int64 * 2),
                 ("t_setup_ms", ctypes.c_double), ("t_iter_ms", ctypes.c_double), ("t_total_ms", ctypes.c_double),
                 ("t_bin_ms", ctypes.c_double), ("t_apply_ms", ctypes.c_double), ("t_unbin_ms", ctypes.c_double),
-                ("t_update_ms", ctypes.c_double), ("n_runs", ctypes.c_int64)]
+                ("t_update_ms", ctypes.c_double), ("n_runs", ctypes.c_int64), ("n_components", ctypes.c_int64)]
 
 
 SCAN_FIELDS = ("sample_rate_hz", "spin_period_s", "elevation_deg", "latitude_deg", "az0_deg", "lst0_rad",
@@ -93,6 +94,7 @@ def library(path: str = LIB_PATH) -> ctypes.CDLL:
         "dst_create": ([ctypes.POINTER(vp), i32], i32),
         "dst_destroy": ([vp], i32),
         "dst_last_error": ([vp], ctypes.c_char_p),
+        "dst_synchronize": ([vp, vp], i32),
         "dst_pixel_setup": ([vp, P, vp, vp, vp, vp], i32),
         "dst_bin": ([vp, P, vp, u32, vp, vp, vp], i32),
         "dst_unbin": ([vp, P, vp, vp, vp], i32),
@@ -154,9 +156,53 @@ class Context:
         return rc
 
 
+def _is_float(t) -> bool:
+    import torch
+    return t.dtype in (torch.float32, torch.float64)
+
+
+def _dev_index(t) -> int:
+    return t.device.index if t.device.index is not None else 0
+
+
+def _tensor(name: str, t, shape=None, dtypes=None, device=None, min_numel=None):
+    """Check a tensor argument: a contiguous torch tensor on GPU ``device`` of an allowed dtype and shape."""
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise ValueError(f"{name} must be a torch tensor (got {type(t).__name__})")
+    if t.device.type != "cuda":
+        raise ValueError(f"{name} must be on a GPU (got {t.device})")
+    if device is not None and _dev_index(t) != device:
+        raise ValueError(f"{name} is on cuda:{_dev_index(t)}, the context on cuda:{device}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if dtypes is not None and t.dtype not in dtypes:
+        raise ValueError(f"{name} must have dtype {' or '.join(str(d) for d in dtypes)} (got {t.dtype})")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)} (got {tuple(t.shape)})")
+    if min_numel is not None and t.numel() < min_numel:
+        raise ValueError(f"{name} must hold at least {min_numel} elements (got {t.numel()})")
+    return t
+
+
+def _floats():
+    import torch
+    return (torch.float32, torch.float64)
+
+
+def _f64():
+    import torch
+    return (torch.float64,)
+
+
 @dataclass
 class Problem:
-    """Device-side problem: torch tensors kept alive with the C struct."""
+    """Device-side problem: torch tensors kept alive with the C struct.
+
+    ``pix`` int32 [n_samples]; ``psi`` float32/float64 [n_samples] (None for
+    streams "T"); ``tod`` float32/float64 [n_streams][n_samples] or None; all
+    contiguous on one GPU.
+    """
 
     pix: object
     psi: object
@@ -179,8 +225,28 @@ class Problem:
     def n_streams(self) -> int:
         return N_STREAMS[self.streams]
 
-    def c_struct(self) -> dst_problem:
+    def validate(self, device=None, need_tod: bool = False) -> None:
+        """Raise ValueError unless the arrays have the dtypes, shapes and device the C ABI reads."""
         import torch
+        if self.streams not in STREAMS:
+            raise ValueError(f"streams must be one of {sorted(STREAMS)} (got {self.streams!r})")
+        _tensor("pix", self.pix, dtypes=(torch.int32,), device=device)
+        if self.pix.dim() != 1:
+            raise ValueError(f"pix must be 1-D (got shape {tuple(self.pix.shape)})")
+        dev = _dev_index(self.pix) if device is None else device
+        n = self.n_samples
+        if self.psi is not None:
+            _tensor("psi", self.psi, shape=(n,), dtypes=_floats(), device=dev)
+        elif self.streams != "T":
+            raise ValueError(f"psi is needed for streams {self.streams!r}")
+        if self.tod is not None:
+            _tensor("tod", self.tod, shape=(self.n_streams, n), dtypes=_floats(), device=dev)
+        elif need_tod:
+            raise ValueError("tod is needed by this call")
+
+    def c_struct(self, device=None, need_tod: bool = False) -> dst_problem:
+        import torch
+        self.validate(device, need_tod)
         s = dst_problem()
         s.n_samples = self.n_samples
         s.n_pix = int(self.n_pix)
@@ -221,54 +287,65 @@ def _empty(shape, dtype, device):
     return torch.empty(shape, dtype=dtype, device=device)
 
 
+def dst_synchronize(ctx: Context) -> None:
+    """Wait for the current stream; raise DstError (DST_EBOUNDS) for a device-detected error since the last report."""
+    ctx.check(ctx.lib.dst_synchronize(ctx.handle, _stream()))
+
+
 def dst_pixel_setup(ctx: Context, prob: Problem):
-    """Hits [n_pix] int32, blocks [n_pix][4] f64 (M_II, M_QQ, M_QU, M_UU), valid [n_pix] uint8."""
+    """Hits [n_pix] int32, blocks [n_pix][4] f64 (M_II, M_QQ, M_QU, M_UU), valid [n_pix] uint8 (asynchronous)."""
     import torch
+    s = prob.c_struct(ctx.device)
     dev = prob.pix.device
     hits = _empty((prob.n_pix,), torch.int32, dev)
     blocks = _empty((prob.n_pix, 4), torch.float64, dev)
     valid = _empty((prob.n_pix,), torch.uint8, dev)
-    s = prob.c_struct()
     ctx.check(ctx.lib.dst_pixel_setup(ctx.handle, ctypes.byref(s), _ptr(hits), _ptr(blocks), _ptr(valid), _stream()))
     return hits, blocks, valid
 
 
 def dst_bin(ctx: Context, prob: Problem, baselines=None, use_tod: bool = True, as_map: bool = False):
-    """Sum maps s = A^T W (d - F a) (or the map M^-1 s with ``as_map``) [n_pix][3], and hits."""
+    """Sum maps s = A^T W (d - F a) (or the map M^-1 s with ``as_map``) [n_pix][3], and hits (asynchronous)."""
     import torch
+    s = prob.c_struct(ctx.device, need_tod=use_tod)
+    if baselines is not None:
+        _tensor("baselines", baselines, shape=(prob.n_streams, prob.n_baselines), dtypes=_f64(), device=ctx.device)
     dev = prob.pix.device
     out = _empty((prob.n_pix, 3), torch.float64, dev)
     hits = _empty((prob.n_pix,), torch.int32, dev)
     flags = (DST_BIN_USE_TOD if use_tod else 0) | (DST_BIN_MAP if as_map else 0)
-    s = prob.c_struct()
     ctx.check(ctx.lib.dst_bin(ctx.handle, ctypes.byref(s), _ptr(baselines), flags, _ptr(out), _ptr(hits), _stream()))
     return out, hits
 
 
 def dst_unbin(ctx: Context, prob: Problem, m):
-    """Timelines A m [n_streams][n_samples] f64 from a map [n_pix][3]."""
+    """Timelines A m [n_streams][n_samples] f64 from a map [n_pix][3] f64 (asynchronous)."""
     import torch
+    s = prob.c_struct(ctx.device)
+    _tensor("map", m, shape=(prob.n_pix, 3), dtypes=_f64(), device=ctx.device)
     out = _empty((prob.n_streams, prob.n_samples), torch.float64, prob.pix.device)
-    s = prob.c_struct()
-    ctx.check(ctx.lib.dst_unbin(ctx.handle, ctypes.byref(s), _ptr(m.contiguous()), _ptr(out), _stream()))
+    ctx.check(ctx.lib.dst_unbin(ctx.handle, ctypes.byref(s), _ptr(m), _ptr(out), _stream()))
     return out
 
 
 def dst_baseline_reduce(ctx: Context, prob: Problem, x):
-    """F^T W x over valid samples, [n_streams][n_b] f64; x has prob's timeline dtype."""
+    """F^T W x over valid samples, [n_streams][n_b] f64; x float32/float64 [n_streams][n_samples] (asynchronous)."""
     import torch
+    s = prob.c_struct(ctx.device)
+    _tensor("x", x, shape=(prob.n_streams, prob.n_samples), dtypes=_floats(), device=ctx.device)
     out = _empty((prob.n_streams, prob.n_baselines), torch.float64, prob.pix.device)
-    s = prob.c_struct()
     s.tod_dtype = DST_F32 if x.dtype == torch.float32 else DST_F64
-    ctx.check(ctx.lib.dst_baseline_reduce(ctx.handle, ctypes.byref(s), _ptr(x.contiguous()), _ptr(out), _stream()))
+    ctx.check(ctx.lib.dst_baseline_reduce(ctx.handle, ctypes.byref(s), _ptr(x), _ptr(out), _stream()))
     return out
 
 
 def dst_residual(ctx: Context, prob: Problem, a=None, use_tod: bool = True):
-    """F^T Z (d - F a), [n_streams][n_b] f64 (d = 0 without ``use_tod``)."""
+    """F^T Z (d - F a), [n_streams][n_b] f64 (d = 0 without ``use_tod``; asynchronous)."""
     import torch
+    s = prob.c_struct(ctx.device, need_tod=use_tod)
+    if a is not None:
+        _tensor("a", a, shape=(prob.n_streams, prob.n_baselines), dtypes=_f64(), device=ctx.device)
     out = _empty((prob.n_streams, prob.n_baselines), torch.float64, prob.pix.device)
-    s = prob.c_struct()
     if not use_tod:
         s.tod = None
     ctx.check(ctx.lib.dst_residual(ctx.handle, ctypes.byref(s), _ptr(a), _ptr(out), _stream()))
@@ -278,21 +355,14 @@ def dst_residual(ctx: Context, prob: Problem, a=None, use_tod: bool = True):
 def dst_apply_operator(ctx: Context, prob: Problem, v):
     """K v = F^T Z F v, [n_streams][n_b] f64."""
     import torch
+    s = prob.c_struct(ctx.device)
+    _tensor("v", v, shape=(prob.n_streams, prob.n_baselines), dtypes=_f64(), device=ctx.device)
     out = _empty((prob.n_streams, prob.n_baselines), torch.float64, prob.pix.device)
-    s = prob.c_struct()
-    ctx.check(ctx.lib.dst_apply_operator(ctx.handle, ctypes.byref(s), _ptr(v.contiguous()), _ptr(out), _stream()))
+    ctx.check(ctx.lib.dst_apply_operator(ctx.handle, ctypes.byref(s), _ptr(v), _ptr(out), _stream()))
     return out
 
 
-def dst_solve(ctx: Context, prob: Problem, tol: float = 1e-10, max_iter: int = 1000, a0=None, flags: int = 0,
-              check_every: int = 0, maps: bool = True, allow_noconv: bool = True, restart: int = 0) -> dict:
-    """Destripe: baselines, destriped and binned maps, hits and solver info."""
-    import torch
-    dev = prob.pix.device
-    a = _empty((prob.n_streams, prob.n_baselines), torch.float64, dev)
-    m = _empty((prob.n_pix, 3), torch.float64, dev) if maps else None
-    mb = _empty((prob.n_pix, 3), torch.float64, dev) if maps else None
-    hits = _empty((prob.n_pix,), torch.int32, dev)
+def _opts(tol, max_iter, check_every, flags, restart, a0):
     opts = dst_solve_opts()
     opts.tol = tol
     opts.max_iter = max_iter
@@ -300,22 +370,35 @@ def dst_solve(ctx: Context, prob: Problem, tol: float = 1e-10, max_iter: int = 1
     opts.flags = flags
     opts.restart = restart
     opts.a0 = None if a0 is None else a0.data_ptr()
-    info = dst_solve_info()
-    s = prob.c_struct()
-    allow = (DST_OK, DST_ENOCONV) if allow_noconv else (DST_OK,)
-    rc = ctx.check(ctx.lib.dst_solve(ctx.handle, ctypes.byref(s), ctypes.byref(opts), _ptr(a), _ptr(m), _ptr(mb),
-                                     _ptr(hits), ctypes.byref(info), _stream()), allow)
-    out = {k: getattr(info, k) for k, _ in dst_solve_info._fields_}
-    out["n_valid_pix"] = tuple(info.n_valid_pix)
-    out["n_valid_samples"] = tuple(info.n_valid_samples)
-    out.update(status=rc, baselines=a, destriped_map=m, binned_map=mb, hits=hits)
-    return out
+    return opts
 
 
 def _info_dict(info) -> dict:
     out = {k: getattr(info, k) for k, _ in dst_solve_info._fields_}
     out["n_valid_pix"] = tuple(info.n_valid_pix)
     out["n_valid_samples"] = tuple(info.n_valid_samples)
+    return out
+
+
+def dst_solve(ctx: Context, prob: Problem, tol: float = 1e-10, max_iter: int = 1000, a0=None, flags: int = 0,
+              check_every: int = 0, maps: bool = True, allow_noconv: bool = True, restart: int = 0) -> dict:
+    """Destripe: baselines, destriped and binned maps, hits and solver info."""
+    import torch
+    s = prob.c_struct(ctx.device, need_tod=True)
+    if a0 is not None:
+        _tensor("a0", a0, shape=(prob.n_streams, prob.n_baselines), dtypes=_f64(), device=ctx.device)
+    dev = prob.pix.device
+    a = _empty((prob.n_streams, prob.n_baselines), torch.float64, dev)
+    m = _empty((prob.n_pix, 3), torch.float64, dev) if maps else None
+    mb = _empty((prob.n_pix, 3), torch.float64, dev) if maps else None
+    hits = _empty((prob.n_pix,), torch.int32, dev)
+    opts = _opts(tol, max_iter, check_every, flags, restart, a0)
+    info = dst_solve_info()
+    allow = (DST_OK, DST_ENOCONV) if allow_noconv else (DST_OK,)
+    rc = ctx.check(ctx.lib.dst_solve(ctx.handle, ctypes.byref(s), ctypes.byref(opts), _ptr(a), _ptr(m), _ptr(mb),
+                                     _ptr(hits), ctypes.byref(info), _stream()), allow)
+    out = _info_dict(info)
+    out.update(status=rc, baselines=a, destriped_map=m, binned_map=mb, hits=hits)
     return out
 
 
@@ -327,7 +410,7 @@ def dst_solve_batched(ctx: Context, probs, tol: float = 1e-10, max_iter: int = 1
     """
     import torch
     n = len(probs)
-    structs = (dst_problem * n)(*[p.c_struct() for p in probs])
+    structs = (dst_problem * n)(*[p.c_struct(ctx.device, need_tod=True) for p in probs])
     outs = []
     for p in probs:
         dev = p.pix.device
@@ -342,13 +425,7 @@ def dst_solve_batched(ctx: Context, probs, tol: float = 1e-10, max_iter: int = 1
             return None
         return (ctypes.c_void_p * n)(*[o[key].data_ptr() for o in outs])
 
-    opts = dst_solve_opts()
-    opts.tol = tol
-    opts.max_iter = max_iter
-    opts.check_every = check_every
-    opts.flags = flags
-    opts.restart = 0
-    opts.a0 = None
+    opts = _opts(tol, max_iter, check_every, flags, 0, None)
     infos = (dst_solve_info * n)()
     allow = (DST_OK, DST_ENOCONV) if allow_noconv else (DST_OK,)
     b, m, mb, h = ptrs("baselines"), ptrs("destriped_map"), ptrs("binned_map"), ptrs("hits")
@@ -363,13 +440,14 @@ def dst_solve_batched(ctx: Context, probs, tol: float = 1e-10, max_iter: int = 1
 
 
 def dst_pointing_expand(ctx: Context, spec, nside: int, n_samples: int, start: int = 0, psi_dtype=None,
-                        with_psi: bool = True, device="cuda:0"):
+                        with_psi: bool = True, device=None):
     """Pointing of samples start .. start + n_samples - 1 of a scan, computed on the GPU.
 
     ``spec`` is any object with the ``dst_scan`` field names (``synth.ScanSpec``).
     Returns (pix int32 [n], psi [n] float64 / float32 or None).
     """
     import torch
+    device = device or f"cuda:{ctx.device}"
     sc = dst_scan(*[float(getattr(spec, f)) for f in SCAN_FIELDS])
     pix = _empty((n_samples,), torch.int32, device)
     dt = torch.float32 if psi_dtype in ("float32", torch.float32) or getattr(psi_dtype, "__name__", "") == "float32" \
@@ -383,11 +461,16 @@ def dst_pointing_expand(ctx: Context, spec, nside: int, n_samples: int, start: i
 
 def dst_noise_generate(ctx: Context, seed: int, stream_id: int, n_samples: int, segment: int,
                        sample_rate_hz: float, sigma: float, fknee_hz: float, alpha: float, out=None,
-                       dtype=None, accumulate: bool = False, device="cuda:0"):
-    """White + 1/f noise timeline on the GPU (into ``out`` when given; added to it with ``accumulate``)."""
+                       dtype=None, accumulate: bool = False, device=None):
+    """White + 1/f noise timeline on the GPU (into ``out`` when given; added to it with ``accumulate``).
+
+    ``out``: contiguous float32/float64 tensor on the context's GPU with at least n_samples elements.
+    """
     import torch
+    device = device or f"cuda:{ctx.device}"
     if out is None:
         out = torch.zeros((n_samples,), dtype=dtype or torch.float64, device=device)
+    _tensor("out", out, dtypes=_floats(), device=ctx.device, min_numel=int(n_samples))
     code = DST_F32 if out.dtype == torch.float32 else DST_F64
     ctx.check(ctx.lib.dst_noise_generate(ctx.handle, int(seed), int(stream_id), int(n_samples), int(segment),
                                          float(sample_rate_hz), float(sigma), float(fknee_hz), float(alpha),

@@ -31,7 +31,7 @@ def test_library_exports_every_declared_symbol():
     for name in declared():
         assert name in syms, name
     lib = dst.library()
-    assert lib.dst_version() == 1
+    assert lib.dst_version() == 2
 
 
 def test_struct_layouts():
@@ -39,7 +39,7 @@ def test_struct_layouts():
     assert ctypes.sizeof(dst.dst_problem) == 96
     assert dst.dst_problem.pix.offset == 40 and dst.dst_problem.weight.offset == 64
     assert ctypes.sizeof(dst.dst_solve_opts) == 32 and dst.dst_solve_opts.a0.offset == 24
-    assert ctypes.sizeof(dst.dst_solve_info) == 128
+    assert ctypes.sizeof(dst.dst_solve_info) == 136
     assert ctypes.sizeof(dst.dst_scan) == 64
 
 
@@ -53,7 +53,7 @@ def test_layouts_agree_with_the_c_compiler(tmp_path):
     exe = tmp_path / "layout"
     subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
     got = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()
-    assert got == ["96", "40", "64", "32", "24", "128", "64", "56"]
+    assert got == ["96", "40", "64", "32", "24", "136", "64", "56"]
     assert dst.dst_scan.sidereal_day_s.offset == 56
 
 

@@ -62,15 +62,14 @@ def test_iqu_solve(ctx, name, solver):
     assert np.array_equal(out["hits"].cpu().numpy(), ref.hits)
     assert out["n_valid_pix"][0] == int(ref.valid_T.sum())
     assert out["n_valid_pix"][0] < int((ref.hits > 0).sum())  # the 3x3 cut drops pixels here
-    # with few valid pixels the baseline-pixel graph splits into components; the library fixes
-    # one global T mean, the oracle one mean per component: compare in the oracle's canonical form
+    # with few valid pixels the baseline-pixel graph splits into components, each with its own
+    # null vector; both sides report zero mean per component, so they compare directly
     st = O.prepare(p.pix, p.psi, p.n_pix, p.baseline_length, p.streams, p.weights)
-    a = O.canonical_compact(st, out["baselines"].cpu().numpy())
-    assert rel(a, ref.baselines) < 1e-9
+    _, lab = O.t_components(st)
+    assert out["n_components"] == len(np.unique(lab[lab >= 0]))
+    assert rel(out["baselines"].cpu().numpy(), ref.baselines) < 1e-9
     ok = ref.valid_T
-    # the destriped map is the oracle's map of the data minus the library's own baselines
-    m_ref = O.map_compact(st, p.tod, out["baselines"].cpu().numpy())
-    assert rel(out["destriped_map"].cpu().numpy()[ok], m_ref[ok]) < 1e-9
+    assert rel(out["destriped_map"].cpu().numpy()[ok], ref.destriped_map[ok]) < 1e-9
     assert rel(out["binned_map"].cpu().numpy()[ok], ref.binned_map[ok]) < 1e-12
     assert np.all(out["destriped_map"].cpu().numpy()[~ok] == 0.0)
     assert abs(out["iterations"] - ref.iterations) <= 2

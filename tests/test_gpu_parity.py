@@ -214,9 +214,32 @@ def test_errors(ctx):
     # pixel index out of range is detected on the device
     bad = dst.Problem(dp.pix.clone(), dp.psi, dp.tod, dp.n_pix, dp.baseline_length, dp.streams, dp.weights)
     bad.pix[17] = p.n_pix + 5
+    dst.dst_bin(ctx, bad)  # asynchronous: the flag is reported at the next synchronisation
     with pytest.raises(dst.DstError) as e:
-        dst.dst_bin(ctx, bad)
+        dst.dst_synchronize(ctx)
     assert e.value.code == -6
+    dst.dst_synchronize(ctx)  # reported once, then cleared
+    with pytest.raises(dst.DstError) as e:
+        dst.dst_solve(ctx, bad)  # a synchronising call reports its own
+    assert e.value.code == -6
+    dst.dst_unbin(ctx, bad, torch.zeros((p.n_pix, 3), dtype=torch.float64, device="cuda"))
+    with pytest.raises(dst.DstError) as e:
+        dst.dst_synchronize(ctx)
+    assert e.value.code == -6
+    # the binding rejects arrays the library would misread
+    for kw in (dict(pix=dp.pix.to(torch.int64)), dict(psi=dp.psi.half()), dict(tod=dp.tod[:, ::2]),
+               dict(tod=dp.tod.t().contiguous()), dict(psi=dp.psi.cpu())):
+        q = dst.Problem(dp.pix, dp.psi, dp.tod, dp.n_pix, dp.baseline_length, dp.streams, dp.weights)
+        for k, val in kw.items():
+            setattr(q, k, val)
+        with pytest.raises(ValueError):
+            dst.dst_bin(ctx, q)
+    with pytest.raises(ValueError):
+        dst.dst_noise_generate(ctx, 1, 0, 1000, 256, 50.0, 1e-3, 0.0, 1.0,
+                               out=torch.zeros(999, dtype=torch.float64, device="cuda"))
+    with pytest.raises(ValueError):
+        dst.dst_noise_generate(ctx, 1, 0, 1000, 256, 50.0, 1e-3, 0.0, 1.0,
+                               out=torch.zeros(1000, dtype=torch.float16, device="cuda"))
     # argument errors
     for kw in (dict(baseline_length=0), dict(n_pix=0), dict(weights=(1.0, -1.0, 1.0)), dict(streams="T"),
                dict(rcond_cut=1.0)):

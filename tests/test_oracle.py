@@ -42,9 +42,53 @@ def test_golden_hand_cases():
             sol = O.solve(pix, psi, tod, c["n_pix"], c["baseline_length"], c["streams"], c["weights"], tol=1e-15)
             assert np.allclose(sol.baselines, c["baselines"], atol=1e-13)
             assert np.allclose(sol.destriped_map, c["destriped_map"], atol=1e-13)
+        if "components" in c:
+            _, lab = O.t_components(st)
+            groups = sorted(sorted(np.nonzero(lab == g)[0].tolist()) for g in np.unique(lab[lab >= 0]))
+            assert groups == sorted(c["components"])
+
+
+def test_two_islands_need_one_mean_each():
+    """A single mean over all valid baselines (instead of one per island) fails the two-island hand case."""
+    c = [x for x in json.load(open(GOLDEN))["cases"] if x["name"] == "T_two_islands_and_an_empty_baseline"][0]
+    st = O.prepare(np.array(c["pix"]), None, c["n_pix"], c["baseline_length"], "T", c["weights"])
+    a = np.array(c["baselines"], dtype=float)
+    shifted = a.copy()
+    shifted[0, :2] += 1.0
+    shifted[0, 2:4] -= 1.0  # global mean unchanged, island means moved
+    assert np.allclose(O.canonical_compact(st, shifted), a, atol=1e-14)
+    # the same null vectors for K: adding the shift changes no residual
+    tod = np.array(c["tod"])
+    assert np.allclose(O.K_compact(st, shifted - a), 0.0, atol=1e-12)
+    assert np.allclose(O.rhs_compact(st, tod) - O.K_compact(st, a), 0.0, atol=1e-12)
 
 
 # --------------------------------------------------------------------------- setup pins
+
+@pytest.mark.parametrize("kw", [dict(), dict(mask_fraction=0.08), dict(streams="T"), dict(streams="QU"),
+                                dict(weights=(2.0e6, 5.0e6, 0.7e6)), dict(streams="IQU", n_samples=20000, L=400)])
+def test_jacobi_is_inverse_diagonal_of_FtWF(kw):
+    """The preconditioner is 1 / diag(F^T W F) over valid samples (0 for empty baselines), checked against the
+    explicit entries of the dense route and against a loop over samples."""
+    p = toy(**kw)
+    st = O.prepare(*[args(p)[i] for i in (0, 1, 3, 4, 5, 6)])
+    J = O._compact(st.pt, O.jacobi(st))
+    d = D.baseline_weights(*[args(p)[i] for i in (0, 1, 3, 4, 5, 6)])
+    want = np.where(d > 0, 1.0 / np.where(d > 0, d, 1.0), 0.0)
+    assert np.allclose(J, want, rtol=1e-15, atol=0)
+    # loop: every valid (sample, stream) adds w_k to its baseline
+    rows = O.ROWS[p.streams]
+    brute = np.zeros_like(d)
+    for t in range(p.n_samples):
+        q = p.pix[t]
+        if q < 0:
+            continue
+        for r, k in enumerate(rows):
+            ok = st.valid_T[q] if (k == 0 or p.streams == "IQU") else st.valid_QU[q]
+            if ok:
+                brute[r, t // p.baseline_length] += p.weights[k]
+    assert np.array_equal(brute, d)
+    assert np.any(d == 0) == bool(np.any(J == 0))
 
 def test_hits_brute_force():
     p = toy(mask_fraction=0.05)

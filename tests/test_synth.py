@@ -8,14 +8,14 @@ from synth.noise import one_over_f, segmented
 from synth.scan import one_period
 
 
-@pytest.mark.parametrize("nside", [1, 2, 4, 8, 64])
+@pytest.mark.parametrize("nside", [1, 2, 4, 8, 64, 256, 512])
 def test_ring_round_trip_all_centres(nside):
     p = np.arange(nside2npix(nside))
     th, ph = pix2ang_ring(nside, p)
     assert np.array_equal(ang2pix_ring(nside, th, ph), p)
 
 
-@pytest.mark.parametrize("nside", [1, 4, 16])
+@pytest.mark.parametrize("nside", [1, 4, 16, 256, 512])
 def test_ring_structure(nside):
     counts = ring_of_pixel_counts(nside)
     assert counts.sum() == 12 * nside * nside
@@ -35,6 +35,21 @@ def test_ring_structure(nside):
         assert abs(zs[i - 1] - (1 - i * i / (3.0 * nside * nside))) < 1e-12
     for i in range(nside, 3 * nside + 1):
         assert abs(zs[i - 1] - (4.0 / 3.0 - 2.0 * i / (3.0 * nside))) < 1e-12
+
+
+@pytest.mark.parametrize("nside", [256, 512])
+def test_points_near_a_centre_fall_in_its_pixel(nside):
+    """Directions a small fraction of a pixel away from a centre map to that pixel (the benchmark resolutions)."""
+    rng = np.random.default_rng(nside)
+    p = rng.integers(0, nside2npix(nside), 200000)
+    th, ph = pix2ang_ring(nside, p)
+    size = np.sqrt(4 * np.pi / nside2npix(nside))
+    dth = rng.uniform(-0.05, 0.05, p.size) * size
+    dph = rng.uniform(-0.05, 0.05, p.size) * size / np.maximum(np.sin(th), 1e-12)
+    # stay clear of the poles, where the phi jitter is not small in angle
+    keep = np.sin(th) > 4 * size
+    got = ang2pix_ring(nside, np.clip(th + dth, 0, np.pi), np.mod(ph + dph, 2 * np.pi))
+    assert np.array_equal(got[keep], p[keep])
 
 
 def test_poles_and_boundaries():
