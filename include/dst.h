@@ -154,6 +154,21 @@ enum { DST_BIN_USE_TOD = 1u, DST_BIN_MAP = 2u };
 int dst_bin(dst_ctx* ctx, const dst_problem* prob, const double* baselines, uint32_t flags, double* map_out,
             int32_t* hits_out, void* stream);
 
+/* dst_bin without any device allocation, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc).  Same arguments, results and asynchrony as dst_bin;
+ * the per-pixel work arrays (hits, blocks, inverse, validity, sums: 101 bytes
+ * per pixel) live in one fixed device array of the library, sized for
+ * n_pix <= 786432 (12 * 256^2, a full N_side 256 sky; about 79 MB), which
+ * each GPU the library runs on holds until the process ends.
+ *   n_pix > 786432  -> DST_EINVAL (nothing launched).
+ * Every call on one GPU shares that GPU's array (across contexts too) and
+ * leaves its contents behind; the call clears what it accumulates into, but
+ * calls that overlap in time on one GPU (different streams or contexts
+ * without synchronisation in between) race on it. */
+int dst_bin_noalloc(dst_ctx* ctx, const dst_problem* prob, const double* baselines, uint32_t flags, double* map_out,
+                    int32_t* hits_out, void* stream);
+
 /* Scan a map to timelines (the P and R matrices of Eqs. 2-6):
  *   tod_out_k(t) = A_k(t) . map[p(t)] for unmasked samples, 0 for masked ones.
  *   map [n_pix][3] f64, tod_out [n_streams][n_samples] f64.  Validity is not

@@ -38,6 +38,7 @@ struct dst_ctx {
   CgCtl* ctl_host = nullptr;  // pinned mirror of the device CG scalars
   int* err_host = nullptr;    // pinned mirror of the device error flag
   int* err_dev = nullptr;     // device error flag (sticky: set by kernels, cleared when reported)
+  unsigned char* scratch = nullptr;  // device address of this device's fixed scratch (dst_bin_noalloc)
   // pinned mirrors of the setup's four counts and of the true residual norm
   struct Readback {
     unsigned long long counts[4];
@@ -209,21 +210,29 @@ struct Setup {
   int* err = nullptr;
 };
 
-int run_setup(dst_ctx* ctx, const dst_problem* prob, Setup& S, bool baselines, double* blocks_out, hipStream_t st) {
-  View& v = S.v;
+// Hits, blocks, inverse and validity into the buffers S already names
+// (hits, M4, Minv4, valid, counts); allocates nothing.
+int setup_pixels(dst_ctx* ctx, const dst_problem* prob, Setup& S, double* blocks_out, hipStream_t st) {
+  const View& v = S.v;
   S.psi_f32 = prob->psi_dtype == DST_F32;
   S.tod_f32 = prob->tod_dtype == DST_F32;
-  DST_TRY(ws(ctx, "hits", v.n_pix, &S.hits));
-  DST_TRY(ws(ctx, "M4", 4 * v.n_pix, &S.M4));
-  DST_TRY(ws(ctx, "Minv4", 4 * v.n_pix, &S.Minv4));
-  DST_TRY(ws(ctx, "valid", v.n_pix, &S.valid));
-  DST_TRY(ws(ctx, "counts", 4, &S.counts));
   S.err = ctx->err_dev;
   HIP_TRY(dst::launch_fill_u32(reinterpret_cast<uint32_t*>(S.hits), v.n_pix, 0u, st));
   HIP_TRY(dst::launch_fill(S.M4, 4 * v.n_pix, 0.0, st));
   HIP_TRY(dst::launch_fill_u32(reinterpret_cast<uint32_t*>(S.counts), 8, 0u, st));
   HIP_TRY(dst::launch_pointing(v, S.psi_f32, S.hits, S.M4, S.err, st));
   HIP_TRY(dst::launch_invert(v, S.hits, S.M4, prob->rcond_cut, S.Minv4, S.valid, blocks_out, S.counts, st));
+  return DST_OK;
+}
+
+int run_setup(dst_ctx* ctx, const dst_problem* prob, Setup& S, bool baselines, double* blocks_out, hipStream_t st) {
+  const View& v = S.v;
+  DST_TRY(ws(ctx, "hits", v.n_pix, &S.hits));
+  DST_TRY(ws(ctx, "M4", 4 * v.n_pix, &S.M4));
+  DST_TRY(ws(ctx, "Minv4", 4 * v.n_pix, &S.Minv4));
+  DST_TRY(ws(ctx, "valid", v.n_pix, &S.valid));
+  DST_TRY(ws(ctx, "counts", 4, &S.counts));
+  DST_TRY(setup_pixels(ctx, prob, S, blocks_out, st));
   if (baselines) {
     DST_TRY(ws(ctx, "nvalid", 2 * v.n_b, &S.nvalid));
     DST_TRY(ws(ctx, "J", (size_t)v.n_streams * v.n_b, &S.J));
@@ -260,6 +269,60 @@ hipError_t copy4to3(double* dst3, const double* src4, int64_t n_pix, hipStream_t
   return hipMemcpy2DAsync(dst3, 3 * sizeof(double), src4, 4 * sizeof(double), 3 * sizeof(double), (size_t)n_pix,
                           hipMemcpyDeviceToDevice, st);
 }
+
+int check_bin_args(dst_ctx* ctx, const dst_problem* prob, uint32_t flags, const double* map_out, View& v) {
+  DST_TRY(check_problem(ctx, prob, (flags & DST_BIN_USE_TOD) != 0, v));
+  if (v.iqu) return fail(ctx, DST_EINVAL, "DST_IQU streams are not supported by this entry point");
+  if (!map_out) return fail(ctx, DST_EINVAL, "map_out is NULL");
+  if (flags & ~(uint32_t)(DST_BIN_USE_TOD | DST_BIN_MAP)) return fail(ctx, DST_EINVAL, "unknown flags %u", flags);
+  return DST_OK;
+}
+
+// Binning after the pixel setup: s = A^T W (d - F a) into s4, then the sum
+// map or M^-1 s into map_out, and the hits.  Allocates nothing.
+int bin_pass(dst_ctx* ctx, const dst_problem* prob, const Setup& S, const double* baselines, uint32_t flags,
+             double* s4, double* map_out, int32_t* hits_out, hipStream_t st) {
+  const View& v = S.v;
+  const bool use_tod = flags & DST_BIN_USE_TOD;
+  HIP_TRY(dst::launch_fill(s4, 4 * v.n_pix, 0.0, st));
+  if (use_tod || baselines)
+    HIP_TRY(dst::launch_bin(v, S.psi_f32, use_tod ? prob->tod : nullptr, S.tod_f32, baselines, -1.0, S.valid, s4,
+                            S.err, nullptr, st));
+  if (flags & DST_BIN_MAP) {
+    HIP_TRY(dst::launch_apply(v.n_pix, s4, S.Minv4, map_out, 3, nullptr, nullptr, st));
+  } else {
+    HIP_TRY(copy4to3(map_out, s4, v.n_pix, st));
+  }
+  if (hits_out) HIP_TRY(hipMemcpyAsync(hits_out, S.hits, v.n_pix * sizeof(int32_t), hipMemcpyDeviceToDevice, st));
+  return issued(ctx);
+}
+
+// Fixed scratch of dst_bin_noalloc: per pixel the hits (4 B), blocks (32 B),
+// block inverse (32 B), validity (1 B) and sums (32 B), plus four counters,
+// each array on a 256-byte boundary, for up to kNoAllocMaxPix pixels (a full
+// N_side 256 sky).  Host code reaches it only through the device address
+// hipGetSymbolAddress gives at context creation (dst_ctx::scratch).
+constexpr int64_t kNoAllocMaxPix = 12 * 256 * 256;
+constexpr size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+constexpr size_t kScratchBytes = align256(4 * kNoAllocMaxPix) + 2 * align256(32 * kNoAllocMaxPix) +
+                                 align256(kNoAllocMaxPix) + align256(32 * kNoAllocMaxPix) + 256;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+void carve_scratch(unsigned char* base, int64_t n_pix, Setup& S, double** s4) {
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    unsigned char* p = base + off;
+    off += align256(bytes);
+    return p;
+  };
+  S.hits = reinterpret_cast<int32_t*>(take(4 * (size_t)n_pix));
+  S.M4 = reinterpret_cast<double*>(take(32 * (size_t)n_pix));
+  S.Minv4 = reinterpret_cast<double*>(take(32 * (size_t)n_pix));
+  S.valid = take((size_t)n_pix);
+  *s4 = reinterpret_cast<double*>(take(32 * (size_t)n_pix));
+  S.counts = reinterpret_cast<unsigned long long*>(take(4 * sizeof(unsigned long long)));
+}
+
 
 // out = F^T Z x with x = tod + bsign * F base (either may be NULL).
 int operator_pass(dst_ctx* ctx, Setup& S, const void* tod, const double* base, double bsign, double* out,
@@ -981,6 +1044,12 @@ int dst_create(dst_ctx** out, int device) {
     dst_destroy(ctx);
     return DST_ENOMEM;
   }
+  // the fixed scratch of dst_bin_noalloc: its address on this device (each
+  // device holds its own copy of the array)
+  if (hipGetSymbolAddress(reinterpret_cast<void**>(&ctx->scratch), HIP_SYMBOL(scratch)) != hipSuccess) {
+    (void)hipGetLastError();
+    ctx->scratch = nullptr;
+  }
   *out = ctx;
   return DST_OK;
 }
@@ -1028,31 +1097,35 @@ int dst_pixel_setup(dst_ctx* ctx, const dst_problem* prob, int32_t* hits_out, do
 int dst_bin(dst_ctx* ctx, const dst_problem* prob, const double* baselines, uint32_t flags, double* map_out,
             int32_t* hits_out, void* stream) {
   View v{};
-  const bool use_tod = flags & DST_BIN_USE_TOD;
-  DST_TRY(check_problem(ctx, prob, use_tod, v));
-  if (v.iqu) return fail(ctx, DST_EINVAL, "DST_IQU streams are not supported by this entry point");
-  if (!map_out) return fail(ctx, DST_EINVAL, "map_out is NULL");
-  if (flags & ~(uint32_t)(DST_BIN_USE_TOD | DST_BIN_MAP)) return fail(ctx, DST_EINVAL, "unknown flags %u", flags);
+  DST_TRY(check_bin_args(ctx, prob, flags, map_out, v));
   ctx->err.clear();
   DeviceGuard g(ctx->device);
   hipStream_t st = static_cast<hipStream_t>(stream);
   Setup S;
   S.v = v;
   DST_TRY(run_setup(ctx, prob, S, false, nullptr, st));
-  double *s4 = nullptr, *m4 = nullptr;
+  double* s4 = nullptr;
   DST_TRY(ws(ctx, "s4", 4 * v.n_pix, &s4));
-  HIP_TRY(dst::launch_fill(s4, 4 * v.n_pix, 0.0, st));
-  if (use_tod || baselines)
-    HIP_TRY(dst::launch_bin(v, S.psi_f32, use_tod ? prob->tod : nullptr, S.tod_f32, baselines, -1.0, S.valid, s4,
-                            S.err, nullptr, st));
-  if (flags & DST_BIN_MAP) {
-    HIP_TRY(dst::launch_apply(v.n_pix, s4, S.Minv4, map_out, 3, nullptr, nullptr, st));
-  } else {
-    HIP_TRY(copy4to3(map_out, s4, v.n_pix, st));
-  }
-  (void)m4;
-  if (hits_out) HIP_TRY(hipMemcpyAsync(hits_out, S.hits, v.n_pix * sizeof(int32_t), hipMemcpyDeviceToDevice, st));
-  return issued(ctx);
+  return bin_pass(ctx, prob, S, baselines, flags, s4, map_out, hits_out, st);
+}
+
+int dst_bin_noalloc(dst_ctx* ctx, const dst_problem* prob, const double* baselines, uint32_t flags, double* map_out,
+                    int32_t* hits_out, void* stream) {
+  View v{};
+  DST_TRY(check_bin_args(ctx, prob, flags, map_out, v));
+  if (v.n_pix > kNoAllocMaxPix)
+    return fail(ctx, DST_EINVAL, "dst_bin_noalloc: n_pix %lld exceeds the fixed scratch limit of %lld pixels",
+                (long long)v.n_pix, (long long)kNoAllocMaxPix);
+  if (!ctx->scratch) return fail(ctx, DST_EHIP, "dst_bin_noalloc: the scratch array has no device address");
+  ctx->err.clear();
+  DeviceGuard g(ctx->device);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  Setup S;
+  S.v = v;
+  double* s4 = nullptr;
+  carve_scratch(ctx->scratch, v.n_pix, S, &s4);
+  DST_TRY(setup_pixels(ctx, prob, S, nullptr, st));
+  return bin_pass(ctx, prob, S, baselines, flags, s4, map_out, hits_out, st);
 }
 
 int dst_unbin(dst_ctx* ctx, const dst_problem* prob, const double* map, double* tod_out, void* stream) {

@@ -32,7 +32,7 @@ DST_SOLVE_GMRES = 32
 DST_NOISE_ACCUMULATE = 1
 
 EXPORTS = ("dst_version", "dst_create", "dst_destroy", "dst_last_error", "dst_synchronize", "dst_pixel_setup",
-           "dst_bin", "dst_unbin",
+           "dst_bin", "dst_bin_noalloc", "dst_unbin",
            "dst_baseline_reduce", "dst_residual", "dst_apply_operator", "dst_solve", "dst_solve_batched",
            "dst_pointing_expand", "dst_noise_generate")
 
@@ -97,6 +97,7 @@ def library(path: str = LIB_PATH) -> ctypes.CDLL:
         "dst_synchronize": ([vp, vp], i32),
         "dst_pixel_setup": ([vp, P, vp, vp, vp, vp], i32),
         "dst_bin": ([vp, P, vp, u32, vp, vp, vp], i32),
+        "dst_bin_noalloc": ([vp, P, vp, u32, vp, vp, vp], i32),
         "dst_unbin": ([vp, P, vp, vp, vp], i32),
         "dst_baseline_reduce": ([vp, P, vp, vp, vp], i32),
         "dst_residual": ([vp, P, vp, vp, vp], i32),
@@ -316,6 +317,23 @@ def dst_bin(ctx: Context, prob: Problem, baselines=None, use_tod: bool = True, a
     flags = (DST_BIN_USE_TOD if use_tod else 0) | (DST_BIN_MAP if as_map else 0)
     ctx.check(ctx.lib.dst_bin(ctx.handle, ctypes.byref(s), _ptr(baselines), flags, _ptr(out), _ptr(hits), _stream()))
     return out, hits
+
+
+def dst_bin_noalloc(ctx: Context, prob: Problem, map_out, hits_out=None, baselines=None, use_tod: bool = True,
+                    as_map: bool = False):
+    """As ``dst_bin``, into caller-given ``map_out`` [n_pix][3] f64 (and ``hits_out`` [n_pix] int32), with the
+    library's fixed scratch: the call allocates no device memory (n_pix <= 786432)."""
+    import torch
+    s = prob.c_struct(ctx.device, need_tod=use_tod)
+    if baselines is not None:
+        _tensor("baselines", baselines, shape=(prob.n_streams, prob.n_baselines), dtypes=_f64(), device=ctx.device)
+    _tensor("map_out", map_out, shape=(prob.n_pix, 3), dtypes=_f64(), device=ctx.device)
+    if hits_out is not None:
+        _tensor("hits_out", hits_out, shape=(prob.n_pix,), dtypes=(torch.int32,), device=ctx.device)
+    flags = (DST_BIN_USE_TOD if use_tod else 0) | (DST_BIN_MAP if as_map else 0)
+    ctx.check(ctx.lib.dst_bin_noalloc(ctx.handle, ctypes.byref(s), _ptr(baselines), flags, _ptr(map_out),
+                                      _ptr(hits_out), _stream()))
+    return map_out, hits_out
 
 
 def dst_unbin(ctx: Context, prob: Problem, m):
