@@ -15,10 +15,12 @@
 #include <map>
 #include <tuple>
 #include <unordered_map>
+#include <unordered_set>
 #include <vector>
 
 #include "dst.h"
 #include "dst_comp.h"
+#include "dst_group.h"
 #include "dst_internal.h"
 #include "dst_multi.h"
 #include "dst_pixel.h"
@@ -26,6 +28,8 @@
 
 using dst::CgCtl;
 using dst::View;
+
+constexpr int kMaxGroup = 64;  // problems advanced together by one group of launches
 
 struct dst_ctx {
   int device = 0;
@@ -35,6 +39,8 @@ struct dst_ctx {
     size_t bytes = 0;
   };
   std::unordered_map<std::string, Buf> ws;
+  std::string ws_prefix;      // prepended to slot names (one namespace per problem of a group)
+  std::unordered_set<std::string> ws_shared;  // slots that stay unprefixed (setup-only arrays)
   CgCtl* ctl_host = nullptr;  // pinned mirror of the device CG scalars
   int* err_host = nullptr;    // pinned mirror of the device error flag
   int* err_dev = nullptr;     // device error flag (sticky: set by kernels, cleared when reported)
@@ -47,6 +53,7 @@ struct dst_ctx {
   };
   Readback* rb_host = nullptr;
   dst::MultiCtl* mctl_host = nullptr;  // pinned mirror of the batched CG state
+  CgCtl* gctl_host = nullptr;          // pinned mirrors of the CG scalars of a problem group [kMaxGroup]
   hipStream_t cap = nullptr;  // private stream on which iteration graphs are captured
   int unbin_bpw = 4;          // launch shape of the run rescan (baselines per wavefront)
   int bin_lpp = 0;            // launch shape of the run binning (lanes per pixel; 0: default 32)
@@ -93,10 +100,12 @@ int fail(dst_ctx* ctx, int code, const char* fmt, ...) {
     if (rc_ != DST_OK) return rc_; \
   } while (0)
 
-// Device workspace slot `name`, grown to at least `bytes`.
+// Device workspace slot `name` (inside the context's current slot prefix),
+// grown to at least `bytes`.
 int ws_get(dst_ctx* ctx, const char* name, size_t bytes, void** out) {
   if (bytes == 0) bytes = 256;
-  auto& b = ctx->ws[name];
+  auto& b = ctx->ws[(ctx->ws_prefix.empty() || ctx->ws_shared.count(name)) ? std::string(name)
+                                                                           : ctx->ws_prefix + name];
   if (b.bytes < bytes) {
     if (b.ptr) (void)hipFree(b.ptr);
     b.ptr = nullptr;
@@ -111,6 +120,14 @@ int ws_get(dst_ctx* ctx, const char* name, size_t bytes, void** out) {
   }
   *out = b.ptr;
   return DST_OK;
+}
+
+// Frees slot `name` of the current prefix (no-op when absent).
+void ws_release(dst_ctx* ctx, const char* name) {
+  auto it = ctx->ws.find(ctx->ws_prefix + name);
+  if (it == ctx->ws.end()) return;
+  if (it->second.ptr) (void)hipFree(it->second.ptr);
+  ctx->ws.erase(it);
 }
 
 template <typename T>
@@ -355,6 +372,7 @@ struct Plan {
   int lpp = 0;            // launch shapes of the run binning (0: default) and rescan
   int bpw = 4;
   dst::Comp C;            // components of the baseline-pixel graph (streams with a T-like row)
+  int dense_t = 0;        // run form, intensity only: p and m kept as one double per baseline / pixel
   const int32_t* cid() const { return runs ? W.cid : T.cid; }
   dst::CompView cv() const { return C.ncomp ? C.view() : dst::CompView{}; }
 };
@@ -387,6 +405,7 @@ int build_runs_plan(dst_ctx* ctx, const dst_problem* prob, Plan& P, const void* 
   S.psi_f32 = prob->psi_dtype == DST_F32;
   S.tod_f32 = prob->tod_dtype == DST_F32;
   dst::Runs& W = P.W;
+  P.dense_t = (v.rowT >= 0 && v.rowQ < 0 && !v.iqu) ? 1 : 0;
   DST_TRY(ws(ctx, "r_tcount", dst::run_tiles(v.n_t), &W.tcount));
   DST_TRY(ws(ctx, "r_toff", dst::run_tiles(v.n_t), &W.toff));
   size_t tmp_bytes = 0;
@@ -558,7 +577,7 @@ int plan_unbin(dst_ctx* ctx, Plan& P, const double* p, double* q, CgCtl* ctl, do
 // out = K v = F^T Z F v through the solver's kernels.
 int plan_operator(dst_ctx* ctx, Plan& P, const double* vin, double* out, hipStream_t st) {
   Setup& S = P.S;
-  HIP_TRY(dst::launch_p_update4(S.v, const_cast<double*>(vin), nullptr, P.pw4, nullptr, 0, st));
+  HIP_TRY(dst::launch_p_update4(S.v, const_cast<double*>(vin), nullptr, P.pw4, nullptr, 0, P.dense_t, st));
   DST_TRY(plan_bin(ctx, P, nullptr, st));
   DST_TRY(plan_unbin(ctx, P, vin, out, nullptr, nullptr, st));
   return DST_OK;
@@ -835,6 +854,301 @@ int solve_group(dst_ctx* ctx, const dst_problem* problems, const std::vector<int
   return DST_OK;
 }
 
+// Independent problems with different pointing (the channels of a survey)
+// solved together: each problem gets its own run setup, right-hand side and
+// PCG state (workspace slots under its own prefix; the setup-only arrays are
+// freed once built), then every iteration advances all of them with one
+// launch per phase (bin, rescan, step length, update, beta, p) over one
+// list of workgroups, replayed from one captured graph; a problem that has
+// stopped leaves its workgroups idle.  Outputs as dst_solve per problem.
+int solve_uneven(dst_ctx* ctx, const dst_problem* problems, const std::vector<int>& idx, const dst_solve_opts& opts,
+                 int check_every, const BatchOut& out, hipStream_t st, int* status) {
+  const int n = (int)idx.size();
+  const bool profile = opts.flags & DST_SOLVE_PROFILE;
+  const bool use_graph = !(opts.flags & (DST_SOLVE_NO_GRAPH | DST_SOLVE_PROFILE));
+  struct Member {
+    Plan P;
+    View v;
+    double *b = nullptr, *a = nullptr, *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr, *ka = nullptr;
+    double *part = nullptr, *part2 = nullptr, *rnorm = nullptr, *sd4 = nullptr, *md4 = nullptr;
+    CgCtl* ctl = nullptr;
+    std::string prefix;
+    unsigned long long counts[4] = {0, 0, 0, 0};
+    int32_t ncomp = 0;
+  };
+  std::vector<Member> M(n);
+  EventSet evs;
+  hipEvent_t ev[4];
+  for (auto& e : ev) HIP_TRY(evs.add(&e));
+  HIP_TRY(hipEventRecord(ev[0], st));
+  struct PrefixGuard {
+    dst_ctx* c;
+    ~PrefixGuard() {
+      c->ws_prefix.clear();
+      c->ws_shared.clear();
+    }
+  } pg{ctx};
+  CgCtl* ctls = nullptr;
+  {
+    ctx->ws_prefix.clear();
+    DST_TRY(ws(ctx, "grp_ctl", kMaxGroup, &ctls));
+  }
+  // arrays only the setup reads: one set serves every problem's setup in turn
+  for (const char* name : {"r_tcount", "r_toff", "r_rec", "r_raw", "r_keys0", "r_keys1", "r_vals0", "r_vals1",
+                           "r_t0", "r_tmp", "r_pb", "r_pn", "r_tpix", "r_tn", "r_seg", "r_pk0", "r_pk1", "r_bkey0",
+                           "r_bkey1", "r_nobs", "r_nout", "r_ccount", "sd4", "comp_parent", "comp_cursor", "counts"})
+    ctx->ws_shared.insert(name);
+  for (int k = 0; k < n; ++k) {
+    Member& m = M[k];
+    const dst_problem& pr = problems[idx[k]];
+    DST_TRY(check_problem(ctx, &pr, true, m.v));
+    m.prefix = "grp" + std::to_string(k) + "/";
+    ctx->ws_prefix = m.prefix;
+    const View& v = m.v;
+    const int64_t N = (int64_t)v.n_streams * v.n_b;
+    m.P.full = v;
+    m.P.runs = true;
+    m.P.lpp = 32;
+    m.P.bpw = 4;
+    DST_TRY(ws(ctx, "cg_b", N, &m.b));
+    DST_TRY(build_runs_plan(ctx, &pr, m.P, pr.tod, &m.sd4, &m.md4, m.b, st));
+    if (m.P.W.nb <= 0) return fail(ctx, DST_EHIP, "problem %d: run keys do not pack (internal)", idx[k]);
+    DST_TRY(ws(ctx, "cg_a", N, &m.a));
+    DST_TRY(ws(ctx, "cg_r", N, &m.r));
+    DST_TRY(ws(ctx, "cg_z", N, &m.z));
+    DST_TRY(ws(ctx, "cg_p", N, &m.p));
+    DST_TRY(ws(ctx, "cg_q", N, &m.q));
+    DST_TRY(ws(ctx, "cg_ka", N, &m.ka));
+    const View& vc = m.P.S.v;
+    DST_TRY(ws(ctx, "cg_part", 3 * (size_t)std::max<int64_t>({(int64_t)dst::group_unbin_blocks(vc), v.n_b, 4096}),
+               &m.part));
+    DST_TRY(ws(ctx, "cg_part2", 2 * (size_t)dst::group_vec_blocks(v), &m.part2));
+    DST_TRY(ws(ctx, "cg_rnorm", 1, &m.rnorm));
+    m.ctl = ctls + k;
+    HIP_TRY(dst::launch_fill_u32(reinterpret_cast<uint32_t*>(m.ctl), sizeof(CgCtl) / 4, 0u, st));
+    const dst::CompView cv = m.P.cv();
+    HIP_TRY(dst::launch_comp_project(cv, m.b, 1, 1, st));
+    HIP_TRY(dst::launch_cg_start(v, m.b, nullptr, nullptr, m.a, m.r, m.z, m.p, m.P.S.J, m.ctl, m.part, opts.tol,
+                                 opts.max_iter, st));
+    HIP_TRY(dst::launch_p_update4(v, m.p, nullptr, m.P.pw4, nullptr, 0, m.P.dense_t, st));
+    HIP_TRY(hipMemcpyAsync(m.counts, m.P.S.counts, sizeof m.counts, hipMemcpyDeviceToHost, st));
+    if (m.P.C.ncomp) HIP_TRY(hipMemcpyAsync(&m.ncomp, m.P.C.ncomp, sizeof m.ncomp, hipMemcpyDeviceToHost, st));
+    DST_TRY(finish(ctx, &m.P.S, st));
+  }
+  ctx->ws_prefix.clear();
+  ctx->ws_shared.clear();
+  for (int k = 0; k < n; ++k)
+    if (M[k].counts[2] + M[k].counts[3] == 0)
+      return fail(ctx, DST_EDEGENERATE, "problem %d: no valid sample in the problem", idx[k]);
+
+  // the group's work list, problems ordered by kind: per problem its arrays
+  // and its workgroup ranges
+  auto kind_of = [](const View& v) {
+    return v.iqu ? dst::GK_IQU : (v.rowT >= 0 && v.rowQ >= 0 ? dst::GK_TQU : (v.rowQ >= 0 ? dst::GK_QU : dst::GK_T));
+  };
+  std::vector<int> order(n);
+  for (int k = 0; k < n; ++k) order[k] = k;
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int x, int y) { return kind_of(M[x].P.S.v) < kind_of(M[y].P.S.v); });
+  std::vector<dst::GroupProblem> gp(n);
+  std::vector<uint32_t> vec_start(n + 1, 0u);
+  std::vector<uint32_t> ranges;  // per kind: bin starts [count + 1], then rescan starts [count + 1]
+  dst::GroupLaunch G;
+  int f32 = -1;
+  for (int o = 0; o < n; ++o) {
+    Member& m = M[order[o]];
+    const Setup& S = m.P.S;
+    const dst::Runs& W = m.P.W;
+    dst::GroupProblem& g = gp[o];
+    g.v = S.v;
+    g.kind = kind_of(S.v);
+    g.nb = W.nb;
+    g.dense_t = m.P.dense_t;
+    g.unbin_n = dst::group_unbin_blocks(S.v);
+    g.vec_n = dst::group_vec_blocks(S.v);
+    g.pstart = W.pstart;
+    g.pkey = W.pkey;
+    g.pcs = W.pcs;
+    g.bstart = W.bstart;
+    g.border = W.border;
+    g.tkey = W.tkey;
+    g.tcs = W.tcs;
+    g.Minv4 = S.Minv4;
+    g.valid = S.valid;
+    g.m4 = m.P.m4;
+    g.pw4 = m.P.pw4;
+    g.nvalid = S.nvalid;
+    g.J = S.J;
+    g.a = m.a;
+    g.r = m.r;
+    g.z = m.z;
+    g.p = m.p;
+    g.q = m.q;
+    g.ctl = m.ctl;
+    g.part_unbin = m.part;
+    g.part_update = m.part2;
+    g.cv = m.P.cv();
+    if (g.kind != dst::GK_T) {
+      if (f32 >= 0 && f32 != (int)W.f32) return fail(ctx, DST_EINVAL, "internal: mixed angle precision in a group");
+      f32 = (int)W.f32;
+    }
+    vec_start[o + 1] = vec_start[o] + g.vec_n;
+    dst::GroupSlice& sl = G.kind[g.kind];
+    if (sl.count++ == 0) sl.first = o;
+  }
+  std::vector<size_t> roff(4, 0);
+  for (int K = 0; K < 4; ++K) {
+    dst::GroupSlice& sl = G.kind[K];
+    if (sl.count == 0) continue;
+    roff[K] = ranges.size();
+    ranges.resize(ranges.size() + 2 * (sl.count + 1), 0u);
+    uint32_t* bs = ranges.data() + roff[K];
+    uint32_t* us = bs + sl.count + 1;
+    for (int j = 0; j < sl.count; ++j) {
+      const dst::GroupProblem& g = gp[sl.first + j];
+      bs[j + 1] = bs[j] + dst::group_bin_blocks(g.v.n_pix);
+      us[j + 1] = us[j] + g.unbin_n;
+    }
+    sl.bin_total = bs[sl.count];
+    sl.unbin_total = us[sl.count];
+  }
+  dst::GroupProblem* gp_dev = nullptr;
+  uint32_t *vec_dev = nullptr, *ranges_dev = nullptr;
+  DST_TRY(ws(ctx, "grp_desc", n, &gp_dev));
+  DST_TRY(ws(ctx, "grp_vec", n + 1, &vec_dev));
+  DST_TRY(ws(ctx, "grp_ranges", std::max<size_t>(ranges.size(), 1), &ranges_dev));
+  HIP_TRY(hipMemcpyAsync(gp_dev, gp.data(), n * sizeof(dst::GroupProblem), hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(vec_dev, vec_start.data(), (n + 1) * sizeof(uint32_t), hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(ranges_dev, ranges.data(), ranges.size() * sizeof(uint32_t), hipMemcpyHostToDevice, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  G.prob = gp_dev;
+  G.n = n;
+  G.vec_start = vec_dev;
+  G.vec_total = vec_start[n];
+  G.f32 = f32 > 0 ? 1 : 0;
+  for (int K = 0; K < 4; ++K) {
+    dst::GroupSlice& sl = G.kind[K];
+    if (sl.count == 0) continue;
+    sl.bin_start = ranges_dev + roff[K];
+    sl.unbin_start = sl.bin_start + sl.count + 1;
+  }
+  HIP_TRY(hipEventRecord(ev[1], st));
+
+  CgCtl* h = ctx->gctl_host;
+  HIP_TRY(hipMemcpyAsync(h, ctls, n * sizeof(CgCtl), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  auto running = [&]() {
+    for (int k = 0; k < n; ++k)
+      if (h[k].done == dst::DONE_RUNNING) return true;
+    return false;
+  };
+  EventSet pev;
+  auto iteration = [&](hipStream_t s, bool timed) -> int {
+    if (!timed) {
+      HIP_TRY(dst::launch_group_iteration(G, s));
+      return DST_OK;
+    }
+    hipEvent_t e[4];
+    for (auto& x : e) HIP_TRY(pev.add(&x));
+    HIP_TRY(hipEventRecord(e[0], s));
+    for (int phase = 0; phase < 3; ++phase) {
+      HIP_TRY(dst::launch_group_phase(G, phase, s));
+      HIP_TRY(hipEventRecord(e[phase + 1], s));
+    }
+    return DST_OK;
+  };
+  GraphGuard gg;
+  if (use_graph && running())
+    DST_TRY(capture_graph(ctx, 1, [&](hipStream_t s) { return iteration(s, false); }, &gg.exec));
+  HIP_TRY(hipEventRecord(ev[2], st));
+  int launched = 0;
+  while (running() && launched < opts.max_iter) {
+    const int k = std::min(check_every, opts.max_iter - launched);
+    for (int i = 0; i < k; ++i) {
+      if (gg.exec)
+        HIP_TRY(hipGraphLaunch(gg.exec, st));
+      else
+        DST_TRY(iteration(st, profile));
+    }
+    launched += k;
+    HIP_TRY(hipMemcpyAsync(h, ctls, n * sizeof(CgCtl), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+  }
+  HIP_TRY(hipEventRecord(ev[3], st));
+  std::vector<CgCtl> fin(h, h + n);
+
+  // per problem: canonical baselines, true residual, outputs
+  for (int k = 0; k < n; ++k) {
+    Member& m = M[k];
+    const int i = idx[k];
+    ctx->ws_prefix = m.prefix;
+    const View& v = m.v;
+    const int64_t N = (int64_t)v.n_streams * v.n_b;
+    const dst::CompView cv = m.P.cv();
+    if (!(opts.flags & DST_SOLVE_NO_CANON)) {
+      HIP_TRY(dst::launch_comp_project(cv, m.a, 1, 1, st));
+      HIP_TRY(dst::launch_canonicalise(v, m.a, m.P.S.J, m.part, m.ctl, st));
+    }
+    DST_TRY(plan_operator(ctx, m.P, m.a, m.ka, st));
+    HIP_TRY(dst::launch_comp_project(cv, m.ka, 1, 1, st));
+    HIP_TRY(dst::launch_residual_norm(v, m.b, m.ka, m.P.S.J, m.ctl, m.part, m.rnorm, st));
+    HIP_TRY(hipMemcpyAsync(out.baselines[i], m.a, N * sizeof(double), hipMemcpyDeviceToDevice, st));
+    if (out.maps && out.maps[i])
+      HIP_TRY(dst::launch_scatter(v.n_pix, m.P.cid(), nullptr, nullptr, m.md4, m.P.m4, out.maps[i], st, m.P.dense_t));
+    if (out.binned && out.binned[i])
+      HIP_TRY(dst::launch_scatter(v.n_pix, m.P.cid(), nullptr, nullptr, m.md4, nullptr, out.binned[i], st));
+    if (out.hits && out.hits[i])
+      HIP_TRY(dst::launch_scatter(v.n_pix, m.P.cid(), m.P.S.hits, out.hits[i], m.md4, nullptr, nullptr, st));
+  }
+  ctx->ws_prefix.clear();
+  std::vector<double> rn(n, 0.0);
+  for (int k = 0; k < n; ++k) HIP_TRY(hipMemcpyAsync(&rn[k], M[k].rnorm, sizeof(double), hipMemcpyDeviceToHost, st));
+  DST_TRY(finish(ctx, nullptr, st));
+
+  int max_it = 0;
+  for (int k = 0; k < n; ++k) max_it = std::max(max_it, fin[k].iter);
+  float t_setup = 0.f, t_iter = 0.f, t_total = 0.f;
+  HIP_TRY(hipEventElapsedTime(&t_setup, ev[0], ev[1]));
+  HIP_TRY(hipEventElapsedTime(&t_iter, ev[2], ev[3]));
+  HIP_TRY(hipEventElapsedTime(&t_total, ev[0], ev[3]));
+  double tk[3] = {0.0, 0.0, 0.0};
+  if (profile && !pev.ev.empty()) {
+    const size_t used = std::min<size_t>(pev.ev.size() / 4, (size_t)max_it);
+    for (size_t it = 0; it < used; ++it)
+      for (int j = 0; j < 3; ++j) {
+        float t = 0.f;
+        HIP_TRY(hipEventElapsedTime(&t, pev.ev[4 * it + j], pev.ev[4 * it + j + 1]));
+        tk[j] += t;
+      }
+    for (auto& x : tk) x = used ? x / used : 0.0;
+  }
+  for (int k = 0; k < n; ++k) {
+    const CgCtl& f = fin[k];
+    *status = worse(*status, done_status(f.done));
+    if (!out.infos) continue;
+    dst_solve_info& in = out.infos[idx[k]];
+    in = dst_solve_info{};
+    in.iterations = f.iter;
+    in.converged = f.done == dst::DONE_CONVERGED;
+    in.b_norm = f.b_norm;
+    in.rel_residual = f.b_norm > 0.0 ? f.r_norm / f.b_norm : 0.0;
+    in.true_rel_residual = f.b_norm > 0.0 ? rn[k] / f.b_norm : 0.0;
+    in.n_valid_pix[0] = (int64_t)M[k].counts[0];
+    in.n_valid_pix[1] = (int64_t)M[k].counts[1];
+    in.n_valid_samples[0] = (int64_t)M[k].counts[2];
+    in.n_valid_samples[1] = (int64_t)M[k].counts[3];
+    in.n_components = M[k].ncomp;
+    in.t_setup_ms = t_setup;
+    in.t_iter_ms = max_it > 0 ? t_iter / max_it : 0.0;
+    in.t_total_ms = t_total;
+    in.t_bin_ms = tk[0];
+    in.t_unbin_ms = tk[1];
+    in.t_update_ms = tk[2];
+    in.n_runs = M[k].P.W.R;
+  }
+  return DST_OK;
+}
+
 // Restarted GMRES on K a = b (Eq. 13), right-preconditioned by the Jacobi
 // diagonal J, with the same T null-space projection as the PCG (b and every
 // K v lose their mean over T-valid baselines).  Arnoldi by classical
@@ -1038,6 +1352,8 @@ int dst_create(dst_ctx** out, int device) {
           hipSuccess ||
       hipHostMalloc(reinterpret_cast<void**>(&ctx->mctl_host), sizeof(dst::MultiCtl), hipHostMallocDefault) !=
           hipSuccess ||
+      hipHostMalloc(reinterpret_cast<void**>(&ctx->gctl_host), kMaxGroup * sizeof(CgCtl), hipHostMallocDefault) !=
+          hipSuccess ||
       hipMalloc(reinterpret_cast<void**>(&ctx->err_dev), 4 * sizeof(int)) != hipSuccess ||
       hipMemset(ctx->err_dev, 0, 4 * sizeof(int)) != hipSuccess) {
     (void)hipGetLastError();
@@ -1065,6 +1381,7 @@ int dst_destroy(dst_ctx* ctx) {
   if (ctx->err_dev) (void)hipFree(ctx->err_dev);
   if (ctx->rb_host) (void)hipHostFree(ctx->rb_host);
   if (ctx->mctl_host) (void)hipHostFree(ctx->mctl_host);
+  if (ctx->gctl_host) (void)hipHostFree(ctx->gctl_host);
   if (ctx->cap) (void)hipStreamDestroy(ctx->cap);
   delete ctx;
   return DST_OK;
@@ -1257,7 +1574,7 @@ int dst_solve(dst_ctx* ctx, const dst_problem* prob, const dst_solve_opts* opts_
     ka_ptr = ka;
   }
   HIP_TRY(dst::launch_cg_start(v, b, ka_ptr, opts.a0, a, r, z, p, S.J, ctl, partials, opts.tol, opts.max_iter, st));
-  HIP_TRY(dst::launch_p_update4(v, p, nullptr, P.pw4, nullptr, 0, st));
+  HIP_TRY(dst::launch_p_update4(v, p, nullptr, P.pw4, nullptr, 0, P.dense_t, st));
   if (opts.flags & DST_SOLVE_AUTOTUNE) DST_TRY(autotune(ctx, P, p, ka, st));
 
   // PCG iterations: pixel-major bin + inverse (m = M^-1 A^T W F p) -> rescan and
@@ -1279,7 +1596,7 @@ int dst_solve(dst_ctx* ctx, const dst_problem* prob, const dst_solve_opts* opts_
     if (timed) HIP_TRY(hipEventRecord(e[3], s));
     HIP_TRY(dst::launch_cg_update(v, a, r, z, p, q, S.J, ctl, partials, s));
     HIP_TRY(dst::launch_cg_beta(dst::cg_update_blocks(v), ctl, partials, s));
-    HIP_TRY(dst::launch_p_update4(v, p, z, P.pw4, ctl, 1, s));
+    HIP_TRY(dst::launch_p_update4(v, p, z, P.pw4, ctl, 1, P.dense_t, s));
     if (timed) HIP_TRY(hipEventRecord(e[4], s));
     return DST_OK;
   };
@@ -1352,7 +1669,7 @@ int dst_solve(dst_ctx* ctx, const dst_problem* prob, const dst_solve_opts* opts_
   HIP_TRY(dst::launch_comp_project(cv, ka, 1, 1, st));
   HIP_TRY(dst::launch_residual_norm(v, b, ka, S.J, ctl, partials, rnorm, st));
   HIP_TRY(hipMemcpyAsync(baselines_out, a, N * sizeof(double), hipMemcpyDeviceToDevice, st));
-  if (map_out) HIP_TRY(dst::launch_scatter(v.n_pix, P.cid(), nullptr, nullptr, md4, P.m4, map_out, st));
+  if (map_out) HIP_TRY(dst::launch_scatter(v.n_pix, P.cid(), nullptr, nullptr, md4, P.m4, map_out, st, P.dense_t));
   if (binned_out) HIP_TRY(dst::launch_scatter(v.n_pix, P.cid(), nullptr, nullptr, md4, nullptr, binned_out, st));
   if (hits_out) HIP_TRY(dst::launch_scatter(v.n_pix, P.cid(), S.hits, hits_out, md4, nullptr, nullptr, st));
   HIP_TRY(hipMemcpyAsync(&ctx->rb_host->rnorm, rnorm, sizeof(double), hipMemcpyDeviceToHost, st));
@@ -1453,19 +1770,50 @@ int dst_solve_batched(dst_ctx* ctx, int32_t n_problems, const dst_problem* probl
   }
   const BatchOut out{baselines_out, map_out, binned_out, hits_out, infos};
   int status = DST_OK;
+  // problems that share the operator with no other: solved together as
+  // groups of independent problems (one group per precision of the angle
+  // sums; intensity-only problems have none and join any group)
+  std::vector<int> solo32, solo64, soloT;
   for (const auto& grp : groups) {
-    if (grp.size() == 1) {
-      const int i = grp[0];
-      dst_solve_opts o = opts;
-      const int rc = dst_solve(ctx, &problems[i], &o, baselines_out[i], map_out ? map_out[i] : nullptr,
-                               binned_out ? binned_out[i] : nullptr, hits_out ? hits_out[i] : nullptr,
-                               infos ? &infos[i] : nullptr, stream);
-      if (rc < 0) return rc;
-      status = worse(status, rc);
-      continue;
-    }
+    if (grp.size() != 1) continue;
+    const dst_problem& pr = problems[grp[0]];
+    if (pr.streams == DST_T)
+      soloT.push_back(grp[0]);
+    else if (pr.psi_dtype == DST_F32)
+      solo32.push_back(grp[0]);
+    else
+      solo64.push_back(grp[0]);
+  }
+  std::vector<std::vector<int>> uneven;
+  for (std::vector<int>* lst : {&solo32, &solo64}) {
+    if (lst->empty()) continue;
+    uneven.push_back(*lst);
+  }
+  if (!soloT.empty()) {
+    if (uneven.empty()) uneven.emplace_back();
+    uneven[0].insert(uneven[0].end(), soloT.begin(), soloT.end());
+  }
+  for (const auto& grp : groups) {
+    if (grp.size() == 1) continue;
     const int rc = solve_group(ctx, problems, grp, opts, check_every, out, st, &status);
     if (rc != DST_OK) return rc;
+  }
+  for (const auto& lst : uneven) {
+    for (size_t c0 = 0; c0 < lst.size(); c0 += kMaxGroup) {
+      const std::vector<int> chunk(lst.begin() + c0, lst.begin() + std::min(lst.size(), c0 + kMaxGroup));
+      if (chunk.size() == 1) {
+        const int i = chunk[0];
+        dst_solve_opts o = opts;
+        const int rc = dst_solve(ctx, &problems[i], &o, baselines_out[i], map_out ? map_out[i] : nullptr,
+                                 binned_out ? binned_out[i] : nullptr, hits_out ? hits_out[i] : nullptr,
+                                 infos ? &infos[i] : nullptr, stream);
+        if (rc < 0) return rc;
+        status = worse(status, rc);
+        continue;
+      }
+      const int rc = solve_uneven(ctx, problems, chunk, opts, check_every, out, st, &status);
+      if (rc != DST_OK) return rc;
+    }
   }
   if (status == DST_ENOCONV) fail(ctx, DST_ENOCONV, "at least one problem did not converge");
   return status;

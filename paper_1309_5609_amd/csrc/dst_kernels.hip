@@ -19,6 +19,7 @@
 #include <cmath>
 #include <cstdint>
 
+#include "dst_cg.h"
 #include "dst_internal.h"
 #include "dst_trig.h"
 
@@ -618,27 +619,8 @@ __global__ void __launch_bounds__(kBlock) k_cg_update(View v, double* __restrict
                                                       double* __restrict__ z, const double* __restrict__ p,
                                                       const double* __restrict__ q, const double* __restrict__ J,
                                                       CgCtl* __restrict__ ctl, double* __restrict__ partials) {
-  if (ctl->done) return;
   __shared__ double lds[2 * 16];
-  const int64_t N = (int64_t)v.n_streams * v.n_b;
-  const double alpha = ctl->alpha, mu = ctl->mu;
-  double acc[2] = {0.0, 0.0};
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (int64_t)gridDim.x * blockDim.x) {
-    const double ji = J[i];
-    const double qi = q[i] - ((v.rowT >= 0 && i < v.n_b && ji > 0.0) ? mu : 0.0);
-    a[i] += alpha * p[i];
-    const double ri = r[i] - alpha * qi;
-    r[i] = ri;
-    const double zi = ji * ri;
-    z[i] = zi;
-    acc[0] += ri * zi;
-    acc[1] += ri * ri;
-  }
-  block_sum<2>(acc, lds);
-  if (threadIdx.x == 0) {
-    partials[blockIdx.x] = acc[0];
-    partials[gridDim.x + blockIdx.x] = acc[1];
-  }
+  cg_update_body(v, a, r, z, p, q, J, ctl, partials, blockIdx.x, gridDim.x, lds);
 }
 
 __global__ void __launch_bounds__(kBlock) k_p_update(int64_t N, double* __restrict__ p, const double* __restrict__ z,

@@ -70,11 +70,12 @@ hipError_t launch_cg_alpha(int64_t n_part, CgCtl* ctl, const double* partials, c
                            const double* p, hipStream_t st);
 hipError_t launch_cg_beta(int n_part, CgCtl* ctl, const double* partials, hipStream_t st);
 // p = z + beta p (z == NULL: p unchanged) and pw4 = interleaved w .* p
+// (dense_t: intensity-only run form, pw4[b] = w_T p_T)
 hipError_t launch_p_update4(const View& v, double* p, const double* z, double* pw4, const CgCtl* ctl, int use_beta,
-                            hipStream_t st);
+                            int dense_t, hipStream_t st);
 // Full-sky outputs: hits[p] and out3[p] = a4[cid[p]] - b4[cid[p]] (0 where unobserved;
-// any of hits / b4 / out3 may be NULL).
+// any of hits / b4 / out3 may be NULL; b_dense: b4 holds one double per pixel, the I value).
 hipError_t launch_scatter(int64_t n_pix, const int32_t* cid, const int32_t* chits, int32_t* hits, const double* a4,
-                          const double* b4, double* out3, hipStream_t st);
+                          const double* b4, double* out3, hipStream_t st, int b_dense = 0);
 
 }  // namespace dst

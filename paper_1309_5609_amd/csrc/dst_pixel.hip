@@ -21,6 +21,7 @@
 #include "dst_internal.h"
 #include "dst_trig.h"
 #include "dst_pixel.h"
+#include "dst_cg.h"
 #include "dst_comp.h"
 
 namespace dst {
@@ -155,7 +156,7 @@ __global__ void __launch_bounds__(kBlock) k_cpix(const int32_t* __restrict__ pix
 __global__ void __launch_bounds__(kBlock) k_scatter(int64_t n_pix, const int32_t* __restrict__ cid,
                                                     const int32_t* __restrict__ chits32, int32_t* __restrict__ hits,
                                                     const double* __restrict__ a4, const double* __restrict__ b4,
-                                                    double* __restrict__ out3) {
+                                                    double* __restrict__ out3, int b_dense) {
   for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n_pix; p += (int64_t)gridDim.x * blockDim.x) {
     const int c = cid[p];
     if (hits) hits[p] = c >= 0 ? chits32[c] : 0;
@@ -165,7 +166,9 @@ __global__ void __launch_bounds__(kBlock) k_scatter(int64_t n_pix, const int32_t
         m0 = a4[4 * (int64_t)c + 0];
         m1 = a4[4 * (int64_t)c + 1];
         m2 = a4[4 * (int64_t)c + 2];
-        if (b4) {
+        if (b4 && b_dense) {
+          m0 -= b4[c];
+        } else if (b4) {
           m0 -= b4[4 * (int64_t)c + 0];
           m1 -= b4[4 * (int64_t)c + 1];
           m2 -= b4[4 * (int64_t)c + 2];
@@ -490,96 +493,24 @@ __global__ void __launch_bounds__(kBlock) k_unbin_cg(View v, const double* __res
   }
 }
 
-// Finishes the step length: the null-space projection of K p and
-// alpha = r.z / p.(P K p), from n_part partials of each kind (per baseline
-// from k_unbin_cg, per workgroup from the run rescan).  With one component
-// of the baseline-pixel graph the projection is mu, the mean of the T part
-// of K p over T-valid baselines (applied by the residual update); with more,
-// q = K p loses each component's mean here, in place, and p.(P K p) the
-// matching sum.  One workgroup; fixed summation order.
 __global__ void __launch_bounds__(1024) k_cg_alpha(int64_t n_part, CgCtl* __restrict__ ctl,
                                                    const double* __restrict__ partials, CompView cv,
                                                    double* __restrict__ q, const double* __restrict__ p) {
-  if (ctl->done) return;
   __shared__ double lds[3 * 16];
   __shared__ double clds[16 * 64];
-  double tot[3] = {0.0, 0.0, 0.0};
-  for (int64_t j = threadIdx.x; j < n_part; j += blockDim.x) {
-    tot[0] += partials[j];
-    tot[1] += partials[n_part + j];
-    tot[2] += partials[2 * n_part + j];
-  }
-  block_sum<3>(tot, lds);
-  const int ncomp = cv.ncomp ? *cv.ncomp : 0;
-  double corr = 0.0;
-  if (ncomp > 1) corr = comp_project_block(cv, ncomp, q, p, 1, 1, clds);
-  if (threadIdx.x == 0) {
-    const double mu = ncomp > 1 ? 0.0 : (ctl->n_e > 0.0 ? tot[1] / ctl->n_e : 0.0);
-    const double pkp = ncomp > 1 ? tot[0] - corr : tot[0] - mu * tot[2];
-    ctl->mu = mu;
-    if (!isfinite(pkp)) {
-      ctl->done = DONE_NAN;
-    } else if (pkp <= 0.0) {
-      ctl->done = DONE_BREAKDOWN;
-    } else {
-      ctl->alpha = ctl->rz / pkp;
-    }
-  }
+  cg_alpha_body(n_part, ctl, partials, cv, q, p, lds, clds);
 }
 
-// Finishes the residual update: the stopping test on ||r|| and
-// beta = r'.z' / r.z, from the per-block partials of k_cg_update.
 __global__ void __launch_bounds__(1024) k_cg_beta(int n_part, CgCtl* __restrict__ ctl,
                                                   const double* __restrict__ partials) {
-  if (ctl->done) return;
   __shared__ double lds[2 * 16];
-  double tot[2] = {0.0, 0.0};
-  for (int j = threadIdx.x; j < n_part; j += blockDim.x) {
-    tot[0] += partials[j];
-    tot[1] += partials[n_part + j];
-  }
-  block_sum<2>(tot, lds);
-  if (threadIdx.x == 0) {
-    const double rz_new = tot[0];
-    const double rn = sqrt(tot[1]);
-    ctl->iter += 1;
-    ctl->r_norm = rn;
-    if (!isfinite(rz_new) || !isfinite(rn)) {
-      ctl->done = DONE_NAN;
-    } else if (rn <= ctl->tol * ctl->b_norm) {
-      ctl->done = DONE_CONVERGED;
-    } else if (ctl->iter >= ctl->max_iter) {
-      ctl->done = DONE_MAXITER;
-    } else {
-      ctl->beta = rz_new / ctl->rz;
-      ctl->rz = rz_new;
-    }
-  }
+  cg_beta_body(n_part, ctl, partials, lds);
 }
 
-// p = z + beta p (skipped once the solve has stopped) and its weighted
-// interleaved copy pw4[b] = (w_T p_T, w_q p_q, w_u p_u, 0) for the pixel-major bin.
 __global__ void __launch_bounds__(kBlock) k_p_update4(View v, double* __restrict__ p, const double* __restrict__ z,
                                                       double* __restrict__ pw4, const CgCtl* __restrict__ ctl,
-                                                      int use_beta) {
-  if (ctl && ctl->done) return;
-  const double beta = use_beta ? ctl->beta : 0.0;
-  const int64_t n_b = v.n_b;
-  for (int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; b < n_b; b += (int64_t)gridDim.x * blockDim.x) {
-    double w4[4] = {0.0, 0.0, 0.0, 0.0};
-    const int rows[3] = {v.rowT, v.rowQ, v.rowU};
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      if (rows[k] < 0) continue;
-      const int64_t i = rows[k] * n_b + b;
-      double pi = z ? z[i] + beta * p[i] : p[i];
-      if (z) p[i] = pi;
-      w4[k] = v.w[k] * pi;
-    }
-    double2* o = reinterpret_cast<double2*>(pw4 + 4 * b);
-    o[0] = make_double2(w4[0], w4[1]);
-    o[1] = make_double2(w4[2], 0.0);
-  }
+                                                      int use_beta, int dense_t) {
+  p_update4_body(v, p, z, pw4, ctl, use_beta, dense_t, blockIdx.x, gridDim.x);
 }
 
 unsigned grid_for(int64_t n, int64_t per_block, unsigned cap) {
@@ -751,9 +682,9 @@ hipError_t launch_rhs_unbin(const View& vc, int psi_f32, const void* tod, int to
 }
 
 hipError_t launch_scatter(int64_t n_pix, const int32_t* cid, const int32_t* chits, int32_t* hits, const double* a4,
-                          const double* b4, double* out3, hipStream_t st) {
+                          const double* b4, double* out3, hipStream_t st, int b_dense) {
   hipLaunchKernelGGL(k_scatter, dim3(grid_for(n_pix, kBlock, 4096)), dim3(kBlock), 0, st, n_pix, cid, chits, hits,
-                     a4, b4, out3);
+                     a4, b4, out3, b_dense);
   return hipGetLastError();
 }
 
@@ -826,9 +757,9 @@ hipError_t launch_cg_beta(int n_part, CgCtl* ctl, const double* partials, hipStr
 }
 
 hipError_t launch_p_update4(const View& v, double* p, const double* z, double* pw4, const CgCtl* ctl, int use_beta,
-                            hipStream_t st) {
+                            int dense_t, hipStream_t st) {
   const unsigned g = grid_for(v.n_b, kBlock, 1024);
-  hipLaunchKernelGGL(k_p_update4, dim3(g), dim3(kBlock), 0, st, v, p, z, pw4, ctl, use_beta);
+  hipLaunchKernelGGL(k_p_update4, dim3(g), dim3(kBlock), 0, st, v, p, z, pw4, ctl, use_beta, dense_t);
   return hipGetLastError();
 }
 

@@ -24,6 +24,8 @@
 
 #include "dst_internal.h"
 #include "dst_runs.h"
+#include "dst_cg.h"
+#include "dst_group.h"
 #include "dst_trig.h"
 
 namespace dst {
@@ -768,22 +770,21 @@ __device__ __forceinline__ void decode_run(uint32_t key, int32_t len, RT c, RT s
 // m = M^-1 A^T W F p per compact pixel from its pixel-order runs.  LPP lanes
 // work on one pixel (64 / LPP pixels per wavefront, each with its own chain of
 // dependent loads in flight); pw4[b] = (w_T p_T, w_q p_q, w_u p_u, 0).
+// The body takes the workgroup's place (vblock of vgrid) in its problem's grid.
 template <typename RT, bool HAS_T, bool HAS_QU, bool IQU, int LPP, bool PK>
-__global__ void __launch_bounds__(kBlock) k_bin_runs(int64_t n_obs, const int64_t* __restrict__ pstart,
-                                                     const uint32_t* __restrict__ pb, const int32_t* __restrict__ pn,
-                                                     int nb,
-                                                     const RT* __restrict__ pcs,
-                                                     const double* __restrict__ pw4,
-                                                     const double* __restrict__ Minv4,
-                                                     const uint8_t* __restrict__ valid, double* __restrict__ m4,
-                                                     const CgCtl* __restrict__ gate) {
-  if (gate && gate->done) return;
+__device__ __forceinline__ void bin_runs_body(int64_t n_obs, const int64_t* __restrict__ pstart,
+                                              const uint32_t* __restrict__ pb, const int32_t* __restrict__ pn,
+                                              int nb, const RT* __restrict__ pcs, const double* __restrict__ pw4,
+                                              const double* __restrict__ Minv4, const uint8_t* __restrict__ valid,
+                                              double* __restrict__ m4, int64_t vblock, int64_t vgrid) {
   constexpr int PPW = 64 / LPP;
   constexpr int U = LPP >= 64 ? 2 : (LPP == 32 ? 4 : 8);
+  // intensity-only problems keep p and m as one double per baseline / pixel
+  constexpr bool TONLY = HAS_T && !HAS_QU && !IQU;
   const int lane = lane_id();
   const int grp = lane / LPP, sub = lane % LPP;
-  const int64_t step = (int64_t)gridDim.x * kWaves * PPW;
-  for (int64_t cb = ((int64_t)blockIdx.x * kWaves + (threadIdx.x >> 6)) * PPW; cb < n_obs; cb += step) {
+  const int64_t step = vgrid * kWaves * PPW;
+  for (int64_t cb = (vblock * kWaves + (threadIdx.x >> 6)) * PPW; cb < n_obs; cb += step) {
     const int64_t c = cb + grp;
     const bool have = c < n_obs && valid[c] != 0;  // m stays 0 on invalid pixels
     int64_t j0 = 0, j1 = 0;
@@ -805,9 +806,14 @@ __global__ void __launch_bounds__(kBlock) k_bin_runs(int64_t n_obs, const int64_
         int32_t bb;
         decode_run<RT, PK>(key[u], len[u], cr[u], sr[u], jb + LPP * u < j1, nb, bb, nn[u], cc[u], ss[u]);
         // runs past j1 read baseline pw4 of run 0 (a valid index) and add nothing
-        const double2* q0 = reinterpret_cast<const double2*>(pw4 + 4 * (int64_t)bb);
-        x0[u] = q0[0];
-        u0[u] = HAS_QU ? q0[1].x : 0.0;
+        if (TONLY) {
+          x0[u] = make_double2(pw4[bb], 0.0);
+          u0[u] = 0.0;
+        } else {
+          const double2* q0 = reinterpret_cast<const double2*>(pw4 + 4 * (int64_t)bb);
+          x0[u] = q0[0];
+          u0[u] = HAS_QU ? q0[1].x : 0.0;
+        }
       }
 #pragma unroll
       for (int u = 0; u < U; ++u) {
@@ -837,7 +843,8 @@ __global__ void __launch_bounds__(kBlock) k_bin_runs(int64_t n_obs, const int64_
                            i01.y * acc[0] + i23.y * acc[1] + i45.x * acc[2]);
       mp[1] = make_double2(i23.x * acc[0] + i45.x * acc[1] + i45.y * acc[2], 0.0);
     }
-    if (!IQU && have && sub == 0) {
+    if (TONLY && have && sub == 0) m4[c] = Minv4[4 * c] * acc[0];
+    if (!IQU && !TONLY && have && sub == 0) {
       const double2* ip = reinterpret_cast<const double2*>(Minv4 + 4 * c);
       const double2 i01 = ip[0], i23 = ip[1];
       double2* mp = reinterpret_cast<double2*>(m4 + 4 * c);
@@ -845,6 +852,20 @@ __global__ void __launch_bounds__(kBlock) k_bin_runs(int64_t n_obs, const int64_
       mp[1] = make_double2(i23.x * acc[1] + i23.y * acc[2], 0.0);
     }
   }
+}
+
+template <typename RT, bool HAS_T, bool HAS_QU, bool IQU, int LPP, bool PK>
+__global__ void __launch_bounds__(kBlock) k_bin_runs(int64_t n_obs, const int64_t* __restrict__ pstart,
+                                                     const uint32_t* __restrict__ pb, const int32_t* __restrict__ pn,
+                                                     int nb,
+                                                     const RT* __restrict__ pcs,
+                                                     const double* __restrict__ pw4,
+                                                     const double* __restrict__ Minv4,
+                                                     const uint8_t* __restrict__ valid, double* __restrict__ m4,
+                                                     const CgCtl* __restrict__ gate) {
+  if (gate && gate->done) return;
+  bin_runs_body<RT, HAS_T, HAS_QU, IQU, LPP, PK>(n_obs, pstart, pb, pn, nb, pcs, pw4, Minv4, valid, m4, blockIdx.x,
+                                                  gridDim.x);
 }
 
 // The same binning with a three-stage software pipeline over the
@@ -1031,27 +1052,29 @@ __global__ void __launch_bounds__(kBlock) k_bin_runs_pipe(int64_t n_obs, const i
 // the T-projection sums, partials[j * gridDim.x + blockIdx.x] for j = 0, 1, 2
 // (summed in a fixed order: a wavefront butterfly, then the wavefronts in
 // turn), so the step length is finished from a few thousand numbers.
+// The body takes the workgroup's place (vblock of vgrid, vgrid a multiple of
+// 8 and the problem's first workgroup on a multiple of 8, so vblock % 8 is
+// the hardware's XCD of the workgroup) in its problem's grid.
 template <typename RT, bool HAS_T, bool HAS_QU, bool IQU, bool CG, int BPW, bool PK>
-__global__ void __launch_bounds__(kBlock) k_unbin_runs(View v, const uint32_t* __restrict__ bstart,
-                                                       const uint32_t* __restrict__ border,
-                                                       const uint32_t* __restrict__ rpix,
-                                                       const int32_t* __restrict__ rn, int nb, const RT* __restrict__ rcs,
-                                                       const double* __restrict__ m4,
-                                                       const int32_t* __restrict__ nvalid,
-                                                       const double* __restrict__ p, double* __restrict__ q,
-                                                       CgCtl* __restrict__ ctl, double* __restrict__ partials) {
+__device__ __forceinline__ void unbin_runs_body(const View& v, const uint32_t* __restrict__ bstart,
+                                                const uint32_t* __restrict__ border,
+                                                const uint32_t* __restrict__ rpix, const int32_t* __restrict__ rn,
+                                                int nb, const RT* __restrict__ rcs, const double* __restrict__ m4,
+                                                const int32_t* __restrict__ nvalid, const double* __restrict__ p,
+                                                double* __restrict__ q, double* __restrict__ partials, int64_t vblock,
+                                                int64_t vgrid) {
   constexpr int SEG = 64 / BPW;  // lanes per baseline
-  if (CG && ctl->done) return;
+  constexpr bool TONLY = HAS_T && !HAS_QU && !IQU;  // m: one double per pixel
   const int lane = lane_id();
   const int64_t n_b = v.n_b;
   const int64_t n_g = ((n_b + BPW - 1) / BPW + kWaves - 1) / kWaves;
   const int64_t per = (n_g + 7) / 8;
-  const int64_t i = blockIdx.x;
+  const int64_t i = vblock;
   const int64_t g = (i & 7) * per + (i >> 3);
   if (g >= n_g) {  // whole workgroup
     if (CG && threadIdx.x == 0) {
 #pragma unroll
-      for (int j = 0; j < 3; ++j) partials[j * (int64_t)gridDim.x + i] = 0.0;
+      for (int j = 0; j < 3; ++j) partials[j * vgrid + i] = 0.0;
     }
     return;
   }
@@ -1100,6 +1123,10 @@ __global__ void __launch_bounds__(kBlock) k_unbin_runs(View v, const uint32_t* _
         m01[u] = make_double2(0.0, 0.0);
         mU[u] = 0.0;
         if (cc_[u] < 0) continue;
+        if (TONLY) {
+          m01[u].x = m4[cc_[u]];
+          continue;
+        }
         const double2* mp = reinterpret_cast<const double2*>(m4 + 4 * (int64_t)cc_[u]);
         m01[u] = mp[0];
         if (HAS_QU || IQU) mU[u] = mp[1].x;
@@ -1164,10 +1191,24 @@ __global__ void __launch_bounds__(kBlock) k_unbin_runs(View v, const uint32_t* _
       for (int j = 0; j < 3; ++j) {
         double x = 0.0;
         for (int w = 0; w < kWaves; ++w) x += red[w][j];
-        partials[j * (int64_t)gridDim.x + i] = x;
+        partials[j * vgrid + i] = x;
       }
     }
   }
+}
+
+template <typename RT, bool HAS_T, bool HAS_QU, bool IQU, bool CG, int BPW, bool PK>
+__global__ void __launch_bounds__(kBlock) k_unbin_runs(View v, const uint32_t* __restrict__ bstart,
+                                                       const uint32_t* __restrict__ border,
+                                                       const uint32_t* __restrict__ rpix,
+                                                       const int32_t* __restrict__ rn, int nb, const RT* __restrict__ rcs,
+                                                       const double* __restrict__ m4,
+                                                       const int32_t* __restrict__ nvalid,
+                                                       const double* __restrict__ p, double* __restrict__ q,
+                                                       CgCtl* __restrict__ ctl, double* __restrict__ partials) {
+  if (CG && ctl->done) return;
+  unbin_runs_body<RT, HAS_T, HAS_QU, IQU, CG, BPW, PK>(v, bstart, border, rpix, rn, nb, rcs, m4, nvalid, p, q,
+                                                       partials, blockIdx.x, gridDim.x);
 }
 
 // Stable sort of the runs by pixel: onesweep passes of ten bits, so the
@@ -1443,10 +1484,12 @@ hipError_t launch_bin_runs(const View& vc, const Runs& W, const double* pw4, con
                            W.nb ? W.pkey : reinterpret_cast<const uint32_t*>(W.pb), W.pn, W.nb,
                            static_cast<const RT*>(W.pcs), pw4, Minv4, valid, m4, gate);
       };
-      if (pipe) {
+      // the pipelined variant keeps the four-double layout: not for intensity-only problems
+      if (pipe && !(HT && !HQ && !HI)) {
         launch(k_bin_runs_pipe<RT, HT, HQ, HI, 64>);
         return;
       }
+      if (pipe) lpp = 64;
       by_bool(W.nb != 0, [&](auto K) {
         constexpr bool PK = decltype(K)::value;
         if (lpp == 16)
@@ -1498,6 +1541,132 @@ hipError_t launch_unbin_runs(const View& vc, const Runs& W, const double* m4, co
     });
   });
   return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- problem groups
+
+namespace {
+
+// Problem of workgroup b: the i with start[i] <= b < start[i + 1].
+__device__ __forceinline__ int group_of(const uint32_t* start, int n, uint32_t b) {
+  int lo = 0, hi = n;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (start[mid] <= b)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
+template <typename RT, int KIND>
+__global__ void __launch_bounds__(kBlock) k_group_bin(GroupLaunch G) {
+  constexpr bool HT = KIND != GK_QU, HQ = KIND == GK_QU || KIND == GK_TQU, HI = KIND == GK_IQU;
+  const GroupSlice& S = G.kind[KIND];
+  const uint32_t b = blockIdx.x;
+  const int j = group_of(S.bin_start, S.count, b);
+  const GroupProblem& P = G.prob[S.first + j];
+  if (P.ctl->done) return;
+  const int64_t vb = b - S.bin_start[j], vg = S.bin_start[j + 1] - S.bin_start[j];
+  bin_runs_body<RT, HT, HQ, HI, 32, true>(P.v.n_pix, P.pstart, P.pkey, nullptr, P.nb, static_cast<const RT*>(P.pcs),
+                                          P.pw4, P.Minv4, P.valid, P.m4, vb, vg);
+}
+
+template <typename RT, int KIND>
+__global__ void __launch_bounds__(kBlock) k_group_unbin(GroupLaunch G) {
+  constexpr bool HT = KIND != GK_QU, HQ = KIND == GK_QU || KIND == GK_TQU, HI = KIND == GK_IQU;
+  const GroupSlice& S = G.kind[KIND];
+  const uint32_t b = blockIdx.x;
+  const int j = group_of(S.unbin_start, S.count, b);
+  const GroupProblem& P = G.prob[S.first + j];
+  if (P.ctl->done) return;
+  const int64_t vb = b - S.unbin_start[j], vg = S.unbin_start[j + 1] - S.unbin_start[j];
+  unbin_runs_body<RT, HT, HQ, HI, true, 4, true>(P.v, P.bstart, P.border, P.tkey, nullptr, P.nb,
+                                                 static_cast<const RT*>(P.tcs), P.m4, P.nvalid, P.p, P.q,
+                                                 P.part_unbin, vb, vg);
+}
+
+// One workgroup per problem.
+__global__ void __launch_bounds__(1024) k_group_alpha(GroupLaunch G) {
+  __shared__ double lds[3 * 16];
+  __shared__ double clds[16 * 64];
+  const int i = blockIdx.x;
+  const GroupProblem& P = G.prob[i];
+  cg_alpha_body(P.unbin_n, P.ctl, P.part_unbin, P.cv, P.q, P.p, lds, clds);
+}
+
+__global__ void __launch_bounds__(kBlock) k_group_update(GroupLaunch G) {
+  __shared__ double lds[2 * 16];
+  const uint32_t b = blockIdx.x;
+  const int i = group_of(G.vec_start, G.n, b);
+  const GroupProblem& P = G.prob[i];
+  const int64_t vb = b - G.vec_start[i], vg = G.vec_start[i + 1] - G.vec_start[i];
+  cg_update_body(P.v, P.a, P.r, P.z, P.p, P.q, P.J, P.ctl, P.part_update, vb, vg, lds);
+}
+
+__global__ void __launch_bounds__(1024) k_group_beta(GroupLaunch G) {
+  __shared__ double lds[2 * 16];
+  const int i = blockIdx.x;
+  const GroupProblem& P = G.prob[i];
+  cg_beta_body((int)P.vec_n, P.ctl, P.part_update, lds);
+}
+
+__global__ void __launch_bounds__(kBlock) k_group_p(GroupLaunch G) {
+  const uint32_t b = blockIdx.x;
+  const int i = group_of(G.vec_start, G.n, b);
+  const GroupProblem& P = G.prob[i];
+  const int64_t vb = b - G.vec_start[i], vg = G.vec_start[i + 1] - G.vec_start[i];
+  p_update4_body(P.v, P.p, P.z, P.pw4, P.ctl, 1, P.dense_t, vb, vg);
+}
+
+}  // namespace
+
+uint32_t group_bin_blocks(int64_t n_obs) {
+  const int64_t ppb = kWaves * (64 / 32);
+  return (uint32_t)std::max<int64_t>(1, std::min<int64_t>((n_obs + ppb - 1) / ppb, 16384));
+}
+
+uint32_t group_unbin_blocks(const View& vc) { return (uint32_t)unbin_runs_parts(vc, 4); }
+
+uint32_t group_vec_blocks(const View& v) {
+  const int64_t n = (int64_t)v.n_streams * v.n_b;
+  return (uint32_t)std::max<int64_t>(1, std::min<int64_t>((n + kBlock - 1) / kBlock, 1024));
+}
+
+hipError_t launch_group_phase(const GroupLaunch& G, int phase, hipStream_t st) {
+  if (G.n <= 0) return hipSuccess;
+  by_float(G.f32 != 0, [&](auto rt) {
+    using RT = typename decltype(rt)::type;
+    auto per_kind = [&](auto bin, auto unbin, int K) {
+      const GroupSlice& S = G.kind[K];
+      if (S.count == 0) return;
+      if (phase == 0)
+        hipLaunchKernelGGL(bin, dim3(S.bin_total), dim3(kBlock), 0, st, G);
+      else
+        hipLaunchKernelGGL(unbin, dim3(S.unbin_total), dim3(kBlock), 0, st, G);
+    };
+    if (phase <= 1) {
+      per_kind(k_group_bin<RT, GK_T>, k_group_unbin<RT, GK_T>, GK_T);
+      per_kind(k_group_bin<RT, GK_QU>, k_group_unbin<RT, GK_QU>, GK_QU);
+      per_kind(k_group_bin<RT, GK_TQU>, k_group_unbin<RT, GK_TQU>, GK_TQU);
+      per_kind(k_group_bin<RT, GK_IQU>, k_group_unbin<RT, GK_IQU>, GK_IQU);
+      if (phase == 1) hipLaunchKernelGGL(k_group_alpha, dim3(G.n), dim3(1024), 0, st, G);
+    } else {
+      hipLaunchKernelGGL(k_group_update, dim3(G.vec_total), dim3(kBlock), 0, st, G);
+      hipLaunchKernelGGL(k_group_beta, dim3(G.n), dim3(1024), 0, st, G);
+      hipLaunchKernelGGL(k_group_p, dim3(G.vec_total), dim3(kBlock), 0, st, G);
+    }
+  });
+  return hipGetLastError();
+}
+
+hipError_t launch_group_iteration(const GroupLaunch& G, hipStream_t st) {
+  for (int phase = 0; phase < 3; ++phase) {
+    const hipError_t e = launch_group_phase(G, phase, st);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 }  // namespace dst
