@@ -380,7 +380,7 @@ struct Plan {
 // Components of the baseline-pixel graph over T-valid samples (after the
 // per-baseline counts); elements elem_start / eb in pixel order.
 int build_components(dst_ctx* ctx, Plan& P, int64_t n_obs, const int64_t* elem_start, const int32_t* eb,
-                     hipStream_t st) {
+                     const dst::ChainSource& cs, hipStream_t st) {
   const View& v = P.full;
   if (v.rowT < 0) return DST_OK;
   dst::Comp& C = P.C;
@@ -390,7 +390,9 @@ int build_components(dst_ctx* ctx, Plan& P, int64_t n_obs, const int64_t* elem_s
   DST_TRY(ws(ctx, "comp_member", v.n_b, &C.member));
   DST_TRY(ws(ctx, "comp_cursor", v.n_b, &C.cursor));
   DST_TRY(ws(ctx, "comp_n", 4, &C.ncomp));
-  HIP_TRY(dst::launch_components(v.n_b, n_obs, elem_start, eb, P.S.valid, P.S.nvalid, C, st));
+  DST_TRY(ws(ctx, "comp_pmin", std::max<int64_t>(n_obs, 1), &C.pmin));
+  DST_TRY(ws(ctx, "comp_flags", dst::kCompFlags, &C.flags));
+  HIP_TRY(dst::launch_components(v.n_b, n_obs, elem_start, eb, P.S.valid, P.S.nvalid, cs, C, st));
   return DST_OK;
 }
 
@@ -478,7 +480,11 @@ int build_runs_plan(dst_ctx* ctx, const dst_problem* prob, Plan& P, const void* 
   S.v = v;
   S.v.n_pix = W.n_obs;
   HIP_TRY(dst::launch_rhs_runs(S.v, W, tod, m4d, S.valid, S.nvalid, S.J, b, st));
-  return build_components(ctx, P, W.n_obs, W.pstart, W.pb, st);
+  dst::ChainSource cs;
+  cs.bstart = W.bstart;
+  cs.tkey = W.nb ? W.tkey : reinterpret_cast<const uint32_t*>(W.tpix);
+  cs.nb = W.nb;
+  return build_components(ctx, P, W.n_obs, W.pstart, W.pb, cs, st);
 }
 
 // With tod: also the sum map sd4, binned map md4 (compact [n_obs][4]) and the
@@ -543,7 +549,11 @@ int build_sample_plan(dst_ctx* ctx, const dst_problem* prob, Plan& P, const void
   HIP_TRY(dst::launch_setup_pixels(v, S.psi_f32, T, tod, S.tod_f32, prob->rcond_cut, S.hits, S.Minv4, S.valid, P.m4,
                                    s4, m4d, S.counts, st));
   HIP_TRY(dst::launch_rhs_unbin(S.v, S.psi_f32, tod, S.tod_f32, m4d, S.valid, S.nvalid, S.J, b, st));
-  return build_components(ctx, P, T.n_obs, T.cstart, T.sb, st);
+  dst::ChainSource cs;
+  cs.cpix = T.cpix;
+  cs.L = v.L;
+  cs.n_t = v.n_t;
+  return build_components(ctx, P, T.n_obs, T.cstart, T.sb, cs, st);
 }
 
 int build_plan(dst_ctx* ctx, const dst_problem* prob, Plan& P, const void* tod, double** sd4, double** md4,
@@ -896,7 +906,7 @@ int solve_uneven(dst_ctx* ctx, const dst_problem* problems, const std::vector<in
   // arrays only the setup reads: one set serves every problem's setup in turn
   for (const char* name : {"r_tcount", "r_toff", "r_rec", "r_raw", "r_keys0", "r_keys1", "r_vals0", "r_vals1",
                            "r_t0", "r_tmp", "r_pb", "r_pn", "r_tpix", "r_tn", "r_seg", "r_pk0", "r_pk1", "r_bkey0",
-                           "r_bkey1", "r_nobs", "r_nout", "r_ccount", "sd4", "comp_parent", "comp_cursor", "counts"})
+                           "r_bkey1", "r_nobs", "r_nout", "r_ccount", "sd4", "comp_parent", "comp_cursor", "comp_pmin", "comp_flags", "counts"})
     ctx->ws_shared.insert(name);
   for (int k = 0; k < n; ++k) {
     Member& m = M[k];

@@ -33,7 +33,9 @@ struct CompView {
 };
 
 // Buffers of the component build (caller's workspace), sizes in elements:
-// parent, label [n_b]; start [n_b + 1]; member, cursor [n_b]; ncomp [4].
+// parent, label [n_b]; start [n_b + 1]; member, cursor [n_b]; ncomp [4];
+// pmin [n_obs]; flags [kCompFlags].
+constexpr int kCompFlags = 16;
 struct Comp {
   int32_t* parent = nullptr;
   int32_t* label = nullptr;
@@ -41,6 +43,8 @@ struct Comp {
   uint32_t* member = nullptr;
   uint32_t* cursor = nullptr;
   int32_t* ncomp = nullptr;
+  int32_t* pmin = nullptr;
+  int32_t* flags = nullptr;
   CompView view() const {
     CompView c;
     c.ncomp = ncomp;
@@ -50,12 +54,24 @@ struct Comp {
   }
 };
 
+// The time-order elements of each baseline: the runs (bstart [n_b + 1], keys
+// c << nb | length - 1, or c when nb = 0) or, without runs, the samples with
+// their compact pixels cpix [n_t] (-1 masked).
+struct ChainSource {
+  const uint32_t* bstart = nullptr;
+  const uint32_t* tkey = nullptr;
+  int nb = 0;
+  const int32_t* cpix = nullptr;
+  int64_t L = 1, n_t = 0;
+};
+
 // Components over the pixels whose T block is valid (bit 0 of valid).
 // Elements elem_start[c] .. elem_start[c + 1] - 1 belong to compact pixel c
 // (runs or samples in pixel order); eb[e] is the baseline of element e;
 // nvalid_T[b] the number of valid samples of baseline b.  Asynchronous.
 hipError_t launch_components(int64_t n_b, int64_t n_obs, const int64_t* elem_start, const int32_t* eb,
-                             const uint8_t* valid, const int32_t* nvalid_T, Comp& C, hipStream_t st);
+                             const uint8_t* valid, const int32_t* nvalid_T, const ChainSource& cs, Comp& C,
+                             hipStream_t st);
 
 // x <- x - (component mean of x) on every baseline of a component, for each of
 // R right-hand sides, when there is more than one component (one component

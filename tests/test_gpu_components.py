@@ -144,3 +144,28 @@ def test_one_component_count(ctx):
     assert out["n_components"] == 1
     q = dst.dst_solve(ctx, dst.to_device(toy(streams="QU")), tol=1e-10)
     assert q["n_components"] == 0
+
+
+def test_long_chain_graph(ctx):
+    """Baseline b sees only pixels b and b + 1, so the graph is one long chain: the label rounds cannot settle it
+    and the union-find pass must finish the job (one component), with a second, separate chain beside it."""
+    from paper_1309_5609_amd import dst
+    L, nb = 40, 120
+    t = np.arange(nb * L)
+    b = t // L
+    pix = np.where((t % L) < L // 2, b, b + 1).astype(np.int32)
+    pix[t >= (nb // 2) * L] += 5  # baselines 60.. form a second chain on pixels 65..
+    n_pix = nb + 10
+    rng = np.random.default_rng(3)
+    sky = rng.standard_normal(n_pix)
+    tod = (sky[pix] + np.repeat(rng.standard_normal(nb), L) + 0.01 * rng.standard_normal(t.size))[None, :]
+    ref = O.solve(pix, None, tod, n_pix, L, "T", (1.0, 1.0, 1.0), tol=1e-13, max_iter=5000)
+    st = O.prepare(pix, None, n_pix, L, "T", (1.0, 1.0, 1.0))
+    _, lab = O.t_components(st)
+    import torch
+    dp = dst.Problem(torch.from_numpy(pix).cuda(), None, torch.from_numpy(tod).cuda(), n_pix, L, "T",
+                     (1.0, 1.0, 1.0))
+    for flags in (0, dst.DST_SOLVE_PER_SAMPLE):
+        out = dst.dst_solve(ctx, dp, tol=1e-13, max_iter=5000, flags=flags)
+        assert out["n_components"] == len(np.unique(lab[lab >= 0])) == 2
+        assert rel(out["baselines"].cpu().numpy(), ref.baselines) < 1e-9
