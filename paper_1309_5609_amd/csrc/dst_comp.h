@@ -35,7 +35,7 @@ struct CompView {
 // Buffers of the component build (caller's workspace), sizes in elements:
 // parent, label [n_b]; start [n_b + 1]; member, cursor [n_b]; ncomp [4];
 // pmin [n_obs]; flags [kCompFlags].
-constexpr int kCompFlags = 16;
+constexpr int kCompFlags = 32;
 struct Comp {
   int32_t* parent = nullptr;
   int32_t* label = nullptr;

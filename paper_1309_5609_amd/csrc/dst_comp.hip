@@ -9,8 +9,9 @@
 // still an ancestor: a find then ends at a node that was a root, and a hook
 // on a node that is no longer a root fails its compare-and-swap and retries
 // from the new parent, so stale reads cost retries, never correctness.
-// Minimum-label rounds without atomics settle a scan's graph first (below);
-// the union-find pass over all elements runs only when they did not.  Then
+// Minimum-label rounds over sampled edges settle a scan's graph first
+// (below); the union-find pass over all elements runs only when they leave
+// more than one self-labelled baseline.  Then
 // each baseline takes its root, roots are numbered in increasing order and,
 // when there is more than one component, the members of each are listed in
 // increasing baseline order (a deterministic order, so sums over a component
@@ -84,34 +85,44 @@ __device__ void uf_union(int32_t* parent, int32_t a, int32_t b) {
   }
 }
 
-__global__ void __launch_bounds__(kBlk) k_uf_init(int64_t n_b, int32_t* __restrict__ parent,
-                                                  int32_t* __restrict__ ncomp) {
-  for (int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; b < n_b; b += (int64_t)gridDim.x * blockDim.x)
-    parent[b] = (int32_t)b;
-  if (blockIdx.x == 0 && threadIdx.x < 4) ncomp[threadIdx.x] = 0;
-}
-
 // Labels by minimum propagation over a subset of the graph's edges (every
 // kStride-th element of each pixel, the pixel's last, and every kStride-th
-// element of each baseline), no atomics: a round takes, per valid pixel, the
-// smallest label of its sampled baselines (pixel order), then lowers each
-// baseline's label to the smallest of its sampled pixels' and jumps once to
-// that label's own label (time order).  Labels only decrease and always name
-// a smaller baseline of the same component.  A round that changes nothing
-// ends the rounds (later ones return at once).  When the rounds settle with
-// a single label among the baselines with valid samples, the graph is
-// connected (every edge used is one of its edges); otherwise the labels seed
-// the union-find (each label a valid parent) and the pass over all elements
-// settles the components exactly.
+// element of each baseline): a round takes, per valid pixel, the smallest
+// label of its sampled baselines (pixel order), then lowers each baseline's
+// label to the smallest of its sampled pixels' and jumps once to that label's
+// own label (time order).  Labels only decrease and always name a smaller
+// baseline of the same component (every edge used is one of the graph's).
+// The rounds end when one changes nothing or when a single baseline with
+// valid samples is still its own label (the graph is then connected);
+// otherwise the labels seed the union-find (each label a valid parent) and
+// the pass over all elements settles the components exactly.
 constexpr int kRounds = 12;
 constexpr int kStride = 8;
-static_assert(kRounds + 4 <= kCompFlags, "the round flags live in the flags buffer");
+static_assert(2 * kRounds + 1 <= kCompFlags, "the round flags live in the flags buffer");
+
+// flags: [0, kRounds) round r changed a label; [kRounds, 2 kRounds) after
+// round r, the baselines with valid samples still labelled by themselves (0
+// when the round did not run); 2 kRounds: the union-find pass is needed.
+// Every label names a smaller baseline of the same component, so following
+// labels from any baseline ends at a self-labelled one: when one is left the
+// graph is connected, which ends the rounds and skips the union-find pass.
+constexpr int kSelf = kRounds, kGate = 2 * kRounds;
+
+__global__ void __launch_bounds__(kBlk) k_lp_zero(int32_t* __restrict__ flags, int32_t* __restrict__ ncomp) {
+  if (threadIdx.x < kCompFlags) flags[threadIdx.x] = 0;
+  if (threadIdx.x < 4) ncomp[threadIdx.x] = 0;
+}
 
 __global__ void __launch_bounds__(kBlk) k_lp_init(int64_t n_b, const int32_t* __restrict__ nvalid_T,
-                                                  int32_t* __restrict__ label, int32_t* __restrict__ flags) {
+                                                  int32_t* __restrict__ label) {
   for (int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; b < n_b; b += (int64_t)gridDim.x * blockDim.x)
     label[b] = nvalid_T[b] > 0 ? (int32_t)b : INT32_MAX;
-  if (blockIdx.x == 0 && threadIdx.x < kRounds + 4) flags[threadIdx.x] = 0;
+}
+
+// Rounds go on while the previous round changed a label and left more than
+// one self-labelled baseline.
+__device__ __forceinline__ bool lp_done(int r, const int32_t* flags) {
+  return r > 0 && (flags[r - 1] == 0 || flags[kSelf + r - 1] <= 1);
 }
 
 // Minimum over the `width` lanes (a power of two) of each lane group.
@@ -128,7 +139,7 @@ __global__ void __launch_bounds__(kBlk) k_lp_pix(int r, int64_t n_obs, const int
                                                  const int32_t* __restrict__ eb, const uint8_t* __restrict__ valid,
                                                  const int32_t* __restrict__ label, int32_t* __restrict__ pmin,
                                                  const int32_t* __restrict__ flags) {
-  if (r > 0 && flags[r - 1] == 0) return;
+  if (lp_done(r, flags)) return;
   const int sub = threadIdx.x % kPixLanes;
   const int64_t ngroup = (int64_t)gridDim.x * (kBlk / kPixLanes);
   for (int64_t cb = ((int64_t)blockIdx.x * (kBlk / kPixLanes) + threadIdx.x / kPixLanes); cb - (cb % (64 / kPixLanes)) < n_obs;
@@ -156,7 +167,11 @@ __global__ void __launch_bounds__(kBlk) k_lp_base(int r, int64_t n_b, const uint
                                                   const int32_t* __restrict__ cpix, int64_t L, int64_t n_t,
                                                   const uint8_t* __restrict__ valid, const int32_t* __restrict__ pmin,
                                                   int32_t* __restrict__ label, int32_t* __restrict__ flags) {
-  if (r > 0 && flags[r - 1] == 0) return;
+  if (lp_done(r, flags)) return;
+  __shared__ int32_t s_self;
+  if (threadIdx.x == 0) s_self = 0;
+  __syncthreads();
+  int32_t self = 0;
   const int sub = threadIdx.x % kBaseLanes;
   const int64_t ngroup = (int64_t)gridDim.x * (kBlk / kBaseLanes);
   for (int64_t bb = ((int64_t)blockIdx.x * (kBlk / kBaseLanes) + threadIdx.x / kBaseLanes);
@@ -187,25 +202,29 @@ __global__ void __launch_bounds__(kBlk) k_lp_base(int r, int64_t n_b, const uint
         label[b] = nw;
         flags[r] = 1;
       }
+      self += nw == (int32_t)b ? 1 : 0;
     }
   }
+  // one atomic per workgroup that still holds a self-labelled baseline
+  if (self) atomicAdd(&s_self, self);
+  __syncthreads();
+  if (threadIdx.x == 0 && s_self) atomicAdd(flags + kSelf + r, s_self);
 }
 
-// Baselines with valid samples that are their own label, into *count.
-__global__ void __launch_bounds__(kBlk) k_lp_count(int64_t n_b, const int32_t* __restrict__ nvalid_T,
-                                                   const int32_t* __restrict__ label, int32_t* __restrict__ count) {
-  for (int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; b < n_b; b += (int64_t)gridDim.x * blockDim.x)
-    if (nvalid_T[b] > 0 && label[b] == (int32_t)b) atomicAdd(count, 1);
-}
-
-// The union-find forest seeded from the labels; *gate = 1 when the pass over
-// all elements is needed (the rounds did not settle, or left several labels).
+// The union-find forest seeded from the labels; flags[kGate] = 1 when the
+// pass over all elements is needed (the last round that ran left more than
+// one self-labelled baseline; every round that runs leaves at least one when
+// any baseline holds a valid sample).
 __global__ void __launch_bounds__(kBlk) k_lp_seed(int64_t n_b, const int32_t* __restrict__ label,
-                                                  int32_t* __restrict__ parent, const int32_t* __restrict__ last_round,
-                                                  const int32_t* __restrict__ count, int32_t* __restrict__ gate) {
+                                                  int32_t* __restrict__ parent, int32_t* __restrict__ flags) {
   for (int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; b < n_b; b += (int64_t)gridDim.x * blockDim.x)
     parent[b] = label[b] < (int32_t)b ? label[b] : (int32_t)b;
-  if (blockIdx.x == 0 && threadIdx.x == 0) *gate = (*last_round != 0 || *count > 1) ? 1 : 0;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    int32_t left = 0;
+    for (int r = 0; r < kRounds; ++r)
+      if (flags[kSelf + r] > 0) left = flags[kSelf + r];
+    flags[kGate] = left > 1 ? 1 : 0;
+  }
 }
 
 
@@ -370,8 +389,8 @@ hipError_t launch_components(int64_t n_b, int64_t n_obs, const int64_t* elem_sta
                              const uint8_t* valid, const int32_t* nvalid_T, const ChainSource& cs, Comp& C,
                              hipStream_t st) {
   const unsigned gb = grid_of(n_b, kBlk, 4096);
-  hipLaunchKernelGGL(k_uf_init, dim3(gb), dim3(kBlk), 0, st, n_b, C.parent, C.ncomp);
-  hipLaunchKernelGGL(k_lp_init, dim3(gb), dim3(kBlk), 0, st, n_b, nvalid_T, C.label, C.flags);
+  hipLaunchKernelGGL(k_lp_zero, dim3(1), dim3(kBlk), 0, st, C.flags, C.ncomp);
+  hipLaunchKernelGGL(k_lp_init, dim3(gb), dim3(kBlk), 0, st, n_b, nvalid_T, C.label);
   for (int r = 0; r < kRounds; ++r) {
     if (n_obs > 0)
       hipLaunchKernelGGL(k_lp_pix, dim3(grid_of(n_obs, kBlk / kPixLanes, 65536)), dim3(kBlk), 0, st, r, n_obs,
@@ -379,13 +398,10 @@ hipError_t launch_components(int64_t n_b, int64_t n_obs, const int64_t* elem_sta
     hipLaunchKernelGGL(k_lp_base, dim3(grid_of(n_b, kBlk / kBaseLanes, 65536)), dim3(kBlk), 0, st, r, n_b, cs.bstart,
                        cs.tkey, cs.nb, cs.cpix, cs.L, cs.n_t, valid, C.pmin, C.label, C.flags);
   }
-  hipLaunchKernelGGL(k_lp_count, dim3(gb), dim3(kBlk), 0, st, n_b, nvalid_T, C.label, C.flags + kRounds);
-  // flags[kRounds]: labels left; flags[kRounds + 1]: the union-find pass is needed
-  hipLaunchKernelGGL(k_lp_seed, dim3(gb), dim3(kBlk), 0, st, n_b, C.label, C.parent, C.flags + (kRounds - 1),
-                     C.flags + kRounds, C.flags + kRounds + 1);
+  hipLaunchKernelGGL(k_lp_seed, dim3(gb), dim3(kBlk), 0, st, n_b, C.label, C.parent, C.flags);
   if (n_obs > 0)
     hipLaunchKernelGGL(k_uf_link, dim3(grid_of(n_obs, kBlk / 64, 65536)), dim3(kBlk), 0, st, n_obs, elem_start, eb,
-                       valid, C.parent, C.flags + kRounds + 1);
+                       valid, C.parent, C.flags + kGate);
   hipLaunchKernelGGL(k_uf_label, dim3(gb), dim3(kBlk), 0, st, n_b, nvalid_T, C.parent, C.label, C.ncomp);
   hipLaunchKernelGGL(k_comp_lists, dim3(1), dim3(1024), 0, st, n_b, C.label, C.start, C.member, C.cursor, C.ncomp);
   return hipGetLastError();

@@ -236,7 +236,7 @@ __global__ void __launch_bounds__(kBlock) k_run_build(View v, const TT* __restri
   const int lane = lane_id();
   const int wave = threadIdx.x >> 6;
   constexpr int iT = 0, iQ = ST ? 1 : 0, iU = iQ + 1;
-  constexpr int U = 4;  // samples whose loads are issued together (direct path)
+  constexpr int U = 2;  // samples whose loads are issued together (direct path)
   const bool gaps = *n_out != 0;
   for (int64_t rb = ((int64_t)blockIdx.x * kWaves + wave) * 64; rb < R; rb += (int64_t)gridDim.x * kWaves * 64) {
     const int64_t r = rb + lane;
@@ -261,13 +261,34 @@ __global__ void __launch_bounds__(kBlock) k_run_build(View v, const TT* __restri
     const int64_t lo = __shfl(ts, 0, 64), hi = __shfl(te, last, 64);
     const bool staged = hi - lo <= kStage;
     if (staged) {
-      for (int i = lane; i < hi - lo; i += 64) {
-        const int64_t t = lo + i;
-        if (SA) s_psi[SA ? wave : 0][i] = psi[t];
-        if (ST) s_tod[wave][iT][i] = tod[v.rowT * n_t + t];
-        if (SQ) {
-          s_tod[wave][iQ][i] = tod[v.rowQ * n_t + t];
-          s_tod[wave][SQ ? iU : 0][i] = tod[v.rowU * n_t + t];
+      // every load of the span is issued before the first LDS write
+      constexpr int KS = kStage / 64;
+      const int span = (int)(hi - lo);
+      for (int k0 = 0; k0 < kStage / 64; k0 += KS) {
+        PT sp[KS];
+        TT s0[KS], s1[KS], s2[KS];
+#pragma unroll
+        for (int k = 0; k < KS; ++k) {
+          const int i = lane + 64 * (k0 + k);
+          const bool in = i < span;
+          const int64_t t = lo + i;
+          if (SA) sp[k] = in ? psi[t] : PT(0);
+          if (ST) s0[k] = in ? tod[v.rowT * n_t + t] : TT(0);
+          if (SQ) {
+            s1[k] = in ? tod[v.rowQ * n_t + t] : TT(0);
+            s2[k] = in ? tod[v.rowU * n_t + t] : TT(0);
+          }
+        }
+#pragma unroll
+        for (int k = 0; k < KS; ++k) {
+          const int i = lane + 64 * (k0 + k);
+          if (i >= span) break;
+          if (SA) s_psi[SA ? wave : 0][SA ? i : 0] = sp[k];
+          if (ST) s_tod[wave][iT][i] = s0[k];
+          if (SQ) {
+            s_tod[wave][iQ][i] = s1[k];
+            s_tod[wave][SQ ? iU : 0][i] = s2[k];
+          }
         }
       }
       // LDS operations of one wavefront execute in issue order; the barrier
@@ -276,51 +297,58 @@ __global__ void __launch_bounds__(kBlock) k_run_build(View v, const TT* __restri
     }
     double C = 0.0, S = 0.0, cc = 0.0, cs = 0.0;
     double dT = 0.0, dq = 0.0, du = 0.0, dQ = 0.0, dU = 0.0;
-    for (int k0 = 0; k0 < n; k0 += U) {
-      double ps_[U], xT[U], xq[U], xu[U];
+    // one sample: angle and timeline values in, the run's sums updated
+    auto take = [&](double ps, double xT, double xq, double xu) {
+      double c = 1.0, s = 0.0;
+      if (SA) {
+        rot2(ps, c, s);
+        C += c;
+        S += s;
+        cc += c * c;
+        cs += c * s;
+      }
+      if (TOD && IQU) {
+        // radiometer row (1, c, s): sums of d and of the weighted c d, s d
+        const double wx = v.w[0] * xT;
+        dT += xT;
+        dQ += c * wx;
+        dU += s * wx;
+      } else if (TOD) {
+        if (HAS_T) dT += xT;
+        if (HAS_QU) {
+          dq += xq;
+          du += xu;
+          const double wq = v.w[1] * xq, wu = v.w[2] * xu;
+          dQ += c * wq - s * wu;
+          dU += s * wq + c * wu;
+        }
+      }
+    };
+    if (staged) {
+      const int i0 = (int)(ts - lo);
+#pragma unroll 1
+      for (int k = 0; k < n; ++k) {
+        const int i = i0 + k;
+        take(SA ? (double)s_psi[SA ? wave : 0][SA ? i : 0] : 0.0,
+             ST ? (double)s_tod[NROW > 0 ? wave : 0][0][NROW > 0 ? i : 0] : 0.0,
+             SQ ? (double)s_tod[wave][iQ][i] : 0.0, SQ ? (double)s_tod[wave][SQ ? iU : 0][i] : 0.0);
+      }
+    } else {
+      for (int k0 = 0; k0 < n; k0 += U) {
+        double ps_[U], xT[U], xq[U], xu[U];
 #pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const int64_t t = ts + k0 + u;
-        const bool in = k0 + u < n;
-        const int64_t i = t - lo;
-        if (staged) {
-          ps_[u] = (SA && in) ? (double)s_psi[SA ? wave : 0][SA ? i : 0] : 0.0;
-          xT[u] = (ST && in) ? (double)s_tod[NROW > 0 ? wave : 0][0][NROW > 0 ? i : 0] : 0.0;
-          xq[u] = (SQ && in) ? (double)s_tod[wave][iQ][i] : 0.0;
-          xu[u] = (SQ && in) ? (double)s_tod[wave][SQ ? iU : 0][i] : 0.0;
-        } else {
+        for (int u = 0; u < U; ++u) {
+          const int64_t t = ts + k0 + u;
+          const bool in = k0 + u < n;
           ps_[u] = (SA && in) ? (double)psi[t] : 0.0;
           xT[u] = (ST && in) ? (double)tod[v.rowT * n_t + t] : 0.0;
           xq[u] = (SQ && in) ? (double)tod[v.rowQ * n_t + t] : 0.0;
           xu[u] = (SQ && in) ? (double)tod[v.rowU * n_t + t] : 0.0;
         }
-      }
 #pragma unroll
-      for (int u = 0; u < U; ++u) {
-        if (k0 + u >= n) break;
-        double c = 1.0, s = 0.0;
-        if (SA) {
-          rot2(ps_[u], c, s);
-          C += c;
-          S += s;
-          cc += c * c;
-          cs += c * s;
-        }
-        if (TOD && IQU) {
-          // radiometer row (1, c, s): sums of d and of the weighted c d, s d
-          const double wx = v.w[0] * xT[u];
-          dT += xT[u];
-          dQ += c * wx;
-          dU += s * wx;
-        } else if (TOD) {
-          if (HAS_T) dT += xT[u];
-          if (HAS_QU) {
-            dq += xq[u];
-            du += xu[u];
-            const double wq = v.w[1] * xq[u], wu = v.w[2] * xu[u];
-            dQ += c * wq - s * wu;
-            dU += s * wq + c * wu;
-          }
+        for (int u = 0; u < U; ++u) {
+          if (k0 + u >= n) break;
+          take(ps_[u], xT[u], xq[u], xu[u]);
         }
       }
     }
@@ -357,25 +385,34 @@ __global__ void __launch_bounds__(kBlock) k_run_build(View v, const TT* __restri
   }
 }
 
-// Time-order runs: pixel -> compact id and, with nb > 0, the packed
-// iteration key index << nb | (length - 1).
-__global__ void __launch_bounds__(kBlock) k_compact_runs(int64_t R, int nb, const int32_t* __restrict__ cid,
-                                                         int32_t* __restrict__ tpix, const int32_t* __restrict__ tn,
-                                                         uint32_t* __restrict__ tkey) {
-  for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < R; r += (int64_t)gridDim.x * blockDim.x) {
-    const int32_t c = cid[tpix[r]];
-    tpix[r] = c;
-    if (nb > 0) tkey[r] = ((uint32_t)c << nb) | (uint32_t)(tn[r] - 1);
-  }
-}
-
-// seg[2k], seg[2k+1]: range of key k in the sorted key array.
+// seg[2k], seg[2k+1]: range of key k in the sorted key array.  Four keys
+// per thread, loaded together.
 __global__ void __launch_bounds__(kBlock) k_key_segments(const uint32_t* __restrict__ keys, int64_t n,
                                                          int64_t* __restrict__ seg) {
-  for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n; j += (int64_t)gridDim.x * blockDim.x) {
-    const uint32_t k = keys[j];
-    if (j == 0 || keys[j - 1] != k) seg[2 * (int64_t)k] = j;
-    if (j == n - 1 || keys[j + 1] != k) seg[2 * (int64_t)k + 1] = j + 1;
+  const int64_t nq = (n + 3) / 4;
+  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < nq; q += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t j0 = 4 * q;
+    uint32_t k[6];  // keys j0 - 1 .. j0 + 4; absent neighbours differ from every key
+    if (j0 + 4 <= n) {
+      const uint4 x = reinterpret_cast<const uint4*>(keys)[q];
+      k[1] = x.x;
+      k[2] = x.y;
+      k[3] = x.z;
+      k[4] = x.w;
+    } else {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) k[1 + i] = j0 + i < n ? keys[j0 + i] : 0u;
+    }
+    k[0] = j0 > 0 ? keys[j0 - 1] : ~k[1];
+    k[5] = j0 + 4 < n ? keys[j0 + 4] : ~k[4];
+#pragma unroll
+    for (int i = 1; i <= 4; ++i) {
+      const int64_t j = j0 + i - 1;
+      if (j >= n) break;
+      const uint32_t nx = j == n - 1 ? ~k[i] : k[i + 1];
+      if (k[i - 1] != k[i]) seg[2 * (int64_t)k[i]] = j;
+      if (nx != k[i]) seg[2 * (int64_t)k[i] + 1] = j + 1;
+    }
   }
 }
 
@@ -606,17 +643,42 @@ __global__ void __launch_bounds__(kBlock) k_pixels_from_runs(
   }
 }
 
-// Per baseline: the smallest compact id its runs visit (n_obs when it has
-// none), the key that orders baselines for the rescan; val = baseline index.
-__global__ void __launch_bounds__(kBlock) k_baseline_keys(int64_t n_b, int64_t n_obs,
-                                                          const uint32_t* __restrict__ bstart,
-                                                          const int32_t* __restrict__ rpix,
-                                                          uint32_t* __restrict__ key, uint32_t* __restrict__ val) {
+// One wavefront per baseline: its time-order runs take compact pixel ids
+// (pixel -> cid) and, with nb > 0, the packed iteration keys
+// c << nb | (length - 1); key[b] = the smallest compact id the baseline
+// visits (n_obs when none), which orders baselines for the rescan;
+// val[b] = b.
+__global__ void __launch_bounds__(kBlock) k_compact_baselines(int64_t n_b, int64_t n_obs, int nb,
+                                                              const uint32_t* __restrict__ bstart,
+                                                              const int32_t* __restrict__ cid,
+                                                              int32_t* __restrict__ tpix,
+                                                              const int32_t* __restrict__ tn,
+                                                              uint32_t* __restrict__ tkey, uint32_t* __restrict__ key,
+                                                              uint32_t* __restrict__ val) {
+  constexpr int U = 4;  // runs per lane whose loads are issued together
   const int lane = lane_id();
   const int64_t nw = (int64_t)gridDim.x * kWaves;
   for (int64_t b = (int64_t)blockIdx.x * kWaves + (threadIdx.x >> 6); b < n_b; b += nw) {
     uint32_t m = (uint32_t)n_obs;
-    for (int64_t r = bstart[b] + lane; r < bstart[b + 1]; r += 64) m = min(m, (uint32_t)rpix[r]);
+    const int64_t r0 = bstart[b], r1 = bstart[b + 1];
+    for (int64_t rb = r0 + lane; rb < r1; rb += 64 * U) {
+      int32_t p[U], len[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int64_t r = rb + 64 * u;
+        p[u] = r < r1 ? tpix[r] : 0;
+        len[u] = (nb > 0 && r < r1) ? tn[r] : 1;
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int64_t r = rb + 64 * u;
+        if (r >= r1) break;
+        const int32_t c = cid[p[u]];
+        tpix[r] = c;
+        if (nb > 0) tkey[r] = ((uint32_t)c << nb) | (uint32_t)(len[u] - 1);
+        m = min(m, (uint32_t)c);
+      }
+    }
     for (int off = 32; off > 0; off >>= 1) m = min(m, (uint32_t)__shfl_xor((int)m, off, 64));
     if (lane == 0) {
       key[b] = m;
@@ -1429,13 +1491,11 @@ hipError_t runs_build(const View& v, int psi_f32, const void* tod, int tod_f32, 
     });
     DST_CHECK(hipGetLastError());
   }
-  // 6-7. time-order runs carry compact ids from here on, and their keys
-  hipLaunchKernelGGL(k_compact_runs, dim3(gr), dim3(kBlock), 0, st, R, W.nb, W.cid, W.tpix, W.tn, W.tkey);
-  DST_CHECK(hipGetLastError());
-  // 8. rescan order of the baselines: by the smallest compact id each visits (stable)
+  // 6. time-order runs carry compact ids from here on, and their keys; the
+  // rescan order of the baselines: by the smallest compact id each visits (stable)
   if (v.n_b > 0) {
-    hipLaunchKernelGGL(k_baseline_keys, dim3(grid_for(v.n_b, kWaves, 4096)), dim3(kBlock), 0, st, v.n_b, W.n_obs,
-                       W.bstart, W.tpix, W.bkey[0], W.bord[0]);
+    hipLaunchKernelGGL(k_compact_baselines, dim3(grid_for(v.n_b, kWaves, 16384)), dim3(kBlock), 0, st, v.n_b,
+                       W.n_obs, W.nb, W.bstart, W.cid, W.tpix, W.tn, W.tkey, W.bkey[0], W.bord[0]);
     DST_CHECK(hipGetLastError());
     rocprim::double_buffer<uint32_t> keys(W.bkey[0], W.bkey[1]);
     rocprim::double_buffer<uint32_t> vals(W.bord[0], W.bord[1]);
