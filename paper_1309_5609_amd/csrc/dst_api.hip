@@ -54,6 +54,12 @@ struct dst_ctx {
   Readback* rb_host = nullptr;
   dst::MultiCtl* mctl_host = nullptr;  // pinned mirror of the batched CG state
   CgCtl* gctl_host = nullptr;          // pinned mirrors of the CG scalars of a problem group [kMaxGroup]
+  // GMRES status written by the kernels into pinned memory: slots 0, 1 for
+  // alternate Arnoldi steps, slot 2 for the end of a cycle; gm_dev is the
+  // device's address of the same memory; gm_ev marks the steps.
+  dst::GmStatus* gm_host = nullptr;
+  dst::GmStatus* gm_dev = nullptr;
+  hipEvent_t gm_ev[2] = {nullptr, nullptr};
   hipStream_t cap = nullptr;  // private stream on which iteration graphs are captured
   int unbin_bpw = 4;          // launch shape of the run rescan (baselines per wavefront)
   int bin_lpp = 0;            // launch shape of the run binning (lanes per pixel; 0: default 32)
@@ -1161,117 +1167,77 @@ int solve_uneven(dst_ctx* ctx, const dst_problem* problems, const std::vector<in
 
 // Restarted GMRES on K a = b (Eq. 13), right-preconditioned by the Jacobi
 // diagonal J, with the same T null-space projection as the PCG (b and every
-// K v lose their mean over T-valid baselines).  Arnoldi by classical
-// Gram-Schmidt with one reorthogonalisation (two batched dot / combine
-// passes); Givens rotations and the triangular solve on the host.  On entry
+// K v lose their mean over T-valid baselines, and their component means
+// first when the baseline-pixel graph has several components: cv set).
+// Arnoldi by classical Gram-Schmidt with one reorthogonalisation; the
+// coefficients, rotations and triangular solve stay on the device (GmState).
+// The host enqueues the steps of a cycle and, while the GPU runs step j,
+// reads the status that step j - 1 wrote into pinned memory, so it stops
+// enqueueing one step after the stop with no idle GPU in between; the cycle's
+// end (solution update, restart residual) is followed by one wait.  On entry
 // b is projected, a holds a0 (or 0), r = b - P K a0 and ctl_host the start-up
-// scalars (b_norm, r_norm, n_e).  q is scratch.  With several components of
-// the baseline-pixel graph (cv set), every K v loses its component means
-// first.  *fin receives iterations,
-// stop code and the residual estimate for the common exit path.
+// scalars (b_norm, r_norm, n_e).  q is scratch; partials is the scratch of
+// the rescan's gated form.  *fin receives iterations, stop code and the
+// residual estimate for the common exit path.
 int gmres_loop(dst_ctx* ctx, Plan& P, const View& v, const double* b, double* a, double* r, double* q,
-               const dst_solve_opts& opts, const dst::CompView& cv, CgCtl* fin, hipStream_t st) {
+               double* partials, const dst_solve_opts& opts, const dst::CompView& cv, CgCtl* fin, hipStream_t st) {
   Setup& S = P.S;
   const int64_t N = (int64_t)v.n_streams * v.n_b;
   const int m = opts.restart > 0 ? opts.restart : 50;
   const CgCtl h0 = *ctx->ctl_host;
   const double bnorm = h0.b_norm, n_e = h0.n_e;
-  double *V, *z, *part, *dots;
+  double *V, *z, *part, *gsw;
   DST_TRY(ws(ctx, "gm_V", (size_t)(m + 2) * N, &V));  // slot 0: T mask e; slots 1..m+1: basis
   DST_TRY(ws(ctx, "gm_z", N, &z));
   DST_TRY(ws(ctx, "gm_part", (size_t)(m + 2) * dst::gmres_dot_blocks(N), &part));
-  DST_TRY(ws(ctx, "gm_dots", m + 2, &dots));
+  DST_TRY(ws(ctx, "gm_state", (sizeof(dst::GmState) + sizeof(double) - 1) / sizeof(double), &gsw));
+  dst::GmState* gs = reinterpret_cast<dst::GmState*>(gsw);
+  dst::GmStatus* hs = ctx->gm_host;
+  dst::GmStatus* ds = ctx->gm_dev;
   double* e = V;
   auto slot = [&](int i) { return V + (int64_t)(i + 1) * N; };  // basis vector i
   HIP_TRY(dst::launch_tmask(v, S.J, e, st));
-  std::vector<double> hd(m + 2);
-  auto dot_with = [&](const double* base, int k, const double* w) -> int {
-    HIP_TRY(dst::launch_dots(base, N, k, w, N, part, dots, st));
-    HIP_TRY(hipMemcpyAsync(hd.data(), dots, k * sizeof(double), hipMemcpyDeviceToHost, st));
-    HIP_TRY(hipStreamSynchronize(st));
-    return DST_OK;
-  };
-  int it = 0;
-  double rel = bnorm > 0.0 ? h0.r_norm / bnorm : 0.0;
-  double beta = h0.r_norm;
-  bool broke = false;
-  std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), y(m);
-  auto Hij = [&](int i, int j) -> double& { return H[(size_t)i * m + j]; };
-  if (bnorm > 0.0 && beta > 0.0 && rel > opts.tol && opts.max_iter > 0) {
-    HIP_TRY(dst::launch_scale(r, 1.0 / beta, nullptr, slot(0), N, st));
-  }
-  while (bnorm > 0.0 && beta > 0.0 && rel > opts.tol && it < opts.max_iter && !broke) {
-    std::fill(H.begin(), H.end(), 0.0);
-    std::fill(g.begin(), g.end(), 0.0);
-    g[0] = beta;
-    int k = 0;
-    for (int j = 0; j < m; ++j) {
-      // w = P K J v_j
-      HIP_TRY(dst::launch_scale(slot(j), 0.0, S.J, z, N, st));
-      DST_TRY(plan_operator(ctx, P, z, q, st));
+  const double beta = h0.r_norm;
+  const double rel0 = bnorm > 0.0 ? beta / bnorm : 0.0;
+  const bool run = bnorm > 0.0 && beta > 0.0 && rel0 > opts.tol && opts.max_iter > 0;
+  HIP_TRY(dst::launch_gm_init(gs, bnorm, n_e, opts.tol, opts.max_iter, m, beta, rel0,
+                              run ? dst::DONE_RUNNING : dst::DONE_CONVERGED, ds + 2, st));
+  CgCtl* gate = &gs->ctl;
+  int iters = 0;
+  double rel = rel0;
+  if (run) {
+    for (int s = 0; s < 3; ++s) hs[s].done = dst::DONE_RUNNING;
+    for (;;) {
+      for (int j = 0; j < m; ++j) {
+        // w = P K J v_j, then the two orthogonalisation passes and the Givens step
+        HIP_TRY(dst::launch_gm_next(v, gs, j == 0 ? r : q, slot(j), S.J, z, P.pw4, P.dense_t, st));
+        DST_TRY(plan_bin(ctx, P, gate, st));
+        DST_TRY(plan_unbin(ctx, P, z, q, gate, partials, st));
+        HIP_TRY(dst::launch_comp_project(cv, q, 1, 1, st));
+        HIP_TRY(dst::launch_gm_dots(gs, V, j + 2, q, N, part, gs->h1, st));  // e.w, v_0.w .. v_j.w
+        HIP_TRY(dst::launch_gm_orth(gs, 1, V, j, q, N, part, nullptr, st));
+        HIP_TRY(dst::launch_gm_orth(gs, 2, V, j, q, N, part, ds + (j & 1), st));
+        HIP_TRY(hipEventRecord(ctx->gm_ev[j & 1], st));
+        if (j > 0) {
+          HIP_TRY(hipEventSynchronize(ctx->gm_ev[(j - 1) & 1]));
+          if (hs[(j - 1) & 1].done != dst::DONE_RUNNING) break;
+        }
+      }
+      // a += J V y, then the restart residual r = b - P K a and v_0 = r / ||r||
+      HIP_TRY(dst::launch_gm_update(gs, S.J, V, a, N, st));
+      HIP_TRY(dst::launch_p_update4(S.v, a, nullptr, P.pw4, gate, 0, P.dense_t, st));
+      DST_TRY(plan_bin(ctx, P, gate, st));
+      DST_TRY(plan_unbin(ctx, P, a, q, gate, partials, st));
       HIP_TRY(dst::launch_comp_project(cv, q, 1, 1, st));
-      DST_TRY(dot_with(V, j + 2, q));  // e.w, v_0.w .. v_j.w
-      dst::GmresCoef c{};
-      c.c[0] = n_e > 0.0 ? hd[0] / n_e : 0.0;
-      for (int i = 0; i <= j; ++i) {
-        c.c[i + 1] = hd[i + 1];
-        Hij(i, j) = hd[i + 1];
-      }
-      HIP_TRY(dst::launch_combine(q, V, N, j + 2, c, N, st));
-      DST_TRY(dot_with(slot(0), j + 1, q));  // reorthogonalisation
-      dst::GmresCoef c2{};
-      for (int i = 0; i <= j; ++i) {
-        c2.c[i] = hd[i];
-        Hij(i, j) += hd[i];
-      }
-      HIP_TRY(dst::launch_combine(q, slot(0), N, j + 1, c2, N, st));
-      DST_TRY(dot_with(q, 1, q));
-      const double hn = std::sqrt(std::max(hd[0], 0.0));
-      Hij(j + 1, j) = hn;
-      for (int i = 0; i < j; ++i) {
-        const double t = cs[i] * Hij(i, j) + sn[i] * Hij(i + 1, j);
-        Hij(i + 1, j) = -sn[i] * Hij(i, j) + cs[i] * Hij(i + 1, j);
-        Hij(i, j) = t;
-      }
-      const double den = std::hypot(Hij(j, j), Hij(j + 1, j));
-      if (!(den > 0.0) || !std::isfinite(den)) {
-        broke = true;
-        break;
-      }
-      cs[j] = Hij(j, j) / den;
-      sn[j] = Hij(j + 1, j) / den;
-      Hij(j, j) = den;
-      Hij(j + 1, j) = 0.0;
-      g[j + 1] = -sn[j] * g[j];
-      g[j] = cs[j] * g[j];
-      ++it;
-      k = j + 1;
-      rel = std::fabs(g[j + 1]) / bnorm;
-      if (rel <= opts.tol || it >= opts.max_iter || hn == 0.0) break;
-      HIP_TRY(dst::launch_scale(q, 1.0 / hn, nullptr, slot(j + 1), N, st));
+      HIP_TRY(dst::launch_gm_restart(gs, b, q, e, r, N, part, ds + 2, st));
+      HIP_TRY(hipStreamSynchronize(st));
+      if (hs[2].done != dst::DONE_RUNNING) break;
     }
-    if (k == 0) break;
-    for (int i = k - 1; i >= 0; --i) {
-      double sum = g[i];
-      for (int l = i + 1; l < k; ++l) sum -= Hij(i, l) * y[l];
-      y[i] = sum / Hij(i, i);
-    }
-    dst::GmresCoef yc{};
-    for (int i = 0; i < k; ++i) yc.c[i] = y[i];
-    HIP_TRY(dst::launch_xupdate(a, S.J, slot(0), N, k, yc, N, st));
-    if (rel <= opts.tol || it >= opts.max_iter || broke) break;
-    // restart from r = b - P K a
-    DST_TRY(plan_operator(ctx, P, a, q, st));
-    HIP_TRY(dst::launch_comp_project(cv, q, 1, 1, st));
-    DST_TRY(dot_with(e, 1, q));
-    const double mu = n_e > 0.0 ? hd[0] / n_e : 0.0;
-    HIP_TRY(dst::launch_restart_resid(b, q, mu, e, r, N, st));
-    DST_TRY(dot_with(r, 1, r));
-    beta = std::sqrt(std::max(hd[0], 0.0));
-    if (beta > 0.0) HIP_TRY(dst::launch_scale(r, 1.0 / beta, nullptr, slot(0), N, st));
+    iters = hs[2].iter;
+    rel = hs[2].rel;
   }
   *fin = h0;
-  fin->iter = it;
+  fin->iter = iters;
   fin->r_norm = rel * bnorm;
   fin->done = !std::isfinite(rel) ? dst::DONE_NAN : (rel <= opts.tol ? dst::DONE_CONVERGED : dst::DONE_MAXITER);
   return DST_OK;
@@ -1364,6 +1330,11 @@ int dst_create(dst_ctx** out, int device) {
           hipSuccess ||
       hipHostMalloc(reinterpret_cast<void**>(&ctx->gctl_host), kMaxGroup * sizeof(CgCtl), hipHostMallocDefault) !=
           hipSuccess ||
+      hipHostMalloc(reinterpret_cast<void**>(&ctx->gm_host), 3 * sizeof(dst::GmStatus), hipHostMallocCoherent) !=
+          hipSuccess ||
+      hipHostGetDevicePointer(reinterpret_cast<void**>(&ctx->gm_dev), ctx->gm_host, 0) != hipSuccess ||
+      hipEventCreateWithFlags(&ctx->gm_ev[0], hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&ctx->gm_ev[1], hipEventDisableTiming) != hipSuccess ||
       hipMalloc(reinterpret_cast<void**>(&ctx->err_dev), 4 * sizeof(int)) != hipSuccess ||
       hipMemset(ctx->err_dev, 0, 4 * sizeof(int)) != hipSuccess) {
     (void)hipGetLastError();
@@ -1392,6 +1363,9 @@ int dst_destroy(dst_ctx* ctx) {
   if (ctx->rb_host) (void)hipHostFree(ctx->rb_host);
   if (ctx->mctl_host) (void)hipHostFree(ctx->mctl_host);
   if (ctx->gctl_host) (void)hipHostFree(ctx->gctl_host);
+  if (ctx->gm_host) (void)hipHostFree(ctx->gm_host);
+  for (auto e : ctx->gm_ev)
+    if (e) (void)hipEventDestroy(e);
   if (ctx->cap) (void)hipStreamDestroy(ctx->cap);
   delete ctx;
   return DST_OK;
@@ -1647,7 +1621,7 @@ int dst_solve(dst_ctx* ctx, const dst_problem* prob, const dst_solve_opts* opts_
   if (use_gmres) {
     // restarted GMRES from the projected residual of the start-up
     HIP_TRY(hipEventRecord(ev[2], st));
-    DST_TRY(gmres_loop(ctx, P, v, b, a, r, q, opts, ncomp > 1 ? cv : dst::CompView{}, &fin, st));
+    DST_TRY(gmres_loop(ctx, P, v, b, a, r, q, partials, opts, ncomp > 1 ? cv : dst::CompView{}, &fin, st));
     HIP_TRY(hipEventRecord(ev[3], st));
   } else {
   // batches of check_every iterations between convergence checks

@@ -102,22 +102,49 @@ hipError_t launch_noise(uint64_t seed, uint64_t stream, int64_t n, int64_t S, do
                         double alpha, void* out, int out_f32, int accumulate, double2* buf0, double2* buf1,
                         hipStream_t st);
 
-// ---- restarted GMRES vector kernels (dst_gmres.hip) ------------------------
-constexpr int kMaxKrylov = 128;  // basis vectors + the T mask in one dot / combine launch
-struct GmresCoef {
-  double c[kMaxKrylov];
+// ---- restarted GMRES on the device (dst_gmres.hip) ------------------------
+constexpr int kMaxKrylov = 128;  // basis vectors + the T mask in one dot launch; restart <= kMaxKrylov - 2
+constexpr int kMaxRestart = kMaxKrylov - 2;
+// ctl.done of a cycle that stopped early on an invariant Krylov space (new
+// basis vector of norm zero): the steps left in the cycle do nothing and the
+// restart resumes.
+constexpr int DONE_PAUSE = 5;
+
+// Device state of one GMRES solve.  ctl.done gates every kernel of the
+// iteration (the operator's included); ctl.iter counts Arnoldi steps.
+struct GmState {
+  CgCtl ctl;
+  double bnorm, n_e, tol, rel, inv_h;
+  int32_t m, k, pad0, pad1;  // restart length; columns of the current cycle
+  double h1[kMaxKrylov];     // e.w, v_0.w .. v_j.w of the step
+  double h2[kMaxKrylov];     // the reorthogonalisation's v_i.w
+  double cs[kMaxRestart], sn[kMaxRestart], g[kMaxRestart + 1], y[kMaxRestart];
+  double H[(kMaxRestart + 1) * kMaxRestart];  // Hessenberg (i, j) at i * kMaxRestart + j
 };
+// What the host reads back (pinned memory written by the kernels).
+struct GmStatus {
+  int32_t iter, done, k, pad;
+  double rel;
+};
+
 int gmres_dot_blocks(int64_t N);
 hipError_t launch_tmask(const View& v, const double* J, double* e, hipStream_t st);
-// out[i] = V_i . w for i < k (V_i = V + i ldv); partial: k * gmres_dot_blocks(N) doubles.
-hipError_t launch_dots(const double* V, int64_t ldv, int k, const double* w, int64_t N, double* partial, double* out,
-                       hipStream_t st);
-hipError_t launch_combine(double* w, const double* V, int64_t ldv, int k, const GmresCoef& c, int64_t N,
-                          hipStream_t st);
-hipError_t launch_scale(const double* w, double s, const double* J, double* out, int64_t N, hipStream_t st);
-hipError_t launch_xupdate(double* x, const double* J, const double* V, int64_t ldv, int k, const GmresCoef& y,
-                          int64_t N, hipStream_t st);
-hipError_t launch_restart_resid(const double* b, const double* q, double mu, const double* e, double* r, int64_t N,
-                                hipStream_t st);
+hipError_t launch_gm_init(GmState* s, double bnorm, double n_e, double tol, int max_iter, int m, double beta,
+                          double rel, int done, GmStatus* status, hipStream_t st);
+// v_j = inv_h src; z = J v_j; pw4 = the per-baseline weighted z (binning layout).
+hipError_t launch_gm_next(const View& v, GmState* s, const double* src, double* vj, const double* J, double* z,
+                          double* pw4, int dense_t, hipStream_t st);
+// out[i] = V_i . w for i < k (V_i = V + i N); partial: k * gmres_dot_blocks(N) doubles.
+hipError_t launch_gm_dots(GmState* s, const double* V, int k, const double* w, int64_t N, double* partial,
+                          double* out, hipStream_t st);
+// mode 1: w -= (h1_0 / n_e) e + sum_{i <= j} h1_{i+1} v_i, then partial dots v_i . w (i <= j) into h2;
+// mode 2: w -= sum_{i <= j} h2_i v_i, then ||w||^2, the Givens step j and the status.
+hipError_t launch_gm_orth(GmState* s, int mode, const double* V, int j, double* w, int64_t N, double* partial,
+                          GmStatus* status, hipStream_t st);
+// y = R^-1 g over the cycle's k columns, then a += J sum_i y_i v_i; resumes a paused solve.
+hipError_t launch_gm_update(GmState* s, const double* J, const double* V, double* a, int64_t N, hipStream_t st);
+// r = b - (q - (e.q / n_e) e) with e.q in h1_0, beta = ||r||, the next cycle's start, the status.
+hipError_t launch_gm_restart(GmState* s, const double* b, const double* q, const double* e, double* r, int64_t N,
+                             double* partial, GmStatus* status, hipStream_t st);
 
 }  // namespace dst
