@@ -1858,8 +1858,10 @@ int dst_noise_generate(dst_ctx* ctx, uint64_t seed, uint64_t stream_id, int64_t 
   double2 *b0 = nullptr, *b1 = nullptr;
   DST_TRY(ws(ctx, "noise_b0", nbuf, &b0));
   DST_TRY(ws(ctx, "noise_b1", nbuf, &b1));
+  double2* tw = nullptr;
+  DST_TRY(ws(ctx, "noise_tw", (size_t)dst::noise_twiddle_count(segment), &tw));
   HIP_TRY(dst::launch_noise(seed, stream_id, n_samples, segment, sample_rate_hz, sigma, fknee_hz, alpha, out,
-                            out_dtype == DST_F32, (flags & DST_NOISE_ACCUMULATE) ? 1 : 0, b0, b1, st));
+                            out_dtype == DST_F32, (flags & DST_NOISE_ACCUMULATE) ? 1 : 0, b0, b1, tw, st));
   HIP_TRY(hipStreamSynchronize(st));
   return DST_OK;
 }

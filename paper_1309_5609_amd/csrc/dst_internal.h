@@ -97,10 +97,12 @@ hipError_t launch_expand(int64_t nside, int64_t start, int64_t n, int64_t n_per,
 
 // ---- Monte Carlo noise (dst_noise.hip) -------------------------------------
 int64_t noise_pairs_per_chunk(int64_t S);
-// buf0, buf1: noise_pairs_per_chunk(S) * S complex values each.
+int64_t noise_twiddle_count(int64_t S);
+// buf0, buf1: noise_pairs_per_chunk(S) * S complex values each; tw:
+// noise_twiddle_count(S) complex values.
 hipError_t launch_noise(uint64_t seed, uint64_t stream, int64_t n, int64_t S, double rate, double sigma, double fknee,
                         double alpha, void* out, int out_f32, int accumulate, double2* buf0, double2* buf1,
-                        hipStream_t st);
+                        double2* tw, hipStream_t st);
 
 // ---- restarted GMRES on the device (dst_gmres.hip) ------------------------
 constexpr int kMaxKrylov = 128;  // basis vectors + the T mask in one dot launch; restart <= kMaxKrylov - 2
