@@ -566,8 +566,10 @@ int build_plan(dst_ctx* ctx, const dst_problem* prob, Plan& P, const void* tod, 
                double* b, hipStream_t st) {
   P.lpp = ctx->bin_lpp;
   P.bpw = ctx->unbin_bpw;
-  return P.runs ? build_runs_plan(ctx, prob, P, tod, sd4, md4, b, st)
-                : build_sample_plan(ctx, prob, P, tod, sd4, md4, b, st);
+  if (!P.runs) return build_sample_plan(ctx, prob, P, tod, sd4, md4, b, st);
+  DST_TRY(build_runs_plan(ctx, prob, P, tod, sd4, md4, b, st));
+  if (P.lpp == 0) P.lpp = dst::bin_lanes_for(P.W.R, P.W.n_obs);
+  return DST_OK;
 }
 
 // The two halves of K p: m = M^-1 A^T W F p (pixel order), then
@@ -967,6 +969,7 @@ int solve_uneven(dst_ctx* ctx, const dst_problem* problems, const std::vector<in
   std::stable_sort(order.begin(), order.end(),
                    [&](int x, int y) { return kind_of(M[x].P.S.v) < kind_of(M[y].P.S.v); });
   std::vector<dst::GroupProblem> gp(n);
+  std::vector<int64_t> n_runs(n);
   std::vector<uint32_t> vec_start(n + 1, 0u);
   std::vector<uint32_t> ranges;  // per kind: bin starts [count + 1], then rescan starts [count + 1]
   dst::GroupLaunch G;
@@ -976,6 +979,7 @@ int solve_uneven(dst_ctx* ctx, const dst_problem* problems, const std::vector<in
     const Setup& S = m.P.S;
     const dst::Runs& W = m.P.W;
     dst::GroupProblem& g = gp[o];
+    n_runs[o] = W.R;
     g.v = S.v;
     g.kind = kind_of(S.v);
     g.nb = W.nb;
@@ -1016,13 +1020,20 @@ int solve_uneven(dst_ctx* ctx, const dst_problem* problems, const std::vector<in
   for (int K = 0; K < 4; ++K) {
     dst::GroupSlice& sl = G.kind[K];
     if (sl.count == 0) continue;
+    // lanes per pixel of the kind's binning from its runs per observed pixel
+    int64_t runs = 0, obs = 0;
+    for (int j = 0; j < sl.count; ++j) {
+      runs += n_runs[sl.first + j];
+      obs += gp[sl.first + j].v.n_pix;
+    }
+    sl.lpp = dst::bin_lanes_for(runs, obs);
     roff[K] = ranges.size();
     ranges.resize(ranges.size() + 2 * (sl.count + 1), 0u);
     uint32_t* bs = ranges.data() + roff[K];
     uint32_t* us = bs + sl.count + 1;
     for (int j = 0; j < sl.count; ++j) {
       const dst::GroupProblem& g = gp[sl.first + j];
-      bs[j + 1] = bs[j] + dst::group_bin_blocks(g.v.n_pix);
+      bs[j + 1] = bs[j] + dst::group_bin_blocks(g.v.n_pix, sl.lpp);
       us[j + 1] = us[j] + g.unbin_n;
     }
     sl.bin_total = bs[sl.count];
@@ -1277,7 +1288,7 @@ int autotune(dst_ctx* ctx, Plan& P, const double* p, double* scratch, hipStream_
     };
     int best_lpp = P.lpp, best_bpw = P.bpw;
     float tb = 1e30f, tu = 1e30f;
-    for (int lpp : {64, 32, 16, -64}) {
+    for (int lpp : {64, 32, 16, 8, 4, -64}) {
       const float t = time_of([&] {
         return dst::launch_bin_runs(S.v, P.W, P.pw4, S.Minv4, S.valid, P.m4, nullptr, lpp, st);
       });

@@ -57,6 +57,7 @@ struct GroupSlice {
   const uint32_t* bin_start = nullptr;    // device [count + 1]
   const uint32_t* unbin_start = nullptr;  // device [count + 1]
   uint32_t bin_total = 0, unbin_total = 0;
+  int lpp = 32;  // lanes per pixel of the binning (4, 8, 16 or 32)
 };
 struct GroupLaunch {
   const GroupProblem* prob = nullptr;  // device [n]
@@ -68,7 +69,7 @@ struct GroupLaunch {
 };
 
 // Workgroups each phase gives one problem.
-uint32_t group_bin_blocks(int64_t n_obs);
+uint32_t group_bin_blocks(int64_t n_obs, int lpp);
 uint32_t group_unbin_blocks(const View& vc);  // a multiple of 8
 uint32_t group_vec_blocks(const View& v);
 

@@ -286,9 +286,14 @@ __global__ void __launch_bounds__(kBlock) k_multi_bin(View vc, int R, int Rp, co
   const int nS = vc.n_streams;
   const int oT = vc.rowT * Rp, oQ = vc.rowQ * Rp, oU = vc.rowU * Rp;
   const double w0 = vc.w[0], w1 = vc.w[1], w2 = vc.w[2];
+  // each XCD (workgroup i runs on XCD i mod 8) sweeps a contiguous eighth of
+  // the compact pixels, so the pixels it works on at a time are neighbours,
+  // visited by the same baselines, whose p rows stay in its L2
   const int64_t n_obs = vc.n_pix;
-  const int64_t nw = (int64_t)gridDim.x * kWaves;
-  for (int64_t c = (int64_t)blockIdx.x * kWaves + (threadIdx.x >> 6); c < n_obs; c += nw) {
+  const int64_t per = (n_obs + 7) / 8;
+  const int64_t xcd = blockIdx.x & 7, kb = blockIdx.x >> 3, nk = gridDim.x >> 3;
+  const int64_t lo = xcd * per, hi = std::min(n_obs, lo + per);
+  for (int64_t c = lo + kb * kWaves + (threadIdx.x >> 6); c < hi; c += nk * kWaves) {
     const int64_t j0 = pstart[c], j1 = pstart[c + 1];
     double acc[3 * V];  // [row][v]
 #pragma unroll
@@ -940,7 +945,8 @@ hipError_t launch_multi_pixsum(int64_t n_obs, const View& vc, const Runs& W, con
 
 hipError_t launch_multi_bin(const View& vc, const Runs& W, const Multi& mu, const double* p, const double* Minv4,
                             double* m, const MultiCtl* ctl, hipStream_t st) {
-  const unsigned g = grid_for(vc.n_pix, kWaves, 16384);
+  const int64_t per = (vc.n_pix + 7) / 8;
+  const unsigned g = (unsigned)(8 * std::max<int64_t>(1, std::min<int64_t>((per + kWaves - 1) / kWaves, 2048)));
   by_float(W.f32, [&](auto rt) {
     using RT = typename decltype(rt)::type;
     by_streams(vc, [&](auto T, auto Q) {

@@ -120,8 +120,10 @@ hipError_t runs_build(const View& v, int psi_f32, const void* tod, int tod_f32, 
 // Per baseline: n_valid, Jacobi diagonal, and with tod b = F^T W (d - A m_d).
 hipError_t launch_rhs_runs(const View& vc, const Runs& W, const void* tod, const double* md4, const uint8_t* valid,
                            int32_t* nvalid, double* J, double* b, hipStream_t st);
+// Lanes per pixel of the binning for `runs` runs over n_obs pixels.
+int bin_lanes_for(int64_t runs, int64_t n_obs);
 // m = M^-1 A^T W F p (pw4 = interleaved w .* p).
-// lpp: lanes per pixel (64, 32 or 16; -64: 64 with the pixel pipeline; 0: 32).
+// lpp: lanes per pixel (64, 32, 16, 8 or 4; -64: 64 with the pixel pipeline; 0: 32).
 hipError_t launch_bin_runs(const View& vc, const Runs& W, const double* pw4, const double* Minv4,
                            const uint8_t* valid, double* m4, const CgCtl* gate, int lpp, hipStream_t st);
 // q = K p; with ctl the per-workgroup CG partials, unbin_runs_parts(vc, bpw)

@@ -1527,10 +1527,20 @@ hipError_t launch_rhs_runs(const View& vc, const Runs& W, const void* tod, const
   return hipGetLastError();
 }
 
+int bin_lanes_for(int64_t runs, int64_t n_obs) {
+  // sparse pixels (few runs each) take fewer lanes, so that most lanes are
+  // not idle: lanes per pixel times runs per lane and step (8 for LPP <= 16)
+  // near the mean runs per pixel; dense ones 32 lanes
+  const double mean = n_obs > 0 ? (double)runs / (double)n_obs : 0.0;
+  if (mean <= 32.0) return 4;
+  if (mean <= 64.0) return 8;
+  return 32;
+}
+
 hipError_t launch_bin_runs(const View& vc, const Runs& W, const double* pw4, const double* Minv4,
                            const uint8_t* valid, double* m4, const CgCtl* gate, int lpp, hipStream_t st) {
   if (lpp == 0) lpp = 32;  // the default
-  if (lpp != 64 && lpp != 32 && lpp != 16 && lpp != -64) lpp = 32;
+  if (lpp != 64 && lpp != 32 && lpp != 16 && lpp != 8 && lpp != 4 && lpp != -64) lpp = 32;
   const bool pipe = lpp < 0;
   if (pipe) lpp = -lpp;
   const int64_t ppb = kWaves * (64 / lpp);
@@ -1552,7 +1562,11 @@ hipError_t launch_bin_runs(const View& vc, const Runs& W, const double* pw4, con
       if (pipe) lpp = 64;
       by_bool(W.nb != 0, [&](auto K) {
         constexpr bool PK = decltype(K)::value;
-        if (lpp == 16)
+        if (lpp == 4)
+          launch(k_bin_runs<RT, HT, HQ, HI, 4, PK>);
+        else if (lpp == 8)
+          launch(k_bin_runs<RT, HT, HQ, HI, 8, PK>);
+        else if (lpp == 16)
           launch(k_bin_runs<RT, HT, HQ, HI, 16, PK>);
         else if (lpp == 32)
           launch(k_bin_runs<RT, HT, HQ, HI, 32, PK>);
@@ -1620,7 +1634,7 @@ __device__ __forceinline__ int group_of(const uint32_t* start, int n, uint32_t b
   return lo;
 }
 
-template <typename RT, int KIND>
+template <typename RT, int KIND, int LPP>
 __global__ void __launch_bounds__(kBlock) k_group_bin(GroupLaunch G) {
   constexpr bool HT = KIND != GK_QU, HQ = KIND == GK_QU || KIND == GK_TQU, HI = KIND == GK_IQU;
   const GroupSlice& S = G.kind[KIND];
@@ -1629,8 +1643,8 @@ __global__ void __launch_bounds__(kBlock) k_group_bin(GroupLaunch G) {
   const GroupProblem& P = G.prob[S.first + j];
   if (P.ctl->done) return;
   const int64_t vb = b - S.bin_start[j], vg = S.bin_start[j + 1] - S.bin_start[j];
-  bin_runs_body<RT, HT, HQ, HI, 32, true>(P.v.n_pix, P.pstart, P.pkey, nullptr, P.nb, static_cast<const RT*>(P.pcs),
-                                          P.pw4, P.Minv4, P.valid, P.m4, vb, vg);
+  bin_runs_body<RT, HT, HQ, HI, LPP, true>(P.v.n_pix, P.pstart, P.pkey, nullptr, P.nb, static_cast<const RT*>(P.pcs),
+                                           P.pw4, P.Minv4, P.valid, P.m4, vb, vg);
 }
 
 template <typename RT, int KIND>
@@ -1682,8 +1696,8 @@ __global__ void __launch_bounds__(kBlock) k_group_p(GroupLaunch G) {
 
 }  // namespace
 
-uint32_t group_bin_blocks(int64_t n_obs) {
-  const int64_t ppb = kWaves * (64 / 32);
+uint32_t group_bin_blocks(int64_t n_obs, int lpp) {
+  const int64_t ppb = kWaves * (64 / lpp);
   return (uint32_t)std::max<int64_t>(1, std::min<int64_t>((n_obs + ppb - 1) / ppb, 16384));
 }
 
@@ -1698,19 +1712,26 @@ hipError_t launch_group_phase(const GroupLaunch& G, int phase, hipStream_t st) {
   if (G.n <= 0) return hipSuccess;
   by_float(G.f32 != 0, [&](auto rt) {
     using RT = typename decltype(rt)::type;
-    auto per_kind = [&](auto bin, auto unbin, int K) {
+    auto per_kind = [&](auto kind) {
+      constexpr int K = decltype(kind)::value;
       const GroupSlice& S = G.kind[K];
       if (S.count == 0) return;
-      if (phase == 0)
-        hipLaunchKernelGGL(bin, dim3(S.bin_total), dim3(kBlock), 0, st, G);
-      else
-        hipLaunchKernelGGL(unbin, dim3(S.unbin_total), dim3(kBlock), 0, st, G);
+      if (phase == 1) {
+        hipLaunchKernelGGL((k_group_unbin<RT, K>), dim3(S.unbin_total), dim3(kBlock), 0, st, G);
+        return;
+      }
+      switch (S.lpp) {
+        case 4: hipLaunchKernelGGL((k_group_bin<RT, K, 4>), dim3(S.bin_total), dim3(kBlock), 0, st, G); break;
+        case 8: hipLaunchKernelGGL((k_group_bin<RT, K, 8>), dim3(S.bin_total), dim3(kBlock), 0, st, G); break;
+        case 16: hipLaunchKernelGGL((k_group_bin<RT, K, 16>), dim3(S.bin_total), dim3(kBlock), 0, st, G); break;
+        default: hipLaunchKernelGGL((k_group_bin<RT, K, 32>), dim3(S.bin_total), dim3(kBlock), 0, st, G); break;
+      }
     };
     if (phase <= 1) {
-      per_kind(k_group_bin<RT, GK_T>, k_group_unbin<RT, GK_T>, GK_T);
-      per_kind(k_group_bin<RT, GK_QU>, k_group_unbin<RT, GK_QU>, GK_QU);
-      per_kind(k_group_bin<RT, GK_TQU>, k_group_unbin<RT, GK_TQU>, GK_TQU);
-      per_kind(k_group_bin<RT, GK_IQU>, k_group_unbin<RT, GK_IQU>, GK_IQU);
+      per_kind(std::integral_constant<int, GK_T>{});
+      per_kind(std::integral_constant<int, GK_QU>{});
+      per_kind(std::integral_constant<int, GK_TQU>{});
+      per_kind(std::integral_constant<int, GK_IQU>{});
       if (phase == 1) hipLaunchKernelGGL(k_group_alpha, dim3(G.n), dim3(1024), 0, st, G);
     } else {
       hipLaunchKernelGGL(k_group_update, dim3(G.vec_total), dim3(kBlock), 0, st, G);
