@@ -731,6 +731,16 @@ int solve_group(dst_ctx* ctx, const dst_problem* problems, const std::vector<int
   DST_TRY(ws(ctx, "mb_part", (size_t)dst::multi_unbin_blocks(vc) * 3 * mu.Rp, &part));
   DST_TRY(ws(ctx, "mb_part2", (size_t)std::max(dst::multi_update_blocks(v, mu), 256) * 2 * mu.Rp, &part2));
   DST_TRY(ws(ctx, "mb_ctl", 1, &ctl));
+  // With FP32 angles and timelines the iterations keep FP32 copies of p and m
+  // for the gathers of the binning and the rescan (sums, the CG and the
+  // final outputs stay FP64).
+  bool g32 = W.f32 != 0;
+  for (int k = 0; k < mu.R; ++k) g32 = g32 && problems[idx[k]].tod_dtype == DST_F32;
+  float *p32 = nullptr, *m32 = nullptr;
+  if (g32) {
+    DST_TRY(ws(ctx, "mb_p32", NV, &p32));
+    DST_TRY(ws(ctx, "mb_m32", NM, &m32));
+  }
   HIP_TRY(dst::launch_fill(m, NM, 0.0, st));
   HIP_TRY(dst::launch_fill(md, NM, 0.0, st));
   HIP_TRY(dst::launch_fill(braw, NV, 0.0, st));
@@ -756,6 +766,7 @@ int solve_group(dst_ctx* ctx, const dst_problem* problems, const std::vector<int
   const int64_t sbm = (int64_t)v.n_streams * mu.Rp;  // stride of one baseline in the multi layout
   HIP_TRY(dst::launch_comp_project(cv, b, sbm, mu.Rp, st));
   HIP_TRY(dst::launch_multi_start(v, mu, b, a, r, z, p, S.J, ctl, part2, opts.tol, opts.max_iter, st));
+  if (g32) HIP_TRY(dst::launch_to_f32(p, p32, (int64_t)NV, st));
   HIP_TRY(hipEventRecord(ev[1], st));
   dst::MultiCtl& h = *ctx->mctl_host;
   HIP_TRY(hipMemcpyAsync(&h, ctl, sizeof(dst::MultiCtl), hipMemcpyDeviceToHost, st));
@@ -775,15 +786,21 @@ int solve_group(dst_ctx* ctx, const dst_problem* problems, const std::vector<int
       for (auto& x : e) HIP_TRY(pev.add(&x));
       HIP_TRY(hipEventRecord(e[0], s));
     }
-    HIP_TRY(dst::launch_multi_bin(vc, W, mu, p, S.Minv4, m, ctl, s));
+    if (g32)
+      HIP_TRY(dst::launch_multi_bin(vc, W, mu, p32, S.Minv4, m32, ctl, s));
+    else
+      HIP_TRY(dst::launch_multi_bin(vc, W, mu, p, S.Minv4, m, ctl, s));
     if (timed) HIP_TRY(hipEventRecord(e[1], s));
-    HIP_TRY(dst::launch_multi_unbin(vc, W, mu, dst::UNBIN_CG, m, S.nvalid, p, nullptr, q, ctl, part, s));
+    if (g32)
+      HIP_TRY(dst::launch_multi_unbin(vc, W, mu, dst::UNBIN_CG, m32, S.nvalid, p, nullptr, q, ctl, part, s));
+    else
+      HIP_TRY(dst::launch_multi_unbin(vc, W, mu, dst::UNBIN_CG, m, S.nvalid, p, nullptr, q, ctl, part, s));
     if (ncomp > 1) HIP_TRY(dst::launch_multi_comp(v, mu, cv, q, p, ctl, s));
     HIP_TRY(dst::launch_multi_alpha(vc, mu, ctl, part, cv, s));
     if (timed) HIP_TRY(hipEventRecord(e[2], s));
     HIP_TRY(dst::launch_multi_update(v, mu, a, r, z, q, p, S.J, ctl, part2, s));
     HIP_TRY(dst::launch_multi_beta(v, mu, ctl, part2, s));
-    HIP_TRY(dst::launch_multi_p(v, mu, p, z, ctl, s));
+    HIP_TRY(dst::launch_multi_p(v, mu, p, z, ctl, s, p32));
     if (timed) HIP_TRY(hipEventRecord(e[3], s));
     return DST_OK;
   };

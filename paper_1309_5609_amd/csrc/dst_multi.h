@@ -80,14 +80,21 @@ hipError_t launch_multi_pixsum(int64_t n_obs, const View& vc, const Runs& W, con
                                const double* Minv4, int Rp, int ri0, double* md, hipStream_t st);
 
 // m = M^-1 A^T W F p for every active right-hand side (ctl NULL: all R).
+// The float form reads p and writes m in FP32 (sums in FP64): the
+// mixed-precision iterations of a batch with FP32 angles and timelines.
 hipError_t launch_multi_bin(const View& vc, const Runs& W, const Multi& mu, const double* p, const double* Minv4,
                             double* m, const MultiCtl* ctl, hipStream_t st);
+hipError_t launch_multi_bin(const View& vc, const Runs& W, const Multi& mu, const float* p, const double* Minv4,
+                            float* m, const MultiCtl* ctl, hipStream_t st);
 // Modes of the rescan + baseline sum.
 enum MultiUnbinMode { UNBIN_OPERATOR = 0, UNBIN_CG = 1, UNBIN_RHS = 2 };
 // OPERATOR: q = K p.  CG: q = K p for running right-hand sides plus per-block
 // partials of p.q and of the T-projection sums.  RHS: q = braw - F^T W A m.
 int multi_unbin_blocks(const View& vc);
 hipError_t launch_multi_unbin(const View& vc, const Runs& W, const Multi& mu, int mode, const double* m,
+                              const int32_t* nvalid, const double* p, const double* braw, double* q, MultiCtl* ctl,
+                              double* partials, hipStream_t st);
+hipError_t launch_multi_unbin(const View& vc, const Runs& W, const Multi& mu, int mode, const float* m,
                               const int32_t* nvalid, const double* p, const double* braw, double* q, MultiCtl* ctl,
                               double* partials, hipStream_t st);
 
@@ -106,8 +113,11 @@ int multi_update_blocks(const View& v, const Multi& mu);
 hipError_t launch_multi_update(const View& v, const Multi& mu, double* a, double* r, double* z, const double* q,
                                const double* p, const double* J, MultiCtl* ctl, double* partials, hipStream_t st);
 hipError_t launch_multi_beta(const View& v, const Multi& mu, MultiCtl* ctl, const double* partials, hipStream_t st);
+// p = z + beta p; with p32, its FP32 copy too.
 hipError_t launch_multi_p(const View& v, const Multi& mu, double* p, const double* z, const MultiCtl* ctl,
-                          hipStream_t st);
+                          hipStream_t st, float* p32 = nullptr);
+// y = (float) x, N values.
+hipError_t launch_to_f32(const double* x, float* y, int64_t N, hipStream_t st);
 // a_T -= its mean over T-valid baselines (0 elsewhere), per right-hand side.
 hipError_t launch_multi_canonicalise(const View& v, const Multi& mu, double* a, const double* J, MultiCtl* ctl,
                                      double* partials, hipStream_t st);

@@ -249,27 +249,32 @@ __device__ __forceinline__ bool lane_active(int r, int R, const MultiCtl* ctl) {
 
 // V consecutive realizations' values of one row (V = 1 or 2; 16-byte aligned
 // when V = 2 because Rp is even then).
-template <int V>
-__device__ __forceinline__ void load_v(const double* q, double (&x)[V]) {
-  if constexpr (V == 2) {
+template <int V, typename GT>
+__device__ __forceinline__ void load_v(const GT* q, double (&x)[V]) {
+  if constexpr (V == 2 && sizeof(GT) == 8) {
     const double2 t = *reinterpret_cast<const double2*>(q);
     x[0] = t.x;
     x[1] = t.y;
+  } else if constexpr (V == 2) {
+    const float2 t = *reinterpret_cast<const float2*>(q);
+    x[0] = (double)t.x;
+    x[1] = (double)t.y;
   } else {
-    x[0] = q[0];
+    x[0] = (double)q[0];
   }
 }
 
 // m = M^-1 A^T W F p per compact pixel (one wavefront per pixel), for every
 // active realization.  p is unweighted; the weights are applied here.  Each
 // lane carries V consecutive realizations, so one gather instruction serves
-// 64 V / Rp runs.
-template <typename RT, bool HAS_T, bool HAS_QU, int V>
+// 64 V / Rp runs.  GT: the storage type of p and m (double, or float in the
+// mixed-precision iterations; sums in FP64 either way).
+template <typename RT, bool HAS_T, bool HAS_QU, int V, typename GT>
 __global__ void __launch_bounds__(kBlock) k_multi_bin(View vc, int R, int Rp, const int64_t* __restrict__ pstart,
                                                       const int32_t* __restrict__ pb, const int32_t* __restrict__ pn,
-                                                      const RT* __restrict__ pcs, const double* __restrict__ p,
+                                                      const RT* __restrict__ pcs, const GT* __restrict__ p,
                                                       const double* __restrict__ Minv4,
-                                                      double* __restrict__ m, const MultiCtl* __restrict__ ctl) {
+                                                      GT* __restrict__ m, const MultiCtl* __restrict__ ctl) {
   if (ctl && ctl->running == 0) return;
   const int lane = lane_id();
   const int Rl = Rp / V;  // lanes per slot
@@ -317,7 +322,7 @@ __global__ void __launch_bounds__(kBlock) k_multi_bin(View vc, int R, int Rp, co
         const int nn = __shfl(w_n, src, 64);
         const double C = (double)__shfl(w_c, src, 64), S = (double)__shfl(w_s, src, 64);
         if (!any || kk >= nwin || bb < 0) continue;
-        const double* pr = p + (int64_t)bb * nS * Rp + r0;
+        const GT* pr = p + (int64_t)bb * nS * Rp + r0;
         if (HAS_T) {
           double t[V];
           load_v<V>(pr + oT, t);
@@ -341,14 +346,14 @@ __global__ void __launch_bounds__(kBlock) k_multi_bin(View vc, int R, int Rp, co
     if (slot == 0 && any) {
       const double2* ip = reinterpret_cast<const double2*>(Minv4 + 4 * c);
       const double2 i01 = ip[0], i23 = ip[1];
-      double* mo = m + c * nS * Rp + r0;
+      GT* mo = m + c * nS * Rp + r0;
 #pragma unroll
       for (int v = 0; v < V; ++v) {
         if (!actv[v]) continue;
-        if (HAS_T) mo[oT + v] = i01.x * acc[v];
+        if (HAS_T) mo[oT + v] = (GT)(i01.x * acc[v]);
         if (HAS_QU) {
-          mo[oQ + v] = i01.y * acc[V + v] + i23.x * acc[2 * V + v];
-          mo[oU + v] = i23.x * acc[V + v] + i23.y * acc[2 * V + v];
+          mo[oQ + v] = (GT)(i01.y * acc[V + v] + i23.x * acc[2 * V + v]);
+          mo[oU + v] = (GT)(i23.x * acc[V + v] + i23.y * acc[2 * V + v]);
         }
       }
     }
@@ -363,12 +368,12 @@ __global__ void __launch_bounds__(kBlock) k_multi_bin(View vc, int R, int Rp, co
 //   RHS:            q = braw - w sum_runs A . m         (= F^T Z d with m = m_d)
 // CG also writes per-workgroup partials [block][3][Rp] of p.q and of the
 // T-projection sums (q_T and p_T over T-valid baselines).
-template <typename RT, bool HAS_T, bool HAS_QU, int MODE, int V>
+template <typename RT, bool HAS_T, bool HAS_QU, int MODE, int V, typename GT>
 __global__ void __launch_bounds__(kBlock) k_multi_unbin(View vc, int R, int Rp, const uint32_t* __restrict__ bstart,
                                                         const uint32_t* __restrict__ border,
                                                         const int32_t* __restrict__ tpix,
                                                         const int32_t* __restrict__ tn, const RT* __restrict__ tcs,
-                                                        const double* __restrict__ m,
+                                                        const GT* __restrict__ m,
                                                         const int32_t* __restrict__ nvalid,
                                                         const double* __restrict__ p, const double* __restrict__ braw,
                                                         double* __restrict__ q, MultiCtl* __restrict__ ctl,
@@ -422,7 +427,7 @@ __global__ void __launch_bounds__(kBlock) k_multi_unbin(View vc, int R, int Rp, 
         const int nn = __shfl(w_n, src, 64);
         const double C = (double)__shfl(w_C, src, 64), S = (double)__shfl(w_S, src, 64);
         if (!any || kk >= nwin || cc < 0) continue;
-        const double* mr = m + (int64_t)cc * nS * Rp + r0;
+        const GT* mr = m + (int64_t)cc * nS * Rp + r0;
         if (HAS_T) {
           double t[V];
           load_v<V>(mr + oT, t);
@@ -764,14 +769,24 @@ __global__ void __launch_bounds__(kBlock) k_multi_beta(int n_part, int Rp, Multi
   }
 }
 
+// p = z + beta p; with p32, its FP32 copy too (the mixed-precision gathers).
 __global__ void __launch_bounds__(kBlock) k_multi_p(int64_t N, int Rp, double* __restrict__ p,
-                                                    const double* __restrict__ z, const MultiCtl* __restrict__ ctl) {
+                                                    const double* __restrict__ z, const MultiCtl* __restrict__ ctl,
+                                                    float* __restrict__ p32) {
   if (ctl->running == 0) return;
   const int ri = threadIdx.x & (Rp - 1);
   if (ctl->done[ri] != DONE_RUNNING) return;
   const double beta = ctl->beta[ri];
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (int64_t)gridDim.x * blockDim.x) {
+    const double x = z[i] + beta * p[i];
+    p[i] = x;
+    if (p32) p32[i] = (float)x;
+  }
+}
+
+__global__ void __launch_bounds__(kBlock) k_to_f32(int64_t N, const double* __restrict__ x, float* __restrict__ y) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (int64_t)gridDim.x * blockDim.x)
-    p[i] = z[i] + beta * p[i];
+    y[i] = (float)x[i];
 }
 
 __global__ void __launch_bounds__(kBlock) k_multi_canon_apply(View v, int Rp, double* __restrict__ a,
@@ -943,8 +958,9 @@ hipError_t launch_multi_pixsum(int64_t n_obs, const View& vc, const Runs& W, con
   return hipGetLastError();
 }
 
-hipError_t launch_multi_bin(const View& vc, const Runs& W, const Multi& mu, const double* p, const double* Minv4,
-                            double* m, const MultiCtl* ctl, hipStream_t st) {
+template <typename GT>
+hipError_t multi_bin_impl(const View& vc, const Runs& W, const Multi& mu, const GT* p, const double* Minv4, GT* m,
+                          const MultiCtl* ctl, hipStream_t st) {
   const int64_t per = (vc.n_pix + 7) / 8;
   const unsigned g = (unsigned)(8 * std::max<int64_t>(1, std::min<int64_t>((per + kWaves - 1) / kWaves, 2048)));
   by_float(W.f32, [&](auto rt) {
@@ -955,12 +971,22 @@ hipError_t launch_multi_bin(const View& vc, const Runs& W, const Multi& mu, cons
                            static_cast<const RT*>(W.pcs), p, Minv4, m, ctl);
       };
       if (mu.Rp >= 2)
-        launch(k_multi_bin<RT, decltype(T)::value, decltype(Q)::value, 2>);
+        launch(k_multi_bin<RT, decltype(T)::value, decltype(Q)::value, 2, GT>);
       else
-        launch(k_multi_bin<RT, decltype(T)::value, decltype(Q)::value, 1>);
+        launch(k_multi_bin<RT, decltype(T)::value, decltype(Q)::value, 1, GT>);
     });
   });
   return hipGetLastError();
+}
+
+hipError_t launch_multi_bin(const View& vc, const Runs& W, const Multi& mu, const double* p, const double* Minv4,
+                            double* m, const MultiCtl* ctl, hipStream_t st) {
+  return multi_bin_impl<double>(vc, W, mu, p, Minv4, m, ctl, st);
+}
+
+hipError_t launch_multi_bin(const View& vc, const Runs& W, const Multi& mu, const float* p, const double* Minv4,
+                            float* m, const MultiCtl* ctl, hipStream_t st) {
+  return multi_bin_impl<float>(vc, W, mu, p, Minv4, m, ctl, st);
 }
 
 int multi_unbin_blocks(const View& vc) {
@@ -969,9 +995,10 @@ int multi_unbin_blocks(const View& vc) {
   return (int)(8 * g);
 }
 
-hipError_t launch_multi_unbin(const View& vc, const Runs& W, const Multi& mu, int mode, const double* m,
-                              const int32_t* nvalid, const double* p, const double* braw, double* q, MultiCtl* ctl,
-                              double* partials, hipStream_t st) {
+template <typename GT>
+hipError_t multi_unbin_impl(const View& vc, const Runs& W, const Multi& mu, int mode, const GT* m,
+                            const int32_t* nvalid, const double* p, const double* braw, double* q, MultiCtl* ctl,
+                            double* partials, hipStream_t st) {
   const unsigned g = (unsigned)multi_unbin_blocks(vc);
   by_float(W.f32, [&](auto rt) {
     using RT = typename decltype(rt)::type;
@@ -984,11 +1011,11 @@ hipError_t launch_multi_unbin(const View& vc, const Runs& W, const Multi& mu, in
       auto by_mode = [&](auto VV) {
         constexpr int V = decltype(VV)::value;
         if (mode == UNBIN_CG)
-          launch(k_multi_unbin<RT, HT, HQ, UNBIN_CG, V>);
+          launch(k_multi_unbin<RT, HT, HQ, UNBIN_CG, V, GT>);
         else if (mode == UNBIN_RHS)
-          launch(k_multi_unbin<RT, HT, HQ, UNBIN_RHS, V>);
+          launch(k_multi_unbin<RT, HT, HQ, UNBIN_RHS, V, GT>);
         else
-          launch(k_multi_unbin<RT, HT, HQ, UNBIN_OPERATOR, V>);
+          launch(k_multi_unbin<RT, HT, HQ, UNBIN_OPERATOR, V, GT>);
       };
       if (mu.Rp >= 2)
         by_mode(std::integral_constant<int, 2>{});
@@ -997,6 +1024,18 @@ hipError_t launch_multi_unbin(const View& vc, const Runs& W, const Multi& mu, in
     });
   });
   return hipGetLastError();
+}
+
+hipError_t launch_multi_unbin(const View& vc, const Runs& W, const Multi& mu, int mode, const double* m,
+                              const int32_t* nvalid, const double* p, const double* braw, double* q, MultiCtl* ctl,
+                              double* partials, hipStream_t st) {
+  return multi_unbin_impl<double>(vc, W, mu, mode, m, nvalid, p, braw, q, ctl, partials, st);
+}
+
+hipError_t launch_multi_unbin(const View& vc, const Runs& W, const Multi& mu, int mode, const float* m,
+                              const int32_t* nvalid, const double* p, const double* braw, double* q, MultiCtl* ctl,
+                              double* partials, hipStream_t st) {
+  return multi_unbin_impl<float>(vc, W, mu, mode, m, nvalid, p, braw, q, ctl, partials, st);
 }
 
 int multi_update_blocks(const View& v, const Multi& mu) {
@@ -1043,9 +1082,14 @@ hipError_t launch_multi_beta(const View& v, const Multi& mu, MultiCtl* ctl, cons
 }
 
 hipError_t launch_multi_p(const View& v, const Multi& mu, double* p, const double* z, const MultiCtl* ctl,
-                          hipStream_t st) {
+                          hipStream_t st, float* p32) {
   const int64_t N = (int64_t)v.n_b * v.n_streams * mu.Rp;
-  hipLaunchKernelGGL(k_multi_p, dim3(grid_for(N, kBlock, 2048)), dim3(kBlock), 0, st, N, mu.Rp, p, z, ctl);
+  hipLaunchKernelGGL(k_multi_p, dim3(grid_for(N, kBlock, 2048)), dim3(kBlock), 0, st, N, mu.Rp, p, z, ctl, p32);
+  return hipGetLastError();
+}
+
+hipError_t launch_to_f32(const double* x, float* y, int64_t N, hipStream_t st) {
+  hipLaunchKernelGGL(k_to_f32, dim3(grid_for(N, kBlock, 2048)), dim3(kBlock), 0, st, N, x, y);
   return hipGetLastError();
 }
 
