@@ -270,6 +270,37 @@ def cpu_parallel(p, iters_gpu: dict, uneven: dict | None) -> dict:
     return res
 
 
+def noise_form(ctx, n: int, segment: int = 1 << 24, reps: int = 3) -> dict:
+    """dst_noise_generate on the workload's three FP64 timelines (white 1 mK + 1/f, f_k 50 mHz, alpha 1.7)."""
+    import torch
+
+    from paper_1309_5609_amd import dst
+    out = torch.empty((3, n), dtype=torch.float64, device="cuda")
+    for k in range(3):
+        dst.dst_noise_generate(ctx, 1, k, n, segment, 50.0, SIGMA, 0.05, 1.7, out=out[k])
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for r in range(reps):
+        for k in range(3):
+            dst.dst_noise_generate(ctx, 2 + r, k, n, segment, 50.0, SIGMA, 0.05, 1.7, out=out[k])
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t) / reps
+    m = segment.bit_length() - 1
+    passes = -(-m // 8)
+    # per complex value (two samples): white write 16 B; each FFT pass reads and
+    # writes 16 B, forward and inverse; the unpack reads 16 B and writes 2 x 8 B
+    per_sample = (16 + 2 * passes * 32 + 16 + 16) / 2
+    gbs = 3 * n * per_sample / dt / 1e9
+    del out
+    torch.cuda.empty_cache()
+    return {"value": 3 * n / dt, "unit": "samples/s", "ms": dt * 1e3, "n_samples": 3 * n, "segment": segment,
+            "fft_passes_per_transform": passes, "model_bytes_per_sample": per_sample, "achieved_GBs": gbs,
+            "frac": gbs / HBM_PEAK_GBS,
+            "method": "Philox4x64-10 + Box-Muller white noise, filtered per segment pair by one complex FFT: "
+                      f"{passes} Stockham passes of radix <= 256 each way, computed in LDS; gain applied as the "
+                      "inverse transform reads the spectrum"}
+
+
 def batched_form(ctx, p, dp, n_real: int, tol: float, steps: int, warmup: int, plain_value: float) -> dict:
     """Monte Carlo batch: n_real realizations sharing dp's pointing, FP32 timelines, one batched solve."""
     import numpy as np
@@ -323,8 +354,10 @@ def batched_form(ctx, p, dp, n_real: int, tol: float, steps: int, warmup: int, p
            "model_bytes_per_iteration": b_iter, "iteration_hbm_frac": b_iter / (it_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
            "vs_plain_fp64": value / plain_value,
            "map_rms_error_ratio_vs_fp64": ratio,
+           "true_rel_residual_max": max(float(r["true_rel_residual"]) for r in res),
            "equal_accuracy_reference": "realization 0's unrounded FP64 timelines solved by the plain FP64 path",
-           "dtype": "f32 timelines and angles, f64 accumulation / inverse / CG",
+           "dtype": "f32 timelines and angles; f32 copies of p and m for the iterations' gathers; f64 sums, "
+                    "inverse, CG and outputs",
            "inputs": ("sky signal of the 30-day workload scanned by dst_unbin + per-realization white 1 mK and 1/f "
                       "noise (f_k 50 mHz, alpha 1.7) drawn by dst_noise_generate (Eq. 1, seeds 1309_5609_000 + r)")}
     del probs, tods, tod0, res, prof, ref, sky_d
@@ -607,6 +640,9 @@ def main() -> int:
                                        torch.linalg.norm(cg["baselines"]))}
         del gm, cg
         log(f"GMRES {line['gmres_vs_pcg']['gmres']['iterations']} / PCG {line['gmres_vs_pcg']['pcg']['iterations']}")
+
+        # the Monte Carlo noise generator (Eq. 1) on the workload's three timelines
+        line["noise_form"] = noise_form(ctx, p.n_samples)
 
         # the per-sample form of the same solve, for comparison with the per-sample byte model
         ps = dst.dst_solve(ctx, dp, tol=args.tol, max_iter=3000, maps=False,

@@ -603,8 +603,9 @@ int plan_operator(dst_ctx* ctx, Plan& P, const double* vin, double* out, hipStre
 
 // Captures `reps` calls of body(stream) on the context's private stream and
 // instantiates the graph.  The iteration kernels read their scalars from
-// device memory and return at once after the stop, so one graph of one
-// iteration serves every iteration of the solve.
+// device memory and return at once after the stop (convergence or the
+// iteration limit, both decided on the device), so one graph of check_every
+// iterations, replayed between the host's checks, serves the whole solve.
 template <typename F>
 int capture_graph(dst_ctx* ctx, int reps, F&& body, hipGraphExec_t* exec) {
   *exec = nullptr;
@@ -804,19 +805,18 @@ int solve_group(dst_ctx* ctx, const dst_problem* problems, const std::vector<int
     if (timed) HIP_TRY(hipEventRecord(e[3], s));
     return DST_OK;
   };
-  // one iteration captured once, replayed check_every times per check
+  // check_every iterations captured once, replayed once per check
   GraphGuard gg;
   if (use_graph && h.running > 0)
-    DST_TRY(capture_graph(ctx, 1, [&](hipStream_t s) { return iteration(s, false); }, &gg.exec));
+    DST_TRY(capture_graph(ctx, check_every, [&](hipStream_t s) { return iteration(s, false); }, &gg.exec));
   HIP_TRY(hipEventRecord(ev[2], st));
   int launched = 0;
   while (h.running > 0 && launched < opts.max_iter) {
     const int k = std::min(check_every, opts.max_iter - launched);
-    for (int i = 0; i < k; ++i) {
-      if (gg.exec)
-        HIP_TRY(hipGraphLaunch(gg.exec, st));
-      else
-        DST_TRY(iteration(st, profile));
+    if (gg.exec) {
+      HIP_TRY(hipGraphLaunch(gg.exec, st));  // check_every iterations (those past the stop return at once)
+    } else {
+      for (int i = 0; i < k; ++i) DST_TRY(iteration(st, profile));
     }
     launched += k;
     HIP_TRY(hipMemcpyAsync(&h, ctl, sizeof(dst::MultiCtl), hipMemcpyDeviceToHost, st));
@@ -1103,16 +1103,15 @@ int solve_uneven(dst_ctx* ctx, const dst_problem* problems, const std::vector<in
   };
   GraphGuard gg;
   if (use_graph && running())
-    DST_TRY(capture_graph(ctx, 1, [&](hipStream_t s) { return iteration(s, false); }, &gg.exec));
+    DST_TRY(capture_graph(ctx, check_every, [&](hipStream_t s) { return iteration(s, false); }, &gg.exec));
   HIP_TRY(hipEventRecord(ev[2], st));
   int launched = 0;
   while (running() && launched < opts.max_iter) {
     const int k = std::min(check_every, opts.max_iter - launched);
-    for (int i = 0; i < k; ++i) {
-      if (gg.exec)
-        HIP_TRY(hipGraphLaunch(gg.exec, st));
-      else
-        DST_TRY(iteration(st, profile));
+    if (gg.exec) {
+      HIP_TRY(hipGraphLaunch(gg.exec, st));  // check_every iterations (those past the stop return at once)
+    } else {
+      for (int i = 0; i < k; ++i) DST_TRY(iteration(st, profile));
     }
     launched += k;
     HIP_TRY(hipMemcpyAsync(h, ctls, n * sizeof(CgCtl), hipMemcpyDeviceToHost, st));
@@ -1613,11 +1612,11 @@ int dst_solve(dst_ctx* ctx, const dst_problem* prob, const dst_solve_opts* opts_
     return DST_OK;
   };
 
-  // One iteration is captured once and replayed, unless profiling or asked
-  // not to; captured here, while the setup still runs on the GPU.
+  // check_every iterations are captured once and replayed, unless profiling
+  // or asked not to; captured here, while the setup still runs on the GPU.
   GraphGuard gg;
   if (!use_gmres && !(opts.flags & (DST_SOLVE_NO_GRAPH | DST_SOLVE_PROFILE)))
-    DST_TRY(capture_graph(ctx, 1, [&](hipStream_t s) { return one_iteration(s, false); }, &gg.exec));
+    DST_TRY(capture_graph(ctx, check_every, [&](hipStream_t s) { return one_iteration(s, false); }, &gg.exec));
   HIP_TRY(hipEventRecord(ev[1], st));
   HIP_TRY(hipMemcpyAsync(ctx->ctl_host, ctl, sizeof(CgCtl), hipMemcpyDeviceToHost, st));
   HIP_TRY(hipMemcpyAsync(ctx->rb_host->counts, S.counts, 4 * sizeof(unsigned long long), hipMemcpyDeviceToHost,
@@ -1658,11 +1657,10 @@ int dst_solve(dst_ctx* ctx, const dst_problem* prob, const dst_solve_opts* opts_
   int launched = 0;
   while (h.done == dst::DONE_RUNNING && launched < opts.max_iter) {
     const int k = std::min(check_every, opts.max_iter - launched);
-    for (int i = 0; i < k; ++i) {
-      if (gg.exec)
-        HIP_TRY(hipGraphLaunch(gg.exec, st));
-      else
-        DST_TRY(one_iteration(st, profile));
+    if (gg.exec) {
+      HIP_TRY(hipGraphLaunch(gg.exec, st));  // check_every iterations (those past the stop return at once)
+    } else {
+      for (int i = 0; i < k; ++i) DST_TRY(one_iteration(st, profile));
     }
     launched += k;
     HIP_TRY(hipMemcpyAsync(ctx->ctl_host, ctl, sizeof(CgCtl), hipMemcpyDeviceToHost, st));
