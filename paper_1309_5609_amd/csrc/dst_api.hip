@@ -568,7 +568,10 @@ int build_plan(dst_ctx* ctx, const dst_problem* prob, Plan& P, const void* tod, 
   P.bpw = ctx->unbin_bpw;
   if (!P.runs) return build_sample_plan(ctx, prob, P, tod, sd4, md4, b, st);
   DST_TRY(build_runs_plan(ctx, prob, P, tod, sd4, md4, b, st));
-  if (P.lpp == 0) P.lpp = dst::bin_lanes_for(P.W.R, P.W.n_obs);
+  if (P.lpp == 0) {
+    const View& v = P.S.v;
+    P.lpp = dst::bin_lanes_for(P.W.R, P.W.n_obs, v.rowT >= 0 && v.rowQ < 0 && !v.iqu);
+  }
   return DST_OK;
 }
 
@@ -889,6 +892,13 @@ int solve_group(dst_ctx* ctx, const dst_problem* problems, const std::vector<int
   return DST_OK;
 }
 
+// Baselines per wavefront of a group's rescan for problems of one kind.
+int group_bpw(const dst_ctx* ctx, int kind) {
+  (void)kind;
+  const int b = ctx->unbin_bpw;
+  return (b == 1 || b == 2 || b == 8) ? b : 4;
+}
+
 // Independent problems with different pointing (the channels of a survey)
 // solved together: each problem gets its own run setup, right-hand side and
 // PCG state (workspace slots under its own prefix; the setup-only arrays are
@@ -955,7 +965,7 @@ int solve_uneven(dst_ctx* ctx, const dst_problem* problems, const std::vector<in
     DST_TRY(ws(ctx, "cg_q", N, &m.q));
     DST_TRY(ws(ctx, "cg_ka", N, &m.ka));
     const View& vc = m.P.S.v;
-    DST_TRY(ws(ctx, "cg_part", 3 * (size_t)std::max<int64_t>({(int64_t)dst::group_unbin_blocks(vc), v.n_b, 4096}),
+    DST_TRY(ws(ctx, "cg_part", 3 * (size_t)std::max<int64_t>({(int64_t)dst::group_unbin_blocks(vc, 1), v.n_b, 4096}),
                &m.part));
     DST_TRY(ws(ctx, "cg_part2", 2 * (size_t)dst::group_vec_blocks(v), &m.part2));
     DST_TRY(ws(ctx, "cg_rnorm", 1, &m.rnorm));
@@ -1001,7 +1011,7 @@ int solve_uneven(dst_ctx* ctx, const dst_problem* problems, const std::vector<in
     g.kind = kind_of(S.v);
     g.nb = W.nb;
     g.dense_t = m.P.dense_t;
-    g.unbin_n = dst::group_unbin_blocks(S.v);
+    g.unbin_n = dst::group_unbin_blocks(S.v, group_bpw(ctx, g.kind));
     g.vec_n = dst::group_vec_blocks(S.v);
     g.pstart = W.pstart;
     g.pkey = W.pkey;
@@ -1043,7 +1053,9 @@ int solve_uneven(dst_ctx* ctx, const dst_problem* problems, const std::vector<in
       runs += n_runs[sl.first + j];
       obs += gp[sl.first + j].v.n_pix;
     }
-    sl.lpp = dst::bin_lanes_for(runs, obs);
+    sl.lpp = dst::bin_lanes_for(runs, obs, K == dst::GK_T);
+    sl.bpw = group_bpw(ctx, K);
+    if (ctx->bin_lpp == 4 || ctx->bin_lpp == 8 || ctx->bin_lpp == 16 || ctx->bin_lpp == 32) sl.lpp = ctx->bin_lpp;
     roff[K] = ranges.size();
     ranges.resize(ranges.size() + 2 * (sl.count + 1), 0u);
     uint32_t* bs = ranges.data() + roff[K];

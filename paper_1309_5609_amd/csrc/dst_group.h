@@ -58,6 +58,7 @@ struct GroupSlice {
   const uint32_t* unbin_start = nullptr;  // device [count + 1]
   uint32_t bin_total = 0, unbin_total = 0;
   int lpp = 32;  // lanes per pixel of the binning (4, 8, 16 or 32)
+  int bpw = 4;   // baselines per wavefront of the rescan (1, 2, 4 or 8)
 };
 struct GroupLaunch {
   const GroupProblem* prob = nullptr;  // device [n]
@@ -70,7 +71,7 @@ struct GroupLaunch {
 
 // Workgroups each phase gives one problem.
 uint32_t group_bin_blocks(int64_t n_obs, int lpp);
-uint32_t group_unbin_blocks(const View& vc);  // a multiple of 8
+uint32_t group_unbin_blocks(const View& vc, int bpw);  // a multiple of 8
 uint32_t group_vec_blocks(const View& v);
 
 // One PCG iteration of every running problem: binning (m = M^-1 A^T W F p),

@@ -120,8 +120,9 @@ hipError_t runs_build(const View& v, int psi_f32, const void* tod, int tod_f32, 
 // Per baseline: n_valid, Jacobi diagonal, and with tod b = F^T W (d - A m_d).
 hipError_t launch_rhs_runs(const View& vc, const Runs& W, const void* tod, const double* md4, const uint8_t* valid,
                            int32_t* nvalid, double* J, double* b, hipStream_t st);
-// Lanes per pixel of the binning for `runs` runs over n_obs pixels.
-int bin_lanes_for(int64_t runs, int64_t n_obs);
+// Lanes per pixel of the binning for `runs` runs over n_obs pixels
+// (t_only: an intensity-only problem).
+int bin_lanes_for(int64_t runs, int64_t n_obs, bool t_only);
 // m = M^-1 A^T W F p (pw4 = interleaved w .* p).
 // lpp: lanes per pixel (64, 32, 16, 8 or 4; -64: 64 with the pixel pipeline; 0: 32).
 hipError_t launch_bin_runs(const View& vc, const Runs& W, const double* pw4, const double* Minv4,

@@ -1527,13 +1527,15 @@ hipError_t launch_rhs_runs(const View& vc, const Runs& W, const void* tod, const
   return hipGetLastError();
 }
 
-int bin_lanes_for(int64_t runs, int64_t n_obs) {
+int bin_lanes_for(int64_t runs, int64_t n_obs, bool t_only) {
   // sparse pixels (few runs each) take fewer lanes, so that most lanes are
   // not idle: lanes per pixel times runs per lane and step (8 for LPP <= 16)
-  // near the mean runs per pixel; dense ones 32 lanes
+  // near the mean runs per pixel; dense ones 32 lanes.  Intensity-only runs
+  // (one 4-byte key each) do best with 8 pixels per wavefront even when
+  // dense (measured: 365 days at N_side 512, 285 runs per pixel).
   const double mean = n_obs > 0 ? (double)runs / (double)n_obs : 0.0;
   if (mean <= 32.0) return 4;
-  if (mean <= 64.0) return 8;
+  if (mean <= 64.0 || t_only) return 8;
   return 32;
 }
 
@@ -1647,7 +1649,7 @@ __global__ void __launch_bounds__(kBlock) k_group_bin(GroupLaunch G) {
                                            P.pw4, P.Minv4, P.valid, P.m4, vb, vg);
 }
 
-template <typename RT, int KIND>
+template <typename RT, int KIND, int BPW>
 __global__ void __launch_bounds__(kBlock) k_group_unbin(GroupLaunch G) {
   constexpr bool HT = KIND != GK_QU, HQ = KIND == GK_QU || KIND == GK_TQU, HI = KIND == GK_IQU;
   const GroupSlice& S = G.kind[KIND];
@@ -1656,9 +1658,9 @@ __global__ void __launch_bounds__(kBlock) k_group_unbin(GroupLaunch G) {
   const GroupProblem& P = G.prob[S.first + j];
   if (P.ctl->done) return;
   const int64_t vb = b - S.unbin_start[j], vg = S.unbin_start[j + 1] - S.unbin_start[j];
-  unbin_runs_body<RT, HT, HQ, HI, true, 4, true>(P.v, P.bstart, P.border, P.tkey, nullptr, P.nb,
-                                                 static_cast<const RT*>(P.tcs), P.m4, P.nvalid, P.p, P.q,
-                                                 P.part_unbin, vb, vg);
+  unbin_runs_body<RT, HT, HQ, HI, true, BPW, true>(P.v, P.bstart, P.border, P.tkey, nullptr, P.nb,
+                                                   static_cast<const RT*>(P.tcs), P.m4, P.nvalid, P.p, P.q,
+                                                   P.part_unbin, vb, vg);
 }
 
 // One workgroup per problem.
@@ -1701,7 +1703,7 @@ uint32_t group_bin_blocks(int64_t n_obs, int lpp) {
   return (uint32_t)std::max<int64_t>(1, std::min<int64_t>((n_obs + ppb - 1) / ppb, 16384));
 }
 
-uint32_t group_unbin_blocks(const View& vc) { return (uint32_t)unbin_runs_parts(vc, 4); }
+uint32_t group_unbin_blocks(const View& vc, int bpw) { return (uint32_t)unbin_runs_parts(vc, bpw); }
 
 uint32_t group_vec_blocks(const View& v) {
   const int64_t n = (int64_t)v.n_streams * v.n_b;
@@ -1717,7 +1719,12 @@ hipError_t launch_group_phase(const GroupLaunch& G, int phase, hipStream_t st) {
       const GroupSlice& S = G.kind[K];
       if (S.count == 0) return;
       if (phase == 1) {
-        hipLaunchKernelGGL((k_group_unbin<RT, K>), dim3(S.unbin_total), dim3(kBlock), 0, st, G);
+        switch (S.bpw) {
+          case 1: hipLaunchKernelGGL((k_group_unbin<RT, K, 1>), dim3(S.unbin_total), dim3(kBlock), 0, st, G); break;
+          case 2: hipLaunchKernelGGL((k_group_unbin<RT, K, 2>), dim3(S.unbin_total), dim3(kBlock), 0, st, G); break;
+          case 8: hipLaunchKernelGGL((k_group_unbin<RT, K, 8>), dim3(S.unbin_total), dim3(kBlock), 0, st, G); break;
+          default: hipLaunchKernelGGL((k_group_unbin<RT, K, 4>), dim3(S.unbin_total), dim3(kBlock), 0, st, G); break;
+        }
         return;
       }
       switch (S.lpp) {
