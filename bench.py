@@ -454,6 +454,8 @@ def main() -> int:
     ap.add_argument("--realizations", type=int, default=32, help="batch size of the Monte Carlo form (0: skip)")
     ap.add_argument("--no-uneven", action="store_true", help="skip the uneven survey batch (N_side 512)")
     ap.add_argument("--no-extra", action="store_true", help="only the headline solve and its roofline")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="copy 1 GiB device to device once (the reference kernel that scales HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): the destriping path of this library is "
@@ -480,6 +482,14 @@ def main() -> int:
     ctx = dst.Context(0)
     ceil = ceilings()
     log(f"ceilings: copy {ceil['copy_GBs']:.0f} GB/s, read {ceil['read_GBs']:.0f} GB/s")
+    if args.copy_calibration:
+        src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+        dst_t = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst_t.copy_(src)
+        torch.cuda.synchronize()
+        log("copy calibration: 1 GiB device to device")
+        del src, dst_t
 
     # timed: K solves as a caller runs them (CG iterations replayed from a captured graph)
     for i in range(args.warmup):
