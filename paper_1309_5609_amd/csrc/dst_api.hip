@@ -60,6 +60,9 @@ struct dst_ctx {
   dst::GmStatus* gm_host = nullptr;
   dst::GmStatus* gm_dev = nullptr;
   hipEvent_t gm_ev[2] = {nullptr, nullptr};
+  // instantiated iteration graphs kept between solves (single solve,
+  // shared-pointing batch, problem group), updated in place by each capture
+  hipGraphExec_t graphs[3] = {nullptr, nullptr, nullptr};
   hipStream_t cap = nullptr;  // private stream on which iteration graphs are captured
   int unbin_bpw = 4;          // launch shape of the run rescan (baselines per wavefront)
   int bin_lpp = 0;            // launch shape of the run binning (lanes per pixel; 0: default 32)
@@ -604,13 +607,18 @@ int plan_operator(dst_ctx* ctx, Plan& P, const double* vin, double* out, hipStre
   return DST_OK;
 }
 
-// Captures `reps` calls of body(stream) on the context's private stream and
-// instantiates the graph.  The iteration kernels read their scalars from
-// device memory and return at once after the stop (convergence or the
-// iteration limit, both decided on the device), so one graph of check_every
-// iterations, replayed between the host's checks, serves the whole solve.
+// The iteration kernels read their scalars from device memory and return at
+// once after the stop (convergence or the iteration limit, both decided on
+// the device), so one graph of check_every iterations, replayed between the
+// host's checks, serves the whole solve.
+// Captures `reps` calls of body(stream) on the context's private stream into
+// the graph kept in ctx->graphs[slot]: the new capture
+// updates the kept executable graph in place when its topology is unchanged
+// (same kernels in the same order: only arguments and grids differ), which
+// costs far less than instantiating it again; otherwise the new graph is
+// instantiated and kept.  *exec stays owned by the context.
 template <typename F>
-int capture_graph(dst_ctx* ctx, int reps, F&& body, hipGraphExec_t* exec) {
+int capture_graph_kept(dst_ctx* ctx, int slot, int reps, F&& body, hipGraphExec_t* exec) {
   *exec = nullptr;
   if (!ctx->cap) HIP_TRY(hipStreamCreateWithFlags(&ctx->cap, hipStreamNonBlocking));
   HIP_TRY(hipStreamBeginCapture(ctx->cap, hipStreamCaptureModeThreadLocal));
@@ -623,21 +631,28 @@ int capture_graph(dst_ctx* ctx, int reps, F&& body, hipGraphExec_t* exec) {
     return rc;
   }
   if (e != hipSuccess) return fail(ctx, DST_EHIP, "graph capture: %s", hipGetErrorString(e));
-  const hipError_t e2 = hipGraphInstantiate(exec, g, nullptr, nullptr, 0);
+  hipGraphExec_t& kept = ctx->graphs[slot];
+  if (kept) {
+    hipGraphNode_t err_node = nullptr;
+    hipGraphExecUpdateResult res = hipGraphExecUpdateError;
+    if (hipGraphExecUpdate(kept, g, &err_node, &res) == hipSuccess && res == hipGraphExecUpdateSuccess) {
+      (void)hipGraphDestroy(g);
+      *exec = kept;
+      return DST_OK;
+    }
+    (void)hipGetLastError();
+    (void)hipGraphExecDestroy(kept);
+    kept = nullptr;
+  }
+  const hipError_t e2 = hipGraphInstantiate(&kept, g, nullptr, nullptr, 0);
   (void)hipGraphDestroy(g);
   if (e2 != hipSuccess) {
-    *exec = nullptr;
+    kept = nullptr;
     return fail(ctx, DST_EHIP, "graph instantiation: %s", hipGetErrorString(e2));
   }
+  *exec = kept;
   return DST_OK;
 }
-
-struct GraphGuard {
-  hipGraphExec_t exec = nullptr;
-  ~GraphGuard() {
-    if (exec) (void)hipGraphExecDestroy(exec);
-  }
-};
 
 struct EventSet {
   std::vector<hipEvent_t> ev;
@@ -809,9 +824,11 @@ int solve_group(dst_ctx* ctx, const dst_problem* problems, const std::vector<int
     return DST_OK;
   };
   // check_every iterations captured once, replayed once per check
-  GraphGuard gg;
+  struct {
+    hipGraphExec_t exec = nullptr;  // kept by the context
+  } gg;
   if (use_graph && h.running > 0)
-    DST_TRY(capture_graph(ctx, check_every, [&](hipStream_t s) { return iteration(s, false); }, &gg.exec));
+    DST_TRY(capture_graph_kept(ctx, 1, check_every, [&](hipStream_t s) { return iteration(s, false); }, &gg.exec));
   HIP_TRY(hipEventRecord(ev[2], st));
   int launched = 0;
   while (h.running > 0 && launched < opts.max_iter) {
@@ -1113,9 +1130,11 @@ int solve_uneven(dst_ctx* ctx, const dst_problem* problems, const std::vector<in
     }
     return DST_OK;
   };
-  GraphGuard gg;
+  struct {
+    hipGraphExec_t exec = nullptr;  // kept by the context
+  } gg;
   if (use_graph && running())
-    DST_TRY(capture_graph(ctx, check_every, [&](hipStream_t s) { return iteration(s, false); }, &gg.exec));
+    DST_TRY(capture_graph_kept(ctx, 2, check_every, [&](hipStream_t s) { return iteration(s, false); }, &gg.exec));
   HIP_TRY(hipEventRecord(ev[2], st));
   int launched = 0;
   while (running() && launched < opts.max_iter) {
@@ -1405,6 +1424,8 @@ int dst_destroy(dst_ctx* ctx) {
   if (ctx->gm_host) (void)hipHostFree(ctx->gm_host);
   for (auto e : ctx->gm_ev)
     if (e) (void)hipEventDestroy(e);
+  for (auto g : ctx->graphs)
+    if (g) (void)hipGraphExecDestroy(g);
   if (ctx->cap) (void)hipStreamDestroy(ctx->cap);
   delete ctx;
   return DST_OK;
@@ -1626,9 +1647,12 @@ int dst_solve(dst_ctx* ctx, const dst_problem* prob, const dst_solve_opts* opts_
 
   // check_every iterations are captured once and replayed, unless profiling
   // or asked not to; captured here, while the setup still runs on the GPU.
-  GraphGuard gg;
+  struct {
+    hipGraphExec_t exec = nullptr;  // kept by the context
+  } gg;
   if (!use_gmres && !(opts.flags & (DST_SOLVE_NO_GRAPH | DST_SOLVE_PROFILE)))
-    DST_TRY(capture_graph(ctx, check_every, [&](hipStream_t s) { return one_iteration(s, false); }, &gg.exec));
+    DST_TRY(capture_graph_kept(ctx, 0, check_every,
+                               [&](hipStream_t s) { return one_iteration(s, false); }, &gg.exec));
   HIP_TRY(hipEventRecord(ev[1], st));
   HIP_TRY(hipMemcpyAsync(ctx->ctl_host, ctl, sizeof(CgCtl), hipMemcpyDeviceToHost, st));
   HIP_TRY(hipMemcpyAsync(ctx->rb_host->counts, S.counts, 4 * sizeof(unsigned long long), hipMemcpyDeviceToHost,
