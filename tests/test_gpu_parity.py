@@ -282,7 +282,7 @@ def test_bin_launch_shapes_agree(name):
     from paper_1309_5609_amd import dst
     p = make(name)
     out = {}
-    for lpp in ("32", "64", "16", "-64"):
+    for lpp in ("32", "64", "16", "8", "4", "-64"):
         os.environ["DST_BIN_LPP"] = lpp
         try:
             c = dst.Context(0)
@@ -290,7 +290,7 @@ def test_bin_launch_shapes_agree(name):
             del os.environ["DST_BIN_LPP"]
         out[lpp] = dst.dst_solve(c, dev(p), tol=1e-13, max_iter=3000)
         c.close()
-    for lpp in ("64", "16", "-64"):
+    for lpp in ("64", "16", "8", "4", "-64"):
         assert abs(out[lpp]["iterations"] - out["32"]["iterations"]) <= 1
         assert rel(out[lpp]["baselines"].cpu().numpy(), out["32"]["baselines"].cpu().numpy()) < 1e-10
 

@@ -133,3 +133,28 @@ def test_uneven_with_split_graph_member(ctx):
     assert res[0]["n_components"] == 3 and res[1]["n_components"] == 1 and res[2]["n_components"] == 3
     for p, out in zip(ps, res):
         check(p, out)
+
+
+@pytest.mark.parametrize("env", [("DST_BIN_LPP", "4"), ("DST_BIN_LPP", "8"), ("DST_BIN_LPP", "16"),
+                                 ("DST_BIN_LPP", "32"), ("DST_UNBIN_BPW", "1"), ("DST_UNBIN_BPW", "2"),
+                                 ("DST_UNBIN_BPW", "8")])
+def test_uneven_launch_shapes_agree(ctx, env):
+    """Every lanes-per-pixel of the group binning and baselines-per-wavefront of the group rescan gives the
+    solve of the default shapes (chosen from each kind's runs per pixel), summation order aside."""
+    import os
+    from paper_1309_5609_amd import dst
+    ps = survey()
+    dps = [dst.to_device(p) for p in ps]
+    _, ref = dst.dst_solve_batched(ctx, dps, tol=1e-13, max_iter=3000)
+    os.environ[env[0]] = env[1]
+    try:
+        c = dst.Context(0)
+    finally:
+        del os.environ[env[0]]
+    try:
+        _, res = dst.dst_solve_batched(c, dps, tol=1e-13, max_iter=3000)
+    finally:
+        c.close()
+    for x, y in zip(res, ref):
+        assert abs(x["iterations"] - y["iterations"]) <= 1
+        assert rel(x["baselines"].cpu().numpy(), y["baselines"].cpu().numpy()) < 1e-10
