@@ -65,5 +65,26 @@ __device__ __forceinline__ void block_sum(T (&v)[N], T* lds) {
   __syncthreads();
 }
 
+// Copies n 4-byte words from global memory to a wavefront's own LDS range
+// through the LDS-direct load path (one word per lane and instruction; lane l
+// writes dst + 4 (i + l)), so a whole stage is in flight at once with no
+// registers.  The source needs 4-byte alignment only.  Call from the whole
+// wavefront with dst uniform; the data are in LDS after lds_copy_wait().
+__device__ __forceinline__ void lds_copy_words(const void* src, void* dst, int n) {
+  const uint32_t* s = static_cast<const uint32_t*>(src);
+  uint32_t* d = static_cast<uint32_t*>(dst);
+  const int lane = lane_id();
+  for (int i = 0; i < n; i += 64) {
+    if (i + lane < n) __builtin_amdgcn_global_load_lds(s + i + lane, d + i, 4, 0, 0);
+  }
+}
+
+// Waits for every outstanding load of the wavefront (the LDS-direct ones
+// included); the wave barrier keeps the compiler from moving LDS reads above.
+__device__ __forceinline__ void lds_copy_wait() {
+  __builtin_amdgcn_s_waitcnt(0);
+  __builtin_amdgcn_wave_barrier();
+}
+
 }  // namespace dev
 }  // namespace dst

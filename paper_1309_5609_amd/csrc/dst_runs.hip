@@ -261,39 +261,17 @@ __global__ void __launch_bounds__(kBlock) k_run_build(View v, const TT* __restri
     const int64_t lo = __shfl(ts, 0, 64), hi = __shfl(te, last, 64);
     const bool staged = hi - lo <= kStage;
     if (staged) {
-      // every load of the span is issued before the first LDS write
-      constexpr int KS = kStage / 64;
+      // the span's angles and timelines go straight into LDS, every row in
+      // flight at once (LDS-direct loads: no registers)
       const int span = (int)(hi - lo);
-      for (int k0 = 0; k0 < kStage / 64; k0 += KS) {
-        PT sp[KS];
-        TT s0[KS], s1[KS], s2[KS];
-#pragma unroll
-        for (int k = 0; k < KS; ++k) {
-          const int i = lane + 64 * (k0 + k);
-          const bool in = i < span;
-          const int64_t t = lo + i;
-          if (SA) sp[k] = in ? psi[t] : PT(0);
-          if (ST) s0[k] = in ? tod[v.rowT * n_t + t] : TT(0);
-          if (SQ) {
-            s1[k] = in ? tod[v.rowQ * n_t + t] : TT(0);
-            s2[k] = in ? tod[v.rowU * n_t + t] : TT(0);
-          }
-        }
-#pragma unroll
-        for (int k = 0; k < KS; ++k) {
-          const int i = lane + 64 * (k0 + k);
-          if (i >= span) break;
-          if (SA) s_psi[SA ? wave : 0][SA ? i : 0] = sp[k];
-          if (ST) s_tod[wave][iT][i] = s0[k];
-          if (SQ) {
-            s_tod[wave][iQ][i] = s1[k];
-            s_tod[wave][SQ ? iU : 0][i] = s2[k];
-          }
-        }
+      if (SA) dev::lds_copy_words(psi + lo, &s_psi[SA ? wave : 0][0], span * (int)sizeof(PT) / 4);
+      const int nw = span * (int)sizeof(TT) / 4;
+      if (ST) dev::lds_copy_words(tod + v.rowT * n_t + lo, &s_tod[wave][iT][0], nw);
+      if (SQ) {
+        dev::lds_copy_words(tod + v.rowQ * n_t + lo, &s_tod[wave][iQ][0], nw);
+        dev::lds_copy_words(tod + v.rowU * n_t + lo, &s_tod[wave][SQ ? iU : 0][0], nw);
       }
-      // LDS operations of one wavefront execute in issue order; the barrier
-      // keeps the compiler from moving the reads above the writes.
-      __builtin_amdgcn_wave_barrier();
+      dev::lds_copy_wait();
     }
     double C = 0.0, S = 0.0, cc = 0.0, cs = 0.0;
     double dT = 0.0, dq = 0.0, du = 0.0, dQ = 0.0, dU = 0.0;
