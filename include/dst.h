@@ -209,7 +209,8 @@ enum {
 typedef struct {
   double tol;               /* stop when ||r||_2 <= tol ||b||_2 (recurrence residual) */
   int32_t max_iter;
-  int32_t check_every;      /* iterations per host convergence check (<= 0: automatic) */
+  int32_t check_every;      /* iterations per host convergence check and per captured graph
+                               (<= 0: 10); iterations past the stop inside a graph do nothing */
   uint32_t flags;
   int32_t restart;          /* GMRES restart length in [1, 126] (0: 50); must be 0 without DST_SOLVE_GMRES */
   const double* a0;         /* device [n_streams][n_b] initial guess, or NULL for 0 */
@@ -311,7 +312,11 @@ int dst_noise_generate(dst_ctx* ctx, uint64_t seed, uint64_t stream_id, int64_t 
  * applies K to every right-hand side in one pass over the pointing, and each
  * problem keeps its own CG scalars and stops when it meets the tolerance
  * (later iterations leave its solution unchanged).  Each problem has its own
- * tod (its tod_dtype may differ).  Problems that share the operator with no
+ * tod (its tod_dtype may differ).  When every problem of such a group has
+ * FP32 angles and timelines, the iterations gather p and the per-pixel map
+ * from FP32 copies (sums, CG scalars and outputs stay FP64): the operator
+ * then carries a relative error near 1e-8, so the true residual levels off
+ * near 1e-9 while the recurrence residual meets tol.  Problems that share the operator with no
  * other are solved one after another as by dst_solve.
  *   n_problems     >= 1
  *   problems       host array [n_problems]
