@@ -1256,6 +1256,13 @@ int gmres_loop(dst_ctx* ctx, Plan& P, const View& v, const double* b, double* a,
   auto slot = [&](int i) { return V + (int64_t)(i + 1) * N; };  // basis vector i
   HIP_TRY(dst::launch_tmask(v, S.J, e, st));
   const double beta = h0.r_norm;
+  if (h0.done == dst::DONE_NAN || !std::isfinite(bnorm) || !std::isfinite(beta)) {
+    // a non-finite right-hand side or start-up residual: nothing to iterate on
+    *fin = h0;
+    fin->iter = 0;
+    fin->done = dst::DONE_NAN;
+    return DST_OK;
+  }
   const double rel0 = bnorm > 0.0 ? beta / bnorm : 0.0;
   const bool run = bnorm > 0.0 && beta > 0.0 && rel0 > opts.tol && opts.max_iter > 0;
   HIP_TRY(dst::launch_gm_init(gs, bnorm, n_e, opts.tol, opts.max_iter, m, beta, rel0,

@@ -263,6 +263,32 @@ def test_errors(ctx):
     assert e.value.code == -5
 
 
+@pytest.mark.parametrize("form", ["runs", "samples", "gmres", "batched", "uneven"])
+def test_nan_timeline_reports_enan(ctx, form):
+    """A non-finite timeline sample makes the CG recurrences non-finite: the solve reports DST_ENAN (-4) instead
+    of returning numbers, and the context stays usable."""
+    from paper_1309_5609_amd import dst
+    p = toy()
+    dp = dev(p)
+    tod = dp.tod.clone()
+    tod[1, 1234] = float("nan")
+    bad = dst.Problem(dp.pix, dp.psi, tod, dp.n_pix, dp.baseline_length, dp.streams, dp.weights)
+    flags = {"runs": 0, "samples": dst.DST_SOLVE_PER_SAMPLE, "gmres": dst.DST_SOLVE_GMRES}.get(form, 0)
+    with pytest.raises(dst.DstError) as e:
+        if form in ("batched", "uneven"):
+            # a realization sharing the pointing (one batched group), or a problem with its own (an uneven group)
+            good = (dst.Problem(dp.pix, dp.psi, dp.tod, dp.n_pix, dp.baseline_length, dp.streams, dp.weights)
+                    if form == "batched" else dev(toy(n_samples=9000, L=300, cfg=326)))
+            rc, _ = dst.dst_solve_batched(ctx, [good, bad], tol=1e-10)
+            if rc != 0:
+                raise dst.DstError(rc, "batched")
+        else:
+            dst.dst_solve(ctx, bad, tol=1e-10, flags=flags)
+    assert e.value.code == -4
+    out = dst.dst_solve(ctx, dp, tol=1e-10, flags=flags)
+    assert out["converged"] == 1
+
+
 def test_autotuned_solve_matches(ctx):
     """The autotuner only changes launch shapes: same iterations (within one), same solution."""
     from paper_1309_5609_amd import dst
