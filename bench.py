@@ -454,6 +454,9 @@ def main() -> int:
     ap.add_argument("--realizations", type=int, default=32, help="batch size of the Monte Carlo form (0: skip)")
     ap.add_argument("--no-uneven", action="store_true", help="skip the uneven survey batch (N_side 512)")
     ap.add_argument("--no-extra", action="store_true", help="only the headline solve and its roofline")
+    ap.add_argument("--no-single-extras", action="store_true",
+                    help="skip the single-problem rows (workload 0, other knee frequencies, FP32, GMRES, noise, "
+                         "per-sample form); the batched rows still run")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="copy 1 GiB device to device once (the reference kernel that scales HBM counters)")
     args = ap.parse_args()
@@ -574,7 +577,7 @@ def main() -> int:
         "true_rel_residual": r0["true_rel_residual"],
     }
 
-    if args.workload == 1 and not args.no_extra:
+    if args.workload == 1 and not args.no_extra and not args.no_single_extras:
         # workload 0: six hours at N_side 64 (cache-resident; microseconds per iteration)
         p0 = workload(0)
         d0 = dst.to_device(p0)

@@ -243,6 +243,24 @@ __global__ void __launch_bounds__(kBlock) k_multi_pixsum(int64_t n_obs, View vc,
 
 // ---------------------------------------------------------------- operator
 
+// Steps of the run loops whose gathers are issued together (each step takes
+// one run per slot of lanes): two in the binning, four in the rescan (four in
+// both, or two in both, measured slower).
+constexpr int kStepsBin = 2, kStepsUnbin = 4;
+
+// Value of v in the lane whose byte address (4 x lane) is a4.
+template <typename T>
+__device__ __forceinline__ T from_lane(int a4, T v) {
+  if constexpr (sizeof(T) == 4) {
+    return __builtin_bit_cast(T, __builtin_amdgcn_ds_bpermute(a4, __builtin_bit_cast(int, v)));
+  } else {
+    static_assert(sizeof(T) == 8, "32- or 64-bit values");
+    const int2 w = __builtin_bit_cast(int2, v);
+    return __builtin_bit_cast(
+        T, make_int2(__builtin_amdgcn_ds_bpermute(a4, w.x), __builtin_amdgcn_ds_bpermute(a4, w.y)));
+  }
+}
+
 __device__ __forceinline__ bool lane_active(int r, int R, const MultiCtl* ctl) {
   return r < R && (ctl == nullptr || ctl->done[r] == DONE_RUNNING);
 }
@@ -281,6 +299,7 @@ __global__ void __launch_bounds__(kBlock) k_multi_bin(View vc, int R, int Rp, co
   const int r0 = (lane & (Rl - 1)) * V;
   const int slot = lane / Rl;
   const int slots = 64 / Rl;
+  const int slot4 = 4 * slot;
   bool actv[V];
   bool any = false;
 #pragma unroll
@@ -300,47 +319,75 @@ __global__ void __launch_bounds__(kBlock) k_multi_bin(View vc, int R, int Rp, co
   const int64_t lo = xcd * per, hi = std::min(n_obs, lo + per);
   for (int64_t c = lo + kb * kWaves + (threadIdx.x >> 6); c < hi; c += nk * kWaves) {
     const int64_t j0 = pstart[c], j1 = pstart[c + 1];
-    double acc[3 * V];  // [row][v]
+    // per realization: sum n p_T, and the four products of the angle sums
+    // with p_Q, p_U (the weights of the rows are applied once per pixel)
+    double aT[V], aCQ[V], aSU[V], aSQ[V], aCU[V];
 #pragma unroll
-    for (int i = 0; i < 3 * V; ++i) acc[i] = 0.0;
-    // The run data of 64 runs at a time are loaded once, one run per lane
+    for (int v = 0; v < V; ++v) aT[v] = aCQ[v] = aSU[v] = aSQ[v] = aCU[v] = 0.0;
+    // The run data of 63 runs at a time are loaded once, one run per lane
     // (coalesced), and handed to the slots by shuffles, so the only loads
-    // left in the run loop are the gathers of p.
-    for (int64_t wb = j0; wb < j1; wb += 64) {
+    // left in the run loop are the gathers of p: those of kStepsBin steps are
+    // issued together, with no branch between them.  Lane 63 never holds a
+    // run (zero length and angle sums, baseline -1), so a step past the
+    // window reads it and gathers row 0 with zero weight.
+    const int o0 = HAS_T ? oT : oQ;  // the first row gathered
+    const GT* pT = p + r0 + o0;
+    const int64_t dQ = oQ - o0, dU = oU - o0;
+    const uint32_t rowB = (uint32_t)(nS * Rp * sizeof(GT));  // bytes per baseline's block of rows
+    for (int64_t wb = j0; wb < j1; wb += 63) {
       const int64_t jl = wb + lane;
-      const bool inw = jl < j1;
+      const bool inw = lane < 63 && jl < j1;
       const int w_b = inw ? pb[jl] : -1;
       const int w_n = (HAS_T && inw) ? pn[jl] : 0;
       const CS2<RT> w_cs = (HAS_QU && inw) ? reinterpret_cast<const CS2<RT>*>(pcs)[jl] : make_cs<RT>(0.0, 0.0);
       const RT w_c = w_cs.x, w_s = w_cs.y;
-      const int nwin = j1 - wb < 64 ? (int)(j1 - wb) : 64;
-#pragma unroll 2
-      for (int k0 = 0; k0 < nwin; k0 += slots) {  // uniform: every lane takes part in the shuffles
-        const int kk = k0 + slot;
-        const int src = kk < nwin ? kk : 0;
-        const int bb = __shfl(w_b, src, 64);
-        const int nn = __shfl(w_n, src, 64);
-        const double C = (double)__shfl(w_c, src, 64), S = (double)__shfl(w_s, src, 64);
-        if (!any || kk >= nwin || bb < 0) continue;
-        const GT* pr = p + (int64_t)bb * nS * Rp + r0;
-        if (HAS_T) {
-          double t[V];
-          load_v<V>(pr + oT, t);
+      const int nwin = j1 - wb < 63 ? (int)(j1 - wb) : 63;
+      for (int k0 = 0; k0 < nwin; k0 += kStepsBin * slots) {  // uniform: every lane takes part in the shuffles
+        int nn[kStepsBin];
+        RT cu[kStepsBin], su[kStepsBin];
+        const GT* pr[kStepsBin];
 #pragma unroll
-          for (int v = 0; v < V; ++v) acc[v] += (double)nn * (w0 * t[v]);
+        for (int u = 0; u < kStepsBin; ++u) {
+          const int a4 = min(4 * (k0 + u * slots) + slot4, 4 * 63);
+          const int bb = from_lane(a4, w_b);
+          nn[u] = from_lane(a4, w_n);
+          cu[u] = from_lane(a4, w_c);
+          su[u] = from_lane(a4, w_s);
+          pr[u] = reinterpret_cast<const GT*>(reinterpret_cast<const char*>(pT) +
+                                              (uint64_t)(uint32_t)max(bb, 0) * rowB);
         }
-        if (HAS_QU) {
-          double tq[V], tu[V];
-          load_v<V>(pr + oQ, tq);
-          load_v<V>(pr + oU, tu);
+        if (!any) continue;
+        double t[kStepsBin][V], tq[kStepsBin][V], tu[kStepsBin][V];
+#pragma unroll
+        for (int u = 0; u < kStepsBin; ++u) {
+          if (HAS_T) load_v<V>(pr[u], t[u]);
+          if (HAS_QU) {
+            load_v<V>(pr[u] + dQ, tq[u]);
+            load_v<V>(pr[u] + dU, tu[u]);
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < kStepsBin; ++u) {
+          const double N = (double)nn[u], C = (double)cu[u], S = (double)su[u];
 #pragma unroll
           for (int v = 0; v < V; ++v) {
-            const double xq = w1 * tq[v], xu = w2 * tu[v];
-            acc[V + v] += C * xq - S * xu;
-            acc[2 * V + v] += S * xq + C * xu;
+            if (HAS_T) aT[v] = fma(N, t[u][v], aT[v]);
+            if (HAS_QU) {
+              aCQ[v] = fma(C, tq[u][v], aCQ[v]);
+              aSU[v] = fma(S, tu[u][v], aSU[v]);
+              aSQ[v] = fma(S, tq[u][v], aSQ[v]);
+              aCU[v] = fma(C, tu[u][v], aCU[v]);
+            }
           }
         }
       }
+    }
+    double acc[3 * V];  // [row][v]: the weighted sums A^T W F p
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+      acc[v] = w0 * aT[v];
+      acc[V + v] = w1 * aCQ[v] - w2 * aSU[v];
+      acc[2 * V + v] = w1 * aSQ[v] + w2 * aCU[v];
     }
     dev::lane_group_sum<3 * V>(acc, Rl);
     if (slot == 0 && any) {
@@ -386,6 +433,7 @@ __global__ void __launch_bounds__(kBlock) k_multi_unbin(View vc, int R, int Rp, 
   const int r0 = (lane & (Rl - 1)) * V;
   const int slot = lane / Rl;
   const int slots = 64 / Rl;
+  const int slot4 = 4 * slot;
   bool actv[V];
   bool any = false;
 #pragma unroll
@@ -400,6 +448,10 @@ __global__ void __launch_bounds__(kBlock) k_multi_unbin(View vc, int R, int Rp, 
   const int64_t per = (n_b + 7) / 8;
   const int64_t x = blockIdx.x & 7, k = blockIdx.x >> 3, nk = gridDim.x >> 3;
   const int64_t lo = x * per, hi = std::min(n_b, lo + per);
+  const int o0 = HAS_T ? oT : oQ;  // the first row gathered
+  const GT* mT = m + r0 + o0;
+  const int64_t dQ = oQ - o0, dU = oU - o0;
+  const uint32_t rowB = (uint32_t)(nS * Rp * sizeof(GT));  // bytes per pixel row block
   double dots[3 * V];  // [kind][v]
 #pragma unroll
   for (int i = 0; i < 3 * V; ++i) dots[i] = 0.0;
@@ -409,39 +461,54 @@ __global__ void __launch_bounds__(kBlock) k_multi_unbin(View vc, int R, int Rp, 
     double acc[3 * V];  // [row][v]
 #pragma unroll
     for (int i = 0; i < 3 * V; ++i) acc[i] = 0.0;
-    // run data of 64 runs at a time: one coalesced load per lane, handed to
-    // the slots by shuffles; the run loop only gathers m
-    for (int64_t wb = rs0; wb < rs1; wb += 64) {
+    // run data of 63 runs at a time: one coalesced load per lane, handed to
+    // the slots by shuffles; the run loop only gathers m, kStepsUnbin steps at
+    // a time with no branch between the gathers (lane 63 holds no run, so a
+    // step past the window reads it and gathers row 0 with zero weight)
+    for (int64_t wb = rs0; wb < rs1; wb += 63) {
       const int64_t jl = wb + lane;
-      const bool inw = jl < rs1;
+      const bool inw = lane < 63 && jl < rs1;
       const int w_c = inw ? tpix[jl] : -1;
       const int w_n = (HAS_T && inw) ? tn[jl] : 0;
       const CS2<RT> w_cs = (HAS_QU && inw) ? reinterpret_cast<const CS2<RT>*>(tcs)[jl] : make_cs<RT>(0.0, 0.0);
       const RT w_C = w_cs.x, w_S = w_cs.y;
-      const int nwin = rs1 - wb < 64 ? (int)(rs1 - wb) : 64;
-#pragma unroll 2
-      for (int k0 = 0; k0 < nwin; k0 += slots) {  // uniform: every lane takes part in the shuffles
-        const int kk = k0 + slot;
-        const int src = kk < nwin ? kk : 0;
-        const int cc = __shfl(w_c, src, 64);
-        const int nn = __shfl(w_n, src, 64);
-        const double C = (double)__shfl(w_C, src, 64), S = (double)__shfl(w_S, src, 64);
-        if (!any || kk >= nwin || cc < 0) continue;
-        const GT* mr = m + (int64_t)cc * nS * Rp + r0;
-        if (HAS_T) {
-          double t[V];
-          load_v<V>(mr + oT, t);
+      const int nwin = rs1 - wb < 63 ? (int)(rs1 - wb) : 63;
+      for (int k0 = 0; k0 < nwin; k0 += kStepsUnbin * slots) {  // uniform: every lane takes part in the shuffles
+        int nn[kStepsUnbin];
+        RT cu[kStepsUnbin], su[kStepsUnbin];
+        const GT* mr[kStepsUnbin];
 #pragma unroll
-          for (int v = 0; v < V; ++v) acc[v] += (double)nn * t[v];
+        for (int u = 0; u < kStepsUnbin; ++u) {
+          const int a4 = min(4 * (k0 + u * slots) + slot4, 4 * 63);
+          const int cc = from_lane(a4, w_c);
+          nn[u] = from_lane(a4, w_n);
+          cu[u] = from_lane(a4, w_C);
+          su[u] = from_lane(a4, w_S);
+          mr[u] = reinterpret_cast<const GT*>(reinterpret_cast<const char*>(mT) +
+                                              (uint64_t)(uint32_t)max(cc, 0) * rowB);
         }
-        if (HAS_QU) {
-          double mQ[V], mU[V];
-          load_v<V>(mr + oQ, mQ);
-          load_v<V>(mr + oU, mU);
+        if (!any) continue;
+        double t[kStepsUnbin][V], mQ[kStepsUnbin][V], mU[kStepsUnbin][V];
+#pragma unroll
+        for (int u = 0; u < kStepsUnbin; ++u) {
+          if (HAS_T) load_v<V>(mr[u], t[u]);
+          if (HAS_QU) {
+            load_v<V>(mr[u] + dQ, mQ[u]);
+            load_v<V>(mr[u] + dU, mU[u]);
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < kStepsUnbin; ++u) {
+          const double N = (double)nn[u], C = (double)cu[u], S = (double)su[u];
 #pragma unroll
           for (int v = 0; v < V; ++v) {
-            acc[V + v] += C * mQ[v] + S * mU[v];
-            acc[2 * V + v] += C * mU[v] - S * mQ[v];
+            if (HAS_T) acc[v] = fma(N, t[u][v], acc[v]);
+            if (HAS_QU) {
+              acc[V + v] = fma(C, mQ[u][v], acc[V + v]);
+              acc[V + v] = fma(S, mU[u][v], acc[V + v]);
+              acc[2 * V + v] = fma(C, mU[u][v], acc[2 * V + v]);
+              acc[2 * V + v] = fma(-S, mQ[u][v], acc[2 * V + v]);
+            }
           }
         }
       }
