@@ -72,6 +72,8 @@ VARIANTS = {
     "QU": (3, dict(streams="QU")),
     "T": (2, dict(streams="T")),
     "L37": (3, dict(n_samples=3001, L=37)),
+    # about 100 runs per pixel: the binning goes through several 63-run windows per pixel
+    "dense": (3, dict(n_samples=60000, L=16, nside=2)),
 }
 
 
