@@ -97,7 +97,7 @@ def key_bits(n: int) -> int:
 
 
 def model_bytes(n_t: int, n_obs: int, n_b: int, s_psi: int, n_streams: int = 3) -> dict:
-    """Algorithmic bytes of one CG iteration in the per-sample form of the method (the survey's model).
+    """Algorithmic bytes of one CG iteration in the per-sample form of the method (the per-sample byte model).
 
     bin:   per sample the pixel (4 B) and angle (s_psi); per observed pixel the
            block inverse read (4 x 8 B; 8 B intensity only) and the map written
