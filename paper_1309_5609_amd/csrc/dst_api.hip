@@ -488,7 +488,7 @@ int build_runs_plan(dst_ctx* ctx, const dst_problem* prob, Plan& P, const void* 
                           S.counts, st));
   S.v = v;
   S.v.n_pix = W.n_obs;
-  HIP_TRY(dst::launch_rhs_runs(S.v, W, tod, m4d, S.valid, S.nvalid, S.J, b, st));
+  HIP_TRY(dst::launch_rhs_runs(S.v, W, tod, S.tod_f32, m4d, S.valid, S.nvalid, S.J, b, st));
   dst::ChainSource cs;
   cs.bstart = W.bstart;
   cs.tkey = W.nb ? W.tkey : reinterpret_cast<const uint32_t*>(W.tpix);

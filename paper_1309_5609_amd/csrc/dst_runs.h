@@ -71,7 +71,8 @@ struct Runs {
   int32_t* tpix = nullptr;
   int32_t* tn = nullptr;
   void* tcs = nullptr;  // [2 R] CS2 pairs per run, time order
-  double* raw = nullptr;       // [3 R] sums of d_T, d_q, d_u per run (time order); [R] (d_T) for T only
+  double* raw = nullptr;       // [3 R] ([R] for T only), time order: at each run that ends its baseline or a
+                               // 64-run window, the sums of d_T, d_q, d_u over the baseline's runs in the window
   RunRecord* rec = nullptr;    // [R] per-run records (time order); RunRecordT for T only
   uint32_t* keys[2] = {nullptr, nullptr};
   uint32_t* vals[2] = {nullptr, nullptr};
@@ -117,9 +118,11 @@ hipError_t runs_count(const View& v, Runs& W, int* err, hipStream_t st);
 hipError_t runs_build(const View& v, int psi_f32, const void* tod, int tod_f32, double rcond_cut, Runs& W,
                       int32_t* hits, double* Minv4, uint8_t* valid, double* m4_zero, double* sd4, double* md4,
                       unsigned long long* counts, hipStream_t st);
-// Per baseline: n_valid, Jacobi diagonal, and with tod b = F^T W (d - A m_d).
-hipError_t launch_rhs_runs(const View& vc, const Runs& W, const void* tod, const double* md4, const uint8_t* valid,
-                           int32_t* nvalid, double* J, double* b, hipStream_t st);
+// Per baseline: n_valid, Jacobi diagonal, and with tod b = F^T W (d - A m_d)
+// (tod as given to runs_build; the data part comes from the run build's
+// per-baseline window sums, less the runs on pixels left out of the map).
+hipError_t launch_rhs_runs(const View& vc, const Runs& W, const void* tod, int tod_f32, const double* md4,
+                           const uint8_t* valid, int32_t* nvalid, double* J, double* b, hipStream_t st);
 // Lanes per pixel of the binning for `runs` runs over n_obs pixels
 // (t_only: an intensity-only problem).
 int bin_lanes_for(int64_t runs, int64_t n_obs, bool t_only);

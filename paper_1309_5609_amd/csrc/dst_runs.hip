@@ -331,23 +331,49 @@ __global__ void __launch_bounds__(kBlock) k_run_build(View v, const TT* __restri
       }
     }
     if (staged) __builtin_amdgcn_wave_barrier();  // reads done before the next stage overwrites
+    if (TOD) {
+      // sums of d over the wavefront's runs of each baseline (the data part
+      // of b = F^T Z d before the invalid pixels' runs are taken out): a scan
+      // inside each stretch of lanes with the same baseline; the stretch's
+      // last lane stores it at its run, so that raw holds, at every run that
+      // ends a baseline or a 64-run window, the sum over that baseline's runs
+      // in the window (the other entries are never read)
+      const int bl = has ? (int)(ts / v.L) : -1 - lane;
+      double s0 = dT, s1 = dq, s2 = du;
+#pragma unroll
+      for (int off = 1; off < 64; off <<= 1) {
+        const int bo = __shfl_up(bl, off, 64);
+        const double a0 = __shfl_up(s0, off, 64);
+        const double a1 = TONLY ? 0.0 : __shfl_up(s1, off, 64);
+        const double a2 = TONLY ? 0.0 : __shfl_up(s2, off, 64);
+        if (lane >= off && bo == bl) {
+          s0 += a0;
+          s1 += a1;
+          s2 += a2;
+        }
+      }
+      const int bn = __shfl_down(bl, 1, 64);
+      if (has && (lane == 63 || bn != bl)) {
+        if (TONLY) {
+          raw[r] = s0;
+        } else {
+          raw[3 * r + 0] = s0;
+          raw[3 * r + 1] = s1;
+          raw[3 * r + 2] = s2;
+        }
+      }
+    }
     if (!has) continue;
     rpix[r] = v.pix[ts];
     rn[r] = n;
     if (SA) reinterpret_cast<CS2<RT>*>(rcs)[r] = make_cs<RT>(C, S);
     if (TONLY) {
-      if (TOD) raw[r] = dT;
       RunRecordT x;
       x.n = n;
       x.b = (int32_t)(ts / v.L);
       x.dT = dT;
       reinterpret_cast<RunRecordT*>(rec)[r] = x;
       continue;
-    }
-    if (TOD) {
-      raw[3 * r + 0] = dT;
-      raw[3 * r + 1] = dq;
-      raw[3 * r + 2] = du;
     }
     RunRecord x;
     x.n = n;
@@ -669,13 +695,14 @@ __global__ void __launch_bounds__(kBlock) k_compact_baselines(int64_t n_b, int64
 //   b_k = w_k sum_{runs, valid_k} (sum of d_k over the run - A-weighted m_d).
 // The rescan's layout: 16 lanes per baseline, four baselines per wavefront in
 // the rescan order, the loads of four runs per lane issued together.
-template <typename RT, bool HAS_T, bool HAS_QU, bool IQU, bool TOD, bool PK>
+template <typename RT, typename TT, bool HAS_T, bool HAS_QU, bool IQU, bool TOD, bool PK>
 __global__ void __launch_bounds__(kBlock) k_rhs_runs(View v, const uint32_t* __restrict__ bstart,
                                                      const uint32_t* __restrict__ border,
                                                      const uint32_t* __restrict__ rkey,
                                                      const int32_t* __restrict__ rn, int nb,
                                                      const RT* __restrict__ rcs,
                                                      const double* __restrict__ raw, const double* __restrict__ md4,
+                                                     const TT* __restrict__ tod, const uint32_t* __restrict__ t0,
                                                      const uint8_t* __restrict__ valid, int32_t* __restrict__ nvalid,
                                                      double* __restrict__ J, double* __restrict__ b_out) {
   constexpr int BPW = 4, SEG = 64 / BPW;
@@ -725,17 +752,43 @@ __global__ void __launch_bounds__(kBlock) k_rhs_runs(View v, const uint32_t* __r
         if (c[u] < 0) continue;
         const int64_t r = rb + SEG * u;
         const double n = (double)nn[u];
-        const double* m = raw + (HAS_T && !HAS_QU && !IQU ? 1 : 3) * r;
+        constexpr int RW = HAS_T && !HAS_QU && !IQU ? 1 : 3;  // raw sums per run
+        if (TOD && ((r & 63) == 63 || r == r1 - 1)) {
+          // the run ends the baseline or a 64-run window: raw holds the sums
+          // of d over the baseline's runs in that window
+          if (HAS_T || IQU) acc[0] += raw[RW * r];
+          if (HAS_QU && !IQU) {
+            acc[1] += raw[RW * r + 1];
+            acc[2] += raw[RW * r + 2];
+          }
+        }
+        const bool tin = (HAS_T || IQU) && !(f[u] & 1), qin = HAS_QU && !IQU && !(f[u] & 2);
+        if (TOD && (tin || qin)) {
+          // a run on a pixel left out of the map (for T or for q/u): its own
+          // sums of d come out of the baseline's data part again
+          const int64_t ts = t0[r];
+          double sT = 0.0, sq = 0.0, su = 0.0;
+          for (int k = 0; k < nn[u]; ++k) {
+            if (tin) sT += (double)tod[v.rowT * v.n_t + ts + k];
+            if (qin) {
+              sq += (double)tod[v.rowQ * v.n_t + ts + k];
+              su += (double)tod[v.rowU * v.n_t + ts + k];
+            }
+          }
+          acc[0] -= sT;
+          acc[1] -= sq;
+          acc[2] -= su;
+        }
         if (IQU && (f[u] & 1)) {
           acc[3] += n;
           if (TOD) {
             const CS2<RT> cs = reinterpret_cast<const CS2<RT>*>(rcs)[r];
             const double C = (double)cs.x, S = (double)cs.y;
-            acc[0] += m[0] - (n * m01[u].x + C * m01[u].y + S * m2x[u]);
+            acc[0] -= n * m01[u].x + C * m01[u].y + S * m2x[u];
           }
         } else if (HAS_T && (f[u] & 1)) {
           acc[3] += n;
-          if (TOD) acc[0] += m[0] - n * m01[u].x;
+          if (TOD) acc[0] -= n * m01[u].x;
         }
         if (HAS_QU && (f[u] & 2)) {
           acc[4] += n;
@@ -743,8 +796,8 @@ __global__ void __launch_bounds__(kBlock) k_rhs_runs(View v, const uint32_t* __r
             const CS2<RT> cs = reinterpret_cast<const CS2<RT>*>(rcs)[r];
             const double C = (double)cs.x, S = (double)cs.y;
             const double mQ = m01[u].y, mU = m2x[u];
-            acc[1] += m[1] - (C * mQ + S * mU);
-            acc[2] += m[2] - (C * mU - S * mQ);
+            acc[1] -= C * mQ + S * mU;
+            acc[2] -= C * mU - S * mQ;
           }
         }
       }
@@ -1484,20 +1537,24 @@ hipError_t runs_build(const View& v, int psi_f32, const void* tod, int tod_f32, 
   return hipGetLastError();
 }
 
-hipError_t launch_rhs_runs(const View& vc, const Runs& W, const void* tod, const double* md4, const uint8_t* valid,
-                           int32_t* nvalid, double* J, double* b, hipStream_t st) {
+hipError_t launch_rhs_runs(const View& vc, const Runs& W, const void* tod, int tod_f32, const double* md4,
+                           const uint8_t* valid, int32_t* nvalid, double* J, double* b, hipStream_t st) {
   const int64_t n_g = ((vc.n_b + 3) / 4 + kWaves - 1) / kWaves;  // four baselines per wavefront
   const unsigned g = (unsigned)(8 * ((n_g + 7) / 8));
   by_float(W.f32, [&](auto rt) {
     using RT = typename decltype(rt)::type;
-    by_streams(vc, [&](auto T, auto Q, auto I) {
-      by_bool(tod != nullptr, [&](auto D) {
-        by_bool(W.nb != 0, [&](auto K) {
-          hipLaunchKernelGGL((k_rhs_runs<RT, decltype(T)::value, decltype(Q)::value, decltype(I)::value,
-                                          decltype(D)::value, decltype(K)::value>),
-                             dim3(g), dim3(kBlock), 0, st, vc, W.bstart, W.border,
-                             W.nb ? W.tkey : reinterpret_cast<const uint32_t*>(W.tpix), W.tn, W.nb,
-                             static_cast<const RT*>(W.tcs), W.raw, md4, valid, nvalid, J, b);
+    by_float(tod_f32 != 0, [&](auto tt) {
+      using TT = typename decltype(tt)::type;
+      by_streams(vc, [&](auto T, auto Q, auto I) {
+        by_bool(tod != nullptr, [&](auto D) {
+          by_bool(W.nb != 0, [&](auto K) {
+            hipLaunchKernelGGL((k_rhs_runs<RT, TT, decltype(T)::value, decltype(Q)::value, decltype(I)::value,
+                                            decltype(D)::value, decltype(K)::value>),
+                               dim3(g), dim3(kBlock), 0, st, vc, W.bstart, W.border,
+                               W.nb ? W.tkey : reinterpret_cast<const uint32_t*>(W.tpix), W.tn, W.nb,
+                               static_cast<const RT*>(W.tcs), W.raw, md4, static_cast<const TT*>(tod), W.t0,
+                               valid, nvalid, J, b);
+          });
         });
       });
     });
