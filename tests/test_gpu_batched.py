@@ -29,10 +29,15 @@ def ctx():
     c.close()
 
 
-def family(n_real, make=toy, scan=TOY_SCAN, **kw):
-    """n_real problems on one pointing and sky; realization r draws its own noise."""
+def family(n_real, make=toy, scan=TOY_SCAN, freeze_every=0, **kw):
+    """n_real problems on one pointing and sky; realization r draws its own noise.  freeze_every > 0: one fixed
+    angle on every freeze_every-th observed pixel (shared by all realizations)."""
     base = make(**kw)
     psi = base.psi if base.psi is not None else pointing(scan, base.nside, base.n_samples)[1]
+    if freeze_every:
+        psi = np.array(psi, copy=True)
+        psi[np.isin(base.pix, np.unique(base.pix[base.pix >= 0])[::freeze_every])] = 0.4
+        base.psi = psi
     kw2 = {k: v for k, v in kw.items() if k != "mask_fraction"}
     out = [base]
     for r in range(1, n_real):
@@ -74,6 +79,8 @@ VARIANTS = {
     "L37": (3, dict(n_samples=3001, L=37)),
     # about 100 runs per pixel: the binning goes through several 63-run windows per pixel
     "dense": (3, dict(n_samples=60000, L=16, nside=2)),
+    # a weak u stream and one fixed angle on every fifth pixel: 22 of 88 q/u blocks fail the cut
+    "qucut": (3, dict(weights=(1.0e6, 1.0e6, 1.0e2), freeze_every=5)),
 }
 
 

@@ -50,11 +50,21 @@ VARIANTS = {
     "fewpix": dict(nside=1, n_samples=200000, L=50),
     # baselines longer than a 4096-sample tile of the run detection, with masked samples
     "longbase": dict(n_samples=23011, L=5003, mask_fraction=0.05),
+    # a weak u stream and one fixed angle on every fifth pixel: their q/u blocks fail the
+    # condition cut (22 of 88 pixels), so their runs leave the q/u right-hand side
+    "qucut": dict(weights=(1.0e6, 1.0e6, 1.0e2), freeze_every=5),
 }
 
 
 def make(name):
-    return toy(**VARIANTS[name])
+    kw = dict(VARIANTS[name])
+    every = kw.pop("freeze_every", 0)
+    p = toy(**kw)
+    if every:
+        frozen = np.unique(p.pix[p.pix >= 0])[::every]
+        p.psi = np.array(p.psi, copy=True)
+        p.psi[np.isin(p.pix, frozen)] = 0.4
+    return p
 
 
 @pytest.mark.parametrize("name", list(VARIANTS))
