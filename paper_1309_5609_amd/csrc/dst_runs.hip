@@ -94,11 +94,6 @@ __device__ __forceinline__ void sym3_eig_range(double a00, double a01, double a0
   lmin = q + 2.0 * pp * cos(phi + 2.0943951023931957);  // + 2 pi / 3
 }
 
-__global__ void __launch_bounds__(kBlock) k_iota(uint32_t* __restrict__ x, int64_t n) {
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-    x[i] = (uint32_t)i;
-}
-
 unsigned grid_for(int64_t n, int64_t per_block, unsigned cap) {
   int64_t g = (n + per_block - 1) / per_block;
   if (g < 1) g = 1;
@@ -181,10 +176,12 @@ __global__ void __launch_bounds__(kBlock) k_tile_heads(const int32_t* __restrict
 
 // First sample of each run (t0, time order) and the first run of each
 // baseline (bstart); toff = exclusive scan of the tile counts, R runs in all.
+// skey / sval: each run's pixel and index, the input of the sort by pixel.
 __global__ void __launch_bounds__(kBlock) k_tile_starts(const int32_t* __restrict__ pix, int64_t n_t, int64_t n_pix,
                                                         int64_t L, uint32_t smask, int64_t n_b, int64_t n_tiles,
                                                         const uint32_t* __restrict__ toff, uint32_t R,
-                                                        uint32_t* __restrict__ t0, uint32_t* __restrict__ bstart) {
+                                                        uint32_t* __restrict__ t0, uint32_t* __restrict__ bstart,
+                                                        uint32_t* __restrict__ skey, uint32_t* __restrict__ sval) {
   const int lane = lane_id();
   const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));  // lanes below this one
   const int64_t nw = (int64_t)gridDim.x * kWaves;
@@ -198,7 +195,11 @@ __global__ void __launch_bounds__(kBlock) k_tile_starts(const int32_t* __restric
       for (int k = 0; k < kChunks; ++k) {
         const int64_t t = c0 + 64 * k + lane;
         const uint32_t idx = run + (uint32_t)__popcll(h.head[k] & lt);
-        if ((h.head[k] >> lane) & 1ull) t0[idx] = (uint32_t)t;
+        if ((h.head[k] >> lane) & 1ull) {
+          t0[idx] = (uint32_t)t;
+          skey[idx] = (uint32_t)h.p[k];  // the run's pixel and index: the sort's input
+          sval[idx] = idx;
+        }
         if (t < z && ((uint32_t)t % (uint32_t)L) == 0u) bstart[(uint32_t)t / (uint32_t)L] = idx;
         run += (uint32_t)__popcll(h.head[k]);
       }
@@ -209,7 +210,8 @@ __global__ void __launch_bounds__(kBlock) k_tile_starts(const int32_t* __restric
 
 // One thread per run: length, sums of cos 2psi and sin 2psi, and the setup
 // sums.  Time-order outputs feed the rescan and the right-hand side (pixel,
-// length, C, S, and the sums of d_T, d_q, d_u); a 64-byte record per run
+// length, C, S, and per baseline and 64-run window the sums of d_T, d_q,
+// d_u); a 64-byte record per run
 // feeds the per-pixel setup, which reads it in pixel order with one aligned
 // access.  Samples are summed in time order.  A wavefront takes 64
 // consecutive runs; when the samples they span fit kStage, the wavefront
@@ -1436,7 +1438,8 @@ hipError_t runs_build(const View& v, int psi_f32, const void* tod, int tod_f32, 
   const unsigned g = grid_for(n_t, kBlock, 8192);
   // 1. run starts and per-baseline run ranges
   hipLaunchKernelGGL(k_tile_starts, dim3(grid_for(run_tiles(n_t), kWaves, 8192)), dim3(kBlock), 0, st, v.pix, n_t,
-                     v.n_pix, v.L, W.smask, v.n_b, run_tiles(n_t), W.toff, (uint32_t)R, W.t0, W.bstart);
+                     v.n_pix, v.L, W.smask, v.n_b, run_tiles(n_t), W.toff, (uint32_t)R, W.t0, W.bstart, W.keys[0],
+                     W.vals[0]);
   DST_CHECK(hipGetLastError());
   // 2. run records and setup moments (time order)
   const bool pf = psi_f32 && (v.rowQ >= 0 || v.iqu);
@@ -1462,9 +1465,6 @@ hipError_t runs_build(const View& v, int psi_f32, const void* tod, int tod_f32, 
   DST_CHECK(hipGetLastError());
   // 3. runs sorted by pixel (stable: time order inside a pixel)
   const unsigned gr = grid_for(R, kBlock, 8192);
-  DST_CHECK(hipMemcpyAsync(W.keys[0], W.tpix, R * sizeof(uint32_t), hipMemcpyDeviceToDevice, st));
-  hipLaunchKernelGGL(k_iota, dim3(gr), dim3(kBlock), 0, st, W.vals[0], R);
-  DST_CHECK(hipGetLastError());
   {
     rocprim::double_buffer<uint32_t> keys(W.keys[0], W.keys[1]);
     rocprim::double_buffer<uint32_t> vals(W.vals[0], W.vals[1]);
