@@ -218,6 +218,9 @@ __global__ void __launch_bounds__(kBlock) k_tile_starts(const int32_t* __restric
 // first copies them (angles and timelines) into LDS with coalesced loads and
 // each lane then reads its run from there.
 constexpr int kStage = 256;
+// Runs per wavefront of the run build: windows [k kRunWindow, (k + 1) kRunWindow)
+// of the time-order runs, whose per-baseline sums of d the right-hand side reads.
+constexpr int kRunWindow = 64;
 
 template <typename PT, typename TT, typename RT, bool HAS_T, bool HAS_QU, bool IQU, bool TOD>
 __global__ void __launch_bounds__(kBlock) k_run_build(View v, const TT* __restrict__ tod,
@@ -240,7 +243,9 @@ __global__ void __launch_bounds__(kBlock) k_run_build(View v, const TT* __restri
   constexpr int iT = 0, iQ = ST ? 1 : 0, iU = iQ + 1;
   constexpr int U = 2;  // samples whose loads are issued together (direct path)
   const bool gaps = *n_out != 0;
-  for (int64_t rb = ((int64_t)blockIdx.x * kWaves + wave) * 64; rb < R; rb += (int64_t)gridDim.x * kWaves * 64) {
+  static_assert(kRunWindow == 64, "one run per lane");
+  for (int64_t rb = ((int64_t)blockIdx.x * kWaves + wave) * kRunWindow; rb < R;
+       rb += (int64_t)gridDim.x * kWaves * kRunWindow) {
     const int64_t r = rb + lane;
     const bool has = r < R;
     int64_t ts = 0, te = 0;
@@ -355,7 +360,7 @@ __global__ void __launch_bounds__(kBlock) k_run_build(View v, const TT* __restri
         }
       }
       const int bn = __shfl_down(bl, 1, 64);
-      if (has && (lane == 63 || bn != bl)) {
+      if (has && (lane == kRunWindow - 1 || bn != bl)) {
         if (TONLY) {
           raw[r] = s0;
         } else {
@@ -695,8 +700,11 @@ __global__ void __launch_bounds__(kBlock) k_compact_baselines(int64_t n_b, int64
 
 // Per baseline (time-order runs): n_valid, the Jacobi diagonal and with TOD
 //   b_k = w_k sum_{runs, valid_k} (sum of d_k over the run - A-weighted m_d).
-// The rescan's layout: 16 lanes per baseline, four baselines per wavefront in
-// the rescan order, the loads of four runs per lane issued together.
+// The sums of d come from the run build's per-window sums (all runs of the
+// baseline) less the runs on pixels not valid for stream k, whose samples are
+// read again here.  The rescan's layout: 16 lanes per baseline, four
+// baselines per wavefront in the rescan order, the loads of four runs per
+// lane issued together.
 template <typename RT, typename TT, bool HAS_T, bool HAS_QU, bool IQU, bool TOD, bool PK>
 __global__ void __launch_bounds__(kBlock) k_rhs_runs(View v, const uint32_t* __restrict__ bstart,
                                                      const uint32_t* __restrict__ border,
@@ -755,7 +763,7 @@ __global__ void __launch_bounds__(kBlock) k_rhs_runs(View v, const uint32_t* __r
         const int64_t r = rb + SEG * u;
         const double n = (double)nn[u];
         constexpr int RW = HAS_T && !HAS_QU && !IQU ? 1 : 3;  // raw sums per run
-        if (TOD && ((r & 63) == 63 || r == r1 - 1)) {
+        if (TOD && (r % kRunWindow == kRunWindow - 1 || r == r1 - 1)) {
           // the run ends the baseline or a 64-run window: raw holds the sums
           // of d over the baseline's runs in that window
           if (HAS_T || IQU) acc[0] += raw[RW * r];
