@@ -1515,7 +1515,10 @@ hipError_t runs_build(const View& v, int psi_f32, const void* tod, int tod_f32, 
     W.nb = (int)nb;
   // 5. per-pixel setup from the runs; pixel-order run arrays and keys
   if (W.n_obs > 0) {
-    const unsigned gw = grid_for(W.n_obs, 2 * kWaves, 4096);  // two pixels per wavefront
+    // two pixels per wavefront; at most 16384 workgroups, each taking pixels
+    // 131072 apart (4096: setup +0.04 ms, 1024: +0.24 ms; one step per
+    // workgroup, about 39000 of them: +1.0 ms)
+    const unsigned gw = grid_for(W.n_obs, 2 * kWaves, 16384);
     by_float(W.f32, [&](auto rt) {
       using RT = typename decltype(rt)::type;
       by_streams(v, [&](auto T, auto Q, auto I) {
